@@ -1,0 +1,182 @@
+/*
+ * cox.h -- C ABI of libcoxhip: l1-regularised Cox proportional-hazards
+ * regression by proximal gradient (ISTA) on one AMD Instinct MI355X (gfx950).
+ *
+ * The problem (Ko, Zhou, Zhou and Won, "DistStat.jl", Section 5.3): subjects
+ * i = 1..n with covariate row x_i (p SNPs), observed time y_i = min(t_i, c_i)
+ * and event indicator delta_i.  The Breslow log partial likelihood is
+ *     L(beta) = sum_i delta_i [ eta_i - log sum_{j: y_j >= y_i} exp(eta_j) ],
+ *     eta = X~ beta,
+ * (ties share their risk set, Breslow's convention of Section 6), and the
+ * library minimises  f_lambda(beta) = -L(beta) + lambda ||beta||_1,  the
+ * minimisation form of the paper's "maximise L - lambda ||beta||_1", with the
+ * iteration of Section 5.3:
+ *     w = exp(eta),  W_j = sum_{i: y_i >= y_j} w_i,
+ *     r = (I - P) delta,  P_ij = 1(y_i >= y_j) w_i / W_j,
+ *     beta <- S_{sigma lambda}(beta + sigma X~' r)
+ * where S is the soft-thresholding operator of Section 4.2 and sigma the step.
+ * (The paper writes the threshold as lambda; the threshold of the proximal map
+ * of sigma * lambda ||.||_1 is sigma * lambda, which is what is used here.)
+ *
+ * Data layout.  X is dense, column-major (each SNP column contiguous), n rows
+ * by p columns with leading dimension ldx >= n, the column split of Section
+ * 4.1.  X~ is X itself for COX_X_F32.  For the 1-byte genotype types X holds
+ * allele counts g and X~_ij = (g_ij - col_center[j]) * col_scale[j] is formed
+ * on the fly (NULL center = 0, NULL scale = 1).  Vectors for B coefficient
+ * vectors are stored b-major: beta[b*p + j], eta[b*n + i].
+ *
+ * Conventions shared by every entry point.
+ *  - Return value: a cox_status.  No C++ exception or abort crosses the ABI.
+ *  - Argument errors are detected before any device work and leave outputs and
+ *    the context untouched (COX_ERR_INVALID_ARG).
+ *  - Pointers marked "dev" are device memory of the context's GPU; "host" are
+ *    host memory.  The caller owns every buffer it passes.  X, col_center and
+ *    col_scale are BORROWED: they must stay valid and unchanged until
+ *    cox_destroy; X is never copied.
+ *  - All device work is ordered on the stream given to cox_setup.  Entry points
+ *    that return host values synchronise that stream before returning;
+ *    device outputs are otherwise stream-ordered.
+ *  - A context is not thread-safe; use one context per stream.
+ *  - Results are deterministic: no floating-point atomics, fixed reduction order.
+ */
+#ifndef COX_H
+#define COX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cox_ctx cox_ctx;
+
+typedef enum {
+    COX_OK = 0,
+    COX_ERR_INVALID_ARG = 1,   /* bad shape, pointer, time, event, batch size or option */
+    COX_ERR_OUT_OF_MEMORY = 2, /* device or host allocation failed; nothing leaked */
+    COX_ERR_DEVICE = 3,        /* a HIP runtime call failed */
+    COX_ERR_NUMERIC = 4,       /* the loss or the gradient became non-finite */
+    COX_ERR_NOT_CONVERGED = 5, /* max_iter reached; outputs are valid */
+    COX_ERR_UNSUPPORTED = 6    /* valid request this build does not serve */
+} cox_status;
+
+typedef enum {
+    COX_X_F32 = 0,      /* float, used as given */
+    COX_X_FP8_E4M3 = 1, /* OCP FP8 E4M3 (e4m3fn) codes of the allele counts */
+    COX_X_INT8 = 2      /* signed 8-bit allele counts */
+} cox_xtype;
+
+typedef struct {
+    const void *X;           /* dev, column-major, element (i, j) at X[j*ldx + i]; borrowed */
+    int32_t xtype;           /* cox_xtype */
+    int64_t n, p, ldx;       /* 1 <= n < 2^31, 1 <= p < 2^31, ldx >= n */
+    const float *col_center; /* dev [p] or NULL: genotype centre mu_j; borrowed; 1-byte types only */
+    const float *col_scale;  /* dev [p] or NULL: genotype scale s_j (1/SD); borrowed; 1-byte types only */
+} cox_matrix;
+
+/* Create a context for one data set (Section 5.3's X, y, delta).
+ *   time  host [n], finite observed times y_i; copied.  Subjects are ordered
+ *         internally by non-increasing time (stable by index), so the risk-set
+ *         sums become cumulative sums (Section 5.3); tied times form Breslow
+ *         groups (Section 6).
+ *   event host [n], each 0 (censored) or 1 (event); copied.
+ *   max_batch  the largest B any later call passes (1..64); sizes the workspace.
+ *   hip_stream a hipStream_t (NULL: the default stream).
+ * Returns INVALID_ARG (bad X descriptor, ldx < n, non-finite time, event not
+ * 0/1, max_batch out of range, NULL pointers), OUT_OF_MEMORY or DEVICE on
+ * failure, with *out set to NULL. */
+cox_status cox_setup(cox_ctx **out, const cox_matrix *X, const double *time, const int32_t *event,
+                     int32_t max_batch, void *hip_stream);
+
+/* Free the context's workspace.  NULL is accepted. */
+cox_status cox_destroy(cox_ctx *ctx);
+
+/* Static text for a status code. */
+const char *cox_status_string(cox_status s);
+
+/* Human-readable detail of the last error on ctx (empty if none), NUL-terminated
+ * into buf[len].  INVALID_ARG if ctx or buf is NULL or len is 0. */
+cox_status cox_last_error(const cox_ctx *ctx, char *buf, size_t len);
+
+/* Value and gradient of the NEGATIVE log partial likelihood, -L(beta_b), for B
+ * coefficient vectors (Section 5.3: the gradient of L is X~'(I - P) delta).
+ *   beta  dev [B][p] float
+ *   loss  host [B] double: -L(beta_b)
+ *   grad  dev [B][p] float, or NULL for the loss only: -X~' r_b
+ * NUMERIC if a loss is non-finite (e.g. NaN in beta). Synchronises. */
+cox_status cox_loss_grad(cox_ctx *ctx, const float *beta, int32_t B, double *loss, float *grad);
+
+/* One proximal-gradient (ISTA) step in place for each b (Section 5.3):
+ *   beta_b <- S_{step*lambda_b}(beta_b + step * X~' r_b)
+ *   beta        dev [B][p] float, in/out
+ *   lambdas     host [B], each >= 0 and finite
+ *   step        sigma > 0
+ *   obj_before  host [B] or NULL: f_lambda_b(beta_b) before the step.
+ * Synchronises when obj_before is not NULL. */
+cox_status cox_prox_step(cox_ctx *ctx, float *beta, int32_t B, const double *lambdas, double step,
+                         double *obj_before);
+
+/* Apply the soft-threshold update alone (the elementwise kernel), given a
+ * gradient of the negative log likelihood:
+ *   beta_b <- S_{step*lambda_b}(beta_b - step * grad_b)
+ *   beta dev [B][p] in/out; grad dev [B][p]; lambdas host [B] >= 0; step > 0. */
+cox_status cox_prox_apply(cox_ctx *ctx, float *beta, const float *grad, int32_t B, const double *lambdas,
+                          double step);
+
+typedef struct {
+    int32_t max_iter;   /* >= 0: the largest number of steps for each b */
+    double tol;         /* >= 0: stop b when |f_k - f_{k-lag}| / (|f_k| + 1) < tol (Section 6); 0: never */
+    int32_t lag;        /* 1..32; the paper uses 10 */
+    double step;        /* > 0: sigma; <= 0: 1 / (2 ||X~||_2^2) from cox_opnorm2 (Section 5.3) */
+    int32_t warm_start; /* 1: start from the beta passed in; 0: start from beta = 0 */
+    int32_t eta_mode;   /* 0: eta updated from the columns whose beta changed (FP64 accumulator);
+                           1: eta recomputed by a dense pass over X every step (two X passes) */
+    int32_t poll;       /* steps between host checks of the convergence flags; <= 0: 16 */
+} cox_fit_opts;
+
+/* Solve B problems (one per lambda_b) by ISTA, all sharing each pass over X.
+ * For each b, from beta_0 (0, or the input when warm_start): at step k the
+ * objective f_k = f_lambda_b(beta_k) is evaluated; b stops at the first k with
+ * k >= lag and |f_k - f_{k-lag}| / (|f_k| + 1) < tol, or at k = max_iter; else
+ * beta_{k+1} = S_{sigma lambda_b}(beta_k + sigma X~' r).
+ *   lambdas host [B] >= 0; opts host (NULL: max_iter 1000, tol 1e-5, lag 10,
+ *           step from cox_opnorm2, cold start, eta_mode 0, poll 16)
+ *   beta  dev [B][p] float: the start if warm_start, and the result beta_{k_b}
+ *   iters host [B] or NULL: k_b, the number of steps taken
+ *   obj   host [B] or NULL: f_lambda_b(beta_{k_b})
+ * Returns OK when every b met the tolerance, NOT_CONVERGED (outputs valid) when
+ * some b reached max_iter, NUMERIC on a non-finite objective.  Synchronises. */
+cox_status cox_fit_path(cox_ctx *ctx, const double *lambdas, int32_t B, const cox_fit_opts *opts, float *beta,
+                        int32_t *iters, double *obj);
+
+/* lambda_max = ||X~' r(0)||_inf, the smallest lambda for which beta = 0 is a
+ * fixed point of the iteration.  At beta = 0 every w_i = 1 and r is delta minus
+ * the Breslow cumulative hazard.  host [1].  Synchronises. */
+cox_status cox_lambda_max(cox_ctx *ctx, double *lambda_max);
+
+/* ||X~||_2^2 by power iteration on X~'X~ (Section 4.3, opnorm(X, 2;
+ * method = "power"); the paper's defaults are tol 1e-6, maxiter 1000, seed
+ * 95376).  Start vector: entries uniform on [-1, 1) from SplitMix64 seeded
+ * with `seed` (top 53 bits of each output), normalised.  Stops when the
+ * estimate changes by less than tol relative to itself.  Centring is exact.
+ *   s2 host [1]; iters host [1] or NULL.  Synchronises. */
+cox_status cox_opnorm2(cox_ctx *ctx, double tol, int32_t maxiter, uint64_t seed, double *s2, int32_t *iters);
+
+/* Negative log partial likelihood as a function of the linear predictor, for
+ * automatic differentiation (the adjoint of the risk-set sums).
+ * forward:  loss_b = -L(eta_b)   for eta dev [B][n] (float when eta_f64 = 0,
+ *           double when 1); loss dev [B] double.  Keeps w and the reverse
+ *           cumulative sums in the context for the next backward.
+ * backward: grad_eta_b = -grad_loss_b * r_b, with r_b = delta - w_b * c_b the
+ *           derivative of L at the eta of the last forward (Section 5.3's
+ *           (I - P) delta).  grad_loss dev [B] double; grad_eta dev [B][n],
+ *           float or double as in the forward.  The forward must have been
+ *           called with the same B.  Neither call synchronises. */
+cox_status cox_nll_forward(cox_ctx *ctx, const void *eta, int32_t eta_f64, int32_t B, double *loss);
+cox_status cox_nll_backward(cox_ctx *ctx, const double *grad_loss, int32_t B, void *grad_eta);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COX_H */

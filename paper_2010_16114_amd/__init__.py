@@ -1,0 +1,234 @@
+"""MI355X-native l1-regularised Cox regression by proximal gradient (ISTA).
+
+A thin ctypes binding of libcoxhip (include/cox.h).  Every step of the method
+runs in the library's HIP kernels; this module only marshals arguments.
+PyTorch provides device memory and the stream.  There is no CPU fallback: if
+the library is not built, importing the binding's entry points raises.
+
+Matrices are column-major n x p: a torch tensor of shape (p, ldx) whose row j
+is SNP column j (first n entries used).  Coefficients are (B, p) float32,
+linear predictors (B, n).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcoxhip.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "cox.h")
+
+X_F32, X_FP8_E4M3, X_INT8 = 0, 1, 2
+OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NUMERIC, ERR_NOT_CONVERGED, ERR_UNSUPPORTED = range(7)
+
+
+class CoxError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(msg)
+        self.status = status
+
+
+class _Matrix(ctypes.Structure):
+    _fields_ = [("X", ctypes.c_void_p), ("xtype", ctypes.c_int32), ("n", ctypes.c_int64), ("p", ctypes.c_int64),
+                ("ldx", ctypes.c_int64), ("col_center", ctypes.c_void_p), ("col_scale", ctypes.c_void_p)]
+
+
+class FitOpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("lag", ctypes.c_int32),
+                ("step", ctypes.c_double), ("warm_start", ctypes.c_int32), ("eta_mode", ctypes.c_int32),
+                ("poll", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def declared_symbols() -> list[str]:
+    """Function names declared by include/cox.h."""
+    src = open(HEADER).read()
+    return re.findall(r"^(?:cox_status|const char \*)\s*(cox_\w+)\s*\(", src, flags=re.M)
+
+
+def lib():
+    """The loaded libcoxhip (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2010_16114_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64
+    sig = {
+        "cox_setup": [ctypes.POINTER(vp), ctypes.POINTER(_Matrix), vp, vp, i32, vp],
+        "cox_destroy": [vp],
+        "cox_last_error": [vp, ctypes.c_char_p, ctypes.c_size_t],
+        "cox_loss_grad": [vp, vp, i32, vp, vp],
+        "cox_prox_step": [vp, vp, i32, vp, dbl, vp],
+        "cox_prox_apply": [vp, vp, vp, i32, vp, dbl],
+        "cox_fit_path": [vp, vp, i32, ctypes.POINTER(FitOpts), vp, vp, vp],
+        "cox_lambda_max": [vp, ctypes.POINTER(dbl)],
+        "cox_opnorm2": [vp, dbl, i32, u64, ctypes.POINTER(dbl), ctypes.POINTER(i32)],
+        "cox_nll_forward": [vp, vp, i32, i32, vp],
+        "cox_nll_backward": [vp, vp, i32, vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.cox_status_string.argtypes = [ctypes.c_int]
+    L.cox_status_string.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Cox:
+    """One data set on the GPU (cox_setup).  X, center and scale are borrowed:
+    this object keeps references to them for its lifetime."""
+
+    def __init__(self, X, time, event, xtype: int | None = None, n: int | None = None, center=None, scale=None,
+                 max_batch: int = 1, stream=None):
+        import torch
+        self._torch = torch
+        if not X.is_cuda:
+            raise ValueError("X must be a device tensor")
+        if xtype is None:
+            xtype = {torch.float32: X_F32, torch.int8: X_INT8, torch.uint8: X_FP8_E4M3,
+                     torch.float8_e4m3fn: X_FP8_E4M3}[X.dtype]
+        assert X.dim() == 2 and X.stride(1) == 1
+        p, ldx = X.shape[0], X.stride(0)
+        n = X.shape[1] if n is None else int(n)
+        self.X, self.center, self.scale = X, center, scale
+        self.n, self.p, self.max_batch, self.xtype = n, p, max_batch, xtype
+        self.device = X.device
+        self.stream = torch.cuda.current_stream(X.device) if stream is None else stream
+        t = np.ascontiguousarray(time, dtype=np.float64)
+        e = np.ascontiguousarray(event, dtype=np.int32)
+        if t.shape != (n,) or e.shape != (n,):
+            raise ValueError("time and event must have length n")
+        m = _Matrix(X.data_ptr(), xtype, n, p, ldx, center.data_ptr() if center is not None else None,
+                    scale.data_ptr() if scale is not None else None)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(X.device):
+            st = lib().cox_setup(ctypes.byref(h), ctypes.byref(m), _np_ptr(t), _np_ptr(e), max_batch,
+                                 self.stream.cuda_stream)
+        if st != OK:
+            raise CoxError(st, f"cox_setup: {lib().cox_status_string(st).decode()}")
+        self._h = h
+        self.last_forward_key = None
+
+    # -- helpers
+    def _check(self, st, what, allow=(OK,)):
+        if st in allow:
+            return st
+        buf = ctypes.create_string_buffer(512)
+        lib().cox_last_error(self._h, buf, 512)
+        raise CoxError(st, f"{what}: {lib().cox_status_string(st).decode()} ({buf.value.decode()})")
+
+    def _beta(self, beta):
+        torch = self._torch
+        assert beta.dtype == torch.float32 and beta.is_cuda and beta.is_contiguous()
+        beta2 = beta.view(-1, self.p)
+        return beta2, beta2.shape[0]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cox_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- entry points
+    def loss_grad(self, beta, want_grad: bool = True):
+        """(-L(beta_b) for each b as numpy, gradient of -L as a (B, p) tensor or None)."""
+        beta2, B = self._beta(beta)
+        loss = np.empty(B, np.float64)
+        grad = self._torch.empty_like(beta2) if want_grad else None
+        st = lib().cox_loss_grad(self._h, beta2.data_ptr(), B, _np_ptr(loss),
+                                 grad.data_ptr() if want_grad else None)
+        self._check(st, "cox_loss_grad")
+        return loss, grad
+
+    def prox_step(self, beta, lambdas, step: float, want_obj: bool = True):
+        beta2, B = self._beta(beta)
+        lam = np.ascontiguousarray(np.broadcast_to(np.asarray(lambdas, np.float64), (B,)))
+        obj = np.empty(B, np.float64)
+        st = lib().cox_prox_step(self._h, beta2.data_ptr(), B, _np_ptr(lam), float(step),
+                                 _np_ptr(obj) if want_obj else None)
+        self._check(st, "cox_prox_step")
+        return obj if want_obj else None
+
+    def prox_apply(self, beta, grad, lambdas, step: float):
+        beta2, B = self._beta(beta)
+        lam = np.ascontiguousarray(np.broadcast_to(np.asarray(lambdas, np.float64), (B,)))
+        st = lib().cox_prox_apply(self._h, beta2.data_ptr(), grad.data_ptr(), B, _np_ptr(lam), float(step))
+        self._check(st, "cox_prox_apply")
+
+    def fit_path(self, lambdas, max_iter: int = 1000, tol: float = 1e-5, lag: int = 10, step: float = 0.0,
+                 beta=None, eta_mode: int = 0, poll: int = 16):
+        """ISTA for each lambda.  Returns (beta (B, p) tensor, iters, obj, status)."""
+        torch = self._torch
+        lam = np.ascontiguousarray(np.asarray(lambdas, np.float64).reshape(-1))
+        B = lam.shape[0]
+        warm = beta is not None
+        if beta is None:
+            beta = torch.zeros((B, self.p), dtype=torch.float32, device=self.device)
+        beta2, Bb = self._beta(beta)
+        assert Bb == B
+        iters = np.zeros(B, np.int32)
+        obj = np.zeros(B, np.float64)
+        o = FitOpts(int(max_iter), float(tol), int(lag), float(step), int(warm), int(eta_mode), int(poll))
+        st = lib().cox_fit_path(self._h, _np_ptr(lam), B, ctypes.byref(o), beta2.data_ptr(), _np_ptr(iters),
+                                _np_ptr(obj))
+        self._check(st, "cox_fit_path", allow=(OK, ERR_NOT_CONVERGED))
+        return beta2, iters, obj, st
+
+    def lambda_max(self) -> float:
+        out = ctypes.c_double()
+        self._check(lib().cox_lambda_max(self._h, ctypes.byref(out)), "cox_lambda_max")
+        return out.value
+
+    def opnorm2(self, tol: float = 1e-6, maxiter: int = 1000, seed: int = 95376):
+        s2 = ctypes.c_double()
+        it = ctypes.c_int32()
+        st = lib().cox_opnorm2(self._h, float(tol), int(maxiter), int(seed) & (2**64 - 1), ctypes.byref(s2),
+                               ctypes.byref(it))
+        self._check(st, "cox_opnorm2")
+        return s2.value, it.value
+
+    def nll_forward(self, eta):
+        """-L(eta_b) for eta of shape (B, n) (float32 or float64): a (B,) float64 tensor."""
+        torch = self._torch
+        assert eta.is_cuda and eta.is_contiguous() and eta.dtype in (torch.float32, torch.float64)
+        eta2 = eta.view(-1, self.n)
+        B = eta2.shape[0]
+        loss = torch.empty(B, dtype=torch.float64, device=self.device)
+        st = lib().cox_nll_forward(self._h, eta2.data_ptr(), int(eta.dtype == torch.float64), B, loss.data_ptr())
+        self._check(st, "cox_nll_forward")
+        self.last_forward_key = self.forward_key(eta)
+        return loss
+
+    @staticmethod
+    def forward_key(eta):
+        return (eta.data_ptr(), eta._version, tuple(eta.shape), eta.dtype)
+
+    def nll_backward(self, grad_loss, like):
+        """-grad_loss_b * r_b at the eta of the last forward, shaped and typed like `like`."""
+        torch = self._torch
+        gl = grad_loss.to(torch.float64).contiguous().view(-1)
+        out = torch.empty_like(like)
+        st = lib().cox_nll_backward(self._h, gl.data_ptr(), gl.shape[0], out.data_ptr())
+        self._check(st, "cox_nll_backward")
+        return out
+
+
+from .autograd import BreslowNLL, CoxLinearNLL  # noqa: E402

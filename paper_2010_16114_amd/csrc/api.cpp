@@ -1,0 +1,654 @@
+// api.cpp -- host runtime of libcoxhip: the C ABI declared in include/cox.h.
+//
+// The context owns the time order and tie groups (computed once on the host),
+// the FP64 linear predictor, the FP64 iterate of cox_fit_path and every
+// workspace buffer, all allocated in cox_setup for the largest batch and freed
+// in cox_destroy.  Every entry point validates its arguments before touching
+// the device, and converts every HIP failure into a status code with a message
+// kept in the context.  All device work is enqueued on the context's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "cox.h"
+#include "internal.h"
+
+using namespace cox;
+
+namespace {
+
+constexpr int kMaxBatch = 64;
+constexpr int kGroup = 8;  // coefficient vectors per VALU pass over X
+
+int64_t round_up(int64_t a, int64_t m) { return (a + m - 1) / m * m; }
+
+}  // namespace
+
+struct cox_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    XDesc x{};
+    int64_t n = 0, p = 0;
+    int Bmax = 0;
+    int64_t rstride = 0;
+    int nblk = 0, ncg = 0, ncb = 0;
+    std::string err;
+    std::vector<void*> allocs;
+    void* pinned = nullptr;  // small host staging buffer (page-locked)
+    size_t pinned_bytes = 0;
+
+    int32_t *perm = nullptr, *gstart = nullptr, *gend = nullptr;
+    uint8_t* ev = nullptr;
+    double *eta = nullptr, *w = nullptr, *S = nullptr, *T = nullptr, *r64 = nullptr;
+    float* r32 = nullptr;
+    double *part_upd = nullptr, *part_gemv = nullptr;
+    double *beta64 = nullptr, *coef = nullptr, *dcoef = nullptr, *g64 = nullptr;
+    int32_t *chg_flag = nullptr, *chg_cnt = nullptr, *chg_idx = nullptr, *sel = nullptr, *nsel = nullptr;
+    double *l1old = nullptr, *l1new = nullptr;
+    double *L = nullptr, *sumr = nullptr, *lam = nullptr, *fobj = nullptr, *hist = nullptr, *scal = nullptr;
+    int32_t *kit = nullptr, *active = nullptr, *iters = nullptr, *status = nullptr;
+    int fwd_B = 0, fwd_f64 = 0;
+    int64_t n_events = 0;
+};
+
+namespace {
+
+cox_status fail(cox_ctx* c, cox_status s, const std::string& msg)
+{
+    if (c) c->err = msg;
+    return s;
+}
+
+cox_status dev_fail(cox_ctx* c, hipError_t e, const char* what)
+{
+    return fail(c, COX_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(expr, what)                                \
+    do {                                                  \
+        hipError_t _e = (expr);                           \
+        if (_e != hipSuccess) return dev_fail(c, _e, what); \
+    } while (0)
+
+#define STCHK(expr)                        \
+    do {                                   \
+        cox_status _s = (expr);            \
+        if (_s != COX_OK) return _s;       \
+    } while (0)
+
+bool fault_injected(const char* what)
+{
+    const char* f = std::getenv("COXHIP_FAULT");
+    return f && std::strcmp(f, what) == 0;
+}
+
+template <class T>
+bool dalloc(cox_ctx* c, T** out, size_t count)
+{
+    *out = nullptr;
+    if (fault_injected("alloc")) return false;
+    void* p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    c->allocs.push_back(p);
+    *out = static_cast<T*>(p);
+    return true;
+}
+
+void release(cox_ctx* c)
+{
+    for (void* p : c->allocs) (void)hipFree(p);
+    c->allocs.clear();
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    c->pinned = nullptr;
+}
+
+cox_status check_ctx(cox_ctx* c)
+{
+    if (!c) return COX_ERR_INVALID_ARG;
+    c->err.clear();
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, COX_ERR_DEVICE, "hipSetDevice failed");
+    return COX_OK;
+}
+
+cox_status check_batch(cox_ctx* c, int32_t B)
+{
+    if (B < 1 || B > c->Bmax)
+        return fail(c, COX_ERR_INVALID_ARG, "B must be in 1..max_batch (" + std::to_string(c->Bmax) + ")");
+    return COX_OK;
+}
+
+cox_status check_lambdas(cox_ctx* c, const double* lambdas, int32_t B)
+{
+    if (!lambdas) return fail(c, COX_ERR_INVALID_ARG, "lambdas is NULL");
+    for (int b = 0; b < B; ++b)
+        if (!std::isfinite(lambdas[b]) || lambdas[b] < 0)
+            return fail(c, COX_ERR_INVALID_ARG, "lambdas must be finite and >= 0");
+    return COX_OK;
+}
+
+cox_status sync(cox_ctx* c)
+{
+    HIPCHK(hipStreamSynchronize(c->stream), "stream synchronize");
+    return COX_OK;
+}
+
+// Copy m bytes device -> host through the pinned buffer (synchronises).
+cox_status d2h(cox_ctx* c, void* host, const void* dev, size_t m)
+{
+    if (m <= c->pinned_bytes) {
+        HIPCHK(hipMemcpyAsync(c->pinned, dev, m, hipMemcpyDeviceToHost, c->stream), "copy to host");
+        STCHK(sync(c));
+        std::memcpy(host, c->pinned, m);
+    } else {
+        HIPCHK(hipMemcpyAsync(host, dev, m, hipMemcpyDeviceToHost, c->stream), "copy to host");
+        STCHK(sync(c));
+    }
+    return COX_OK;
+}
+
+// Copy m bytes host -> device; the host buffer may be reused on return.
+cox_status h2d(cox_ctx* c, void* dev, const void* host, size_t m)
+{
+    if (m <= c->pinned_bytes) {
+        STCHK(sync(c));  // the pinned buffer may still feed an earlier copy
+        std::memcpy(c->pinned, host, m);
+        HIPCHK(hipMemcpyAsync(dev, c->pinned, m, hipMemcpyHostToDevice, c->stream), "copy to device");
+        STCHK(sync(c));
+    } else {
+        HIPCHK(hipMemcpyAsync(dev, host, m, hipMemcpyHostToDevice, c->stream), "copy to device");
+        STCHK(sync(c));
+    }
+    return COX_OK;
+}
+
+const float* geno_scale(const cox_ctx* c) { return c->x.xt == XT_F32 ? nullptr : c->x.scale; }
+
+// eta[b] = X~ coef[b] (no centring) for b < B; coef is b-major [B][p].
+cox_status dense_eta(cox_ctx* c, const double* coef, int B, const double* shift)
+{
+    for (int b0 = 0; b0 < B; b0 += kGroup) {
+        const int nb = std::min(kGroup, B - b0);
+        HIPCHK(launch_gemv(c->x, coef, b0, nb, c->part_gemv, c->ncb, c->eta, shift, c->stream), "dense X beta");
+    }
+    return COX_OK;
+}
+
+RiskArgs risk_args(cox_ctx* c, int B)
+{
+    RiskArgs a{};
+    a.n = c->n;
+    a.B = B;
+    a.ord = Order{c->perm, c->gstart, c->gend, c->ev};
+    a.eta_in = c->eta;
+    a.eta_in_f32 = 0;
+    a.eta_out = nullptr;
+    a.part = nullptr;
+    a.ncg = c->ncg;
+    a.part_cstride = (int64_t)c->Bmax * c->n;
+    a.nsel = c->nsel;
+    a.w = c->w;
+    a.S = c->S;
+    a.T = c->T;
+    a.r32 = c->r32;
+    a.r64 = nullptr;
+    a.L = c->L;
+    a.sumr = c->sumr;
+    a.rstride = c->rstride;
+    a.use_ctl = 0;
+    return a;
+}
+
+GemvtArgs gemvt_args(cox_ctx* c, int mode)
+{
+    GemvtArgs g{};
+    g.x = c->x;
+    g.r32 = c->r32;
+    g.rstride = c->rstride;
+    g.sumr = c->sumr;
+    g.mode = mode;
+    g.nblk = c->nblk;
+    g.dcoef = c->dcoef;
+    g.chg_flag = c->chg_flag;
+    g.chg_cnt = c->chg_cnt;
+    g.chg_idx = c->chg_idx;
+    g.l1old = c->l1old;
+    g.l1new = c->l1new;
+    return g;
+}
+
+cox_status run_gemvt(cox_ctx* c, GemvtArgs g, int B)
+{
+    for (int b0 = 0; b0 < B; b0 += kGroup) {
+        g.b0 = b0;
+        g.nb = std::min(kGroup, B - b0);
+        g.first_group = b0 == 0;
+        HIPCHK(launch_gemvt(g, c->stream), "X' r");
+    }
+    return COX_OK;
+}
+
+// Uniform [-1, 1) start vector from SplitMix64 (Steele, Lea and Flood 2014),
+// top 53 bits of each output.
+void splitmix_start(uint64_t seed, std::vector<double>& v)
+{
+    uint64_t st = seed;
+    double nv = 0.0;
+    for (double& x : v) {
+        uint64_t z = (st += 0x9E3779B97F4A7C15ULL);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+        z ^= z >> 31;
+        x = (double)(z >> 11) * 0x1.0p-52 - 1.0;
+        nv += x * x;
+    }
+    nv = std::sqrt(nv);
+    for (double& x : v) x /= nv;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cox_status_string(cox_status s)
+{
+    switch (s) {
+    case COX_OK: return "ok";
+    case COX_ERR_INVALID_ARG: return "invalid argument";
+    case COX_ERR_OUT_OF_MEMORY: return "out of memory";
+    case COX_ERR_DEVICE: return "device error";
+    case COX_ERR_NUMERIC: return "non-finite loss or gradient";
+    case COX_ERR_NOT_CONVERGED: return "maximum number of iterations reached";
+    case COX_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+cox_status cox_last_error(const cox_ctx* ctx, char* buf, size_t len)
+{
+    if (!ctx || !buf || len == 0) return COX_ERR_INVALID_ARG;
+    const size_t m = std::min(len - 1, ctx->err.size());
+    std::memcpy(buf, ctx->err.data(), m);
+    buf[m] = '\0';
+    return COX_OK;
+}
+
+cox_status cox_setup(cox_ctx** out, const cox_matrix* X, const double* time, const int32_t* event,
+                     int32_t max_batch, void* hip_stream)
+{
+    if (!out) return COX_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!X || !X->X || !time || !event) return COX_ERR_INVALID_ARG;
+    if (X->xtype != COX_X_F32 && X->xtype != COX_X_FP8_E4M3 && X->xtype != COX_X_INT8) return COX_ERR_INVALID_ARG;
+    if (X->n < 1 || X->p < 1 || X->n >= (1LL << 31) || X->p >= (1LL << 31) || X->ldx < X->n) return COX_ERR_INVALID_ARG;
+    if (X->ldx > (int64_t(1) << 62) / X->p) return COX_ERR_INVALID_ARG;
+    if (X->xtype == COX_X_F32 && (X->col_center || X->col_scale)) return COX_ERR_INVALID_ARG;
+    if (max_batch < 1 || max_batch > kMaxBatch) return COX_ERR_INVALID_ARG;
+    const int64_t n = X->n, p = X->p;
+    int64_t nev = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!std::isfinite(time[i])) return COX_ERR_INVALID_ARG;
+        if (event[i] != 0 && event[i] != 1) return COX_ERR_INVALID_ARG;
+        nev += event[i];
+    }
+
+    cox_ctx* c = new (std::nothrow) cox_ctx;
+    if (!c) return COX_ERR_OUT_OF_MEMORY;
+    c->n_events = nev;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return COX_ERR_DEVICE;
+    }
+    c->n = n;
+    c->p = p;
+    c->Bmax = max_batch;
+    const size_t elem = X->xtype == COX_X_F32 ? 4 : 1;
+    const uintptr_t base = reinterpret_cast<uintptr_t>(X->X);
+    c->x = XDesc{X->X, X->xtype, n, p, X->ldx, X->col_center, X->col_scale,
+                 (int)(base % 16 == 0 && (X->ldx * (int64_t)elem) % 16 == 0),
+                 (int)(base % 4 == 0 && (X->ldx * (int64_t)elem) % 4 == 0)};
+    c->rstride = round_up(n, 8192);
+    c->nblk = (int)((p + kGemvtCols - 1) / kGemvtCols);
+    const int64_t nslab = (n + kUpdRows - 1) / kUpdRows;
+    c->ncg = (int)std::max<int64_t>(1, std::min<int64_t>(16, 1024 / nslab));
+    c->ncb = (int)std::max<int64_t>(1, std::min<int64_t>((2048 + nslab - 1) / nslab, (p + 255) / 256));
+
+    // Order by non-increasing time, stable; tie groups (Section 5.3, Section 6).
+    std::vector<int32_t> perm(n), gs(n), ge(n);
+    std::vector<uint8_t> evs(n);
+    std::iota(perm.begin(), perm.end(), 0);
+    std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return time[a] > time[b]; });
+    for (int64_t k = 0; k < n;) {
+        int64_t e = k;
+        while (e + 1 < n && time[perm[e + 1]] == time[perm[k]]) ++e;
+        for (int64_t q = k; q <= e; ++q) {
+            gs[q] = (int32_t)k;
+            ge[q] = (int32_t)e;
+        }
+        k = e + 1;
+    }
+    for (int64_t k = 0; k < n; ++k) evs[k] = (uint8_t)event[perm[k]];
+
+    const int64_t Bn = (int64_t)max_batch * n, Bp = (int64_t)max_batch * p;
+    bool ok = dalloc(c, &c->perm, n) && dalloc(c, &c->gstart, n) && dalloc(c, &c->gend, n) && dalloc(c, &c->ev, n) &&
+              dalloc(c, &c->eta, Bn) && dalloc(c, &c->w, Bn) && dalloc(c, &c->S, Bn) && dalloc(c, &c->T, Bn) &&
+              dalloc(c, &c->r64, Bn) && dalloc(c, &c->r32, (size_t)max_batch * c->rstride) &&
+              dalloc(c, &c->part_upd, (size_t)c->ncg * Bn) && dalloc(c, &c->part_gemv, (size_t)c->ncb * kGroup * n) &&
+              dalloc(c, &c->beta64, Bp) && dalloc(c, &c->coef, Bp) && dalloc(c, &c->dcoef, Bp) &&
+              dalloc(c, &c->g64, Bp) && dalloc(c, &c->chg_flag, p) && dalloc(c, &c->chg_cnt, c->nblk) &&
+              dalloc(c, &c->chg_idx, (size_t)c->nblk * kGemvtCols) && dalloc(c, &c->sel, p) &&
+              dalloc(c, &c->nsel, 1) && dalloc(c, &c->l1old, (size_t)max_batch * c->nblk) &&
+              dalloc(c, &c->l1new, (size_t)max_batch * c->nblk) && dalloc(c, &c->L, max_batch) &&
+              dalloc(c, &c->sumr, max_batch) && dalloc(c, &c->lam, max_batch) && dalloc(c, &c->fobj, max_batch) &&
+              dalloc(c, &c->hist, (size_t)max_batch * kMaxHist) && dalloc(c, &c->scal, 16) &&
+              dalloc(c, &c->kit, max_batch) && dalloc(c, &c->active, max_batch) && dalloc(c, &c->iters, max_batch) &&
+              dalloc(c, &c->status, max_batch);
+    if (ok) {
+        c->pinned_bytes = 64 * 1024;
+        if (hipHostMalloc(&c->pinned, c->pinned_bytes, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            c->pinned = nullptr;
+            ok = false;
+        }
+    }
+    if (!ok) {
+        release(c);
+        delete c;
+        return COX_ERR_OUT_OF_MEMORY;
+    }
+    cox_status st = COX_OK;
+    auto up = [&](void* d, const void* h, size_t m) {
+        if (st == COX_OK && hipMemcpyAsync(d, h, m, hipMemcpyHostToDevice, c->stream) != hipSuccess) st = COX_ERR_DEVICE;
+    };
+    up(c->perm, perm.data(), sizeof(int32_t) * n);
+    up(c->gstart, gs.data(), sizeof(int32_t) * n);
+    up(c->gend, ge.data(), sizeof(int32_t) * n);
+    up(c->ev, evs.data(), n);
+    auto chk = [&](hipError_t e) {
+        if (st == COX_OK && e != hipSuccess) st = COX_ERR_DEVICE;
+    };
+    chk(launch_fill_f64(reinterpret_cast<double*>(c->r32), 0.0, (int64_t)max_batch * c->rstride / 2, c->stream));
+    chk(launch_fill_i32(c->chg_flag, 0, p, c->stream));
+    chk(launch_fill_i32(c->nsel, 0, 1, c->stream));
+    chk(launch_fill_f64(c->eta, 0.0, Bn, c->stream));
+    if (st == COX_OK && hipStreamSynchronize(c->stream) != hipSuccess) st = COX_ERR_DEVICE;
+    if (st != COX_OK) {
+        (void)hipGetLastError();
+        release(c);
+        delete c;
+        return st;
+    }
+    *out = c;
+    return COX_OK;
+}
+
+cox_status cox_destroy(cox_ctx* c)
+{
+    if (!c) return COX_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    release(c);
+    delete c;
+    return COX_OK;
+}
+
+cox_status cox_loss_grad(cox_ctx* c, const float* beta, int32_t B, double* loss, float* grad)
+{
+    STCHK(check_ctx(c));
+    if (!beta || !loss) return fail(c, COX_ERR_INVALID_ARG, "beta and loss must not be NULL");
+    STCHK(check_batch(c, B));
+    const int64_t Bp = (int64_t)B * c->p;
+    HIPCHK(launch_f32_to_f64(beta, c->beta64, Bp, c->stream), "beta to FP64");
+    HIPCHK(launch_scale_coef(c->beta64, geno_scale(c), c->coef, c->p, B, c->stream), "coefficients");
+    STCHK(dense_eta(c, c->coef, B, nullptr));
+    RiskArgs ra = risk_args(c, B);
+    if (!grad) ra.r32 = nullptr;
+    HIPCHK(launch_risk(ra, c->stream), "risk-set sums");
+    if (grad) {
+        GemvtArgs g = gemvt_args(c, GT_GRAD);
+        g.out32 = grad;
+        STCHK(run_gemvt(c, g, B));
+    }
+    std::vector<double> L(B);
+    STCHK(d2h(c, L.data(), c->L, sizeof(double) * B));
+    bool finite = true;
+    for (int b = 0; b < B; ++b) {
+        loss[b] = -L[b];
+        finite = finite && std::isfinite(loss[b]);
+    }
+    if (!finite) return fail(c, COX_ERR_NUMERIC, "non-finite loss");
+    return COX_OK;
+}
+
+cox_status cox_prox_step(cox_ctx* c, float* beta, int32_t B, const double* lambdas, double step, double* obj_before)
+{
+    STCHK(check_ctx(c));
+    if (!beta) return fail(c, COX_ERR_INVALID_ARG, "beta is NULL");
+    STCHK(check_batch(c, B));
+    STCHK(check_lambdas(c, lambdas, B));
+    if (!(step > 0) || !std::isfinite(step)) return fail(c, COX_ERR_INVALID_ARG, "step must be finite and > 0");
+    STCHK(h2d(c, c->lam, lambdas, sizeof(double) * B));
+    const int64_t Bp = (int64_t)B * c->p;
+    HIPCHK(launch_f32_to_f64(beta, c->beta64, Bp, c->stream), "beta to FP64");
+    HIPCHK(launch_scale_coef(c->beta64, geno_scale(c), c->coef, c->p, B, c->stream), "coefficients");
+    STCHK(dense_eta(c, c->coef, B, nullptr));
+    HIPCHK(launch_risk(risk_args(c, B), c->stream), "risk-set sums");
+    GemvtArgs g = gemvt_args(c, GT_PROX);
+    g.beta = c->beta64;
+    g.lam = c->lam;
+    g.step = step;
+    g.active = nullptr;
+    STCHK(run_gemvt(c, g, B));
+    HIPCHK(launch_f64_to_f32(c->beta64, beta, Bp, c->stream), "beta to FP32");
+    if (obj_before) {
+        HIPCHK(launch_rowsum(c->l1old, c->nblk, B, 1.0, c->scal, c->stream), "l1 norm");
+        std::vector<double> v(2 * B);
+        STCHK(d2h(c, v.data(), c->L, sizeof(double) * B));
+        STCHK(d2h(c, v.data() + B, c->scal, sizeof(double) * B));
+        bool finite = true;
+        for (int b = 0; b < B; ++b) {
+            obj_before[b] = -v[b] + lambdas[b] * v[B + b];
+            finite = finite && std::isfinite(obj_before[b]);
+        }
+        if (!finite) return fail(c, COX_ERR_NUMERIC, "non-finite objective");
+    }
+    return COX_OK;
+}
+
+cox_status cox_prox_apply(cox_ctx* c, float* beta, const float* grad, int32_t B, const double* lambdas, double step)
+{
+    STCHK(check_ctx(c));
+    if (!beta || !grad) return fail(c, COX_ERR_INVALID_ARG, "beta and grad must not be NULL");
+    STCHK(check_batch(c, B));
+    STCHK(check_lambdas(c, lambdas, B));
+    if (!(step > 0) || !std::isfinite(step)) return fail(c, COX_ERR_INVALID_ARG, "step must be finite and > 0");
+    STCHK(h2d(c, c->lam, lambdas, sizeof(double) * B));
+    HIPCHK(launch_prox_apply(beta, grad, c->lam, step, c->p, B, c->stream), "soft threshold");
+    return COX_OK;
+}
+
+cox_status cox_lambda_max(cox_ctx* c, double* lambda_max)
+{
+    STCHK(check_ctx(c));
+    if (!lambda_max) return fail(c, COX_ERR_INVALID_ARG, "lambda_max is NULL");
+    HIPCHK(launch_fill_f64(c->eta, 0.0, c->n, c->stream), "zero eta");
+    HIPCHK(launch_risk(risk_args(c, 1), c->stream), "risk-set sums");
+    GemvtArgs g = gemvt_args(c, GT_RAW);
+    g.out64 = c->g64;
+    STCHK(run_gemvt(c, g, 1));
+    std::vector<double> gh(c->p);
+    STCHK(d2h(c, gh.data(), c->g64, sizeof(double) * c->p));
+    double mx = 0.0;
+    for (double v : gh) mx = std::max(mx, std::fabs(v));
+    if (!std::isfinite(mx)) return fail(c, COX_ERR_NUMERIC, "non-finite gradient");
+    *lambda_max = mx;
+    return COX_OK;
+}
+
+cox_status cox_opnorm2(cox_ctx* c, double tol, int32_t maxiter, uint64_t seed, double* s2, int32_t* iters)
+{
+    STCHK(check_ctx(c));
+    if (!s2 || !(tol >= 0) || maxiter < 1) return fail(c, COX_ERR_INVALID_ARG, "bad opnorm2 arguments");
+    std::vector<double> v(c->p);
+    splitmix_start(seed, v);
+    STCHK(h2d(c, c->beta64, v.data(), sizeof(double) * c->p));
+    const float* scale = geno_scale(c);
+    const bool centred = c->x.xt != XT_F32 && c->x.center;
+    HIPCHK(launch_scale_coef(c->beta64, scale, c->coef, c->p, 1, c->stream), "coefficients");
+    double est = 0.0, prev = 0.0;
+    int it = 0;
+    while (it < maxiter) {
+        if (centred) HIPCHK(launch_center_shift(c->x.center, scale, c->beta64, c->p, c->scal + 0, c->stream), "shift");
+        STCHK(dense_eta(c, c->coef, 1, centred ? c->scal + 0 : nullptr));
+        HIPCHK(launch_dot(c->eta, c->eta, c->n, c->scal + 1, c->stream), "norm of X v");
+        HIPCHK(launch_to_r32(c->eta, nullptr, c->r32, c->sumr, c->n, c->stream), "u to FP32");
+        GemvtArgs g = gemvt_args(c, GT_RAW);
+        g.out64 = c->g64;
+        STCHK(run_gemvt(c, g, 1));
+        HIPCHK(launch_dot(c->g64, c->g64, c->p, c->scal + 2, c->stream), "norm of X' u");
+        double h[2];
+        STCHK(d2h(c, h, c->scal + 1, sizeof(h)));
+        ++it;
+        prev = est;
+        est = h[0];
+        if (!std::isfinite(est) || !std::isfinite(h[1])) return fail(c, COX_ERR_NUMERIC, "non-finite power iteration");
+        if (h[1] == 0.0) break;
+        HIPCHK(launch_normalize(c->g64, c->scal + 2, scale, c->beta64, c->coef, c->p, c->stream), "normalise");
+        if (it > 1 && std::fabs(est - prev) < tol * est) break;
+    }
+    *s2 = est;
+    if (iters) *iters = it;
+    return COX_OK;
+}
+
+cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_fit_opts* opts_in, float* beta,
+                        int32_t* iters, double* obj)
+{
+    STCHK(check_ctx(c));
+    if (!beta) return fail(c, COX_ERR_INVALID_ARG, "beta is NULL");
+    STCHK(check_batch(c, B));
+    STCHK(check_lambdas(c, lambdas, B));
+    cox_fit_opts o{1000, 1e-5, 10, 0.0, 0, 0, 16};
+    if (opts_in) o = *opts_in;
+    if (o.max_iter < 0 || !(o.tol >= 0) || o.lag < 1 || o.lag > kMaxHist - 1 || !std::isfinite(o.step) ||
+        (o.warm_start != 0 && o.warm_start != 1) || (o.eta_mode != 0 && o.eta_mode != 1))
+        return fail(c, COX_ERR_INVALID_ARG, "bad cox_fit_opts");
+    const int poll = o.poll > 0 ? o.poll : 16;
+    double step = o.step;
+    if (step <= 0) {
+        double s2 = 0;
+        STCHK(cox_opnorm2(c, 1e-6, 1000, 95376, &s2, nullptr));
+        if (!(s2 > 0)) return fail(c, COX_ERR_NUMERIC, "||X||_2 is zero; no step size");
+        step = 1.0 / (2.0 * s2);
+    }
+    STCHK(h2d(c, c->lam, lambdas, sizeof(double) * B));
+    const int64_t Bp = (int64_t)B * c->p, Bn = (int64_t)B * c->n;
+    if (o.warm_start) {
+        HIPCHK(launch_f32_to_f64(beta, c->beta64, Bp, c->stream), "beta to FP64");
+        HIPCHK(launch_scale_coef(c->beta64, geno_scale(c), c->coef, c->p, B, c->stream), "coefficients");
+        STCHK(dense_eta(c, c->coef, B, nullptr));
+        HIPCHK(launch_l1_blocks(c->beta64, c->p, B, c->nblk, c->l1new, c->stream), "l1 blocks");
+    } else {
+        HIPCHK(launch_fill_f64(c->beta64, 0.0, Bp, c->stream), "zero beta");
+        HIPCHK(launch_fill_f64(c->eta, 0.0, Bn, c->stream), "zero eta");
+        HIPCHK(launch_fill_f64(c->l1new, 0.0, (int64_t)B * c->nblk, c->stream), "zero l1");
+    }
+    HIPCHK(launch_fill_i32(c->nsel, 0, 1, c->stream), "reset");
+    HIPCHK(launch_fill_i32(c->kit, 0, B, c->stream), "reset");
+    HIPCHK(launch_fill_i32(c->active, 1, B, c->stream), "reset");
+    HIPCHK(launch_fill_i32(c->status, 0, B, c->stream), "reset");
+    HIPCHK(launch_fill_i32(c->iters, 0, B, c->stream), "reset");
+    HIPCHK(launch_fill_f64(c->hist, 0.0, (int64_t)B * kMaxHist, c->stream), "reset");
+
+    RiskArgs ra = risk_args(c, B);
+    ra.eta_out = c->eta;
+    ra.part = o.eta_mode == 0 ? c->part_upd : nullptr;
+    ra.use_ctl = 1;
+    ra.ctl = FitCtl{c->lam, c->l1new, c->nblk, c->hist, c->kit, c->active, c->iters, c->status, c->fobj,
+                    o.max_iter, o.lag, o.tol};
+    GemvtArgs g = gemvt_args(c, GT_PROX);
+    g.beta = c->beta64;
+    g.lam = c->lam;
+    g.step = step;
+    g.active = c->active;
+    const int64_t cstride = (int64_t)c->Bmax * c->n;
+
+    for (int it = 0; it <= o.max_iter; ++it) {
+        if (it > 0) {
+            if (o.eta_mode == 0) {
+                for (int b0 = 0; b0 < B; b0 += kGroup)
+                    HIPCHK(launch_eta_update(c->x, c->sel, c->nsel, c->dcoef, b0, std::min(kGroup, B - b0),
+                                             c->part_upd, cstride, c->ncg, c->active, c->stream),
+                           "eta update");
+            } else {
+                HIPCHK(launch_scale_coef(c->beta64, geno_scale(c), c->coef, c->p, B, c->stream), "coefficients");
+                STCHK(dense_eta(c, c->coef, B, nullptr));
+            }
+        }
+        HIPCHK(launch_risk(ra, c->stream), "risk-set sums");
+        if (it < o.max_iter) {
+            STCHK(run_gemvt(c, g, B));
+            if (o.eta_mode == 0) HIPCHK(launch_compact(c->chg_cnt, c->chg_idx, c->nblk, c->sel, c->nsel, c->stream), "compact");
+        }
+        if ((it + 1) % poll == 0 && it < o.max_iter) {
+            std::vector<int32_t> act(B);
+            STCHK(d2h(c, act.data(), c->active, sizeof(int32_t) * B));
+            if (std::all_of(act.begin(), act.end(), [](int32_t a) { return a == 0; })) break;
+        }
+    }
+    HIPCHK(launch_f64_to_f32(c->beta64, beta, Bp, c->stream), "beta to FP32");
+    std::vector<int32_t> st(B), itv(B);
+    std::vector<double> fo(B);
+    STCHK(d2h(c, st.data(), c->status, sizeof(int32_t) * B));
+    STCHK(d2h(c, itv.data(), c->iters, sizeof(int32_t) * B));
+    STCHK(d2h(c, fo.data(), c->fobj, sizeof(double) * B));
+    if (iters) std::copy(itv.begin(), itv.end(), iters);
+    if (obj) std::copy(fo.begin(), fo.end(), obj);
+    bool numeric = false, notconv = false;
+    for (int b = 0; b < B; ++b) {
+        numeric = numeric || st[b] == 3;
+        notconv = notconv || st[b] == 2 || st[b] == 0;
+    }
+    if (numeric) return fail(c, COX_ERR_NUMERIC, "non-finite objective");
+    if (notconv) return fail(c, COX_ERR_NOT_CONVERGED, "max_iter reached");
+    return COX_OK;
+}
+
+cox_status cox_nll_forward(cox_ctx* c, const void* eta, int32_t eta_f64, int32_t B, double* loss)
+{
+    STCHK(check_ctx(c));
+    if (!eta || !loss || (eta_f64 != 0 && eta_f64 != 1)) return fail(c, COX_ERR_INVALID_ARG, "bad nll_forward arguments");
+    STCHK(check_batch(c, B));
+    RiskArgs ra = risk_args(c, B);
+    ra.eta_in = eta;
+    ra.eta_in_f32 = !eta_f64;
+    ra.r32 = nullptr;
+    ra.r64 = c->r64;
+    HIPCHK(launch_risk(ra, c->stream), "risk-set sums");
+    HIPCHK(launch_rowsum(c->L, 1, B, -1.0, loss, c->stream), "negate");
+    c->fwd_B = B;
+    c->fwd_f64 = eta_f64;
+    return COX_OK;
+}
+
+cox_status cox_nll_backward(cox_ctx* c, const double* grad_loss, int32_t B, void* grad_eta)
+{
+    STCHK(check_ctx(c));
+    if (!grad_loss || !grad_eta) return fail(c, COX_ERR_INVALID_ARG, "bad nll_backward arguments");
+    if (B != c->fwd_B) return fail(c, COX_ERR_INVALID_ARG, "backward needs a forward with the same B");
+    HIPCHK(launch_nll_backward(c->r64, grad_loss, c->n, B, grad_eta, c->fwd_f64, c->stream), "adjoint");
+    return COX_OK;
+}
+
+}  // extern "C"

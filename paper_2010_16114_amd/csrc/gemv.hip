@@ -1,0 +1,323 @@
+// gemv.hip -- the linear predictor eta = X~ beta (Section 5.3: w = exp(x_i' beta)).
+//
+// Two forms:
+//  * dense: every column of X is read once.  Workgroups tile rows (1024 per
+//    workgroup, 4 consecutive rows per lane) and column blocks; the
+//    coefficients of the block are staged in LDS 256 at a time.  Partial sums of
+//    the column blocks are written out and reduced in a fixed order by a second
+//    kernel, so the result does not depend on scheduling.
+//  * update: eta += X~[:, S] dcoef_S for the set S of columns whose coefficient
+//    changed in the last step (the proximal step keeps most coefficients at
+//    zero, so S is small and only |S| columns are read).  Partial sums of a few
+//    column groups go to a buffer that the risk-set kernel adds in fixed order;
+//    eta itself is held in FP64 so that the running sum tracks X~ beta exactly
+//    to rounding.
+// Both take per-column coefficients already multiplied by the genotype scale
+// s_j; the centring term is a constant shift of eta, to which the partial
+// likelihood is invariant, and is applied only where an exact X~ v is needed.
+#include "device_common.h"
+
+namespace cox {
+namespace {
+
+constexpr int kT = kGemvThreads;
+constexpr int kRows = 4 * kT;  // rows per workgroup
+constexpr int kColStage = 256;
+
+// Four rows of column `col` starting at row r0 (VEC: r0 % 4 == 0, 16- or 4-byte load).
+template <int XT, bool VEC>
+__device__ __forceinline__ void load_rows4(const XDesc& x, int64_t col, int64_t r0, int64_t n, float* o)
+{
+    const int64_t off = col * x.ldx + r0;
+    if (VEC && r0 + 3 < n) {
+        if constexpr (XT == XT_F32) {
+            const float4 v = load_f4(static_cast<const float*>(x.X) + off);
+            o[0] = v.x;
+            o[1] = v.y;
+            o[2] = v.z;
+            o[3] = v.w;
+        } else {
+            const uint32_t w = *reinterpret_cast<const uint32_t*>(static_cast<const uint8_t*>(x.X) + off);
+            decode4<XT>(w, o);
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) o[e] = (r0 + e < n) ? load_x1<XT>(x.X, off + e) : 0.f;
+    }
+}
+
+// Rows owned by this thread: VEC -> 4 consecutive rows; otherwise 4 rows 256 apart.
+template <bool VEC>
+__device__ __forceinline__ int64_t row_of(int64_t slab0, int e)
+{
+    return VEC ? slab0 + (int64_t)threadIdx.x * 4 + e : slab0 + threadIdx.x + (int64_t)kT * e;
+}
+
+template <int XT, int NB, bool VEC>
+__global__ __launch_bounds__(kT) void gemv_kernel(XDesc x, const double* __restrict__ coef, int b0, int nb,
+                                                  int64_t cpb, double* __restrict__ part)
+{
+    __shared__ double sc[NB][kColStage];
+    const int64_t n = x.n, p = x.p;
+    const int64_t slab0 = (int64_t)blockIdx.x * kRows;
+    const int64_t jbeg = (int64_t)blockIdx.y * cpb;
+    const int64_t jend = min(p, jbeg + cpb);
+    double acc[NB][4];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[b][e] = 0.0;
+
+    for (int64_t jc = jbeg; jc < jend; jc += kColStage) {
+        __syncthreads();
+        for (int t = threadIdx.x; t < NB * kColStage; t += kT) {
+            const int b = t / kColStage, q = t % kColStage;
+            sc[b][q] = (b < nb && jc + q < jend) ? coef[(int64_t)(b0 + b) * p + jc + q] : 0.0;
+        }
+        __syncthreads();
+        const int jn = (int)min((int64_t)kColStage, jend - jc);
+        const int64_t r0 = VEC ? slab0 + (int64_t)threadIdx.x * 4 : 0;
+        for (int t = 0; t < jn; t += 8) {
+            float xv[8][4];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (t + u < jn) {
+                    if (VEC) {
+                        load_rows4<XT, true>(x, jc + t + u, r0, n, xv[u]);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int64_t r = row_of<false>(slab0, e);
+                            xv[u][e] = r < n ? load_x1<XT>(x.X, (jc + t + u) * x.ldx + r) : 0.f;
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) xv[u][e] = 0.f;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    const double cf = sc[b][t + u < kColStage ? t + u : 0];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) acc[b][e] = fma((double)xv[u][e], cf, acc[b][e]);
+                }
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        if (b >= nb) break;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t r = row_of<VEC>(slab0, e);
+            if (r < n) part[((int64_t)blockIdx.y * nb + b) * n + r] = acc[b][e];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void gemv_reduce_kernel(const double* __restrict__ part, int ncb, int nb, int64_t n,
+                                                          int b0, const double* __restrict__ shift,
+                                                          double* __restrict__ eta)
+{
+    const int b = blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        double s = 0.0;
+        for (int c = 0; c < ncb; ++c) s += part[((int64_t)c * nb + b) * n + i];
+        if (shift) s += shift[b0 + b];
+        eta[(int64_t)(b0 + b) * n + i] = s;
+    }
+}
+
+template <int XT, int NB, bool VEC>
+__global__ __launch_bounds__(kT) void eta_update_kernel(XDesc x, const int32_t* __restrict__ sel,
+                                                        const int32_t* __restrict__ nsel_p,
+                                                        const double* __restrict__ dcoef, int b0, int nb,
+                                                        double* __restrict__ part, int64_t cstride, int ncg,
+                                                        const int32_t* __restrict__ active)
+{
+    const int nsel = *nsel_p;
+    if (nsel == 0) return;
+    if (active) {
+        int any = 0;
+        for (int b = 0; b < nb; ++b) any |= active[b0 + b];
+        if (!any) return;
+    }
+    const int64_t n = x.n, p = x.p;
+    const int64_t slab0 = (int64_t)blockIdx.x * kRows;
+    const int cg = blockIdx.y;
+    const int chunk = (nsel + ncg - 1) / ncg;
+    const int q0 = cg * chunk;
+    const int q1 = min(nsel, q0 + chunk);
+    double acc[NB][4];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[b][e] = 0.0;
+    const int64_t r0 = slab0 + (int64_t)threadIdx.x * 4;
+    for (int q = q0; q < q1; q += 4) {
+        float xv[4][4];
+        int64_t jj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            jj[u] = q + u < q1 ? sel[q + u] : -1;
+            if (jj[u] >= 0) {
+                if (VEC) {
+                    load_rows4<XT, true>(x, jj[u], r0, n, xv[u]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int64_t r = row_of<false>(slab0, e);
+                        xv[u][e] = r < n ? load_x1<XT>(x.X, jj[u] * x.ldx + r) : 0.f;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (jj[u] < 0) break;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                if (b >= nb) break;
+                const double d = dcoef[(int64_t)(b0 + b) * p + jj[u]];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[b][e] = fma((double)xv[u][e], d, acc[b][e]);
+            }
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        if (b >= nb) break;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t r = row_of<VEC>(slab0, e);
+            if (r < n) part[(int64_t)cg * cstride + (int64_t)(b0 + b) * n + r] = acc[b][e];
+        }
+    }
+}
+
+__global__ __launch_bounds__(1024) void compact_kernel(const int32_t* __restrict__ cnt,
+                                                       const int32_t* __restrict__ idx, int nblk,
+                                                       int32_t* __restrict__ sel, int32_t* __restrict__ nsel)
+{
+    __shared__ int sh[17];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int carry = 0;
+    for (int base = 0; base < nblk; base += 1024) {
+        const int blk = base + threadIdx.x;
+        const int c = blk < nblk ? cnt[blk] : 0;
+        int inc = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += t;
+        }
+        if (lane == 63) sh[wid] = inc;
+        __syncthreads();
+        if (wid == 0) {
+            const int t = lane < 16 ? sh[lane] : 0;
+            int ti = t;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int u = __shfl_up(ti, o, 64);
+                if (lane >= o) ti += u;
+            }
+            if (lane < 16) sh[lane] = ti - t;
+            if (lane == 15) sh[16] = ti;
+        }
+        __syncthreads();
+        const int ex = sh[wid] + inc - c;
+        const int tot = sh[16];
+        for (int q = 0; q < c; ++q) sel[carry + ex + q] = idx[(int64_t)blk * kGemvtCols + q];
+        carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *nsel = carry;
+}
+
+template <int XT, int NB>
+hipError_t gemv_t(const XDesc& x, const double* coef, int b0, int nb, double* part, int ncb, hipStream_t s)
+{
+    const int64_t cpb = (x.p + ncb - 1) / ncb;
+    const dim3 grid((unsigned)((x.n + kRows - 1) / kRows), (unsigned)ncb);
+    const bool vec = x.xt == XT_F32 ? x.vec16 : x.vec4;
+    if (vec)
+        hipLaunchKernelGGL((gemv_kernel<XT, NB, true>), grid, dim3(kT), 0, s, x, coef, b0, nb, cpb, part);
+    else
+        hipLaunchKernelGGL((gemv_kernel<XT, NB, false>), grid, dim3(kT), 0, s, x, coef, b0, nb, cpb, part);
+    return hipGetLastError();
+}
+
+template <int XT>
+hipError_t gemv_x(const XDesc& x, const double* coef, int b0, int nb, double* part, int ncb, hipStream_t s)
+{
+    if (nb <= 1) return gemv_t<XT, 1>(x, coef, b0, nb, part, ncb, s);
+    if (nb <= 2) return gemv_t<XT, 2>(x, coef, b0, nb, part, ncb, s);
+    if (nb <= 4) return gemv_t<XT, 4>(x, coef, b0, nb, part, ncb, s);
+    return gemv_t<XT, 8>(x, coef, b0, nb, part, ncb, s);
+}
+
+template <int XT, int NB>
+hipError_t upd_t(const XDesc& x, const int32_t* sel, const int32_t* nsel, const double* dcoef, int b0, int nb,
+                 double* part, int64_t cstride, int ncg, const int32_t* active, hipStream_t s)
+{
+    const dim3 grid((unsigned)((x.n + kRows - 1) / kRows), (unsigned)ncg);
+    const bool vec = x.xt == XT_F32 ? x.vec16 : x.vec4;
+    if (vec)
+        hipLaunchKernelGGL((eta_update_kernel<XT, NB, true>), grid, dim3(kT), 0, s, x, sel, nsel, dcoef, b0, nb,
+                           part, cstride, ncg, active);
+    else
+        hipLaunchKernelGGL((eta_update_kernel<XT, NB, false>), grid, dim3(kT), 0, s, x, sel, nsel, dcoef, b0, nb,
+                           part, cstride, ncg, active);
+    return hipGetLastError();
+}
+
+template <int XT>
+hipError_t upd_x(const XDesc& x, const int32_t* sel, const int32_t* nsel, const double* dcoef, int b0, int nb,
+                 double* part, int64_t cstride, int ncg, const int32_t* active, hipStream_t s)
+{
+    if (nb <= 1) return upd_t<XT, 1>(x, sel, nsel, dcoef, b0, nb, part, cstride, ncg, active, s);
+    if (nb <= 2) return upd_t<XT, 2>(x, sel, nsel, dcoef, b0, nb, part, cstride, ncg, active, s);
+    if (nb <= 4) return upd_t<XT, 4>(x, sel, nsel, dcoef, b0, nb, part, cstride, ncg, active, s);
+    return upd_t<XT, 8>(x, sel, nsel, dcoef, b0, nb, part, cstride, ncg, active, s);
+}
+
+}  // namespace
+
+hipError_t launch_gemv(const XDesc& x, const double* coef, int b0, int nb, double* part, int ncb, double* eta,
+                       const double* shift, hipStream_t s)
+{
+    if (nb < 1 || nb > 8 || ncb < 1) return hipErrorInvalidValue;
+    hipError_t e;
+    switch (x.xt) {
+    case XT_F32: e = gemv_x<XT_F32>(x, coef, b0, nb, part, ncb, s); break;
+    case XT_FP8: e = gemv_x<XT_FP8>(x, coef, b0, nb, part, ncb, s); break;
+    default: e = gemv_x<XT_I8>(x, coef, b0, nb, part, ncb, s); break;
+    }
+    if (e != hipSuccess) return e;
+    const unsigned gx = (unsigned)min((int64_t)1024, (x.n + 255) / 256);
+    hipLaunchKernelGGL(gemv_reduce_kernel, dim3(gx, nb), dim3(256), 0, s, part, ncb, nb, x.n, b0, shift, eta);
+    return hipGetLastError();
+}
+
+hipError_t launch_eta_update(const XDesc& x, const int32_t* sel, const int32_t* nsel, const double* dcoef, int b0,
+                             int nb, double* part, int64_t part_cstride, int ncg, const int32_t* active,
+                             hipStream_t s)
+{
+    if (nb < 1 || nb > 8 || ncg < 1) return hipErrorInvalidValue;
+    switch (x.xt) {
+    case XT_F32: return upd_x<XT_F32>(x, sel, nsel, dcoef, b0, nb, part, part_cstride, ncg, active, s);
+    case XT_FP8: return upd_x<XT_FP8>(x, sel, nsel, dcoef, b0, nb, part, part_cstride, ncg, active, s);
+    default: return upd_x<XT_I8>(x, sel, nsel, dcoef, b0, nb, part, part_cstride, ncg, active, s);
+    }
+}
+
+hipError_t launch_compact(const int32_t* chg_cnt, const int32_t* chg_idx, int nblk, int32_t* sel, int32_t* nsel,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(1024), 0, s, chg_cnt, chg_idx, nblk, sel, nsel);
+    return hipGetLastError();
+}
+
+}  // namespace cox

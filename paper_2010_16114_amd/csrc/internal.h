@@ -1,0 +1,143 @@
+// internal.h -- launch interfaces between the host runtime (api.cpp) and the
+// HIP kernels of libcoxhip.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cox {
+
+// Element storage of X.
+enum XType : int { XT_F32 = 0, XT_FP8 = 1, XT_I8 = 2 };
+
+// Geometry shared by kernels and the host.
+constexpr int kGemvtThreads = 256;                  // 4 waves
+constexpr int kGemvtColsPerWave = 4;
+constexpr int kGemvtCols = 4 * kGemvtColsPerWave;   // columns per GEMV^T workgroup
+constexpr int kRiskThreads = 1024;
+constexpr int kUpdThreads = 256;                    // eta update: 4 rows per thread
+constexpr int kUpdRows = 4 * kUpdThreads;
+constexpr int kGemvThreads = 256;                   // dense GEMV
+constexpr int kMaxHist = 33;                        // lag <= 32
+
+// Read-only description of X as the kernels see it.
+struct XDesc {
+    const void* X;
+    int xt;
+    int64_t n, p, ldx;
+    const float* center;  // may be null
+    const float* scale;   // may be null
+    int vec16;            // 16-byte loads legal: base and ldx*elem aligned to 16 bytes
+    int vec4;             // 4-byte loads legal for 1-byte types
+};
+
+// Per-subject order and tie groups (sorted position k = 0 .. n-1).
+struct Order {
+    const int32_t* perm;    // subject at sorted position k
+    const int32_t* gstart;  // first position of k's tie group
+    const int32_t* gend;    // last position of k's tie group
+    const uint8_t* ev;      // event indicator at sorted position k
+};
+
+// Convergence bookkeeping of cox_fit_path, one entry per b.
+struct FitCtl {
+    const double* lam;     // [B]
+    const double* l1;      // [B][nblk] partial sums of |beta_k|
+    int nblk;
+    double* hist;          // [B][kMaxHist] ring of objective values
+    int32_t* kit;          // [B] current step k
+    int32_t* active;       // [B] 1 while b is iterating
+    int32_t* iters;        // [B] steps taken at the stop
+    int32_t* status;       // [B] 0 running, 1 converged, 2 max_iter, 3 non-finite
+    double* fobj;          // [B] latest objective
+    int max_iter, lag;
+    double tol;
+};
+
+struct RiskArgs {
+    int64_t n;
+    int B;
+    Order ord;
+    const void* eta_in;    // [B][n] original order; double unless eta_in_f32
+    int eta_in_f32;
+    double* eta_out;       // if not null: eta_in + partials is written here ([B][n])
+    const double* part;    // [ncg][bstride_part] partial eta updates, or null
+    int ncg;
+    int64_t part_cstride;  // elements between column groups
+    const int32_t* nsel;   // partials are added only when *nsel > 0
+    double* w;             // [B][n] scratch, sorted order
+    double* S;             // [B][n] scratch
+    double* T;             // [B][n] scratch
+    float* r32;            // [B][n] residual, original order (nullable)
+    double* r64;           // [B][n] residual, original order (nullable)
+    double* L;             // [B] log partial likelihood
+    double* sumr;          // [B] sum of the stored residual (as stored)
+    int64_t rstride;       // b-stride of r32 (>= n, padded for aligned loads)
+    int use_ctl;           // 1 inside cox_fit_path
+    FitCtl ctl;
+};
+
+enum GemvtMode : int { GT_RAW = 0, GT_GRAD = 1, GT_PROX = 2 };
+
+struct GemvtArgs {
+    XDesc x;
+    const float* r32;      // [B][rstride], b-major; rows n..rstride-1 are zero
+    int64_t rstride;       // multiple of 1024
+    const double* sumr;    // [B] (centring of genotype columns)
+    int b0, nb;            // this launch covers b0 .. b0+nb-1 (nb <= template NB)
+    int mode;
+    double* out64;         // GT_RAW: [B][p]  X~' r
+    float* out32;          // GT_GRAD: [B][p]  -X~' r
+    // GT_PROX
+    double* beta;          // [B][p] in/out
+    const double* lam;     // [B]
+    double step;
+    const int32_t* active; // [B] or null (all active)
+    double* dcoef;         // [B][p] (beta_new - beta_old) * scale_j
+    int32_t* chg_flag;     // [p] 1 if beta_j changed for some b (ORed over launches)
+    int32_t* chg_cnt;      // [nblk] changed columns per workgroup
+    int32_t* chg_idx;      // [nblk][kGemvtCols] their indices, ascending
+    double* l1old;         // [B][nblk]
+    double* l1new;         // [B][nblk]
+    int nblk;
+    int first_group;       // 1 on the launch with b0 == 0: it resets the change lists
+};
+
+// Launchers (return hipError_t of the launch).
+hipError_t launch_risk(const RiskArgs& a, hipStream_t s);
+hipError_t launch_gemvt(const GemvtArgs& a, hipStream_t s);
+// eta partials: part[cg][b][i] for b in [b0, b0+nb) from the compacted change list
+hipError_t launch_eta_update(const XDesc& x, const int32_t* sel, const int32_t* nsel, const double* dcoef,
+                             int b0, int nb, double* part, int64_t part_cstride, int ncg,
+                             const int32_t* active, hipStream_t s);
+// dense eta = X~ coef for b in [b0, b0+nb): partials over column blocks, then reduced
+hipError_t launch_gemv(const XDesc& x, const double* coef, int b0, int nb, double* part, int ncb,
+                       double* eta, const double* shift, hipStream_t s);
+hipError_t launch_compact(const int32_t* chg_cnt, const int32_t* chg_idx, int nblk, int32_t* sel,
+                          int32_t* nsel, hipStream_t s);
+// misc elementwise / reductions
+hipError_t launch_f32_to_f64(const float* in, double* out, int64_t m, hipStream_t s);
+hipError_t launch_f64_to_f32(const double* in, float* out, int64_t m, hipStream_t s);
+hipError_t launch_scale_coef(const double* beta, const float* scale, double* coef, int64_t p, int B,
+                             hipStream_t s);
+hipError_t launch_l1_blocks(const double* beta, int64_t p, int B, int nblk, double* l1, hipStream_t s);
+hipError_t launch_prox_apply(float* beta, const float* grad, const double* lam, double step, int64_t p, int B,
+                             hipStream_t s);
+hipError_t launch_nll_backward(const double* r64, const double* gl, int64_t n, int B, void* out, int out_f64,
+                               hipStream_t s);
+// out[0] = sum_i a_i * (b ? b_i : 1) over m entries, one workgroup, fixed order
+hipError_t launch_dot(const double* a, const double* b, int64_t m, double* out, hipStream_t s);
+// out[0] = -sum_j center_j * scale_j * v_j  (centring shift of X~ v)
+hipError_t launch_center_shift(const float* center, const float* scale, const double* v, int64_t p, double* out,
+                               hipStream_t s);
+// out[j] = in[j] / sqrt(nrm2[0]) * (scale ? scale_j : 1) and vout[j] = in[j] / sqrt(nrm2[0])
+hipError_t launch_normalize(const double* in, const double* nrm2, const float* scale, double* vout, double* coef,
+                            int64_t p, hipStream_t s);
+// r32[i] = (float) u[i] + shift[0]; sumr[0] = sum (double) r32[i]
+hipError_t launch_to_r32(const double* u, const double* shift, float* r32, double* sumr, int64_t n,
+                         hipStream_t s);
+// out[b] = a * sum_i in[b*m + i], one workgroup per b, fixed order
+hipError_t launch_rowsum(const double* in, int64_t m, int B, double a, double* out, hipStream_t s);
+hipError_t launch_fill_f64(double* p, double v, int64_t m, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t m, hipStream_t s);
+
+}  // namespace cox

@@ -1,0 +1,220 @@
+// misc.hip -- small elementwise kernels and fixed-order reductions.
+//
+// prox_apply is the standalone fused elementwise step of Section 5.3,
+// beta <- S_{sigma lambda}(beta - sigma grad), with S the soft-thresholding of
+// Section 4.2; nll_backward is the adjoint of the negative log partial
+// likelihood with respect to eta (-(I - P) delta scaled by the incoming
+// gradient).  Reductions run in one workgroup in a fixed order, so results are
+// reproducible bit for bit.
+#include "device_common.h"
+
+namespace cox {
+namespace {
+
+constexpr int kT = 256;
+
+inline unsigned grid_for(int64_t m) { return (unsigned)min((int64_t)8192, max((int64_t)1, (m + kT - 1) / kT)); }
+
+__global__ void f32_to_f64_kernel(const float* __restrict__ in, double* __restrict__ out, int64_t m)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < m; i += (int64_t)gridDim.x * kT) out[i] = in[i];
+}
+
+__global__ void f64_to_f32_kernel(const double* __restrict__ in, float* __restrict__ out, int64_t m)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < m; i += (int64_t)gridDim.x * kT)
+        out[i] = (float)in[i];
+}
+
+__global__ void scale_coef_kernel(const double* __restrict__ beta, const float* __restrict__ scale,
+                                  double* __restrict__ coef, int64_t p, int B)
+{
+    const int64_t m = p * B;
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < m; i += (int64_t)gridDim.x * kT)
+        coef[i] = scale ? beta[i] * (double)scale[i % p] : beta[i];
+}
+
+// l1[b][blk] = sum over the 16 columns of GEMV^T workgroup blk of |beta_bj|, in column order.
+__global__ void l1_blocks_kernel(const double* __restrict__ beta, int64_t p, int B, int nblk,
+                                 double* __restrict__ l1)
+{
+    const int64_t m = (int64_t)nblk * B;
+    for (int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x; t < m; t += (int64_t)gridDim.x * kT) {
+        const int64_t b = t / nblk, blk = t % nblk;
+        double s = 0.0;
+        for (int c = 0; c < kGemvtCols; ++c) {
+            const int64_t j = blk * kGemvtCols + c;
+            if (j < p) s += fabs(beta[b * p + j]);
+        }
+        l1[t] = s;
+    }
+}
+
+__global__ void prox_apply_kernel(float* __restrict__ beta, const float* __restrict__ grad,
+                                  const double* __restrict__ lam, double step, int64_t p, int B)
+{
+    const int64_t m = p * B;
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < m; i += (int64_t)gridDim.x * kT) {
+        const double t = step * lam[i / p];
+        beta[i] = (float)soft_threshold((double)beta[i] - step * (double)grad[i], t);
+    }
+}
+
+__global__ void nll_backward_kernel(const double* __restrict__ r, const double* __restrict__ gl, int64_t n, int B,
+                                    void* __restrict__ out, int out_f64)
+{
+    const int64_t m = n * B;
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < m; i += (int64_t)gridDim.x * kT) {
+        const double v = -gl[i / n] * r[i];
+        if (out_f64)
+            static_cast<double*>(out)[i] = v;
+        else
+            static_cast<float*>(out)[i] = (float)v;
+    }
+}
+
+__device__ double wg_sum(double v)
+{
+    __shared__ double sh[kT / kWave + 1];
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    v = wave_sum(v);
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int q = 0; q < kT / kWave; ++q) s += sh[q];
+        sh[kT / kWave] = s;
+    }
+    __syncthreads();
+    return sh[kT / kWave];
+}
+
+__global__ void dot_kernel(const double* __restrict__ a, const double* __restrict__ b, int64_t m,
+                           double* __restrict__ out)
+{
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < m; i += kT) s += a[i] * (b ? b[i] : 1.0);
+    s = wg_sum(s);
+    if (threadIdx.x == 0) out[0] = s;
+}
+
+__global__ void center_shift_kernel(const float* __restrict__ center, const float* __restrict__ scale,
+                                    const double* __restrict__ v, int64_t p, double* __restrict__ out)
+{
+    double s = 0.0;
+    for (int64_t j = threadIdx.x; j < p; j += kT) s += (double)center[j] * (scale ? (double)scale[j] : 1.0) * v[j];
+    s = wg_sum(s);
+    if (threadIdx.x == 0) out[0] = -s;
+}
+
+__global__ void normalize_kernel(const double* __restrict__ in, const double* __restrict__ nrm2,
+                                 const float* __restrict__ scale, double* __restrict__ vout,
+                                 double* __restrict__ coef, int64_t p)
+{
+    const double inv = 1.0 / sqrt(nrm2[0]);
+    for (int64_t j = (int64_t)blockIdx.x * kT + threadIdx.x; j < p; j += (int64_t)gridDim.x * kT) {
+        const double v = in[j] * inv;
+        vout[j] = v;
+        coef[j] = scale ? v * (double)scale[j] : v;
+    }
+}
+
+__global__ void to_r32_kernel(const double* __restrict__ u, const double* __restrict__ shift,
+                              float* __restrict__ r32, double* __restrict__ sumr, int64_t n)
+{
+    const double sh = shift ? shift[0] : 0.0;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kT) {
+        const float f = (float)(u[i] + sh);
+        r32[i] = f;
+        s += (double)f;
+    }
+    s = wg_sum(s);
+    if (threadIdx.x == 0) sumr[0] = s;
+}
+
+__global__ void rowsum_kernel(const double* __restrict__ in, int64_t m, double a, double* __restrict__ out)
+{
+    const int64_t b = blockIdx.x;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < m; i += kT) s += in[b * m + i];
+    s = wg_sum(s);
+    if (threadIdx.x == 0) out[b] = a * s;
+}
+
+__global__ void fill_f64_kernel(double* __restrict__ p, double v, int64_t m)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < m; i += (int64_t)gridDim.x * kT) p[i] = v;
+}
+
+__global__ void fill_i32_kernel(int32_t* __restrict__ p, int32_t v, int64_t m)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < m; i += (int64_t)gridDim.x * kT) p[i] = v;
+}
+
+}  // namespace
+
+#define COX_LAUNCH(kernel, grid, ...)                                        \
+    do {                                                                     \
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(kT), 0, s, __VA_ARGS__); \
+        return hipGetLastError();                                            \
+    } while (0)
+
+hipError_t launch_f32_to_f64(const float* in, double* out, int64_t m, hipStream_t s)
+{
+    COX_LAUNCH(f32_to_f64_kernel, grid_for(m), in, out, m);
+}
+hipError_t launch_f64_to_f32(const double* in, float* out, int64_t m, hipStream_t s)
+{
+    COX_LAUNCH(f64_to_f32_kernel, grid_for(m), in, out, m);
+}
+hipError_t launch_scale_coef(const double* beta, const float* scale, double* coef, int64_t p, int B, hipStream_t s)
+{
+    COX_LAUNCH(scale_coef_kernel, grid_for(p * B), beta, scale, coef, p, B);
+}
+hipError_t launch_l1_blocks(const double* beta, int64_t p, int B, int nblk, double* l1, hipStream_t s)
+{
+    COX_LAUNCH(l1_blocks_kernel, grid_for((int64_t)nblk * B), beta, p, B, nblk, l1);
+}
+hipError_t launch_prox_apply(float* beta, const float* grad, const double* lam, double step, int64_t p, int B,
+                             hipStream_t s)
+{
+    COX_LAUNCH(prox_apply_kernel, grid_for(p * B), beta, grad, lam, step, p, B);
+}
+hipError_t launch_nll_backward(const double* r64, const double* gl, int64_t n, int B, void* out, int out_f64,
+                               hipStream_t s)
+{
+    COX_LAUNCH(nll_backward_kernel, grid_for(n * B), r64, gl, n, B, out, out_f64);
+}
+hipError_t launch_dot(const double* a, const double* b, int64_t m, double* out, hipStream_t s)
+{
+    COX_LAUNCH(dot_kernel, 1, a, b, m, out);
+}
+hipError_t launch_center_shift(const float* center, const float* scale, const double* v, int64_t p, double* out,
+                               hipStream_t s)
+{
+    COX_LAUNCH(center_shift_kernel, 1, center, scale, v, p, out);
+}
+hipError_t launch_normalize(const double* in, const double* nrm2, const float* scale, double* vout, double* coef,
+                            int64_t p, hipStream_t s)
+{
+    COX_LAUNCH(normalize_kernel, grid_for(p), in, nrm2, scale, vout, coef, p);
+}
+hipError_t launch_to_r32(const double* u, const double* shift, float* r32, double* sumr, int64_t n, hipStream_t s)
+{
+    COX_LAUNCH(to_r32_kernel, 1, u, shift, r32, sumr, n);
+}
+hipError_t launch_rowsum(const double* in, int64_t m, int B, double a, double* out, hipStream_t s)
+{
+    COX_LAUNCH(rowsum_kernel, B, in, m, a, out);
+}
+hipError_t launch_fill_f64(double* p, double v, int64_t m, hipStream_t s)
+{
+    COX_LAUNCH(fill_f64_kernel, grid_for(m), p, v, m);
+}
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t m, hipStream_t s)
+{
+    COX_LAUNCH(fill_i32_kernel, grid_for(m), p, v, m);
+}
+
+}  // namespace cox

@@ -1,0 +1,57 @@
+"""The C-ABI library loads, exports what include/cox.h declares, and rejects bad
+arguments before any device work (no GPU needed: nothing here launches)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import paper_2010_16114_amd as P
+
+
+def test_exports_every_declared_symbol():
+    L = P.lib()
+    syms = P.declared_symbols()
+    assert len(syms) >= 12
+    missing = [s for s in syms if not hasattr(L, s)]
+    assert not missing
+
+
+def test_status_strings():
+    L = P.lib()
+    assert L.cox_status_string(0) == b"ok"
+    assert L.cox_status_string(1) == b"invalid argument"
+    assert L.cox_status_string(5).startswith(b"maximum")
+    assert L.cox_status_string(99) == b"unknown status"
+
+
+def _setup(X=0x10000, xtype=0, n=10, p=3, ldx=10, center=None, scale=None, time=None, event=None, B=1,
+           null_out=False):
+    L = P.lib()
+    t = np.arange(n, dtype=np.float64) + 1 if time is None else np.asarray(time, np.float64)
+    e = np.ones(n, np.int32) if event is None else np.asarray(event, np.int32)
+    m = P._Matrix(X, xtype, n, p, ldx, center, scale)
+    h = ctypes.c_void_p()
+    out = None if null_out else ctypes.byref(h)
+    return L.cox_setup(out, ctypes.byref(m), P._np_ptr(t), P._np_ptr(e), B, None), h
+
+
+@pytest.mark.parametrize("kw", [dict(null_out=True), dict(X=None), dict(xtype=3), dict(n=0, ldx=0),
+                                dict(p=0), dict(ldx=9), dict(B=0), dict(B=65), dict(center=0x2000),
+                                dict(time=[1, 2, np.nan] + [4] * 7), dict(event=[0, 1, 2] + [1] * 7),
+                                dict(time=[1, np.inf] + [3] * 8)])
+def test_setup_rejects_bad_arguments(kw):
+    st, h = _setup(**kw)
+    assert st == P.ERR_INVALID_ARG
+    assert not h.value
+
+
+def test_null_context_calls():
+    L = P.lib()
+    buf = ctypes.create_string_buffer(16)
+    assert L.cox_last_error(None, buf, 16) == P.ERR_INVALID_ARG
+    assert L.cox_destroy(None) == P.OK
+    d = ctypes.c_double()
+    assert L.cox_lambda_max(None, ctypes.byref(d)) == P.ERR_INVALID_ARG
+    assert L.cox_loss_grad(None, None, 1, None, None) == P.ERR_INVALID_ARG
+    assert L.cox_fit_path(None, None, 1, None, None, None, None) == P.ERR_INVALID_ARG
+    assert L.cox_nll_forward(None, None, 0, 1, None) == P.ERR_INVALID_ARG
