@@ -176,6 +176,18 @@ cox_status cox_opnorm2(cox_ctx *ctx, double tol, int32_t maxiter, uint64_t seed,
 cox_status cox_nll_forward(cox_ctx *ctx, const void *eta, int32_t eta_f64, int32_t B, double *loss);
 cox_status cox_nll_backward(cox_ctx *ctx, const double *grad_loss, int32_t B, void *grad_eta);
 
+/* Measurement: per-phase GPU time, taken with HIP events recorded on the
+ * context's stream around each phase's launches (so it can run inside a timed
+ * region).  Phases: COX_PHASE_XTR (the X~' r pass with its fused proximal
+ * epilogue), COX_PHASE_RISK (the risk-set kernel), COX_PHASE_ETA (the eta
+ * update or dense X~ beta pass).
+ * cox_timing_enable(ctx, 1) starts recording and clears the totals; 0 stops.
+ * cox_timing_read returns the summed milliseconds and the number of timed
+ * launches of a phase since the last enable.  Synchronises. */
+typedef enum { COX_PHASE_XTR = 0, COX_PHASE_RISK = 1, COX_PHASE_ETA = 2 } cox_phase;
+cox_status cox_timing_enable(cox_ctx *ctx, int32_t enable);
+cox_status cox_timing_read(cox_ctx *ctx, int32_t phase, double *total_ms, int64_t *count);
+
 #ifdef __cplusplus
 }
 #endif

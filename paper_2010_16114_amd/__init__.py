@@ -72,6 +72,8 @@ def lib():
         "cox_opnorm2": [vp, dbl, i32, u64, ctypes.POINTER(dbl), ctypes.POINTER(i32)],
         "cox_nll_forward": [vp, vp, i32, i32, vp],
         "cox_nll_backward": [vp, vp, i32, vp],
+        "cox_timing_enable": [vp, i32],
+        "cox_timing_read": [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -216,6 +218,19 @@ class Cox:
         self._check(st, "cox_nll_forward")
         self.last_forward_key = self.forward_key(eta)
         return loss
+
+    PHASES = {"xtr": 0, "risk": 1, "eta": 2}
+
+    def timing(self, enable: bool):
+        self._check(lib().cox_timing_enable(self._h, int(enable)), "cox_timing_enable")
+
+    def timing_read(self, phase: str):
+        """(total milliseconds, number of timed launches) of a phase since timing(True)."""
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        self._check(lib().cox_timing_read(self._h, self.PHASES[phase], ctypes.byref(ms), ctypes.byref(cnt)),
+                    "cox_timing_read")
+        return ms.value, cnt.value
 
     @staticmethod
     def forward_key(eta):

@@ -56,6 +56,11 @@ struct cox_ctx {
     int32_t *kit = nullptr, *active = nullptr, *iters = nullptr, *status = nullptr;
     int fwd_B = 0, fwd_f64 = 0;
     int64_t n_events = 0;
+    // measurement: event pairs recorded around each phase while timing is on
+    bool timing = false;
+    std::vector<hipEvent_t> tev[3];
+    double tms[3] = {0, 0, 0};
+    int64_t tcount[3] = {0, 0, 0};
 };
 
 namespace {
@@ -104,8 +109,32 @@ bool dalloc(cox_ctx* c, T** out, size_t count)
     return true;
 }
 
+void timing_clear(cox_ctx* c)
+{
+    for (int ph = 0; ph < 3; ++ph) {
+        for (hipEvent_t e : c->tev[ph]) (void)hipEventDestroy(e);
+        c->tev[ph].clear();
+        c->tms[ph] = 0;
+        c->tcount[ph] = 0;
+    }
+}
+
+// Record an event on the stream for phase ph (begin and end alternate).
+void tmark(cox_ctx* c, int ph)
+{
+    if (!c->timing) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    (void)hipEventRecord(e, c->stream);
+    c->tev[ph].push_back(e);
+}
+
 void release(cox_ctx* c)
 {
+    timing_clear(c);
     for (void* p : c->allocs) (void)hipFree(p);
     c->allocs.clear();
     if (c->pinned) (void)hipHostFree(c->pinned);
@@ -176,10 +205,12 @@ const float* geno_scale(const cox_ctx* c) { return c->x.xt == XT_F32 ? nullptr :
 // eta[b] = X~ coef[b] (no centring) for b < B; coef is b-major [B][p].
 cox_status dense_eta(cox_ctx* c, const double* coef, int B, const double* shift)
 {
+    tmark(c, COX_PHASE_ETA);
     for (int b0 = 0; b0 < B; b0 += kGroup) {
         const int nb = std::min(kGroup, B - b0);
         HIPCHK(launch_gemv(c->x, coef, b0, nb, c->part_gemv, c->ncb, c->eta, shift, c->stream), "dense X beta");
     }
+    tmark(c, COX_PHASE_ETA);
     return COX_OK;
 }
 
@@ -228,12 +259,14 @@ GemvtArgs gemvt_args(cox_ctx* c, int mode)
 
 cox_status run_gemvt(cox_ctx* c, GemvtArgs g, int B)
 {
+    tmark(c, COX_PHASE_XTR);
     for (int b0 = 0; b0 < B; b0 += kGroup) {
         g.b0 = b0;
         g.nb = std::min(kGroup, B - b0);
         g.first_group = b0 == 0;
         HIPCHK(launch_gemvt(g, c->stream), "X' r");
     }
+    tmark(c, COX_PHASE_XTR);
     return COX_OK;
 }
 
@@ -587,16 +620,20 @@ cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_
     for (int it = 0; it <= o.max_iter; ++it) {
         if (it > 0) {
             if (o.eta_mode == 0) {
+                tmark(c, COX_PHASE_ETA);
                 for (int b0 = 0; b0 < B; b0 += kGroup)
                     HIPCHK(launch_eta_update(c->x, c->sel, c->nsel, c->dcoef, b0, std::min(kGroup, B - b0),
                                              c->part_upd, cstride, c->ncg, c->active, c->stream),
                            "eta update");
+                tmark(c, COX_PHASE_ETA);
             } else {
                 HIPCHK(launch_scale_coef(c->beta64, geno_scale(c), c->coef, c->p, B, c->stream), "coefficients");
                 STCHK(dense_eta(c, c->coef, B, nullptr));
             }
         }
+        tmark(c, COX_PHASE_RISK);
         HIPCHK(launch_risk(ra, c->stream), "risk-set sums");
+        tmark(c, COX_PHASE_RISK);
         if (it < o.max_iter) {
             STCHK(run_gemvt(c, g, B));
             if (o.eta_mode == 0) HIPCHK(launch_compact(c->chg_cnt, c->chg_idx, c->nblk, c->sel, c->nsel, c->stream), "compact");
@@ -648,6 +685,34 @@ cox_status cox_nll_backward(cox_ctx* c, const double* grad_loss, int32_t B, void
     if (!grad_loss || !grad_eta) return fail(c, COX_ERR_INVALID_ARG, "bad nll_backward arguments");
     if (B != c->fwd_B) return fail(c, COX_ERR_INVALID_ARG, "backward needs a forward with the same B");
     HIPCHK(launch_nll_backward(c->r64, grad_loss, c->n, B, grad_eta, c->fwd_f64, c->stream), "adjoint");
+    return COX_OK;
+}
+
+cox_status cox_timing_enable(cox_ctx* c, int32_t enable)
+{
+    STCHK(check_ctx(c));
+    STCHK(sync(c));
+    timing_clear(c);
+    c->timing = enable != 0;
+    return COX_OK;
+}
+
+cox_status cox_timing_read(cox_ctx* c, int32_t phase, double* total_ms, int64_t* count)
+{
+    STCHK(check_ctx(c));
+    if (phase < 0 || phase > 2 || !total_ms) return fail(c, COX_ERR_INVALID_ARG, "bad timing_read arguments");
+    STCHK(sync(c));
+    auto& ev = c->tev[phase];
+    for (size_t q = 0; q + 1 < ev.size(); q += 2) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, ev[q], ev[q + 1]), "event time");
+        c->tms[phase] += ms;
+        c->tcount[phase] += 1;
+    }
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    ev.clear();
+    *total_ms = c->tms[phase];
+    if (count) *count = c->tcount[phase];
     return COX_OK;
 }
 
