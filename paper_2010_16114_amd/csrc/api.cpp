@@ -49,6 +49,12 @@ struct cox_ctx {
     double *eta = nullptr, *w = nullptr, *S = nullptr, *T = nullptr, *r64 = nullptr;
     float* r32 = nullptr;
     double *part_upd = nullptr, *part_gemv = nullptr;
+    int64_t tile = 0;
+    int ntile = 0, nfin = 0;
+    double* part_xtr = nullptr;  // [nsplit][Bmax][p] split partials of X' r
+    int nsplit = 1;
+    int64_t split_rows = 0;
+    double *bmax = nullptr, *mshift = nullptr, *stot = nullptr, *qtot = nullptr, *Lpart = nullptr, *rpart = nullptr;
     double *beta64 = nullptr, *coef = nullptr, *dcoef = nullptr, *g64 = nullptr;
     int32_t *chg_flag = nullptr, *chg_cnt = nullptr, *chg_idx = nullptr, *sel = nullptr, *nsel = nullptr;
     double *l1old = nullptr, *l1new = nullptr;
@@ -222,7 +228,7 @@ RiskArgs risk_args(cox_ctx* c, int B)
     a.ord = Order{c->perm, c->gstart, c->gend, c->ev};
     a.eta_in = c->eta;
     a.eta_in_f32 = 0;
-    a.eta_out = nullptr;
+    a.eta = c->eta;
     a.part = nullptr;
     a.ncg = c->ncg;
     a.part_cstride = (int64_t)c->Bmax * c->n;
@@ -230,6 +236,15 @@ RiskArgs risk_args(cox_ctx* c, int B)
     a.w = c->w;
     a.S = c->S;
     a.T = c->T;
+    a.tile = c->tile;
+    a.ntile = c->ntile;
+    a.nfin = c->nfin;
+    a.bmax = c->bmax;
+    a.mshift = c->mshift;
+    a.stot = c->stot;
+    a.qtot = c->qtot;
+    a.Lpart = c->Lpart;
+    a.rpart = c->rpart;
     a.r32 = c->r32;
     a.r64 = nullptr;
     a.L = c->L;
@@ -245,6 +260,10 @@ GemvtArgs gemvt_args(cox_ctx* c, int mode)
     g.x = c->x;
     g.r32 = c->r32;
     g.rstride = c->rstride;
+    g.part = c->part_xtr;
+    g.nsplit = c->nsplit;
+    g.split_rows = c->split_rows;
+    g.part_sstride = (int64_t)c->Bmax * c->p;
     g.sumr = c->sumr;
     g.mode = mode;
     g.nblk = c->nblk;
@@ -351,11 +370,24 @@ cox_status cox_setup(cox_ctx** out, const cox_matrix* X, const double* time, con
     c->x = XDesc{X->X, X->xtype, n, p, X->ldx, X->col_center, X->col_scale,
                  (int)(base % 16 == 0 && (X->ldx * (int64_t)elem) % 16 == 0),
                  (int)(base % 4 == 0 && (X->ldx * (int64_t)elem) % 4 == 0)};
-    c->rstride = round_up(n, 8192);
+    c->rstride = round_up(n, kSplitRows);
     c->nblk = (int)((p + kGemvtCols - 1) / kGemvtCols);
     const int64_t nslab = (n + kUpdRows - 1) / kUpdRows;
     c->ncg = (int)std::max<int64_t>(1, std::min<int64_t>(16, 1024 / nslab));
     c->ncb = (int)std::max<int64_t>(1, std::min<int64_t>((2048 + nslab - 1) / nslab, (p + 255) / 256));
+    c->tile = 1024 * std::max<int64_t>(1, (n + 1024LL * kMaxTiles - 1) / (1024LL * kMaxTiles));
+    c->ntile = (int)((n + c->tile - 1) / c->tile);
+    c->nfin = (int)((n + kFinElems - 1) / kFinElems);
+    {   // row splits of X' r: enough workgroups for several even rounds over the chip
+        const int64_t cols_wg = X->xtype == COX_X_F32 ? 16 : 64;
+        const int64_t wgs = (p + cols_wg - 1) / cols_wg;
+        const int64_t nchunks = (n + kSplitRows - 1) / kSplitRows;
+        const int64_t target = std::max<int64_t>(1, (12288 + wgs - 1) / wgs);
+        const int64_t ns = std::min(nchunks, target);
+        const int64_t spc = (nchunks + ns - 1) / ns;
+        c->split_rows = spc * kSplitRows;
+        c->nsplit = (int)((nchunks + spc - 1) / spc);
+    }
 
     // Order by non-increasing time, stable; tie groups (Section 5.3, Section 6).
     std::vector<int32_t> perm(n), gs(n), ge(n);
@@ -386,7 +418,11 @@ cox_status cox_setup(cox_ctx** out, const cox_matrix* X, const double* time, con
               dalloc(c, &c->sumr, max_batch) && dalloc(c, &c->lam, max_batch) && dalloc(c, &c->fobj, max_batch) &&
               dalloc(c, &c->hist, (size_t)max_batch * kMaxHist) && dalloc(c, &c->scal, 16) &&
               dalloc(c, &c->kit, max_batch) && dalloc(c, &c->active, max_batch) && dalloc(c, &c->iters, max_batch) &&
-              dalloc(c, &c->status, max_batch);
+              dalloc(c, &c->status, max_batch) && dalloc(c, &c->bmax, (size_t)max_batch * c->nfin) &&
+              dalloc(c, &c->mshift, max_batch) && dalloc(c, &c->stot, (size_t)max_batch * c->ntile) &&
+              dalloc(c, &c->qtot, (size_t)max_batch * c->ntile) && dalloc(c, &c->Lpart, (size_t)max_batch * c->ntile) &&
+              dalloc(c, &c->rpart, (size_t)max_batch * c->ntile) &&
+              dalloc(c, &c->part_xtr, (size_t)c->nsplit * Bp);
     if (ok) {
         c->pinned_bytes = 64 * 1024;
         if (hipHostMalloc(&c->pinned, c->pinned_bytes, hipHostMallocDefault) != hipSuccess) {
@@ -605,7 +641,6 @@ cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_
     HIPCHK(launch_fill_f64(c->hist, 0.0, (int64_t)B * kMaxHist, c->stream), "reset");
 
     RiskArgs ra = risk_args(c, B);
-    ra.eta_out = c->eta;
     ra.part = o.eta_mode == 0 ? c->part_upd : nullptr;
     ra.use_ctl = 1;
     ra.ctl = FitCtl{c->lam, c->l1new, c->nblk, c->hist, c->kit, c->active, c->iters, c->status, c->fobj,

@@ -1,42 +1,44 @@
 // gemvt.hip -- g = X~' r for a group of NB residual vectors, with the
-// proximal step fused into the epilogue (Section 5.3: Delta = X'(I - P) delta,
+// proximal step in the epilogue (Section 5.3: Delta = X'(I - P) delta,
 // beta <- S_{sigma lambda}(beta + sigma Delta)).
 //
-// Layout: X column-major, so column j (one SNP over all subjects) is one
-// contiguous run.  A workgroup of 4 wavefronts owns 16 consecutive columns, 4 per
-// wavefront.  Rows are walked in chunks whose slice of r (for all NB vectors) is
-// staged in LDS (32 KB); within a chunk each lane streams 16-byte loads down its
-// wavefront's 4 columns (4 FP32 rows or 16 one-byte rows per load), so every
-// wavefront load instruction reads 1 KB contiguous per column.  Each r value read
-// from LDS serves all 4 columns.  At the end each column's 64 lane partials are
-// combined by a shuffle tree.
+// Two launches.
+//
+// 1. Column sums.  X is column-major, so column j (one SNP over all subjects) is
+//    one contiguous run.  A workgroup of 4 wavefronts owns 16 (FP32) or 64
+//    (one-byte) consecutive columns and one split of the rows; rows are walked
+//    in chunks whose slice of r (all NB vectors, 32 KB) is staged in LDS.  Each
+//    lane streams 16-byte loads down its wavefront's columns, four columns at a
+//    time (4 FP32 or 16 one-byte rows per load, so one wavefront load reads
+//    1 KB contiguous per column), and every r value read from LDS serves four
+//    columns.  The 64 lane partials of a column are combined by a shuffle tree
+//    and written for the split.  Splitting rows gives enough workgroups to fill
+//    the chip evenly.
+// 2. Epilogue, one thread per column: the split partials are added in a fixed
+//    order, genotype columns are standardised, g_j = s_j (sum_i g_ij r_i -
+//    mu_j sum_i r_i), and the mode's output is written: RAW (g, FP64), GRAD
+//    (-g, FP32: the gradient of -L) or PROX (the soft-threshold step on the FP64
+//    iterate, the list of columns whose coefficient changed and partial sums of
+//    |beta| before and after, for the next eta update and the objective).
 //
 // Arithmetic: FP32 X is multiplied in FP64 (exact products, FP64 sums).  One-
-// byte X (allele counts) is decoded to FP32 and accumulated in FP32 within a
-// chunk, chunks summed in FP64.  Genotype columns are standardised on the fly:
-// g_j = s_j (sum_i g_ij r_i - mu_j sum_i r_i).
-//
-// Epilogue modes: RAW (write g, FP64), GRAD (write -g, FP32: the gradient of
-// -L), PROX (the soft-threshold step on the FP64 iterate, with the list of
-// columns whose coefficient changed and partial sums of |beta| before and
-// after, for the next eta update and the objective).
+// byte X (allele counts) is decoded to FP32 and accumulated in FP32 within an
+// LDS chunk; chunks and splits are summed in FP64.
 #include "device_common.h"
 
 namespace cox {
 namespace {
 
-constexpr int kCPW = kGemvtColsPerWave;
 constexpr int kU = 2;  // row steps in flight per column
 
 template <int XT>
-struct RowsPerLoad {
-    static constexpr int value = XT == XT_F32 ? 4 : 16;
-};
+constexpr int rows_per_load() { return XT == XT_F32 ? 4 : 16; }
+
+template <int XT, int NB>
+constexpr int cols_per_wave() { return XT == XT_F32 ? 4 : (NB == 1 ? 16 : (NB == 2 ? 8 : 4)); }
 
 template <int NB>
-struct Chunk {
-    static constexpr int value = 8192 / NB;  // NB * value floats = 32 KB of LDS
-};
+constexpr int chunk_rows() { return 8192 / NB; }  // NB * rows floats = 32 KB of LDS
 
 // LDS position of chunk row `row` (a multiple of 4): FP32 X reads r in natural
 // order; one-byte X reads 16 consecutive rows per lane, so rows are swizzled to
@@ -54,32 +56,31 @@ __device__ __forceinline__ int lds_pos(int row)
 }
 
 template <int XT, int NB, bool VEC>
-__global__ __launch_bounds__(kGemvtThreads) void gemvt_kernel(GemvtArgs a)
+__global__ __launch_bounds__(kGemvtThreads) void gemvt_sums_kernel(GemvtArgs a)
 {
-    constexpr int RPL = RowsPerLoad<XT>::value;
+    constexpr int RPL = rows_per_load<XT>();
     constexpr int WROWS = kWave * RPL;
-    constexpr int RC = Chunk<NB>::value;
-    static_assert(RC % 1024 == 0, "chunk must hold whole wave steps");
+    constexpr int RC = chunk_rows<NB>();
+    constexpr int CPW = cols_per_wave<XT, NB>();
+    static_assert(RC % 1024 == 0 && kSplitRows % RC == 0, "chunk must hold whole wave steps");
     __shared__ __attribute__((aligned(16))) float sr[NB * RC];
-    __shared__ int s_flag[kGemvtCols];
-    __shared__ double s_l1o[NB][kGemvtCols];
-    __shared__ double s_l1n[NB][kGemvtCols];
 
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
-    const int64_t blk = blockIdx.x;
     const int64_t n = a.x.n, p = a.x.p, ldx = a.x.ldx;
-    const int64_t j0 = blk * kGemvtCols + (int64_t)wid * kCPW;
-    const int ncols = (int)max((int64_t)0, min((int64_t)kCPW, p - j0));
+    const int64_t j0 = ((int64_t)blockIdx.x * 4 + wid) * CPW;
+    const int ncols = (int)max((int64_t)0, min((int64_t)CPW, p - j0));
     const int64_t nvec = VEC ? (n / RPL) * RPL : 0;
+    const int64_t s0 = (int64_t)blockIdx.y * a.split_rows;
+    const int64_t s1 = min(n, s0 + a.split_rows);
 
-    double acc[kCPW][NB];
+    double acc[CPW][NB];
 #pragma unroll
-    for (int c = 0; c < kCPW; ++c)
+    for (int c = 0; c < CPW; ++c)
 #pragma unroll
         for (int b = 0; b < NB; ++b) acc[c][b] = 0.0;
 
-    for (int64_t c0 = 0; c0 < n; c0 += RC) {
+    for (int64_t c0 = s0; c0 < s1; c0 += RC) {
         __syncthreads();  // the previous chunk is consumed
         for (int t = threadIdx.x; t < NB * (RC / 4); t += kGemvtThreads) {
             const int b = t / (RC / 4);
@@ -92,76 +93,76 @@ __global__ __launch_bounds__(kGemvtThreads) void gemvt_kernel(GemvtArgs a)
         if (ncols == 0) continue;
 
         if constexpr (VEC) {
-            const int64_t v1 = min(c0 + RC, nvec);
-            float accf[kCPW][NB];
+            const int64_t v1 = min(min(c0 + RC, s1), nvec);
+            float accf[CPW][NB];
 #pragma unroll
-            for (int c = 0; c < kCPW; ++c)
+            for (int c = 0; c < CPW; ++c)
 #pragma unroll
                 for (int b = 0; b < NB; ++b) accf[c][b] = 0.f;
             for (int64_t rs = c0; rs < v1; rs += (int64_t)WROWS * kU) {
-                uint4 xv[kCPW][kU];
 #pragma unroll
-                for (int u = 0; u < kU; ++u) {
-                    const int64_t row = rs + (int64_t)u * WROWS + (int64_t)lane * RPL;
+                for (int cg = 0; cg < CPW; cg += 4) {
+                    uint4 xv[4][kU];
 #pragma unroll
-                    for (int c = 0; c < kCPW; ++c) {
-                        if (c < ncols && row < v1) {
-                            const int64_t off = (j0 + c) * ldx + row;
-                            xv[c][u] = XT == XT_F32 ? load_u4(static_cast<const float*>(a.x.X) + off)
-                                                    : load_u4(static_cast<const uint8_t*>(a.x.X) + off);
-                        } else {
-                            xv[c][u] = make_uint4(0, 0, 0, 0);
+                    for (int u = 0; u < kU; ++u) {
+                        const int64_t row = rs + (int64_t)u * WROWS + (int64_t)lane * RPL;
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            if (cg + c < ncols && row < v1) {
+                                const int64_t off = (j0 + cg + c) * ldx + row;
+                                xv[c][u] = XT == XT_F32 ? load_u4(static_cast<const float*>(a.x.X) + off)
+                                                        : load_u4(static_cast<const uint8_t*>(a.x.X) + off);
+                            } else {
+                                xv[c][u] = make_uint4(0, 0, 0, 0);
+                            }
                         }
                     }
-                }
 #pragma unroll
-                for (int u = 0; u < kU; ++u) {
-                    const int64_t wrow = rs + (int64_t)u * WROWS;  // first row of the wave step
-                    if (wrow >= v1) break;
-                    const int lrow = (int)(wrow - c0);
-                    if constexpr (XT == XT_F32) {
+                    for (int u = 0; u < kU; ++u) {
+                        const int64_t wrow = rs + (int64_t)u * WROWS;  // first row of the wave step
+                        if (wrow >= v1) break;
+                        const int lrow = (int)(wrow - c0);
+                        if constexpr (XT == XT_F32) {
 #pragma unroll
-                        for (int b = 0; b < NB; ++b) {
-                            const float4 r4 = *reinterpret_cast<const float4*>(&sr[b * RC + lrow + lane * 4]);
-                            const double r0 = r4.x, r1 = r4.y, r2 = r4.z, r3 = r4.w;
+                            for (int b = 0; b < NB; ++b) {
+                                const float4 r4 = *reinterpret_cast<const float4*>(&sr[b * RC + lrow + lane * 4]);
+                                const double r0 = r4.x, r1 = r4.y, r2 = r4.z, r3 = r4.w;
 #pragma unroll
-                            for (int c = 0; c < kCPW; ++c) {
-                                const float4 x4 = __builtin_bit_cast(float4, xv[c][u]);
-                                double s = acc[c][b];
-                                s = fma((double)x4.x, r0, s);
-                                s = fma((double)x4.y, r1, s);
-                                s = fma((double)x4.z, r2, s);
-                                s = fma((double)x4.w, r3, s);
-                                acc[c][b] = s;
+                                for (int c = 0; c < 4; ++c) {
+                                    const float4 x4 = __builtin_bit_cast(float4, xv[c][u]);
+                                    double s = acc[cg + c][b];
+                                    s = fma((double)x4.x, r0, s);
+                                    s = fma((double)x4.y, r1, s);
+                                    s = fma((double)x4.z, r2, s);
+                                    s = fma((double)x4.w, r3, s);
+                                    acc[cg + c][b] = s;
+                                }
                             }
-                        }
-                    } else {
-                        float xf[kCPW][16];
+                        } else {
 #pragma unroll
-                        for (int c = 0; c < kCPW; ++c) {
-                            decode4<XT>(xv[c][u].x, &xf[c][0]);
-                            decode4<XT>(xv[c][u].y, &xf[c][4]);
-                            decode4<XT>(xv[c][u].z, &xf[c][8]);
-                            decode4<XT>(xv[c][u].w, &xf[c][12]);
-                        }
+                            for (int b = 0; b < NB; ++b) {
+                                float r16[16];
 #pragma unroll
-                        for (int b = 0; b < NB; ++b) {
-                            float r16[16];
+                                for (int q = 0; q < 4; ++q) {
+                                    const float4 r4 =
+                                        *reinterpret_cast<const float4*>(&sr[b * RC + lrow + q * 256 + lane * 4]);
+                                    r16[4 * q + 0] = r4.x;
+                                    r16[4 * q + 1] = r4.y;
+                                    r16[4 * q + 2] = r4.z;
+                                    r16[4 * q + 3] = r4.w;
+                                }
 #pragma unroll
-                            for (int q = 0; q < 4; ++q) {
-                                const float4 r4 =
-                                    *reinterpret_cast<const float4*>(&sr[b * RC + lrow + q * 256 + lane * 4]);
-                                r16[4 * q + 0] = r4.x;
-                                r16[4 * q + 1] = r4.y;
-                                r16[4 * q + 2] = r4.z;
-                                r16[4 * q + 3] = r4.w;
-                            }
+                                for (int c = 0; c < 4; ++c) {
+                                    float xf[16];
+                                    decode4<XT>(xv[c][u].x, &xf[0]);
+                                    decode4<XT>(xv[c][u].y, &xf[4]);
+                                    decode4<XT>(xv[c][u].z, &xf[8]);
+                                    decode4<XT>(xv[c][u].w, &xf[12]);
+                                    float s = accf[cg + c][b];
 #pragma unroll
-                            for (int c = 0; c < kCPW; ++c) {
-                                float s = accf[c][b];
-#pragma unroll
-                                for (int e = 0; e < 16; ++e) s = fmaf(xf[c][e], r16[e], s);
-                                accf[c][b] = s;
+                                    for (int e = 0; e < 16; ++e) s = fmaf(xf[e], r16[e], s);
+                                    accf[cg + c][b] = s;
+                                }
                             }
                         }
                     }
@@ -169,17 +170,17 @@ __global__ __launch_bounds__(kGemvtThreads) void gemvt_kernel(GemvtArgs a)
             }
             if constexpr (XT != XT_F32) {
 #pragma unroll
-                for (int c = 0; c < kCPW; ++c)
+                for (int c = 0; c < CPW; ++c)
 #pragma unroll
                     for (int b = 0; b < NB; ++b) acc[c][b] += (double)accf[c][b];
             }
         } else {
             // Any alignment: one element per lane per row step, 64 rows per wavefront step.
-            const int64_t c1 = min(c0 + RC, n);
+            const int64_t c1 = min(c0 + RC, s1);
             for (int64_t row = c0 + lane; row < c1; row += kWave) {
                 const int lrow = (int)(row - c0);
 #pragma unroll
-                for (int c = 0; c < kCPW; ++c) {
+                for (int c = 0; c < CPW; ++c) {
                     if (c >= ncols) break;
                     const double xval = (double)load_x1<XT>(a.x.X, (j0 + c) * ldx + row);
 #pragma unroll
@@ -189,11 +190,11 @@ __global__ __launch_bounds__(kGemvtThreads) void gemvt_kernel(GemvtArgs a)
         }
     }
 
-    // Rows beyond the last whole 16-byte load (fewer than RPL of them).
-    if (VEC && ncols > 0 && nvec + lane < n) {
+    // Rows beyond the last whole 16-byte load (fewer than RPL of them), in the last split.
+    if (VEC && ncols > 0 && nvec + lane < s1 && nvec + lane >= s0) {
         const int64_t row = nvec + lane;
 #pragma unroll
-        for (int c = 0; c < kCPW; ++c) {
+        for (int c = 0; c < CPW; ++c) {
             if (c >= ncols) break;
             const double xval = (double)load_x1<XT>(a.x.X, (j0 + c) * ldx + row);
 #pragma unroll
@@ -204,86 +205,97 @@ __global__ __launch_bounds__(kGemvtThreads) void gemvt_kernel(GemvtArgs a)
     }
 
 #pragma unroll
-    for (int c = 0; c < kCPW; ++c)
+    for (int c = 0; c < CPW; ++c)
 #pragma unroll
         for (int b = 0; b < NB; ++b) acc[c][b] = wave_sum(acc[c][b]);
 
-    const bool geno = XT != XT_F32;
     if (lane == 0) {
+        double* out = a.part + (int64_t)blockIdx.y * a.part_sstride;
 #pragma unroll
-        for (int c = 0; c < kCPW; ++c) {
-            const int cw = wid * kCPW + c;  // column within the workgroup
-            const int64_t j = j0 + c;
-            int changed = 0;
-            const bool valid = c < ncols;
-            double mu = 0.0, sc = 1.0;
-            if (valid && geno) {
-                if (a.x.center) mu = a.x.center[j];
-                if (a.x.scale) sc = a.x.scale[j];
-            }
+        for (int c = 0; c < CPW; ++c) {
+            if (c >= ncols) break;
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                double l1o = 0.0, l1n = 0.0;
-                if (valid && b < a.nb) {
-                    const int bb = a.b0 + b;
-                    double g = acc[c][b];
-                    if (geno) g = sc * (g - mu * a.sumr[bb]);
-                    const int64_t at = (int64_t)bb * p + j;
-                    if (a.mode == GT_RAW) {
-                        a.out64[at] = g;
-                    } else if (a.mode == GT_GRAD) {
-                        a.out32[at] = (float)(-g);
-                    } else {
-                        const double old = a.beta[at];
-                        double nw = old;
-                        if (a.active == nullptr || a.active[bb]) nw = soft_threshold(old + a.step * g, a.step * a.lam[bb]);
-                        a.beta[at] = nw;
-                        const double d = nw - old;
-                        a.dcoef[at] = d * (geno ? sc : 1.0);
-                        changed |= d != 0.0;
-                        l1o = fabs(old);
-                        l1n = fabs(nw);
-                    }
-                }
-                s_l1o[b][cw] = l1o;
-                s_l1n[b][cw] = l1n;
+            for (int b = 0; b < NB; ++b)
+                if (b < a.nb) out[(int64_t)(a.b0 + b) * p + j0 + c] = acc[c][b];
+        }
+    }
+}
+
+// One thread per column; a 16-lane group covers one change-list block.
+__global__ __launch_bounds__(256) void gemvt_epilogue_kernel(GemvtArgs a)
+{
+    const int64_t p = a.x.p;
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool valid = j < p;
+    const bool geno = a.x.xt != XT_F32;
+    double mu = 0.0, sc = 1.0;
+    if (valid && geno) {
+        if (a.x.center) mu = a.x.center[j];
+        if (a.x.scale) sc = a.x.scale[j];
+    }
+    int changed = 0;
+    const int lane16 = threadIdx.x & 15;
+    const int64_t blk = j / kGemvtCols;
+    for (int b = 0; b < a.nb; ++b) {
+        const int bb = a.b0 + b;
+        const int64_t at = (int64_t)bb * p + j;
+        double l1o = 0.0, l1n = 0.0;
+        if (valid) {
+            double g = 0.0;
+            for (int s = 0; s < a.nsplit; ++s) g += a.part[(int64_t)s * a.part_sstride + at];
+            if (geno) g = sc * (g - mu * a.sumr[bb]);
+            if (a.mode == GT_RAW) {
+                a.out64[at] = g;
+            } else if (a.mode == GT_GRAD) {
+                a.out32[at] = (float)(-g);
+            } else {
+                const double old = a.beta[at];
+                double nw = old;
+                if (a.active == nullptr || a.active[bb]) nw = soft_threshold(old + a.step * g, a.step * a.lam[bb]);
+                a.beta[at] = nw;
+                const double d = nw - old;
+                a.dcoef[at] = d * (geno ? sc : 1.0);
+                changed |= d != 0.0;
+                l1o = fabs(old);
+                l1n = fabs(nw);
             }
-            s_flag[cw] = changed;
+        }
+        if (a.mode == GT_PROX) {
+            // sum over the 16 columns of the block, in a fixed tree order
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) {
+                l1o += __shfl_xor(l1o, o, 16);
+                l1n += __shfl_xor(l1n, o, 16);
+            }
+            if (lane16 == 0 && (blk * kGemvtCols) < p) {
+                a.l1old[(int64_t)bb * a.nblk + blk] = l1o;
+                a.l1new[(int64_t)bb * a.nblk + blk] = l1n;
+            }
         }
     }
-    if (a.mode != GT_PROX) return;  // uniform
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int cnt = 0;
-        for (int cw = 0; cw < kGemvtCols; ++cw) {
-            const int64_t j = blk * kGemvtCols + cw;
-            if (j >= p) break;
-            const int f = a.first_group ? s_flag[cw] : (a.chg_flag[j] | s_flag[cw]);
-            a.chg_flag[j] = f;
-            if (f) a.chg_idx[blk * kGemvtCols + cnt++] = (int32_t)j;
-        }
-        a.chg_cnt[blk] = cnt;
+    if (a.mode != GT_PROX) return;
+    int f = 0;
+    if (valid) {
+        f = a.first_group ? changed : (a.chg_flag[j] | changed);
+        a.chg_flag[j] = f;
     }
-    if (threadIdx.x < NB && (int)threadIdx.x < a.nb) {
-        const int b = threadIdx.x;
-        double so = 0.0, sn = 0.0;
-        for (int cw = 0; cw < kGemvtCols; ++cw) {
-            so += s_l1o[b][cw];
-            sn += s_l1n[b][cw];
-        }
-        a.l1old[(int64_t)(a.b0 + b) * a.nblk + blk] = so;
-        a.l1new[(int64_t)(a.b0 + b) * a.nblk + blk] = sn;
-    }
+    // compact the changed columns of the block in ascending order
+    const uint64_t ball = __ballot(f != 0);
+    const int gshift = (threadIdx.x & (kWave - 1)) & ~15;
+    const uint32_t mask = (uint32_t)((ball >> gshift) & 0xFFFFu);
+    if (f) a.chg_idx[blk * kGemvtCols + __popc(mask & ((1u << lane16) - 1u))] = (int32_t)j;
+    if (lane16 == 0 && (blk * kGemvtCols) < p) a.chg_cnt[blk] = __popc(mask);
 }
 
 template <int XT, int NB>
 hipError_t launch_t(const GemvtArgs& a, hipStream_t s)
 {
-    const dim3 grid((unsigned)((a.x.p + kGemvtCols - 1) / kGemvtCols));
+    constexpr int cols_wg = 4 * cols_per_wave<XT, NB>();
+    const dim3 grid((unsigned)((a.x.p + cols_wg - 1) / cols_wg), (unsigned)a.nsplit);
     if (a.x.vec16)
-        hipLaunchKernelGGL((gemvt_kernel<XT, NB, true>), grid, dim3(kGemvtThreads), 0, s, a);
+        hipLaunchKernelGGL((gemvt_sums_kernel<XT, NB, true>), grid, dim3(kGemvtThreads), 0, s, a);
     else
-        hipLaunchKernelGGL((gemvt_kernel<XT, NB, false>), grid, dim3(kGemvtThreads), 0, s, a);
+        hipLaunchKernelGGL((gemvt_sums_kernel<XT, NB, false>), grid, dim3(kGemvtThreads), 0, s, a);
     return hipGetLastError();
 }
 
@@ -300,12 +312,16 @@ hipError_t launch_x(const GemvtArgs& a, hipStream_t s)
 
 hipError_t launch_gemvt(const GemvtArgs& a, hipStream_t s)
 {
-    if (a.nb < 1 || a.nb > 8) return hipErrorInvalidValue;
+    if (a.nb < 1 || a.nb > 8 || a.nsplit < 1 || a.split_rows % kSplitRows != 0) return hipErrorInvalidValue;
+    hipError_t e;
     switch (a.x.xt) {
-    case XT_F32: return launch_x<XT_F32>(a, s);
-    case XT_FP8: return launch_x<XT_FP8>(a, s);
-    default: return launch_x<XT_I8>(a, s);
+    case XT_F32: e = launch_x<XT_F32>(a, s); break;
+    case XT_FP8: e = launch_x<XT_FP8>(a, s); break;
+    default: e = launch_x<XT_I8>(a, s); break;
     }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(gemvt_epilogue_kernel, dim3((unsigned)((a.x.p + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
 }
 
 }  // namespace cox

@@ -11,8 +11,8 @@ enum XType : int { XT_F32 = 0, XT_FP8 = 1, XT_I8 = 2 };
 
 // Geometry shared by kernels and the host.
 constexpr int kGemvtThreads = 256;                  // 4 waves
-constexpr int kGemvtColsPerWave = 4;
-constexpr int kGemvtCols = 4 * kGemvtColsPerWave;   // columns per GEMV^T workgroup
+constexpr int kGemvtCols = 16;                      // columns per change-list / l1 block
+constexpr int kSplitRows = 8192;                    // row splits of X' r are multiples of this
 constexpr int kRiskThreads = 1024;
 constexpr int kUpdThreads = 256;                    // eta update: 4 rows per thread
 constexpr int kUpdRows = 4 * kUpdThreads;
@@ -59,29 +59,45 @@ struct RiskArgs {
     Order ord;
     const void* eta_in;    // [B][n] original order; double unless eta_in_f32
     int eta_in_f32;
-    double* eta_out;       // if not null: eta_in + partials is written here ([B][n])
-    const double* part;    // [ncg][bstride_part] partial eta updates, or null
+    double* eta;           // [B][n] FP64 eta after the partial updates are added (may equal eta_in)
+    const double* part;    // [ncg][part_cstride] partial eta updates, or null
     int ncg;
     int64_t part_cstride;  // elements between column groups
     const int32_t* nsel;   // partials are added only when *nsel > 0
-    double* w;             // [B][n] scratch, sorted order
-    double* S;             // [B][n] scratch
-    double* T;             // [B][n] scratch
-    float* r32;            // [B][n] residual, original order (nullable)
+    double* w;             // [B][n] exp(eta - m), sorted order
+    double* S;             // [B][n] cumulative sum of w within its tile, sorted order
+    double* T;             // [B][n] reverse cumulative sum of delta/W within its tile
+    int64_t tile;          // positions per scan tile (multiple of 1024)
+    int ntile;             // ceil(n / tile) <= kMaxTiles
+    int nfin;              // workgroups per b of the eta pass
+    double* bmax;          // [B][nfin] partial maxima of eta
+    double* mshift;        // [B] m = max eta
+    double* stot;          // [B][ntile] tile totals of w
+    double* qtot;          // [B][ntile] tile totals of delta/W
+    double* Lpart;         // [B][ntile] tile sums of the log-likelihood terms
+    double* rpart;         // [B][ntile] tile sums of r (as stored)
+    float* r32;            // [B][rstride] residual, original order (nullable)
+    int64_t rstride;
     double* r64;           // [B][n] residual, original order (nullable)
     double* L;             // [B] log partial likelihood
-    double* sumr;          // [B] sum of the stored residual (as stored)
-    int64_t rstride;       // b-stride of r32 (>= n, padded for aligned loads)
+    double* sumr;          // [B] sum of the stored residual
     int use_ctl;           // 1 inside cox_fit_path
     FitCtl ctl;
 };
+
+constexpr int kMaxTiles = 4096;
+constexpr int kFinElems = 2048;  // eta elements per workgroup of the eta pass
 
 enum GemvtMode : int { GT_RAW = 0, GT_GRAD = 1, GT_PROX = 2 };
 
 struct GemvtArgs {
     XDesc x;
     const float* r32;      // [B][rstride], b-major; rows n..rstride-1 are zero
-    int64_t rstride;       // multiple of 1024
+    int64_t rstride;       // multiple of kSplitRows
+    double* part;          // [nsplit][Bmax][p] raw column sums of each row split
+    int nsplit;
+    int64_t split_rows;    // rows per split (multiple of kSplitRows)
+    int64_t part_sstride;  // elements between splits (Bmax * p)
     const double* sumr;    // [B] (centring of genotype columns)
     int b0, nb;            // this launch covers b0 .. b0+nb-1 (nb <= template NB)
     int mode;
@@ -94,7 +110,7 @@ struct GemvtArgs {
     const int32_t* active; // [B] or null (all active)
     double* dcoef;         // [B][p] (beta_new - beta_old) * scale_j
     int32_t* chg_flag;     // [p] 1 if beta_j changed for some b (ORed over launches)
-    int32_t* chg_cnt;      // [nblk] changed columns per workgroup
+    int32_t* chg_cnt;      // [nblk] changed columns per 16-column block
     int32_t* chg_idx;      // [nblk][kGemvtCols] their indices, ascending
     double* l1old;         // [B][nblk]
     double* l1new;         // [B][nblk]

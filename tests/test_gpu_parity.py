@@ -90,6 +90,26 @@ def test_ragged_shapes_geno(storage, ldx):
     np.testing.assert_allclose(-grad.cpu().numpy()[0], g, rtol=0, atol=1e-6 * np.abs(g).max())
 
 
+@pytest.mark.parametrize("storage,ldx", [("int8", 20011), ("fp8", 20016), ("f32", 20012), ("fp8", 20011)])
+def test_row_splits(storage, ldx):
+    # n spans several 8192-row splits of X' r, with a ragged tail
+    d = coxsim.genotype_problem(20011, 70, 4, 0.3, 123, days=True)
+    cox, M = device_problem(d, storage, ldx=ldx, max_batch=2)
+    rng = np.random.default_rng(5)
+    beta = (0.1 * rng.standard_normal((2, 70))).astype(np.float32)
+    loss, grad = cox.loss_grad(torch.from_numpy(beta).cuda())
+    for b in range(2):
+        negL, g = oracle.loss_grad(M, d.time, d.event, beta[b].astype(np.float64))
+        assert loss[b] == pytest.approx(negL, rel=1e-12)
+        np.testing.assert_allclose(-grad.cpu().numpy()[b], g, rtol=0, atol=1e-6 * np.abs(g).max())
+    lam = 0.3 * oracle.lambda_max(M, d.time, d.event)
+    s2, _ = oracle.opnorm2(M)
+    bo, tr, _, _ = oracle.fit(M, d.time, d.event, lam, 1 / (2 * s2), max_iter=25)
+    bg, _, obj, _ = cox.fit_path([lam], max_iter=25, tol=0.0, step=1 / (2 * s2))
+    assert rel_beta_err(bg.cpu().numpy()[0], bo) <= BETA_TOL
+    assert obj[0] == pytest.approx(tr[-1], rel=OBJ_TOL)
+
+
 @pytest.mark.parametrize("storage", ["f32", "int8", "fp8"])
 def test_lambda_max_and_opnorm(c0, storage):
     cox, M = device_problem(c0, storage)
