@@ -19,6 +19,7 @@
 
 #include "cox.h"
 #include "internal.h"
+#include "mfma.h"
 
 using namespace cox;
 
@@ -52,6 +53,13 @@ struct cox_ctx {
     int64_t tile = 0;
     int ntile = 0, nfin = 0;
     double* part_xtr = nullptr;  // [nsplit][Bmax][p] split partials of X' r
+    // batched matrix-core pass (one-byte allele counts, B > kGroup)
+    int8_t* limbs = nullptr;     // [3][Bmax16][rstride]
+    int bpad_max = 0;
+    double *qscale = nullptr, *rmaxp = nullptr;
+    long long* rsump = nullptr;
+    int* geno_bad = nullptr;
+    int geno_state = -1;         // -1 unchecked, 0 counts 0/1/2 only, 1 other values
     int nsplit = 1;
     int64_t split_rows = 0;
     double *bmax = nullptr, *mshift = nullptr, *stot = nullptr, *qtot = nullptr, *Lpart = nullptr, *rpart = nullptr;
@@ -220,6 +228,28 @@ cox_status dense_eta(cox_ctx* c, const double* coef, int B, const double* shift)
     return COX_OK;
 }
 
+// The matrix-core pass serves batches of more than kGroup vectors when X holds
+// allele counts (checked once over the whole matrix).
+bool use_mfma(cox_ctx* c, int B)
+{
+    if (!c->limbs || B <= kGroup) return false;
+    const char* off = std::getenv("COXHIP_NO_MFMA");
+    if (off && off[0] == '1') return false;
+    if (c->geno_state < 0) {
+        int bad = 1;
+        if (launch_fill_i32(c->geno_bad, 0, 1, c->stream) == hipSuccess &&
+            launch_geno_check(c->x.X, c->x.xt, c->n, c->p, c->x.ldx, c->geno_bad, c->stream) == hipSuccess &&
+            hipMemcpyAsync(&bad, c->geno_bad, sizeof(int), hipMemcpyDeviceToHost, c->stream) == hipSuccess &&
+            hipStreamSynchronize(c->stream) == hipSuccess) {
+            c->geno_state = bad ? 1 : 0;
+        } else {
+            (void)hipGetLastError();
+            return false;
+        }
+    }
+    return c->geno_state == 0;
+}
+
 RiskArgs risk_args(cox_ctx* c, int B)
 {
     RiskArgs a{};
@@ -251,6 +281,10 @@ RiskArgs risk_args(cox_ctx* c, int B)
     a.sumr = c->sumr;
     a.rstride = c->rstride;
     a.use_ctl = 0;
+    if (use_mfma(c, B)) {  // the matrix-core pass quantises the FP64 residual itself
+        a.r32 = nullptr;
+        a.r64 = c->r64;
+    }
     return a;
 }
 
@@ -278,6 +312,22 @@ GemvtArgs gemvt_args(cox_ctx* c, int mode)
 
 cox_status run_gemvt(cox_ctx* c, GemvtArgs g, int B)
 {
+    if (use_mfma(c, B)) {
+        tmark(c, COX_PHASE_XTR);
+        const int bpad = (int)round_up(B, 16);
+        HIPCHK(launch_quantize(c->r64, c->n, B, c->rmaxp, c->rsump, c->limbs, c->rstride, bpad, c->qscale, c->sumr,
+                               c->stream),
+               "quantise r");
+        MfmaArgs m{c->x.X, c->x.xt, c->n, c->p, c->x.ldx, c->limbs, c->rstride, bpad, B, c->qscale, c->part_xtr};
+        HIPCHK(launch_mfma_xtr(m, c->stream), "X' R on matrix cores");
+        g.b0 = 0;
+        g.nb = B;
+        g.nsplit = 1;
+        g.first_group = 1;
+        HIPCHK(launch_gemvt_epilogue(g, c->stream), "X' r epilogue");
+        tmark(c, COX_PHASE_XTR);
+        return COX_OK;
+    }
     tmark(c, COX_PHASE_XTR);
     for (int b0 = 0; b0 < B; b0 += kGroup) {
         g.b0 = b0;
@@ -423,6 +473,14 @@ cox_status cox_setup(cox_ctx** out, const cox_matrix* X, const double* time, con
               dalloc(c, &c->qtot, (size_t)max_batch * c->ntile) && dalloc(c, &c->Lpart, (size_t)max_batch * c->ntile) &&
               dalloc(c, &c->rpart, (size_t)max_batch * c->ntile) &&
               dalloc(c, &c->part_xtr, (size_t)c->nsplit * Bp);
+    const bool mfma_able = X->xtype != COX_X_F32 && c->x.vec16 && max_batch > kGroup;
+    if (ok && mfma_able) {
+        c->bpad_max = (int)round_up(max_batch, 16);
+        const int nt = mfma_ntile(n);
+        ok = dalloc(c, &c->limbs, (size_t)3 * c->bpad_max * c->rstride) && dalloc(c, &c->qscale, max_batch) &&
+             dalloc(c, &c->rmaxp, (size_t)max_batch * nt) && dalloc(c, &c->rsump, (size_t)max_batch * nt) &&
+             dalloc(c, &c->geno_bad, 1);
+    }
     if (ok) {
         c->pinned_bytes = 64 * 1024;
         if (hipHostMalloc(&c->pinned, c->pinned_bytes, hipHostMallocDefault) != hipSuccess) {
@@ -451,6 +509,9 @@ cox_status cox_setup(cox_ctx** out, const cox_matrix* X, const double* time, con
     chk(launch_fill_i32(c->chg_flag, 0, p, c->stream));
     chk(launch_fill_i32(c->nsel, 0, 1, c->stream));
     chk(launch_fill_f64(c->eta, 0.0, Bn, c->stream));
+    if (c->limbs)
+        chk(launch_fill_f64(reinterpret_cast<double*>(c->limbs), 0.0, (int64_t)3 * c->bpad_max * c->rstride / 8,
+                            c->stream));
     if (st == COX_OK && hipStreamSynchronize(c->stream) != hipSuccess) st = COX_ERR_DEVICE;
     if (st != COX_OK) {
         (void)hipGetLastError();

@@ -310,6 +310,13 @@ hipError_t launch_x(const GemvtArgs& a, hipStream_t s)
 
 }  // namespace
 
+hipError_t launch_gemvt_epilogue(const GemvtArgs& a, hipStream_t s)
+{
+    if (a.nb < 1 || a.nsplit < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(gemvt_epilogue_kernel, dim3((unsigned)((a.x.p + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_gemvt(const GemvtArgs& a, hipStream_t s)
 {
     if (a.nb < 1 || a.nb > 8 || a.nsplit < 1 || a.split_rows % kSplitRows != 0) return hipErrorInvalidValue;

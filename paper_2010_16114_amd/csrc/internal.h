@@ -121,6 +121,8 @@ struct GemvtArgs {
 // Launchers (return hipError_t of the launch).
 hipError_t launch_risk(const RiskArgs& a, hipStream_t s);
 hipError_t launch_gemvt(const GemvtArgs& a, hipStream_t s);
+// the epilogue alone, on column sums already in a.part (nb may exceed 8)
+hipError_t launch_gemvt_epilogue(const GemvtArgs& a, hipStream_t s);
 // eta partials: part[cg][b][i] for b in [b0, b0+nb) from the compacted change list
 hipError_t launch_eta_update(const XDesc& x, const int32_t* sel, const int32_t* nsel, const double* dcoef,
                              int b0, int nb, double* part, int64_t part_cstride, int ncg,

@@ -1,0 +1,293 @@
+// mfma.hip -- X~' R for a batch of residual vectors on the int8 matrix cores.
+//
+// With B coefficient vectors the gradient pass of Section 5.3 becomes the
+// skinny product G' R (p x n times n x B, K = n subjects).  Allele counts
+// g in {0, 1, 2} are exact in int8.  Each residual vector r_b is quantised to
+// integers R_b = round(r_b / q_b) with q_b = max_i |r_bi| / 2^22 and split into
+// three signed 8-bit limbs, R = d0 + 256 d1 + 65536 d2.  Every limb product is
+// then exact on v_mfma_i32_16x16x64_i8 with int32 accumulation (|sum| <=
+// 2 * 128 * n < 2^31 for n < 2^22), and
+//     sum_i g_ij R_bi = acc0 + 256 acc1 + 65536 acc2      (exact, int64)
+// so the only rounding is that of r to 23 significant bits relative to its
+// largest entry.  The raw sums q_b * sum_i g_ij R_bi go to the same epilogue
+// as the vector path (centring with sum_i q_b R_bi, proximal step).
+//
+// Tiling: a workgroup of 4 wavefronts owns 256 SNP columns (4 M tiles of 16 per
+// wavefront) and all 3 * B limb columns (N tiles of 16), and walks K = n in
+// stages of 256 rows.  X is read once per pass for all B vectors.  A fragments
+// (16 rows of one column per lane, one 16-byte load) stream from global memory
+// one stage ahead; the stage's limb tile (3 * B columns x 256 rows) is staged in
+// LDS, double buffered, laid out so that each MFMA B fragment is one 16-byte
+// LDS read per lane, contiguous across lanes.
+#include "device_common.h"
+#include "mfma.h"
+
+namespace cox {
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+constexpr int kT = 256;
+constexpr int kKS = 4;           // MFMA k-steps (64 rows each) per stage
+constexpr int kKC = 64 * kKS;    // rows per stage
+constexpr int kLimbs = 3;
+constexpr int kQBits = 22;       // |R| <= 2^22 keeps the top limb within int8
+
+// Allele-count bytes -> int8 counts.  FP8 E4M3 codes of 0, 1, 2 are 0x00, 0x38,
+// 0x40: bit 3 marks 1 and bit 6 marks 2 (other codes are rejected beforehand).
+template <int XT>
+__device__ __forceinline__ uint32_t counts4(uint32_t w)
+{
+    if constexpr (XT == XT_FP8)
+        return ((w >> 3) & 0x01010101u) | ((w >> 5) & 0x02020202u);
+    else
+        return w;
+}
+
+// 16 rows [row, row + 16) of column col as int8 counts; rows >= n read as 0.
+template <int XT>
+__device__ __forceinline__ v4i load_a(const uint8_t* __restrict__ X, int64_t col, int64_t p, int64_t ldx,
+                                      int64_t row, int64_t n)
+{
+    v4i v = {0, 0, 0, 0};
+    if (col >= p || row >= n) return v;
+    const uint8_t* src = X + col * ldx + row;
+    if (row + 16 <= n) {
+        const uint4 u = *reinterpret_cast<const uint4*>(src);
+        v[0] = (int)counts4<XT>(u.x);
+        v[1] = (int)counts4<XT>(u.y);
+        v[2] = (int)counts4<XT>(u.z);
+        v[3] = (int)counts4<XT>(u.w);
+    } else {
+        uint32_t w[4] = {0, 0, 0, 0};
+        for (int e = 0; e < 16 && row + e < n; ++e) w[e >> 2] |= (uint32_t)src[e] << (8 * (e & 3));
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = (int)counts4<XT>(w[q]);
+    }
+    return v;
+}
+
+template <int XT, int NG>
+__global__ __launch_bounds__(kT, 1) void mfma_xtr_kernel(MfmaArgs a)
+{
+    constexpr int NT = kLimbs * NG;  // N tiles, limb-major: tile = limb * NG + b / 16
+    constexpr int NCOL = 16 * NT;
+    constexpr int CHUNKS = NCOL * (kKC / 16);  // 16-byte chunks of limb data per stage
+    static_assert(CHUNKS % kT == 0, "stage copy must split evenly");
+    __shared__ v4i sR[2][kKS * 4 * NCOL];
+
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int64_t n = a.n, p = a.p, ldx = a.ldx;
+    const int64_t jw = (int64_t)blockIdx.x * 256 + wid * 64;  // first column of this wavefront
+    const uint8_t* __restrict__ X = static_cast<const uint8_t*>(a.X);
+    const int8_t* __restrict__ limbs = a.limbs;
+    const int64_t nstage = (n + kKC - 1) / kKC;
+    const int arow = 16 * (lane >> 4);  // k offset of this lane's 16 bytes within a k-step
+    const int acol = lane & 15;
+
+    v4i acc[4][NT];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = v4i{0, 0, 0, 0};
+
+    // limb data of one stage: chunk c -> (column col, 16-row group q)
+    auto fetch_r = [&](int64_t k0, v4i* regs) {
+#pragma unroll
+        for (int u = 0; u < CHUNKS / kT; ++u) {
+            const int c = threadIdx.x + kT * u;
+            const int col = c / (kKC / 16), q = c % (kKC / 16);
+            const int limb = col / (16 * NG), b = col % (16 * NG);
+            regs[u] = *reinterpret_cast<const v4i*>(limbs + ((int64_t)limb * a.bpad + b) * a.lstride + k0 + 16 * q);
+        }
+    };
+    auto store_r = [&](int buf, const v4i* regs) {
+#pragma unroll
+        for (int u = 0; u < CHUNKS / kT; ++u) {
+            const int c = threadIdx.x + kT * u;
+            const int col = c / (kKC / 16), q = c % (kKC / 16);
+            sR[buf][(q >> 2) * 4 * NCOL + (q & 3) * NCOL + col] = regs[u];
+        }
+    };
+    auto fetch_a = [&](int64_t k0, v4i (&A)[4][kKS]) {
+#pragma unroll
+        for (int ks = 0; ks < kKS; ++ks)
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+                A[mt][ks] = load_a<XT>(X, jw + mt * 16 + acol, p, ldx, k0 + ks * 64 + arow, n);
+    };
+
+    v4i A[4][kKS], An[4][kKS];
+    v4i Rr[CHUNKS / kT];
+    fetch_a(0, A);
+    fetch_r(0, Rr);
+    store_r(0, Rr);
+    __syncthreads();
+
+    for (int64_t s = 0; s < nstage; ++s) {
+        const int buf = (int)(s & 1);
+        const bool more = s + 1 < nstage;
+        if (more) {
+            fetch_a((s + 1) * kKC, An);
+            fetch_r((s + 1) * kKC, Rr);
+        }
+#pragma unroll
+        for (int ks = 0; ks < kKS; ++ks) {
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const v4i bf = sR[buf][ks * 4 * NCOL + (lane >> 4) * NCOL + nt * 16 + acol];
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt][ks], bf, acc[mt][nt], 0, 0, 0);
+            }
+        }
+        if (more) store_r(buf ^ 1, Rr);
+        __syncthreads();
+        if (more) {
+#pragma unroll
+            for (int ks = 0; ks < kKS; ++ks)
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) A[mt][ks] = An[mt][ks];
+        }
+    }
+
+    // C of tile (mt, nt): lane holds rows kMfmaRow(lane, v), column lane & 15.
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int bq = 0; bq < NG; ++bq)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int b = bq * 16 + acol;
+                const int64_t j = jw + mt * 16 + mfma_c_row(lane, v);
+                if (j < p && b < a.B) {
+                    const int64_t tot = (int64_t)acc[mt][bq][v] + 256 * (int64_t)acc[mt][NG + bq][v] +
+                                        65536 * (int64_t)acc[mt][2 * NG + bq][v];
+                    a.out[(int64_t)b * p + j] = a.qscale[b] * (double)tot;
+                }
+            }
+}
+
+// Largest |r| of each vector over a tile of 4096 subjects.
+__global__ __launch_bounds__(kT) void rmax_kernel(const double* __restrict__ r, int64_t n, double* __restrict__ part,
+                                                  int ntile)
+{
+    __shared__ double sh[kT / 64];
+    const int b = blockIdx.y;
+    double m = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 4096 + threadIdx.x; i < min(n, (int64_t)(blockIdx.x + 1) * 4096);
+         i += kT)
+        m = fmax(m, fabs(r[(int64_t)b * n + i]));
+    m = wave_max(m);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) part[(int64_t)b * ntile + blockIdx.x] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+}
+
+// Quantise r to three int8 limbs per vector; exact partial sums of R.
+__global__ __launch_bounds__(kT) void quantize_kernel(const double* __restrict__ r, int64_t n,
+                                                      const double* __restrict__ rmaxp, int ntile,
+                                                      int8_t* __restrict__ limbs, int64_t lstride, int bpad,
+                                                      double* __restrict__ qscale, long long* __restrict__ rsump)
+{
+    __shared__ long long sh[kT / 64];
+    const int b = blockIdx.y;
+    double mx = 0.0;
+    for (int t = 0; t < ntile; ++t) mx = fmax(mx, rmaxp[(int64_t)b * ntile + t]);
+    const double q = mx > 0.0 ? mx / (double)(1 << kQBits) : 1.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) qscale[b] = q;
+    long long sum = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 4096 + threadIdx.x; i < min(n, (int64_t)(blockIdx.x + 1) * 4096);
+         i += kT) {
+        const int R = (int)llrint(r[(int64_t)b * n + i] / q);
+        const int d0 = ((R + 128) & 255) - 128;
+        const int R1 = (R - d0) >> 8;
+        const int d1 = ((R1 + 128) & 255) - 128;
+        const int d2 = (R1 - d1) >> 8;
+        limbs[((int64_t)0 * bpad + b) * lstride + i] = (int8_t)d0;
+        limbs[((int64_t)1 * bpad + b) * lstride + i] = (int8_t)d1;
+        limbs[((int64_t)2 * bpad + b) * lstride + i] = (int8_t)d2;
+        sum += R;
+    }
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) rsump[(int64_t)b * ntile + blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// sumr_b = q_b * sum_i R_bi (the sum of the quantised residual, exact).
+__global__ void rsum_kernel(const long long* __restrict__ rsump, int ntile, const double* __restrict__ qscale,
+                            double* __restrict__ sumr, int B)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    long long s = 0;
+    for (int t = 0; t < ntile; ++t) s += rsump[(int64_t)b * ntile + t];
+    sumr[b] = qscale[b] * (double)s;
+}
+
+// bad[0] |= 1 if any byte of the n x p matrix is not the code of 0, 1 or 2.
+template <int XT>
+__global__ __launch_bounds__(kT) void geno_check_kernel(const uint8_t* __restrict__ X, int64_t n, int64_t ldx,
+                                                        int* __restrict__ bad)
+{
+    const int64_t j = blockIdx.x;
+    int b = 0;
+    for (int64_t i = threadIdx.x; i < n; i += kT) {
+        const uint8_t v = X[j * ldx + i];
+        b |= XT == XT_FP8 ? !(v == 0x00 || v == 0x38 || v == 0x40) : !(v <= 2);
+    }
+    if (__any(b) && (threadIdx.x & 63) == 0) atomicOr(bad, 1);
+}
+
+template <int XT, int NG>
+hipError_t launch_ng(const MfmaArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL((mfma_xtr_kernel<XT, NG>), dim3((unsigned)((a.p + 255) / 256)), dim3(kT), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int XT>
+hipError_t launch_xt(const MfmaArgs& a, hipStream_t s)
+{
+    switch (a.bpad / 16) {
+    case 1: return launch_ng<XT, 1>(a, s);
+    case 2: return launch_ng<XT, 2>(a, s);
+    case 3: return launch_ng<XT, 3>(a, s);
+    default: return launch_ng<XT, 4>(a, s);
+    }
+}
+
+}  // namespace
+
+int mfma_ntile(int64_t n) { return (int)((n + 4095) / 4096); }
+
+hipError_t launch_quantize(const double* r64, int64_t n, int B, double* rmaxp, long long* rsump, int8_t* limbs,
+                           int64_t lstride, int bpad, double* qscale, double* sumr, hipStream_t s)
+{
+    const int nt = mfma_ntile(n);
+    hipLaunchKernelGGL(rmax_kernel, dim3(nt, B), dim3(kT), 0, s, r64, n, rmaxp, nt);
+    hipLaunchKernelGGL(quantize_kernel, dim3(nt, B), dim3(kT), 0, s, r64, n, rmaxp, nt, limbs, lstride, bpad, qscale,
+                       rsump);
+    hipLaunchKernelGGL(rsum_kernel, dim3(1), dim3(64), 0, s, rsump, nt, qscale, sumr, B);
+    return hipGetLastError();
+}
+
+hipError_t launch_mfma_xtr(const MfmaArgs& a, hipStream_t s)
+{
+    if (a.bpad < 16 || a.bpad > 64 || a.bpad % 16 || a.B > a.bpad || a.lstride % kKC) return hipErrorInvalidValue;
+    return a.xt == XT_FP8 ? launch_xt<XT_FP8>(a, s) : launch_xt<XT_I8>(a, s);
+}
+
+hipError_t launch_geno_check(const void* X, int xt, int64_t n, int64_t p, int64_t ldx, int* bad, hipStream_t s)
+{
+    if (xt == XT_FP8)
+        hipLaunchKernelGGL(geno_check_kernel<XT_FP8>, dim3((unsigned)p), dim3(kT), 0, s,
+                           static_cast<const uint8_t*>(X), n, ldx, bad);
+    else
+        hipLaunchKernelGGL(geno_check_kernel<XT_I8>, dim3((unsigned)p), dim3(kT), 0, s,
+                           static_cast<const uint8_t*>(X), n, ldx, bad);
+    return hipGetLastError();
+}
+
+}  // namespace cox

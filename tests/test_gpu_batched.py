@@ -1,0 +1,123 @@
+"""GPU parity of the batched path: many lambdas share each pass over X, which
+runs on the int8 matrix cores for one-byte allele counts.
+
+Each b is compared with its own FP64 oracle run at the same step from beta = 0
+(relative objective <= 1e-6, max|beta - beta_oracle| <= 1e-5 max|beta_oracle|),
+and with the vector path (B = 1 per call) of the same library.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import coxsim
+import oracle
+from tests.gpu_helpers import device_problem, rel_beta_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+import paper_2010_16114_amd as P  # noqa: E402
+
+BETA_TOL = 1e-5
+OBJ_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def prob():
+    # ragged: n not a multiple of 256 (partial stage and 16-row chunk), p not a multiple of 256
+    return coxsim.genotype_problem(3001, 700, 12, 0.8, 4242, days=True)
+
+
+def _setup(prob, storage, B):
+    n = prob.n
+    ldx = (n + 15) // 16 * 16
+    return device_problem(prob, storage, ldx=ldx, max_batch=B)
+
+
+@pytest.mark.parametrize("storage,B", [("int8", 64), ("fp8", 64), ("int8", 20), ("fp8", 33)])
+def test_batched_fit_matches_oracle(prob, storage, B):
+    cox, M = _setup(prob, storage, B)
+    lm = oracle.lambda_max(M, prob.time, prob.event)
+    lams = coxsim.lambda_grid(lm, B, 0.01)
+    lams[0] *= 1 + 1e-6
+    s2, _ = oracle.opnorm2(M)
+    sigma = 1.0 / (2.0 * s2)
+    K = 30
+    beta, iters, obj, _ = cox.fit_path(lams, max_iter=K, tol=0.0, step=sigma)
+    beta = beta.cpu().numpy()
+    worst = 0.0
+    for b in range(0, B, max(1, B // 11)):
+        bo, tr, _, _ = oracle.fit(M, prob.time, prob.event, lams[b], sigma, max_iter=K)
+        if np.abs(bo).max() == 0:
+            assert np.all(beta[b] == 0), b
+        else:
+            e = rel_beta_err(beta[b], bo)
+            worst = max(worst, e)
+            assert e <= BETA_TOL, (b, e)
+        assert obj[b] == pytest.approx(tr[-1], rel=OBJ_TOL), b
+    print(f"worst relative beta error over sampled b: {worst:.2e}")
+
+
+def test_batched_loss_grad(prob):
+    B = 64
+    cox, M = _setup(prob, "int8", B)
+    rng = np.random.default_rng(11)
+    beta = (0.05 * rng.standard_normal((B, prob.p)) * (rng.random((B, prob.p)) < 0.2)).astype(np.float32)
+    loss, grad = cox.loss_grad(torch.from_numpy(beta).cuda())
+    grad = grad.cpu().numpy()
+    for b in (0, 17, 63):
+        negL, g = oracle.loss_grad(M, prob.time, prob.event, beta[b].astype(np.float64))
+        assert loss[b] == pytest.approx(negL, rel=1e-12)
+        assert np.abs(grad[b] + g).max() <= 1e-6 * np.abs(g).max(), b
+
+
+def test_batched_equals_single(prob):
+    """The 64-wide matrix-core pass and 64 separate vector passes agree."""
+    B = 64
+    cox, M = _setup(prob, "fp8", B)
+    lm = cox.lambda_max()
+    lams = coxsim.lambda_grid(lm, B, 0.01)
+    sigma = 1.0 / (2.0 * cox.opnorm2()[0])
+    bb, _, ob, _ = cox.fit_path(lams, max_iter=20, tol=0.0, step=sigma)
+    bb = bb.cpu().numpy()
+    for b in (5, 31, 63):
+        bs, _, os_, _ = cox.fit_path([lams[b]], max_iter=20, tol=0.0, step=sigma)
+        assert rel_beta_err(bb[b], bs.cpu().numpy()[0]) <= BETA_TOL
+        assert ob[b] == pytest.approx(os_[0], rel=OBJ_TOL)
+
+
+def test_non_count_values_use_vector_path(prob):
+    """A value outside {0, 1, 2} is not an allele count: the batch falls back to
+    the vector pass and stays exact."""
+    d = coxsim.genotype_problem(1200, 90, 4, 0.5, 77)
+    d.G[3, 10] = 3
+    cox, M = device_problem(d, "int8", ldx=1200, max_batch=16)
+    lm = oracle.lambda_max(M, d.time, d.event)
+    lams = coxsim.lambda_grid(lm, 16, 0.05)
+    lams[0] *= 1 + 1e-6
+    sigma = 1.0 / (2.0 * oracle.opnorm2(M)[0])
+    beta, _, obj, _ = cox.fit_path(lams, max_iter=15, tol=0.0, step=sigma)
+    for b in (3, 15):
+        bo, tr, _, _ = oracle.fit(M, d.time, d.event, lams[b], sigma, max_iter=15)
+        assert rel_beta_err(beta.cpu().numpy()[b], bo) <= BETA_TOL
+        assert obj[b] == pytest.approx(tr[-1], rel=OBJ_TOL)
+
+
+def test_vector_path_switch(prob, monkeypatch):
+    B = 16
+    cox, M = _setup(prob, "int8", B)
+    lm = cox.lambda_max()
+    lams = coxsim.lambda_grid(lm, B, 0.05)
+    sigma = 1.0 / (2.0 * cox.opnorm2()[0])
+    a, _, oa, _ = cox.fit_path(lams, max_iter=12, tol=0.0, step=sigma)
+    a = a.cpu().numpy()
+    monkeypatch.setenv("COXHIP_NO_MFMA", "1")
+    v, _, ov, _ = cox.fit_path(lams, max_iter=12, tol=0.0, step=sigma)
+    monkeypatch.delenv("COXHIP_NO_MFMA")
+    v = v.cpu().numpy()
+    for b in range(1, B):
+        assert rel_beta_err(a[b], v[b]) <= BETA_TOL
+    np.testing.assert_allclose(oa, ov, rtol=OBJ_TOL)
