@@ -7,6 +7,12 @@ soft-threshold, convergence check.  The timed region runs K steps from beta = 0
 with every input already resident in HBM.  Prints one JSON line.
 
 Workloads (synthetic, seeded; they stand in for the UK Biobank genotypes):
+  geno-fp8-batched (default) : n = 400,000 subjects x p = 500,000 SNPs, allele
+               counts stored as FP8 E4M3 codes (200 GB, generated in HBM),
+               standardised on the fly; 1,000 true effects, 20% events; a path
+               of B = 64 lambdas log-spaced from lambda_max to 0.01 lambda_max
+               solved together; step 1/(2 ||X~||^2) with ||X~|| from 20 power
+               steps; K steps from beta = 0.
   gauss-fp32 : n = 20,000 subjects x p = 50,000 covariates, X ~ N(0,1) FP32,
                50 true effects, ~30% censored, lambda = 0.3 lambda_max,
                step 1/(2 ||X||^2) by power iteration, 500 steps.
@@ -29,6 +35,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Cox prox-grad iters/s + HBM GB/s, FP8-X batched vs plain FP32, equal tolerance"
 HBM_PEAK_GBS = 8000.0
+INT8_MFMA_PEAK_TOPS = 5000.0  # dense int8 matrix-core peak of the MI355X
 
 
 def log(msg):
@@ -134,12 +141,116 @@ def cpu_baseline_gauss(d, lam, sigma, budget_s: float = 15.0):
             "sample": f"first {k} ISTA steps from beta=0 on the full {d.n}x{d.p} FP32 X (FP64 arithmetic)"}
 
 
+def bench_geno_batched(args):
+    import torch
+
+    import coxsim
+    import paper_2010_16114_amd as P
+
+    n, p, B = args.n or 400000, args.p or 500000, args.batch
+    ldx = (n + 15) // 16 * 16
+    log(f"drawing survival times from the causal columns (n={n}, p={p})")
+    d = coxsim.config4(n=n, p=p, materialize=False)
+    log("generating FP8 genotype matrix in HBM")
+    G, c1, c2 = coxsim.genotype_device(n, p, d.seed, d.thresholds, fmt=1, ldx=ldx)
+    mu, sc = coxsim.standardisation(c1, c2, n)
+    mu_d, sc_d = torch.from_numpy(mu).cuda(), torch.from_numpy(sc).cuda()
+    torch.cuda.synchronize()
+    cox = P.Cox(G, d.time, d.event, xtype=P.X_FP8_E4M3, n=n, center=mu_d, scale=sc_d, max_batch=B)
+    lmax = cox.lambda_max()
+    s2, pit = cox.opnorm2(tol=1e-6, maxiter=args.power_steps)
+    sigma = 1.0 / (2.0 * s2)
+    lams = coxsim.lambda_grid(lmax, B, 0.01)
+    log(f"lambda_max={lmax:.6g} ||X~||^2~{s2:.6g} ({pit} power steps) sigma={sigma:.4g}")
+    log(f"warmup {args.warmup} steps (B={B})")
+    cox.fit_path(lams, max_iter=args.warmup, tol=0.0, step=sigma)
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps")
+    cox.timing(True)
+    t0 = time.perf_counter()
+    beta, iters, obj, _ = cox.fit_path(lams, max_iter=args.steps, tol=0.0, step=sigma)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    xtr_ms, xtr_n = cox.timing_read("xtr")
+    risk_ms, risk_n = cox.timing_read("risk")
+    eta_ms, eta_n = cox.timing_read("eta")
+    cox.timing(False)
+    elapsed = t1 - t0
+    nnz = (beta != 0).sum(dim=1).cpu().numpy()
+    log(f"{args.steps} steps x {B} lambdas in {elapsed:.3f} s; nnz per lambda {nnz.min()}..{nnz.max()}")
+    bpad = (B + 15) // 16 * 16
+    # Algorithmic bytes of one gradient pass: X once, the residual limbs once,
+    # the raw column sums written once.
+    xtr_bytes = n * p + 3 * bpad * n + B * p * 8
+    xtr_avg = xtr_ms / max(xtr_n, 1) / 1e3
+    achieved = xtr_bytes / xtr_avg / 1e9
+    tops = 2.0 * n * p * 3 * bpad / xtr_avg / 1e12
+    res = {
+        "metric": METRIC,
+        "value": args.steps * B / elapsed,
+        "unit": "lambda-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp8",
+        "data": "synthetic",
+        "config": {"workload": f"l1-Cox ISTA path, FP8 E4M3 genotype X n={n} p={p} (standardised on the fly), "
+                               f"B={B} lambdas log-spaced lambda_max..0.01*lambda_max, {args.steps} steps from beta=0",
+                   "n": n, "p": p, "B": B, "x_storage": "fp8_e4m3 allele counts", "x_bytes": n * p,
+                   "gradient": "int8 MFMA, residual in 3 exact int8 limbs, int32 accumulation",
+                   "eta": "int8 MFMA over the changed columns, FP64 accumulator"},
+        "iters_per_s": args.steps / elapsed,
+        "phases_ms_per_step": {"xtr_prox": xtr_ms / max(xtr_n, 1), "risk": risk_ms / max(risk_n, 1),
+                               "eta_update": eta_ms / max(eta_n, 1)},
+        "roofline": {"bound": "hbm", "kernel": "mfma_xtr_kernel (X~' R, B lambdas) + epilogue",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "algorithmic_bytes_per_launch": xtr_bytes,
+                     "mfma_tops": tops, "mfma_frac_int8": tops / INT8_MFMA_PEAK_TOPS},
+        "nnz_range": [int(nnz.min()), int(nnz.max())],
+    }
+    del G
+    torch.cuda.empty_cache()
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline_geno(d, lams[-1], sigma, p)
+    return res
+
+
+def cpu_baseline_geno(d, lam, sigma, p_full, p_sample: int = 1000, budget_s: float = 15.0):
+    """The FP64 oracle on a column sample of the genotype workload: its steps
+    from beta = 0 at the smallest lambda, timed on the host cores and scaled to
+    the full column count (the oracle's step cost is linear in p)."""
+    import coxsim
+    import oracle
+
+    cols = np.arange(p_sample)
+    G = coxsim.genotype_columns(d.n, cols, d.seed, d.thresholds[cols])
+    c1, c2 = coxsim.genotype_counts(G, d.n)
+    mu, sc = coxsim.standardisation(c1, c2, d.n)
+    M = oracle.Matrix.genotype(G, mu, sc)
+    t0 = time.perf_counter()
+    oracle.fit(M, d.time, d.event, lam, sigma, max_iter=1)
+    one = time.perf_counter() - t0
+    k = int(max(2, min(50, budget_s / max(one / 2, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.fit(M, d.time, d.event, lam, sigma, max_iter=k)
+    dt = time.perf_counter() - t0
+    return {"value": k / dt * p_sample / p_full, "unit": "lambda-iters/s", "cores": cpu_threads(), "kind": "oracle",
+            "sample": f"first {k} ISTA steps from beta=0 at lambda=0.01*lambda_max on the first {p_sample} of "
+                      f"{p_full} columns (n={d.n}), scaled by {p_sample}/{p_full}"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="gauss-fp32", choices=["gauss-fp32"])
+    ap.add_argument("--steps", type=int, default=0, help="default: 10 (batched) or 500 (gauss-fp32)")
+    ap.add_argument("--warmup", type=int, default=-1, help="default: 2 (batched) or 20 (gauss-fp32)")
+    ap.add_argument("--workload", default="geno-fp8-batched", choices=["geno-fp8-batched", "gauss-fp32"])
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--power-steps", type=int, default=20)
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--p", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
@@ -152,7 +263,12 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    res = {"gauss-fp32": bench_gauss_fp32}[args.workload](args)
+    batched = args.workload == "geno-fp8-batched"
+    if args.steps <= 0:
+        args.steps = 10 if batched else 500
+    if args.warmup < 0:
+        args.warmup = 2 if batched else 20
+    res = {"gauss-fp32": bench_gauss_fp32, "geno-fp8-batched": bench_geno_batched}[args.workload](args)
     print(json.dumps(res), flush=True)
 
 

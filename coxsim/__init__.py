@@ -227,10 +227,15 @@ class CoxData:
     thresholds: np.ndarray | None = None
 
     def standardized32(self) -> np.ndarray:
-        """FP32 standardised genotypes (x~ = (g - mu) s rounded to FP32)."""
+        """FP32 standardised genotypes (x~ = (g - mu) s in FP64, rounded to FP32)."""
         assert self.kind == "genotype" and self.G is not None
-        return ((self.G.astype(np.float64) - self.mu[:, None].astype(np.float64))
-                * self.s[:, None].astype(np.float64)).astype(np.float32)
+        out = np.empty(self.G.shape, np.float32)
+        step = max(1, (1 << 24) // max(1, self.G.shape[1]))
+        for j0 in range(0, self.G.shape[0], step):
+            j1 = min(self.G.shape[0], j0 + step)
+            out[j0:j1] = ((self.G[j0:j1].astype(np.float64) - self.mu[j0:j1, None].astype(np.float64))
+                          * self.s[j0:j1, None].astype(np.float64))
+        return out
 
 
 def _effects(p: int, k: int, rng):

@@ -59,6 +59,9 @@ struct cox_ctx {
     double *qscale = nullptr, *rmaxp = nullptr;
     long long* rsump = nullptr;
     int* geno_bad = nullptr;
+    int8_t* dlimbs = nullptr;    // [3][Bmax16][dstride] eta-update limbs
+    int64_t dstride = 0;
+    double *dscale = nullptr, *dmaxp = nullptr;
     int geno_state = -1;         // -1 unchecked, 0 counts 0/1/2 only, 1 other values
     int nsplit = 1;
     int64_t split_rows = 0;
@@ -477,9 +480,11 @@ cox_status cox_setup(cox_ctx** out, const cox_matrix* X, const double* time, con
     if (ok && mfma_able) {
         c->bpad_max = (int)round_up(max_batch, 16);
         const int nt = mfma_ntile(n);
+        c->dstride = round_up(p, 64);
         ok = dalloc(c, &c->limbs, (size_t)3 * c->bpad_max * c->rstride) && dalloc(c, &c->qscale, max_batch) &&
              dalloc(c, &c->rmaxp, (size_t)max_batch * nt) && dalloc(c, &c->rsump, (size_t)max_batch * nt) &&
-             dalloc(c, &c->geno_bad, 1);
+             dalloc(c, &c->geno_bad, 1) && dalloc(c, &c->dlimbs, (size_t)3 * c->bpad_max * c->dstride) &&
+             dalloc(c, &c->dscale, max_batch) && dalloc(c, &c->dmaxp, (size_t)max_batch * ((c->dstride + 4095) / 4096));
     }
     if (ok) {
         c->pinned_bytes = 64 * 1024;
@@ -701,8 +706,9 @@ cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_
     HIPCHK(launch_fill_i32(c->iters, 0, B, c->stream), "reset");
     HIPCHK(launch_fill_f64(c->hist, 0.0, (int64_t)B * kMaxHist, c->stream), "reset");
 
+    const bool mfma = use_mfma(c, B);
     RiskArgs ra = risk_args(c, B);
-    ra.part = o.eta_mode == 0 ? c->part_upd : nullptr;
+    ra.part = (o.eta_mode == 0 && !mfma) ? c->part_upd : nullptr;
     ra.use_ctl = 1;
     ra.ctl = FitCtl{c->lam, c->l1new, c->nblk, c->hist, c->kit, c->active, c->iters, c->status, c->fobj,
                     o.max_iter, o.lag, o.tol};
@@ -715,7 +721,17 @@ cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_
 
     for (int it = 0; it <= o.max_iter; ++it) {
         if (it > 0) {
-            if (o.eta_mode == 0) {
+            if (o.eta_mode == 0 && mfma) {
+                tmark(c, COX_PHASE_ETA);
+                const int bpad = (int)round_up(B, 16);
+                HIPCHK(launch_quantize_d(c->dcoef, c->p, c->sel, c->nsel, B, c->dmaxp, c->dlimbs, c->dstride, bpad,
+                                         c->dscale, c->stream),
+                       "quantise eta update");
+                MfmaEtaArgs m{c->x.X, c->x.xt, c->n, c->p, c->x.ldx, c->sel, c->nsel, c->dlimbs, c->dstride,
+                              bpad, B, c->dscale, c->eta, c->active};
+                HIPCHK(launch_mfma_eta(m, c->stream), "eta update on matrix cores");
+                tmark(c, COX_PHASE_ETA);
+            } else if (o.eta_mode == 0) {
                 tmark(c, COX_PHASE_ETA);
                 for (int b0 = 0; b0 < B; b0 += kGroup)
                     HIPCHK(launch_eta_update(c->x, c->sel, c->nsel, c->dcoef, b0, std::min(kGroup, B - b0),

@@ -21,7 +21,27 @@ struct MfmaArgs {
     double* out;            // [B][p] raw sums q_b * sum_i g_ij R_bi
 };
 
+// eta_b(i) += q_b * sum_{u < nsel} g(i, sel[u]) D_b(u), D in three int8 limbs.
+struct MfmaEtaArgs {
+    const void* X;
+    int xt;
+    int64_t n, p, ldx;      // ldx % 16 == 0, X 16-byte aligned
+    const int32_t* sel;     // [nsel] changed columns, ascending
+    const int32_t* nsel;    // device count
+    const int8_t* dlimbs;   // [3][bpad][dstride] limbs of D by position in sel, zero past nsel
+    int64_t dstride;        // multiple of 64, >= p
+    int bpad, B;
+    const double* dscale;   // [B]
+    double* eta;            // [B][n] FP64, updated in place
+    const int32_t* active;  // [B] or null
+};
+
 int mfma_ntile(int64_t n);
+// D_b(u) = dcoef[b][sel[u]] -> dlimbs, dscale (per-b step max|D_b| / 2^22)
+hipError_t launch_quantize_d(const double* dcoef, int64_t p, const int32_t* sel, const int32_t* nsel, int B,
+                             double* dmaxp, int8_t* dlimbs, int64_t dstride, int bpad, double* dscale,
+                             hipStream_t s);
+hipError_t launch_mfma_eta(const MfmaEtaArgs& a, hipStream_t s);
 // r64 [B][n] -> limbs, qscale [B], sumr [B] = q_b * sum_i R_bi
 hipError_t launch_quantize(const double* r64, int64_t n, int B, double* rmaxp, long long* rsump, int8_t* limbs,
                            int64_t lstride, int bpad, double* qscale, double* sumr, hipStream_t s);

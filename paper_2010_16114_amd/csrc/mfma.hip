@@ -168,6 +168,176 @@ __global__ __launch_bounds__(kT, 1) void mfma_xtr_kernel(MfmaArgs a)
             }
 }
 
+// eta update on the matrix cores: eta (n x B) += G[:, U] D, contracting over the
+// changed columns U.  M = subjects, N = 3 * B limb columns, K = positions in U.
+// G is stored with subjects contiguous, so a 64-column x 256-row tile is staged
+// in LDS (16-byte chunks, XOR-swizzled by the column's 16-group so that the
+// byte gathers below hit distinct banks) and each A fragment (16 columns of one
+// subject) is gathered byte by byte.  The D limb tile is staged like R above.
+// Each (subject, b) is owned by one lane, so eta is updated in place.
+template <int XT, int NG>
+__global__ __launch_bounds__(kT, 1) void mfma_eta_kernel(MfmaEtaArgs a)
+{
+    constexpr int NT = kLimbs * NG;
+    constexpr int NCOL = 16 * NT;
+    constexpr int DCH = 4 * NCOL;  // 16-byte chunks of D per 64-column step
+    constexpr int DPT = (DCH + kT - 1) / kT;
+    __shared__ uint4 sG[2][64 * 16];
+    __shared__ v4i sD[2][DCH];
+    const int nsel = *a.nsel;
+    if (nsel == 0) return;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int64_t n = a.n, ldx = a.ldx;
+    const int64_t i0 = (int64_t)blockIdx.x * 256;
+    const uint8_t* __restrict__ X = static_cast<const uint8_t*>(a.X);
+    const int nchunk = (nsel + 63) / 64;
+
+    v4i acc[4][NT];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = v4i{0, 0, 0, 0};
+
+    uint4 gr[4];
+    v4i dr[DPT];
+    auto fetch = [&](int c) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int ch = threadIdx.x + kT * k;
+            const int u = ch >> 4, rb = ch & 15;
+            const int pos = c * 64 + u;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (pos < nsel) {
+                const v4i t = load_a<XT>(X, a.sel[pos], a.p, ldx, i0 + 16 * rb, n);
+                v = make_uint4((uint32_t)t[0], (uint32_t)t[1], (uint32_t)t[2], (uint32_t)t[3]);
+            }
+            gr[k] = v;
+        }
+#pragma unroll
+        for (int k = 0; k < DPT; ++k) {
+            const int ch = threadIdx.x + kT * k;
+            if (ch < DCH) {
+                const int col = ch >> 2, kq = ch & 3;
+                const int limb = col / (16 * NG), b = col % (16 * NG);
+                dr[k] = *reinterpret_cast<const v4i*>(a.dlimbs + ((int64_t)limb * a.bpad + b) * a.dstride + c * 64 +
+                                                      16 * kq);
+            }
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int ch = threadIdx.x + kT * k;
+            const int u = ch >> 4, rb = ch & 15;
+            sG[buf][u * 16 + (rb ^ (u >> 4))] = gr[k];
+        }
+#pragma unroll
+        for (int k = 0; k < DPT; ++k) {
+            const int ch = threadIdx.x + kT * k;
+            if (ch < DCH) {
+                const int col = ch >> 2, kq = ch & 3;
+                sD[buf][kq * NCOL + col] = dr[k];
+            }
+        }
+    };
+
+    fetch(0);
+    store(0);
+    __syncthreads();
+    for (int c = 0; c < nchunk; ++c) {
+        const int buf = c & 1;
+        const bool more = c + 1 < nchunk;
+        if (more) fetch(c + 1);
+        const uint8_t* g8 = reinterpret_cast<const uint8_t*>(sG[buf]);
+        v4i A[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const int row = wid * 64 + mt * 16 + (lane & 15);
+            uint32_t w[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int u = 16 * (lane >> 4) + e;
+                const uint32_t byte = g8[u * 256 + 16 * ((row >> 4) ^ (u >> 4)) + (row & 15)];
+                w[e >> 2] |= byte << (8 * (e & 3));
+            }
+            A[mt] = v4i{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
+        }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const v4i bf = sD[buf][(lane >> 4) * NCOL + nt * 16 + (lane & 15)];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], bf, acc[mt][nt], 0, 0, 0);
+        }
+        if (more) store(buf ^ 1);
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int bq = 0; bq < NG; ++bq)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int b = bq * 16 + (lane & 15);
+                const int64_t i = i0 + wid * 64 + mt * 16 + mfma_c_row(lane, v);
+                if (i < n && b < a.B && (a.active == nullptr || a.active[b])) {
+                    const int64_t tot = (int64_t)acc[mt][bq][v] + 256 * (int64_t)acc[mt][NG + bq][v] +
+                                        65536 * (int64_t)acc[mt][2 * NG + bq][v];
+                    a.eta[(int64_t)b * n + i] += a.dscale[b] * (double)tot;
+                }
+            }
+}
+
+// Largest |D_b(u)| over a tile of 4096 positions of the change list.
+__global__ __launch_bounds__(kT) void dmax_kernel(const double* __restrict__ dcoef, int64_t p,
+                                                  const int32_t* __restrict__ sel, const int32_t* __restrict__ nsel,
+                                                  double* __restrict__ part, int ntile)
+{
+    __shared__ double sh[kT / 64];
+    const int b = blockIdx.y;
+    const int m = *nsel;
+    double mx = 0.0;
+    for (int64_t u = (int64_t)blockIdx.x * 4096 + threadIdx.x; u < min((int64_t)m, (int64_t)(blockIdx.x + 1) * 4096);
+         u += kT)
+        mx = fmax(mx, fabs(dcoef[(int64_t)b * p + sel[u]]));
+    mx = wave_max(mx);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) part[(int64_t)b * ntile + blockIdx.x] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+}
+
+// D limbs by position; positions nsel .. round_up(nsel, 64) - 1 are zeroed.
+__global__ __launch_bounds__(kT) void dquant_kernel(const double* __restrict__ dcoef, int64_t p,
+                                                    const int32_t* __restrict__ sel, const int32_t* __restrict__ nsel,
+                                                    const double* __restrict__ dmaxp, int ntile,
+                                                    int8_t* __restrict__ dlimbs, int64_t dstride, int bpad,
+                                                    double* __restrict__ dscale)
+{
+    const int b = blockIdx.y;
+    const int m = *nsel;
+    const int mt = (m + 4095) / 4096;
+    double mx = 0.0;
+    for (int t = 0; t < mt; ++t) mx = fmax(mx, dmaxp[(int64_t)b * ntile + t]);
+    const double q = mx > 0.0 ? mx / (double)(1 << kQBits) : 1.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) dscale[b] = q;
+    const int64_t mpad = ((int64_t)m + 63) / 64 * 64;
+    for (int64_t u = (int64_t)blockIdx.x * 4096 + threadIdx.x; u < min(mpad, (int64_t)(blockIdx.x + 1) * 4096);
+         u += kT) {
+        int d0 = 0, d1 = 0, d2 = 0;
+        if (u < m) {
+            const int R = (int)llrint(dcoef[(int64_t)b * p + sel[u]] / q);
+            d0 = ((R + 128) & 255) - 128;
+            const int R1 = (R - d0) >> 8;
+            d1 = ((R1 + 128) & 255) - 128;
+            d2 = (R1 - d1) >> 8;
+        }
+        dlimbs[((int64_t)0 * bpad + b) * dstride + u] = (int8_t)d0;
+        dlimbs[((int64_t)1 * bpad + b) * dstride + u] = (int8_t)d1;
+        dlimbs[((int64_t)2 * bpad + b) * dstride + u] = (int8_t)d2;
+    }
+}
+
 // Largest |r| of each vector over a tile of 4096 subjects.
 __global__ __launch_bounds__(kT) void rmax_kernel(const double* __restrict__ r, int64_t n, double* __restrict__ part,
                                                   int ntile)
@@ -241,6 +411,24 @@ __global__ __launch_bounds__(kT) void geno_check_kernel(const uint8_t* __restric
 }
 
 template <int XT, int NG>
+hipError_t launch_eta_ng(const MfmaEtaArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL((mfma_eta_kernel<XT, NG>), dim3((unsigned)((a.n + 255) / 256)), dim3(kT), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int XT>
+hipError_t launch_eta_xt(const MfmaEtaArgs& a, hipStream_t s)
+{
+    switch (a.bpad / 16) {
+    case 1: return launch_eta_ng<XT, 1>(a, s);
+    case 2: return launch_eta_ng<XT, 2>(a, s);
+    case 3: return launch_eta_ng<XT, 3>(a, s);
+    default: return launch_eta_ng<XT, 4>(a, s);
+    }
+}
+
+template <int XT, int NG>
 hipError_t launch_ng(const MfmaArgs& a, hipStream_t s)
 {
     hipLaunchKernelGGL((mfma_xtr_kernel<XT, NG>), dim3((unsigned)((a.p + 255) / 256)), dim3(kT), 0, s, a);
@@ -271,6 +459,23 @@ hipError_t launch_quantize(const double* r64, int64_t n, int B, double* rmaxp, l
                        rsump);
     hipLaunchKernelGGL(rsum_kernel, dim3(1), dim3(64), 0, s, rsump, nt, qscale, sumr, B);
     return hipGetLastError();
+}
+
+hipError_t launch_quantize_d(const double* dcoef, int64_t p, const int32_t* sel, const int32_t* nsel, int B,
+                             double* dmaxp, int8_t* dlimbs, int64_t dstride, int bpad, double* dscale,
+                             hipStream_t s)
+{
+    const int nt = (int)((p + 63) / 64 * 64 + 4095) / 4096;
+    hipLaunchKernelGGL(dmax_kernel, dim3(nt, B), dim3(kT), 0, s, dcoef, p, sel, nsel, dmaxp, nt);
+    hipLaunchKernelGGL(dquant_kernel, dim3(nt, B), dim3(kT), 0, s, dcoef, p, sel, nsel, dmaxp, nt, dlimbs, dstride,
+                       bpad, dscale);
+    return hipGetLastError();
+}
+
+hipError_t launch_mfma_eta(const MfmaEtaArgs& a, hipStream_t s)
+{
+    if (a.bpad < 16 || a.bpad > 64 || a.bpad % 16 || a.B > a.bpad || a.dstride % 64) return hipErrorInvalidValue;
+    return a.xt == XT_FP8 ? launch_eta_xt<XT_FP8>(a, s) : launch_eta_xt<XT_I8>(a, s);
 }
 
 hipError_t launch_mfma_xtr(const MfmaArgs& a, hipStream_t s)
