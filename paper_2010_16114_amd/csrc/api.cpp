@@ -426,7 +426,7 @@ cox_status cox_setup(cox_ctx** out, const cox_matrix* X, const double* time, con
     c->rstride = round_up(n, kSplitRows);
     c->nblk = (int)((p + kGemvtCols - 1) / kGemvtCols);
     const int64_t nslab = (n + kUpdRows - 1) / kUpdRows;
-    c->ncg = (int)std::max<int64_t>(1, std::min<int64_t>(16, 1024 / nslab));
+    c->ncg = (int)std::max<int64_t>(1, std::min<int64_t>(4, 512 / nslab));
     c->ncb = (int)std::max<int64_t>(1, std::min<int64_t>((2048 + nslab - 1) / nslab, (p + 255) / 256));
     c->tile = 1024 * std::max<int64_t>(1, (n + 1024LL * kMaxTiles - 1) / (1024LL * kMaxTiles));
     c->ntile = (int)((n + c->tile - 1) / c->tile);

@@ -86,7 +86,7 @@ struct RiskArgs {
 };
 
 constexpr int kMaxTiles = 4096;
-constexpr int kFinElems = 2048;  // eta elements per workgroup of the eta pass
+constexpr int kFinElems = 512;   // eta elements per workgroup of the eta pass
 
 enum GemvtMode : int { GT_RAW = 0, GT_GRAD = 1, GT_PROX = 2 };
 

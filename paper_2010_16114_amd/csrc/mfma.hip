@@ -396,17 +396,33 @@ __global__ void rsum_kernel(const long long* __restrict__ rsump, int ntile, cons
     sumr[b] = qscale[b] * (double)s;
 }
 
-// bad[0] |= 1 if any byte of the n x p matrix is not the code of 0, 1 or 2.
+// bad[0] |= 1 if any byte of the n x p matrix is not the code of 0, 1 or 2
+// (16-byte loads: the matrix-core path requires a 16-byte aligned ldx).
+template <int XT>
+__device__ __forceinline__ bool bad4(uint32_t w)
+{
+    bool b = false;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const uint32_t v = (w >> (8 * e)) & 0xff;
+        b |= XT == XT_FP8 ? !(v == 0x00 || v == 0x38 || v == 0x40) : !(v <= 2);
+    }
+    return b;
+}
+
 template <int XT>
 __global__ __launch_bounds__(kT) void geno_check_kernel(const uint8_t* __restrict__ X, int64_t n, int64_t ldx,
                                                         int* __restrict__ bad)
 {
     const int64_t j = blockIdx.x;
-    int b = 0;
-    for (int64_t i = threadIdx.x; i < n; i += kT) {
-        const uint8_t v = X[j * ldx + i];
-        b |= XT == XT_FP8 ? !(v == 0x00 || v == 0x38 || v == 0x40) : !(v <= 2);
+    const uint8_t* col = X + j * ldx;
+    bool b = false;
+    const int64_t nv = n / 16 * 16;
+    for (int64_t i = (int64_t)threadIdx.x * 16; i < nv; i += (int64_t)kT * 16) {
+        const uint4 u = *reinterpret_cast<const uint4*>(col + i);
+        b |= bad4<XT>(u.x) | bad4<XT>(u.y) | bad4<XT>(u.z) | bad4<XT>(u.w);
     }
+    for (int64_t i = nv + threadIdx.x; i < n; i += kT) b |= bad4<XT>((uint32_t)col[i]);  // zero bytes are valid codes
     if (__any(b) && (threadIdx.x & 63) == 0) atomicOr(bad, 1);
 }
 
