@@ -212,11 +212,54 @@ def bench_geno_batched(args):
                      "mfma_tops": tops, "mfma_frac_int8": tops / INT8_MFMA_PEAK_TOPS},
         "nnz_range": [int(nnz.min()), int(nnz.max())],
     }
+    if args.fp32_slice > 0:
+        res["fp32_comparator"] = fp32_comparator(args, d, G, mu_d, sc_d, lams, sigma, n, p)
+        res["speedup_vs_fp32"] = res["value"] / res["fp32_comparator"]["value_scaled"]
     del G
     torch.cuda.empty_cache()
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline_geno(d, lams[-1], sigma, p)
     return res
+
+
+def fp32_comparator(args, d, G, mu_d, sc_d, lams, sigma, n, p):
+    """The plain FP32 method (one lambda per pass, FP32 standardised X) on the
+    first p_s columns, K steps from beta = 0 at the largest and the smallest
+    lambda of the path.  FP32 X of the full matrix (4 bytes per entry) does not
+    fit in HBM, and the step cost is linear in p, so the rate is scaled by
+    p_s / p."""
+    import torch
+
+    import paper_2010_16114_amd as P
+
+    ps = min(args.fp32_slice, p)
+    log(f"FP32 comparator: standardising {ps} columns to FP32")
+    X32 = torch.empty((ps, G.shape[1]), dtype=torch.float32, device="cuda")
+    for j0 in range(0, ps, 4096):
+        j1 = min(ps, j0 + 4096)
+        code = G[j0:j1].to(torch.int32)
+        cnt = ((code >> 3) & 1) | ((code >> 5) & 2)  # FP8 E4M3 codes of 0, 1, 2 -> counts
+        X32[j0:j1] = (cnt.to(torch.float32) - mu_d[j0:j1, None]) * sc_d[j0:j1, None]
+        del code, cnt
+    X32[:, n:] = 0.0
+    torch.cuda.synchronize()
+    cox = P.Cox(X32, d.time, d.event, n=n, max_batch=1)
+    rates = []
+    for lam in (lams[0], lams[-1]):
+        cox.fit_path([lam], max_iter=2, tol=0.0, step=sigma)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cox.fit_path([lam], max_iter=args.steps, tol=0.0, step=sigma)
+        torch.cuda.synchronize()
+        rates.append(args.steps / (time.perf_counter() - t0))
+    cox.close()
+    del X32
+    torch.cuda.empty_cache()
+    r = float(np.mean(rates))
+    log(f"FP32 comparator: {r:.1f} lambda-iters/s on {ps} columns -> {r * ps / p:.2f} scaled to {p}")
+    return {"value_slice": r, "value_scaled": r * ps / p, "unit": "lambda-iters/s", "columns": ps,
+            "method": "plain FP32 X (standardised), one lambda per pass, same step, "
+                      f"{args.steps} steps from beta=0 at lambda_max and 0.01*lambda_max; rate scaled by {ps}/{p}"}
 
 
 def cpu_baseline_geno(d, lam, sigma, p_full, p_sample: int = 1000, budget_s: float = 15.0):
@@ -251,6 +294,11 @@ def main():
     ap.add_argument("--workload", default="geno-fp8-batched", choices=["geno-fp8-batched", "gauss-fp32"])
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--power-steps", type=int, default=20)
+    ap.add_argument("--fp32-slice", type=int, default=31250,
+                    help="columns of the FP32 comparator of the batched workload (0: skip)")
+    ap.add_argument("--calibrate-copy-gb", type=float, default=0.0,
+                    help="first copy a buffer of this many GB with torch (a plain copy kernel of known size, "
+                         "for scaling the HBM counters)")
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--p", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
@@ -263,6 +311,14 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate_copy_gb > 0:
+        nbytes = int(args.calibrate_copy_gb * 1e9)
+        src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+        dst = src.clone()
+        torch.cuda.synchronize()
+        log(f"copied {nbytes} bytes for counter calibration")
+        del src, dst
+        torch.cuda.empty_cache()
     batched = args.workload == "geno-fp8-batched"
     if args.steps <= 0:
         args.steps = 10 if batched else 500
