@@ -12,8 +12,8 @@
 // largest entry.  The raw sums q_b * sum_i g_ij R_bi go to the same epilogue
 // as the vector path (centring with sum_i q_b R_bi, proximal step).
 //
-// Tiling: a workgroup of 4 wavefronts owns 256 SNP columns (4 M tiles of 16 per
-// wavefront) and all 3 * B limb columns (N tiles of 16), and walks K = n in
+// Tiling: a workgroup of 8 wavefronts (two per SIMD) owns 256 SNP columns (2 M
+// tiles of 16 per wavefront) and all 3 * B limb columns (N tiles of 16), and walks K = n in
 // stages of 256 rows.  X is read once per pass for all B vectors.  A fragments
 // (16 rows of one column per lane, one 16-byte load) stream from global memory
 // one stage ahead; the stage's limb tile (3 * B columns x 256 rows) is staged in
@@ -28,6 +28,8 @@ namespace {
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr int kT = 256;
+constexpr int kTM = 512;         // matrix-core kernels: 8 wavefronts, two per SIMD
+constexpr int kMT = 2;           // M tiles (16 rows each) per wavefront: 8 x 2 x 16 = 256
 constexpr int kKS = 4;           // MFMA k-steps (64 rows each) per stage
 constexpr int kKC = 64 * kKS;    // rows per stage
 constexpr int kLimbs = 3;
@@ -68,57 +70,61 @@ __device__ __forceinline__ v4i load_a(const uint8_t* __restrict__ X, int64_t col
 }
 
 template <int XT, int NG>
-__global__ __launch_bounds__(kT, 1) void mfma_xtr_kernel(MfmaArgs a)
+__global__ __launch_bounds__(kTM, 2) void mfma_xtr_kernel(MfmaArgs a)
 {
     constexpr int NT = kLimbs * NG;  // N tiles, limb-major: tile = limb * NG + b / 16
     constexpr int NCOL = 16 * NT;
     constexpr int CHUNKS = NCOL * (kKC / 16);  // 16-byte chunks of limb data per stage
-    static_assert(CHUNKS % kT == 0, "stage copy must split evenly");
+    constexpr int CPT = (CHUNKS + kTM - 1) / kTM;
     __shared__ v4i sR[2][kKS * 4 * NCOL];
 
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int64_t n = a.n, p = a.p, ldx = a.ldx;
-    const int64_t jw = (int64_t)blockIdx.x * 256 + wid * 64;  // first column of this wavefront
+    const int64_t jw = (int64_t)blockIdx.x * 256 + wid * (16 * kMT);  // first column of this wavefront
     const uint8_t* __restrict__ X = static_cast<const uint8_t*>(a.X);
     const int8_t* __restrict__ limbs = a.limbs;
     const int64_t nstage = (n + kKC - 1) / kKC;
     const int arow = 16 * (lane >> 4);  // k offset of this lane's 16 bytes within a k-step
     const int acol = lane & 15;
 
-    v4i acc[4][NT];
+    v4i acc[kMT][NT];
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
+    for (int mt = 0; mt < kMT; ++mt)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = v4i{0, 0, 0, 0};
 
     // limb data of one stage: chunk c -> (column col, 16-row group q)
     auto fetch_r = [&](int64_t k0, v4i* regs) {
 #pragma unroll
-        for (int u = 0; u < CHUNKS / kT; ++u) {
-            const int c = threadIdx.x + kT * u;
-            const int col = c / (kKC / 16), q = c % (kKC / 16);
-            const int limb = col / (16 * NG), b = col % (16 * NG);
-            regs[u] = *reinterpret_cast<const v4i*>(limbs + ((int64_t)limb * a.bpad + b) * a.lstride + k0 + 16 * q);
+        for (int u = 0; u < CPT; ++u) {
+            const int c = threadIdx.x + kTM * u;
+            if (c < CHUNKS) {
+                const int col = c / (kKC / 16), q = c % (kKC / 16);
+                const int limb = col / (16 * NG), b = col % (16 * NG);
+                regs[u] = *reinterpret_cast<const v4i*>(limbs + ((int64_t)limb * a.bpad + b) * a.lstride + k0 + 16 * q);
+            }
         }
     };
     auto store_r = [&](int buf, const v4i* regs) {
 #pragma unroll
-        for (int u = 0; u < CHUNKS / kT; ++u) {
-            const int c = threadIdx.x + kT * u;
-            const int col = c / (kKC / 16), q = c % (kKC / 16);
-            sR[buf][(q >> 2) * 4 * NCOL + (q & 3) * NCOL + col] = regs[u];
+        for (int u = 0; u < CPT; ++u) {
+            const int c = threadIdx.x + kTM * u;
+            if (c < CHUNKS) {
+                const int col = c / (kKC / 16), q = c % (kKC / 16);
+                sR[buf][(q >> 2) * 4 * NCOL + (q & 3) * NCOL + col] = regs[u];
+            }
         }
     };
-    auto fetch_a = [&](int64_t k0, v4i (&A)[4][kKS]) {
+    auto fetch_a = [&](int64_t k0, v4i (&A)[kMT][kKS]) {
 #pragma unroll
         for (int ks = 0; ks < kKS; ++ks)
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt)
+            for (int mt = 0; mt < kMT; ++mt)
                 A[mt][ks] = load_a<XT>(X, jw + mt * 16 + acol, p, ldx, k0 + ks * 64 + arow, n);
     };
 
-    v4i A[4][kKS], An[4][kKS];
-    v4i Rr[CHUNKS / kT];
+    v4i A[kMT][kKS], An[kMT][kKS];
+    v4i Rr[CPT];
     fetch_a(0, A);
     fetch_r(0, Rr);
     store_r(0, Rr);
@@ -137,7 +143,7 @@ __global__ __launch_bounds__(kT, 1) void mfma_xtr_kernel(MfmaArgs a)
             for (int nt = 0; nt < NT; ++nt) {
                 const v4i bf = sR[buf][ks * 4 * NCOL + (lane >> 4) * NCOL + nt * 16 + acol];
 #pragma unroll
-                for (int mt = 0; mt < 4; ++mt)
+                for (int mt = 0; mt < kMT; ++mt)
                     acc[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt][ks], bf, acc[mt][nt], 0, 0, 0);
             }
         }
@@ -147,13 +153,13 @@ __global__ __launch_bounds__(kT, 1) void mfma_xtr_kernel(MfmaArgs a)
 #pragma unroll
             for (int ks = 0; ks < kKS; ++ks)
 #pragma unroll
-                for (int mt = 0; mt < 4; ++mt) A[mt][ks] = An[mt][ks];
+                for (int mt = 0; mt < kMT; ++mt) A[mt][ks] = An[mt][ks];
         }
     }
 
-    // C of tile (mt, nt): lane holds rows kMfmaRow(lane, v), column lane & 15.
+    // C of tile (mt, nt): lane holds rows mfma_c_row(lane, v), column lane & 15.
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
+    for (int mt = 0; mt < kMT; ++mt)
 #pragma unroll
         for (int bq = 0; bq < NG; ++bq)
 #pragma unroll
@@ -176,12 +182,13 @@ __global__ __launch_bounds__(kT, 1) void mfma_xtr_kernel(MfmaArgs a)
 // subject) is gathered byte by byte.  The D limb tile is staged like R above.
 // Each (subject, b) is owned by one lane, so eta is updated in place.
 template <int XT, int NG>
-__global__ __launch_bounds__(kT, 1) void mfma_eta_kernel(MfmaEtaArgs a)
+__global__ __launch_bounds__(kTM, 2) void mfma_eta_kernel(MfmaEtaArgs a)
 {
     constexpr int NT = kLimbs * NG;
     constexpr int NCOL = 16 * NT;
     constexpr int DCH = 4 * NCOL;  // 16-byte chunks of D per 64-column step
-    constexpr int DPT = (DCH + kT - 1) / kT;
+    constexpr int DPT = (DCH + kTM - 1) / kTM;
+    constexpr int GPT = 1024 / kTM;  // 16-byte chunks of G per thread per step
     __shared__ uint4 sG[2][64 * 16];
     __shared__ v4i sD[2][DCH];
     const int nsel = *a.nsel;
@@ -192,18 +199,18 @@ __global__ __launch_bounds__(kT, 1) void mfma_eta_kernel(MfmaEtaArgs a)
     const uint8_t* __restrict__ X = static_cast<const uint8_t*>(a.X);
     const int nchunk = (nsel + 63) / 64;
 
-    v4i acc[4][NT];
+    v4i acc[kMT][NT];
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
+    for (int mt = 0; mt < kMT; ++mt)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = v4i{0, 0, 0, 0};
 
-    uint4 gr[4];
+    uint4 gr[GPT];
     v4i dr[DPT];
     auto fetch = [&](int c) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int ch = threadIdx.x + kT * k;
+        for (int k = 0; k < GPT; ++k) {
+            const int ch = threadIdx.x + kTM * k;
             const int u = ch >> 4, rb = ch & 15;
             const int pos = c * 64 + u;
             uint4 v = make_uint4(0, 0, 0, 0);
@@ -215,7 +222,7 @@ __global__ __launch_bounds__(kT, 1) void mfma_eta_kernel(MfmaEtaArgs a)
         }
 #pragma unroll
         for (int k = 0; k < DPT; ++k) {
-            const int ch = threadIdx.x + kT * k;
+            const int ch = threadIdx.x + kTM * k;
             if (ch < DCH) {
                 const int col = ch >> 2, kq = ch & 3;
                 const int limb = col / (16 * NG), b = col % (16 * NG);
@@ -226,14 +233,14 @@ __global__ __launch_bounds__(kT, 1) void mfma_eta_kernel(MfmaEtaArgs a)
     };
     auto store = [&](int buf) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int ch = threadIdx.x + kT * k;
+        for (int k = 0; k < GPT; ++k) {
+            const int ch = threadIdx.x + kTM * k;
             const int u = ch >> 4, rb = ch & 15;
             sG[buf][u * 16 + (rb ^ (u >> 4))] = gr[k];
         }
 #pragma unroll
         for (int k = 0; k < DPT; ++k) {
-            const int ch = threadIdx.x + kT * k;
+            const int ch = threadIdx.x + kTM * k;
             if (ch < DCH) {
                 const int col = ch >> 2, kq = ch & 3;
                 sD[buf][kq * NCOL + col] = dr[k];
@@ -249,10 +256,10 @@ __global__ __launch_bounds__(kT, 1) void mfma_eta_kernel(MfmaEtaArgs a)
         const bool more = c + 1 < nchunk;
         if (more) fetch(c + 1);
         const uint8_t* g8 = reinterpret_cast<const uint8_t*>(sG[buf]);
-        v4i A[4];
+        v4i A[kMT];
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            const int row = wid * 64 + mt * 16 + (lane & 15);
+        for (int mt = 0; mt < kMT; ++mt) {
+            const int row = wid * (16 * kMT) + mt * 16 + (lane & 15);
             uint32_t w[4] = {0, 0, 0, 0};
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
@@ -266,7 +273,7 @@ __global__ __launch_bounds__(kT, 1) void mfma_eta_kernel(MfmaEtaArgs a)
         for (int nt = 0; nt < NT; ++nt) {
             const v4i bf = sD[buf][(lane >> 4) * NCOL + nt * 16 + (lane & 15)];
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt)
+            for (int mt = 0; mt < kMT; ++mt)
                 acc[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], bf, acc[mt][nt], 0, 0, 0);
         }
         if (more) store(buf ^ 1);
@@ -274,13 +281,13 @@ __global__ __launch_bounds__(kT, 1) void mfma_eta_kernel(MfmaEtaArgs a)
     }
 
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
+    for (int mt = 0; mt < kMT; ++mt)
 #pragma unroll
         for (int bq = 0; bq < NG; ++bq)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int b = bq * 16 + (lane & 15);
-                const int64_t i = i0 + wid * 64 + mt * 16 + mfma_c_row(lane, v);
+                const int64_t i = i0 + wid * (16 * kMT) + mt * 16 + mfma_c_row(lane, v);
                 if (i < n && b < a.B && (a.active == nullptr || a.active[b])) {
                     const int64_t tot = (int64_t)acc[mt][bq][v] + 256 * (int64_t)acc[mt][NG + bq][v] +
                                         65536 * (int64_t)acc[mt][2 * NG + bq][v];
@@ -429,7 +436,7 @@ __global__ __launch_bounds__(kT) void geno_check_kernel(const uint8_t* __restric
 template <int XT, int NG>
 hipError_t launch_eta_ng(const MfmaEtaArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL((mfma_eta_kernel<XT, NG>), dim3((unsigned)((a.n + 255) / 256)), dim3(kT), 0, s, a);
+    hipLaunchKernelGGL((mfma_eta_kernel<XT, NG>), dim3((unsigned)((a.n + 255) / 256)), dim3(kTM), 0, s, a);
     return hipGetLastError();
 }
 
@@ -447,7 +454,7 @@ hipError_t launch_eta_xt(const MfmaEtaArgs& a, hipStream_t s)
 template <int XT, int NG>
 hipError_t launch_ng(const MfmaArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL((mfma_xtr_kernel<XT, NG>), dim3((unsigned)((a.p + 255) / 256)), dim3(kT), 0, s, a);
+    hipLaunchKernelGGL((mfma_xtr_kernel<XT, NG>), dim3((unsigned)((a.p + 255) / 256)), dim3(kTM), 0, s, a);
     return hipGetLastError();
 }
 
