@@ -211,6 +211,7 @@ def bench_geno_batched(args):
                      "traffic": None, "algorithmic_bytes_per_launch": xtr_bytes,
                      "mfma_tops": tops, "mfma_frac_int8": tops / INT8_MFMA_PEAK_TOPS},
         "nnz_range": [int(nnz.min()), int(nnz.max())],
+        "autotune": cox.mfma_tuning(),
     }
     if args.fp32_slice > 0:
         res["fp32_comparator"] = fp32_comparator(args, d, G, mu_d, sc_d, lams, sigma, n, p)

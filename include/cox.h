@@ -185,6 +185,14 @@ cox_status cox_nll_backward(cox_ctx *ctx, const double *grad_loss, int32_t B, vo
  * cox_timing_read returns the summed milliseconds and the number of timed
  * launches of a phase since the last enable.  Synchronises. */
 typedef enum { COX_PHASE_XTR = 0, COX_PHASE_RISK = 1, COX_PHASE_ETA = 2 } cox_phase;
+
+/* The batched matrix-core passes (X~' R and the eta update, used when X holds
+ * allele counts and B > 8) come in 3 pipeline shapes each.  The first batched
+ * call times every shape once on the live data and keeps the fastest (the
+ * environment variable COXHIP_TUNE_CACHE names a file that caches the choice,
+ * COXHIP_MFMA_VARIANT forces one).  This reports the choices (-1: not yet
+ * tuned) and the tuning times in milliseconds (host [3] each, nullable). */
+cox_status cox_mfma_tuning(cox_ctx *ctx, int32_t *xtr_variant, int32_t *eta_variant, float *xtr_ms, float *eta_ms);
 cox_status cox_timing_enable(cox_ctx *ctx, int32_t enable);
 cox_status cox_timing_read(cox_ctx *ctx, int32_t phase, double *total_ms, int64_t *count);
 

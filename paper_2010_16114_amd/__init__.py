@@ -73,6 +73,7 @@ def lib():
         "cox_nll_forward": [vp, vp, i32, i32, vp],
         "cox_nll_backward": [vp, vp, i32, vp],
         "cox_timing_enable": [vp, i32],
+        "cox_mfma_tuning": [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), vp, vp],
         "cox_timing_read": [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64)],
     }
     for name, args in sig.items():
@@ -220,6 +221,15 @@ class Cox:
         return loss
 
     PHASES = {"xtr": 0, "risk": 1, "eta": 2}
+
+    def mfma_tuning(self):
+        """Pipeline shapes chosen by the autotuner and their tuning times (ms)."""
+        xv, ev = ctypes.c_int32(), ctypes.c_int32()
+        xm = np.zeros(3, np.float32)
+        em = np.zeros(3, np.float32)
+        self._check(lib().cox_mfma_tuning(self._h, ctypes.byref(xv), ctypes.byref(ev), _np_ptr(xm), _np_ptr(em)),
+                    "cox_mfma_tuning")
+        return {"xtr_variant": xv.value, "eta_variant": ev.value, "xtr_ms": xm.tolist(), "eta_ms": em.tolist()}
 
     def timing(self, enable: bool):
         self._check(lib().cox_timing_enable(self._h, int(enable)), "cox_timing_enable")

@@ -10,6 +10,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <fstream>
+#include <sstream>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -62,6 +65,8 @@ struct cox_ctx {
     int8_t* dlimbs = nullptr;    // [3][Bmax16][dstride] eta-update limbs
     int64_t dstride = 0;
     double *dscale = nullptr, *dmaxp = nullptr;
+    int xtr_variant = -1, eta_variant = -1;  // chosen pipeline shapes (-1: not tuned yet)
+    float xtr_tune_ms[kMfmaVariants] = {0, 0, 0}, eta_tune_ms[kMfmaVariants] = {0, 0, 0};
     int geno_state = -1;         // -1 unchecked, 0 counts 0/1/2 only, 1 other values
     int nsplit = 1;
     int64_t split_rows = 0;
@@ -231,6 +236,71 @@ cox_status dense_eta(cox_ctx* c, const double* coef, int B, const double* shift)
     return COX_OK;
 }
 
+// ---- autotuner of the matrix-core pipeline shapes
+// A shape is forced by COXHIP_MFMA_VARIANT, read from the cache file named by
+// COXHIP_TUNE_CACHE (lines "key variant"), or chosen by timing every shape once
+// on the live data and appended to that file.
+int forced_variant()
+{
+    const char* v = std::getenv("COXHIP_MFMA_VARIANT");
+    if (!v || !*v) return -1;
+    const int k = std::atoi(v);
+    return (k >= 0 && k < kMfmaVariants) ? k : -1;
+}
+
+std::string tune_key(const cox_ctx* c, const char* kernel, int bpad)
+{
+    std::ostringstream os;
+    os << kernel << ":xt" << c->x.xt << ":n" << c->n << ":p" << c->p << ":b" << bpad;
+    return os.str();
+}
+
+int tune_cache_lookup(const std::string& key)
+{
+    const char* path = std::getenv("COXHIP_TUNE_CACHE");
+    if (!path) return -1;
+    std::ifstream f(path);
+    std::string k;
+    int v;
+    int found = -1;
+    while (f >> k >> v)
+        if (k == key && v >= 0 && v < kMfmaVariants) found = v;
+    return found;
+}
+
+void tune_cache_store(const std::string& key, int v)
+{
+    const char* path = std::getenv("COXHIP_TUNE_CACHE");
+    if (!path) return;
+    std::ofstream f(path, std::ios::app);
+    f << key << " " << v << "\n";
+}
+
+// Time launch(variant) for every variant with events on the stream; return the fastest.
+template <class F>
+int autotune(cox_ctx* c, F&& launch, float* ms_out)
+{
+    hipEvent_t e[kMfmaVariants + 1];
+    for (auto& ev : e)
+        if (hipEventCreate(&ev) != hipSuccess) return 0;
+    (void)hipEventRecord(e[0], c->stream);
+    for (int v = 0; v < kMfmaVariants; ++v) {
+        launch(v);
+        (void)hipEventRecord(e[v + 1], c->stream);
+    }
+    (void)hipEventSynchronize(e[kMfmaVariants]);
+    int best = 0;
+    for (int v = 0; v < kMfmaVariants; ++v) {
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e[v], e[v + 1]);
+        ms_out[v] = ms;
+        if (ms < ms_out[best]) best = v;
+    }
+    for (auto& ev : e) (void)hipEventDestroy(ev);
+    (void)hipGetLastError();
+    return best;
+}
+
 // The matrix-core pass serves batches of more than kGroup vectors when X holds
 // allele counts (checked once over the whole matrix).
 bool use_mfma(cox_ctx* c, int B)
@@ -321,7 +391,20 @@ cox_status run_gemvt(cox_ctx* c, GemvtArgs g, int B)
         HIPCHK(launch_quantize(c->r64, c->n, B, c->rmaxp, c->rsump, c->limbs, c->rstride, bpad, c->qscale, c->sumr,
                                c->stream),
                "quantise r");
-        MfmaArgs m{c->x.X, c->x.xt, c->n, c->p, c->x.ldx, c->limbs, c->rstride, bpad, B, c->qscale, c->part_xtr};
+        MfmaArgs m{c->x.X, c->x.xt, c->n, c->p, c->x.ldx, c->limbs, c->rstride, bpad, B, c->qscale, c->part_xtr, 0};
+        const int forced = forced_variant();
+        if (forced >= 0) {
+            c->xtr_variant = forced;
+        } else if (c->xtr_variant < 0) {
+            const std::string key = tune_key(c, "xtr", bpad);
+            c->xtr_variant = tune_cache_lookup(key);
+            if (c->xtr_variant < 0) {
+                c->xtr_variant = autotune(
+                    c, [&](int v) { m.variant = v; (void)launch_mfma_xtr(m, c->stream); }, c->xtr_tune_ms);
+                tune_cache_store(key, c->xtr_variant);
+            }
+        }
+        m.variant = c->xtr_variant;
         HIPCHK(launch_mfma_xtr(m, c->stream), "X' R on matrix cores");
         g.b0 = 0;
         g.nb = B;
@@ -728,7 +811,22 @@ cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_
                                          c->dscale, c->stream),
                        "quantise eta update");
                 MfmaEtaArgs m{c->x.X, c->x.xt, c->n, c->p, c->x.ldx, c->sel, c->nsel, c->dlimbs, c->dstride,
-                              bpad, B, c->dscale, c->eta, c->active};
+                              bpad, B, c->dscale, c->eta, c->active, 0};
+                const int forced = forced_variant();
+                if (forced >= 0) {
+                    c->eta_variant = forced;
+                } else if (c->eta_variant < 0) {
+                    const std::string key = tune_key(c, "eta", bpad);
+                    c->eta_variant = tune_cache_lookup(key);
+                    if (c->eta_variant < 0) {
+                        MfmaEtaArgs t = m;
+                        t.eta = c->w;  // scratch: the update is in place, so tuning writes elsewhere
+                        c->eta_variant = autotune(
+                            c, [&](int v) { t.variant = v; (void)launch_mfma_eta(t, c->stream); }, c->eta_tune_ms);
+                        tune_cache_store(key, c->eta_variant);
+                    }
+                }
+                m.variant = c->eta_variant;
                 HIPCHK(launch_mfma_eta(m, c->stream), "eta update on matrix cores");
                 tmark(c, COX_PHASE_ETA);
             } else if (o.eta_mode == 0) {
@@ -797,6 +895,18 @@ cox_status cox_nll_backward(cox_ctx* c, const double* grad_loss, int32_t B, void
     if (!grad_loss || !grad_eta) return fail(c, COX_ERR_INVALID_ARG, "bad nll_backward arguments");
     if (B != c->fwd_B) return fail(c, COX_ERR_INVALID_ARG, "backward needs a forward with the same B");
     HIPCHK(launch_nll_backward(c->r64, grad_loss, c->n, B, grad_eta, c->fwd_f64, c->stream), "adjoint");
+    return COX_OK;
+}
+
+cox_status cox_mfma_tuning(cox_ctx* c, int32_t* xtr_variant, int32_t* eta_variant, float* xtr_ms, float* eta_ms)
+{
+    STCHK(check_ctx(c));
+    if (xtr_variant) *xtr_variant = c->xtr_variant;
+    if (eta_variant) *eta_variant = c->eta_variant;
+    for (int v = 0; v < kMfmaVariants; ++v) {
+        if (xtr_ms) xtr_ms[v] = c->xtr_tune_ms[v];
+        if (eta_ms) eta_ms[v] = c->eta_tune_ms[v];
+    }
     return COX_OK;
 }
 

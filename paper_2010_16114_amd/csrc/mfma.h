@@ -19,7 +19,10 @@ struct MfmaArgs {
     int B;                  // vectors written (<= bpad)
     const double* qscale;   // [B] quantisation step of each vector
     double* out;            // [B][p] raw sums q_b * sum_i g_ij R_bi
+    int variant;            // pipeline shape: 0 = 128-row stages 3 ahead, 1 = 256-row stages 1 ahead,
+                            // 2 = 128-row stages 4 ahead
 };
+constexpr int kMfmaVariants = 3;
 
 // eta_b(i) += q_b * sum_{u < nsel} g(i, sel[u]) D_b(u), D in three int8 limbs.
 struct MfmaEtaArgs {
@@ -34,6 +37,7 @@ struct MfmaEtaArgs {
     const double* dscale;   // [B]
     double* eta;            // [B][n] FP64, updated in place
     const int32_t* active;  // [B] or null
+    int variant;            // prefetch depth in 64-column steps: 0 = 4, 1 = 2, 2 = 6
 };
 
 int mfma_ntile(int64_t n);

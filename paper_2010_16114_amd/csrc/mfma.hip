@@ -69,21 +69,23 @@ __device__ __forceinline__ v4i load_a(const uint8_t* __restrict__ X, int64_t col
     return v;
 }
 
-template <int XT, int NG>
+template <int XT, int NG, int KS, int PF>
 __global__ __launch_bounds__(kTM, 2) void mfma_xtr_kernel(MfmaArgs a)
 {
+    // KS k-steps of 64 rows per stage; loads run PF stages ahead in a register ring.
+    constexpr int KC = 64 * KS;
     constexpr int NT = kLimbs * NG;  // N tiles, limb-major: tile = limb * NG + b / 16
     constexpr int NCOL = 16 * NT;
-    constexpr int CHUNKS = NCOL * (kKC / 16);  // 16-byte chunks of limb data per stage
+    constexpr int CHUNKS = NCOL * (KC / 16);  // 16-byte chunks of limb data per stage
     constexpr int CPT = (CHUNKS + kTM - 1) / kTM;
-    __shared__ v4i sR[2][kKS * 4 * NCOL];
+    __shared__ v4i sR[2][KS * 4 * NCOL];
 
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int64_t n = a.n, p = a.p, ldx = a.ldx;
     const int64_t jw = (int64_t)blockIdx.x * 256 + wid * (16 * kMT);  // first column of this wavefront
     const uint8_t* __restrict__ X = static_cast<const uint8_t*>(a.X);
     const int8_t* __restrict__ limbs = a.limbs;
-    const int64_t nstage = (n + kKC - 1) / kKC;
+    const int64_t nstage = (n + KC - 1) / KC;
     const int arow = 16 * (lane >> 4);  // k offset of this lane's 16 bytes within a k-step
     const int acol = lane & 15;
 
@@ -93,67 +95,67 @@ __global__ __launch_bounds__(kTM, 2) void mfma_xtr_kernel(MfmaArgs a)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = v4i{0, 0, 0, 0};
 
-    // limb data of one stage: chunk c -> (column col, 16-row group q)
-    auto fetch_r = [&](int64_t k0, v4i* regs) {
+    v4i Ab[PF][kMT][KS];
+    v4i Rb[PF][CPT];
+    auto fetch = [&](int64_t t, v4i (&A)[kMT][KS], v4i (&R)[CPT]) {
+        const int64_t k0 = t * KC;
 #pragma unroll
-        for (int u = 0; u < CPT; ++u) {
-            const int c = threadIdx.x + kTM * u;
-            if (c < CHUNKS) {
-                const int col = c / (kKC / 16), q = c % (kKC / 16);
-                const int limb = col / (16 * NG), b = col % (16 * NG);
-                regs[u] = *reinterpret_cast<const v4i*>(limbs + ((int64_t)limb * a.bpad + b) * a.lstride + k0 + 16 * q);
-            }
-        }
-    };
-    auto store_r = [&](int buf, const v4i* regs) {
-#pragma unroll
-        for (int u = 0; u < CPT; ++u) {
-            const int c = threadIdx.x + kTM * u;
-            if (c < CHUNKS) {
-                const int col = c / (kKC / 16), q = c % (kKC / 16);
-                sR[buf][(q >> 2) * 4 * NCOL + (q & 3) * NCOL + col] = regs[u];
-            }
-        }
-    };
-    auto fetch_a = [&](int64_t k0, v4i (&A)[kMT][kKS]) {
-#pragma unroll
-        for (int ks = 0; ks < kKS; ++ks)
+        for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
             for (int mt = 0; mt < kMT; ++mt)
                 A[mt][ks] = load_a<XT>(X, jw + mt * 16 + acol, p, ldx, k0 + ks * 64 + arow, n);
-    };
-
-    v4i A[kMT][kKS], An[kMT][kKS];
-    v4i Rr[CPT];
-    fetch_a(0, A);
-    fetch_r(0, Rr);
-    store_r(0, Rr);
-    __syncthreads();
-
-    for (int64_t s = 0; s < nstage; ++s) {
-        const int buf = (int)(s & 1);
-        const bool more = s + 1 < nstage;
-        if (more) {
-            fetch_a((s + 1) * kKC, An);
-            fetch_r((s + 1) * kKC, Rr);
-        }
 #pragma unroll
-        for (int ks = 0; ks < kKS; ++ks) {
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const v4i bf = sR[buf][ks * 4 * NCOL + (lane >> 4) * NCOL + nt * 16 + acol];
-#pragma unroll
-                for (int mt = 0; mt < kMT; ++mt)
-                    acc[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt][ks], bf, acc[mt][nt], 0, 0, 0);
+        for (int u = 0; u < CPT; ++u) {
+            const int c = threadIdx.x + kTM * u;
+            if (c < CHUNKS) {
+                const int col = c / (KC / 16), q = c % (KC / 16);
+                const int limb = col / (16 * NG), b = col % (16 * NG);
+                R[u] = *reinterpret_cast<const v4i*>(limbs + ((int64_t)limb * a.bpad + b) * a.lstride + k0 + 16 * q);
             }
         }
-        if (more) store_r(buf ^ 1, Rr);
-        __syncthreads();
-        if (more) {
+    };
+    auto store_r = [&](int buf, const v4i (&R)[CPT]) {
 #pragma unroll
-            for (int ks = 0; ks < kKS; ++ks)
+        for (int u = 0; u < CPT; ++u) {
+            const int c = threadIdx.x + kTM * u;
+            if (c < CHUNKS) {
+                const int col = c / (KC / 16), q = c % (KC / 16);
+                sR[buf][(q >> 2) * 4 * NCOL + (q & 3) * NCOL + col] = R[u];
+            }
+        }
+    };
+
 #pragma unroll
-                for (int mt = 0; mt < kMT; ++mt) A[mt][ks] = An[mt][ks];
+    for (int q = 0; q < PF; ++q)
+        if (q < nstage) fetch(q, Ab[q], Rb[q]);
+    store_r(0, Rb[0]);
+    __syncthreads();
+
+    for (int64_t s0 = 0; s0 < nstage; s0 += PF) {
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int64_t t = s0 + q;
+            if (t < nstage) {
+                v4i A[kMT][KS];
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                    for (int mt = 0; mt < kMT; ++mt) A[mt][ks] = Ab[q][mt][ks];
+                if (t + PF < nstage) fetch(t + PF, Ab[q], Rb[q]);
+                const int buf = (int)(t & 1);
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) {
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) {
+                        const v4i bf = sR[buf][ks * 4 * NCOL + (lane >> 4) * NCOL + nt * 16 + acol];
+#pragma unroll
+                        for (int mt = 0; mt < kMT; ++mt)
+                            acc[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt][ks], bf, acc[mt][nt], 0, 0, 0);
+                    }
+                }
+                if (t + 1 < nstage) store_r(buf ^ 1, Rb[(q + 1) % PF]);
+                __syncthreads();
+            }
         }
     }
 
@@ -181,9 +183,10 @@ __global__ __launch_bounds__(kTM, 2) void mfma_xtr_kernel(MfmaArgs a)
 // byte gathers below hit distinct banks) and each A fragment (16 columns of one
 // subject) is gathered byte by byte.  The D limb tile is staged like R above.
 // Each (subject, b) is owned by one lane, so eta is updated in place.
-template <int XT, int NG>
+template <int XT, int NG, int PF>
 __global__ __launch_bounds__(kTM, 2) void mfma_eta_kernel(MfmaEtaArgs a)
 {
+    // One 64-column k-step per stage; loads run PF stages ahead in a register ring.
     constexpr int NT = kLimbs * NG;
     constexpr int NCOL = 16 * NT;
     constexpr int DCH = 4 * NCOL;  // 16-byte chunks of D per 64-column step
@@ -205,9 +208,9 @@ __global__ __launch_bounds__(kTM, 2) void mfma_eta_kernel(MfmaEtaArgs a)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = v4i{0, 0, 0, 0};
 
-    uint4 gr[GPT];
-    v4i dr[DPT];
-    auto fetch = [&](int c) {
+    uint4 gr[PF][GPT];
+    v4i dr[PF][DPT];
+    auto fetch = [&](int c, uint4 (&g)[GPT], v4i (&dd)[DPT]) {
 #pragma unroll
         for (int k = 0; k < GPT; ++k) {
             const int ch = threadIdx.x + kTM * k;
@@ -218,7 +221,7 @@ __global__ __launch_bounds__(kTM, 2) void mfma_eta_kernel(MfmaEtaArgs a)
                 const v4i t = load_a<XT>(X, a.sel[pos], a.p, ldx, i0 + 16 * rb, n);
                 v = make_uint4((uint32_t)t[0], (uint32_t)t[1], (uint32_t)t[2], (uint32_t)t[3]);
             }
-            gr[k] = v;
+            g[k] = v;
         }
 #pragma unroll
         for (int k = 0; k < DPT; ++k) {
@@ -226,58 +229,65 @@ __global__ __launch_bounds__(kTM, 2) void mfma_eta_kernel(MfmaEtaArgs a)
             if (ch < DCH) {
                 const int col = ch >> 2, kq = ch & 3;
                 const int limb = col / (16 * NG), b = col % (16 * NG);
-                dr[k] = *reinterpret_cast<const v4i*>(a.dlimbs + ((int64_t)limb * a.bpad + b) * a.dstride + c * 64 +
+                dd[k] = *reinterpret_cast<const v4i*>(a.dlimbs + ((int64_t)limb * a.bpad + b) * a.dstride + c * 64 +
                                                       16 * kq);
             }
         }
     };
-    auto store = [&](int buf) {
+    auto store = [&](int buf, const uint4 (&g)[GPT], const v4i (&dd)[DPT]) {
 #pragma unroll
         for (int k = 0; k < GPT; ++k) {
             const int ch = threadIdx.x + kTM * k;
             const int u = ch >> 4, rb = ch & 15;
-            sG[buf][u * 16 + (rb ^ (u >> 4))] = gr[k];
+            sG[buf][u * 16 + (rb ^ (u >> 4))] = g[k];
         }
 #pragma unroll
         for (int k = 0; k < DPT; ++k) {
             const int ch = threadIdx.x + kTM * k;
             if (ch < DCH) {
                 const int col = ch >> 2, kq = ch & 3;
-                sD[buf][kq * NCOL + col] = dr[k];
+                sD[buf][kq * NCOL + col] = dd[k];
             }
         }
     };
 
-    fetch(0);
-    store(0);
+#pragma unroll
+    for (int q = 0; q < PF; ++q)
+        if (q < nchunk) fetch(q, gr[q], dr[q]);
+    store(0, gr[0], dr[0]);
     __syncthreads();
-    for (int c = 0; c < nchunk; ++c) {
-        const int buf = c & 1;
-        const bool more = c + 1 < nchunk;
-        if (more) fetch(c + 1);
-        const uint8_t* g8 = reinterpret_cast<const uint8_t*>(sG[buf]);
-        v4i A[kMT];
+    for (int c0 = 0; c0 < nchunk; c0 += PF) {
 #pragma unroll
-        for (int mt = 0; mt < kMT; ++mt) {
-            const int row = wid * (16 * kMT) + mt * 16 + (lane & 15);
-            uint32_t w[4] = {0, 0, 0, 0};
+        for (int q = 0; q < PF; ++q) {
+            const int c = c0 + q;
+            if (c < nchunk) {
+                if (c + PF < nchunk) fetch(c + PF, gr[q], dr[q]);
+                const int buf = c & 1;
+                const uint8_t* g8 = reinterpret_cast<const uint8_t*>(sG[buf]);
+                v4i A[kMT];
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const int u = 16 * (lane >> 4) + e;
-                const uint32_t byte = g8[u * 256 + 16 * ((row >> 4) ^ (u >> 4)) + (row & 15)];
-                w[e >> 2] |= byte << (8 * (e & 3));
+                for (int mt = 0; mt < kMT; ++mt) {
+                    const int row = wid * (16 * kMT) + mt * 16 + (lane & 15);
+                    uint32_t w[4] = {0, 0, 0, 0};
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) {
+                        const int u = 16 * (lane >> 4) + e;
+                        const uint32_t byte = g8[u * 256 + 16 * ((row >> 4) ^ (u >> 4)) + (row & 15)];
+                        w[e >> 2] |= byte << (8 * (e & 3));
+                    }
+                    A[mt] = v4i{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
+                }
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const v4i bf = sD[buf][(lane >> 4) * NCOL + nt * 16 + (lane & 15)];
+#pragma unroll
+                    for (int mt = 0; mt < kMT; ++mt)
+                        acc[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], bf, acc[mt][nt], 0, 0, 0);
+                }
+                if (c + 1 < nchunk) store(buf ^ 1, gr[(q + 1) % PF], dr[(q + 1) % PF]);
+                __syncthreads();
             }
-            A[mt] = v4i{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
         }
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            const v4i bf = sD[buf][(lane >> 4) * NCOL + nt * 16 + (lane & 15)];
-#pragma unroll
-            for (int mt = 0; mt < kMT; ++mt)
-                acc[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], bf, acc[mt][nt], 0, 0, 0);
-        }
-        if (more) store(buf ^ 1);
-        __syncthreads();
     }
 
 #pragma unroll
@@ -436,7 +446,12 @@ __global__ __launch_bounds__(kT) void geno_check_kernel(const uint8_t* __restric
 template <int XT, int NG>
 hipError_t launch_eta_ng(const MfmaEtaArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL((mfma_eta_kernel<XT, NG>), dim3((unsigned)((a.n + 255) / 256)), dim3(kTM), 0, s, a);
+    const dim3 grid((unsigned)((a.n + 255) / 256));
+    switch (a.variant) {
+    case 1: hipLaunchKernelGGL((mfma_eta_kernel<XT, NG, 2>), grid, dim3(kTM), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((mfma_eta_kernel<XT, NG, 6>), grid, dim3(kTM), 0, s, a); break;
+    default: hipLaunchKernelGGL((mfma_eta_kernel<XT, NG, 4>), grid, dim3(kTM), 0, s, a); break;
+    }
     return hipGetLastError();
 }
 
@@ -454,7 +469,12 @@ hipError_t launch_eta_xt(const MfmaEtaArgs& a, hipStream_t s)
 template <int XT, int NG>
 hipError_t launch_ng(const MfmaArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL((mfma_xtr_kernel<XT, NG>), dim3((unsigned)((a.p + 255) / 256)), dim3(kTM), 0, s, a);
+    const dim3 grid((unsigned)((a.p + 255) / 256));
+    switch (a.variant) {
+    case 1: hipLaunchKernelGGL((mfma_xtr_kernel<XT, NG, 4, 1>), grid, dim3(kTM), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((mfma_xtr_kernel<XT, NG, 2, 4>), grid, dim3(kTM), 0, s, a); break;
+    default: hipLaunchKernelGGL((mfma_xtr_kernel<XT, NG, 2, 3>), grid, dim3(kTM), 0, s, a); break;
+    }
     return hipGetLastError();
 }
 
@@ -503,7 +523,7 @@ hipError_t launch_mfma_eta(const MfmaEtaArgs& a, hipStream_t s)
 
 hipError_t launch_mfma_xtr(const MfmaArgs& a, hipStream_t s)
 {
-    if (a.bpad < 16 || a.bpad > 64 || a.bpad % 16 || a.B > a.bpad || a.lstride % kKC) return hipErrorInvalidValue;
+    if (a.bpad < 16 || a.bpad > 64 || a.bpad % 16 || a.B > a.bpad || a.lstride % 256) return hipErrorInvalidValue;
     return a.xt == XT_FP8 ? launch_xt<XT_FP8>(a, s) : launch_xt<XT_I8>(a, s);
 }
 
