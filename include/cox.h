@@ -29,6 +29,10 @@
  *  - Return value: a cox_status.  No C++ exception or abort crosses the ABI.
  *  - Argument errors are detected before any device work and leave outputs and
  *    the context untouched (COX_ERR_INVALID_ARG).
+ *  - Padding: for the 1-byte types with ldx a multiple of 16, kernels read whole
+ *    16-byte runs, so every column -- the last one included -- must be
+ *    allocated up to ldx bytes (rows n..ldx-1 are read and ignored).  A torch
+ *    tensor of shape (p, ldx) satisfies this.
  *  - Pointers marked "dev" are device memory of the context's GPU; "host" are
  *    host memory.  The caller owns every buffer it passes.  X, col_center and
  *    col_scale are BORROWED: they must stay valid and unchanged until

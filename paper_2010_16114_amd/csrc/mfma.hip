@@ -46,25 +46,25 @@ __device__ __forceinline__ uint32_t counts4(uint32_t w)
         return w;
 }
 
-// 16 rows [row, row + 16) of column col as int8 counts; rows >= n read as 0.
+// 16 rows [row, row + 16) of column col as int8 counts; rows >= n and columns
+// >= p read as 0.  Branch-free: one 16-byte load from a clamped address, then
+// byte masks (row is a multiple of 16 and ldx a multiple of 16, so the load
+// never leaves the column's ldx bytes).
 template <int XT>
 __device__ __forceinline__ v4i load_a(const uint8_t* __restrict__ X, int64_t col, int64_t p, int64_t ldx,
                                       int64_t row, int64_t n)
 {
-    v4i v = {0, 0, 0, 0};
-    if (col >= p || row >= n) return v;
-    const uint8_t* src = X + col * ldx + row;
-    if (row + 16 <= n) {
-        const uint4 u = *reinterpret_cast<const uint4*>(src);
-        v[0] = (int)counts4<XT>(u.x);
-        v[1] = (int)counts4<XT>(u.y);
-        v[2] = (int)counts4<XT>(u.z);
-        v[3] = (int)counts4<XT>(u.w);
-    } else {
-        uint32_t w[4] = {0, 0, 0, 0};
-        for (int e = 0; e < 16 && row + e < n; ++e) w[e >> 2] |= (uint32_t)src[e] << (8 * (e & 3));
+    const bool ok = col < p && row < n;
+    const uint8_t* src = X + (ok ? col * ldx + row : 0);
+    const uint4 u = *reinterpret_cast<const uint4*>(src);
+    const int64_t valid = ok ? n - row : 0;  // bytes of this run that are inside the column
+    v4i v;
+    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
 #pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = (int)counts4<XT>(w[q]);
+    for (int q = 0; q < 4; ++q) {
+        const int64_t keep = valid - 4 * q;  // bytes of dword q to keep
+        const uint32_t mask = keep >= 4 ? 0xFFFFFFFFu : (keep <= 0 ? 0u : (0xFFFFFFFFu >> (8 * (4 - keep))));
+        v[q] = (int)(counts4<XT>(w[q]) & mask);
     }
     return v;
 }
