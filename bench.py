@@ -38,6 +38,42 @@ HBM_PEAK_GBS = 8000.0
 INT8_MFMA_PEAK_TOPS = 5000.0  # dense int8 matrix-core peak of the MI355X
 
 
+def kernel_source_hash(files) -> str:
+    """SHA-256 over the sources of a kernel, to tell whether a stored counter
+    reading still describes the code that runs."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(summary: str, sources) -> float | None:
+    """HBM bytes per launch of a kernel, from a committed counter summary under
+    profiles/ (FETCH_SIZE + WRITE_SIZE per dispatch, each scaled by what the
+    same counter reads for a plain copy of known size), or None when there is
+    none or the kernel's sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", summary)
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if ":" in line and line.strip().startswith(("traffic_bytes_per_launch", "source_sha256")):
+            k, v = line.strip().strip("`").split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_sha256") != kernel_source_hash(sources) or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
+MFMA_SOURCES = ("paper_2010_16114_amd/csrc/mfma.hip", "paper_2010_16114_amd/csrc/mfma.h")
+GEMVT_SOURCES = ("paper_2010_16114_amd/csrc/gemvt.hip", "paper_2010_16114_amd/csrc/internal.h")
+
+
 def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
@@ -82,15 +118,16 @@ def bench_gauss_fp32(args):
     xtr_ms, xtr_n = cox.timing_read("xtr")
     risk_ms, risk_n = cox.timing_read("risk")
     eta_ms, eta_n = cox.timing_read("eta")
+    xk_ms, xk_n = cox.timing_read("xtr_kernel")
     cox.timing(False)
     elapsed = t1 - t0
     nnz = int((beta != 0).sum().item())
     log(f"{args.steps} steps in {elapsed:.3f} s; objective {obj[0]:.10g}; nnz {nnz}")
 
-    # Algorithmic bytes of one X~' r launch (B = 1): X once, r once, and the FP64
-    # iterate read and written with its change coefficient written.
-    xtr_bytes = n * p * 4 + n * 4 + p * 8 * 3
-    xtr_avg_s = xtr_ms / max(xtr_n, 1) / 1e3
+    # Algorithmic bytes of one launch of the column-sum kernel (B = 1): X once,
+    # r once, one FP64 sum per column written.
+    xtr_bytes = n * p * 4 + n * 4 + p * 8
+    xtr_avg_s = xk_ms / max(xk_n, 1) / 1e3
     achieved = xtr_bytes / xtr_avg_s / 1e9
     steps_per_s = args.steps / elapsed
     res = {
@@ -112,9 +149,11 @@ def bench_gauss_fp32(args):
                    "eta": "active-set FP64 accumulator"},
         "phases_ms_per_step": {"xtr_prox": xtr_ms / max(xtr_n, 1), "risk": risk_ms / max(risk_n, 1),
                                "eta_update": eta_ms / max(eta_n, 1)},
-        "roofline": {"bound": "hbm", "kernel": "gemvt_kernel (X~' r + prox)", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": "gemvt_sums_kernel (X~' r column sums)", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "algorithmic_bytes_per_launch": xtr_bytes},
+                     "traffic": stored_traffic(f"gemvt_sums_kernel_gauss_fp32_{n}x{p}_traffic.md", GEMVT_SOURCES),
+                     "algorithmic_bytes_per_launch": xtr_bytes, "kernel_ms": 1e3 * xtr_avg_s,
+                     "launches_timed": xk_n},
         "objective": float(obj[0]),
         "nnz": nnz,
     }
@@ -174,15 +213,17 @@ def bench_geno_batched(args):
     xtr_ms, xtr_n = cox.timing_read("xtr")
     risk_ms, risk_n = cox.timing_read("risk")
     eta_ms, eta_n = cox.timing_read("eta")
+    xk_ms, xk_n = cox.timing_read("xtr_kernel")
+    ek_ms, ek_n = cox.timing_read("eta_kernel")
     cox.timing(False)
     elapsed = t1 - t0
     nnz = (beta != 0).sum(dim=1).cpu().numpy()
     log(f"{args.steps} steps x {B} lambdas in {elapsed:.3f} s; nnz per lambda {nnz.min()}..{nnz.max()}")
     bpad = (B + 15) // 16 * 16
-    # Algorithmic bytes of one gradient pass: X once, the residual limbs once,
-    # the raw column sums written once.
+    # Algorithmic bytes of one launch of the matrix-core X~' R kernel: X once,
+    # the residual limbs once, the raw column sums written once.
     xtr_bytes = n * p + 3 * bpad * n + B * p * 8
-    xtr_avg = xtr_ms / max(xtr_n, 1) / 1e3
+    xtr_avg = xk_ms / max(xk_n, 1) / 1e3
     achieved = xtr_bytes / xtr_avg / 1e9
     tops = 2.0 * n * p * 3 * bpad / xtr_avg / 1e12
     res = {
@@ -206,9 +247,11 @@ def bench_geno_batched(args):
         "iters_per_s": args.steps / elapsed,
         "phases_ms_per_step": {"xtr_prox": xtr_ms / max(xtr_n, 1), "risk": risk_ms / max(risk_n, 1),
                                "eta_update": eta_ms / max(eta_n, 1)},
-        "roofline": {"bound": "hbm", "kernel": "mfma_xtr_kernel (X~' R, B lambdas) + epilogue",
+        "kernels_ms_per_launch": {"mfma_xtr_kernel": xk_ms / max(xk_n, 1), "mfma_eta_kernel": ek_ms / max(ek_n, 1)},
+        "roofline": {"bound": "hbm", "kernel": "mfma_xtr_kernel (X~' R for B lambdas)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "algorithmic_bytes_per_launch": xtr_bytes,
+                     "traffic": stored_traffic(f"mfma_xtr_kernel_geno_fp8_{n}x{p}_b{B}_traffic.md", MFMA_SOURCES),
+                     "algorithmic_bytes_per_launch": xtr_bytes, "kernel_ms": 1e3 * xtr_avg, "launches_timed": xk_n,
                      "mfma_tops": tops, "mfma_frac_int8": tops / INT8_MFMA_PEAK_TOPS},
         "nnz_range": [int(nnz.min()), int(nnz.max())],
         "autotune": cox.mfma_tuning(),

@@ -182,20 +182,35 @@ cox_status cox_nll_backward(cox_ctx *ctx, const double *grad_loss, int32_t B, vo
 
 /* Measurement: per-phase GPU time, taken with HIP events recorded on the
  * context's stream around each phase's launches (so it can run inside a timed
- * region).  Phases: COX_PHASE_XTR (the X~' r pass with its fused proximal
- * epilogue), COX_PHASE_RISK (the risk-set kernel), COX_PHASE_ETA (the eta
- * update or dense X~ beta pass).
+ * region).  Phases: COX_PHASE_XTR (the whole X~' r pass: residual quantisation
+ * if any, the column sums, the fused proximal epilogue), COX_PHASE_RISK (the
+ * risk-set kernels), COX_PHASE_ETA (the whole eta update or dense X~ beta
+ * pass), COX_PHASE_XTR_KERNEL (each launch of the column-sum kernel alone:
+ * the matrix-core X~' R kernel, or one vector X~' r launch per group of up to
+ * 8 vectors), COX_PHASE_ETA_KERNEL (each launch of the matrix-core eta kernel
+ * alone).
  * cox_timing_enable(ctx, 1) starts recording and clears the totals; 0 stops.
  * cox_timing_read returns the summed milliseconds and the number of timed
  * launches of a phase since the last enable.  Synchronises. */
-typedef enum { COX_PHASE_XTR = 0, COX_PHASE_RISK = 1, COX_PHASE_ETA = 2 } cox_phase;
+typedef enum {
+    COX_PHASE_XTR = 0,
+    COX_PHASE_RISK = 1,
+    COX_PHASE_ETA = 2,
+    COX_PHASE_XTR_KERNEL = 3,
+    COX_PHASE_ETA_KERNEL = 4
+} cox_phase;
 
 /* The batched matrix-core passes (X~' R and the eta update, used when X holds
- * allele counts and B > 8) come in 3 pipeline shapes each.  The first batched
- * call times every shape once on the live data and keeps the fastest (the
- * environment variable COXHIP_TUNE_CACHE names a file that caches the choice,
- * COXHIP_MFMA_VARIANT forces one).  This reports the choices (-1: not yet
- * tuned) and the tuning times in milliseconds (host [3] each, nullable). */
+ * allele counts and B > 8) come in several pipeline shapes: COX_MFMA_VARIANTS
+ * for X~' R, COX_MFMA_ETA_VARIANTS for the eta update.  The first batched call
+ * times every shape once on the live data and keeps the fastest (the
+ * environment variable COXHIP_TUNE_CACHE names a file that caches the choice;
+ * COXHIP_MFMA_VARIANT and COXHIP_ETA_VARIANT force one).  This reports the
+ * choices (-1: not yet tuned) and the tuning times in milliseconds (host
+ * [COX_MFMA_VARIANTS] each, nullable; entries past a pass's shape count and
+ * entries of a pass that was not timed are 0). */
+#define COX_MFMA_VARIANTS 5
+#define COX_MFMA_ETA_VARIANTS 3
 cox_status cox_mfma_tuning(cox_ctx *ctx, int32_t *xtr_variant, int32_t *eta_variant, float *xtr_ms, float *eta_ms);
 cox_status cox_timing_enable(cox_ctx *ctx, int32_t enable);
 cox_status cox_timing_read(cox_ctx *ctx, int32_t phase, double *total_ms, int64_t *count);

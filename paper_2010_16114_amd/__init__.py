@@ -22,6 +22,8 @@ LIB_PATH = os.path.join(_HERE, "libcoxhip.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "cox.h")
 
 X_F32, X_FP8_E4M3, X_INT8 = 0, 1, 2
+MFMA_VARIANTS = 5  # COX_MFMA_VARIANTS: pipeline shapes of the X~' R pass (and the tuning arrays' length)
+ETA_VARIANTS = 3  # COX_MFMA_ETA_VARIANTS: pipeline shapes of the eta update
 OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NUMERIC, ERR_NOT_CONVERGED, ERR_UNSUPPORTED = range(7)
 
 
@@ -220,13 +222,13 @@ class Cox:
         self.last_forward_key = self.forward_key(eta)
         return loss
 
-    PHASES = {"xtr": 0, "risk": 1, "eta": 2}
+    PHASES = {"xtr": 0, "risk": 1, "eta": 2, "xtr_kernel": 3, "eta_kernel": 4}
 
     def mfma_tuning(self):
         """Pipeline shapes chosen by the autotuner and their tuning times (ms)."""
         xv, ev = ctypes.c_int32(), ctypes.c_int32()
-        xm = np.zeros(3, np.float32)
-        em = np.zeros(3, np.float32)
+        xm = np.zeros(MFMA_VARIANTS, np.float32)
+        em = np.zeros(MFMA_VARIANTS, np.float32)
         self._check(lib().cox_mfma_tuning(self._h, ctypes.byref(xv), ctypes.byref(ev), _np_ptr(xm), _np_ptr(em)),
                     "cox_mfma_tuning")
         return {"xtr_variant": xv.value, "eta_variant": ev.value, "xtr_ms": xm.tolist(), "eta_ms": em.tolist()}

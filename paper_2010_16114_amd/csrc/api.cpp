@@ -26,6 +26,11 @@
 
 using namespace cox;
 
+constexpr int kPhases = 5;  // cox_phase values
+
+static_assert(kMfmaVariants == COX_MFMA_VARIANTS && kMfmaEtaVariants == COX_MFMA_ETA_VARIANTS,
+              "pipeline shape counts differ from the header");
+
 namespace {
 
 constexpr int kMaxBatch = 64;
@@ -66,7 +71,7 @@ struct cox_ctx {
     int64_t dstride = 0;
     double *dscale = nullptr, *dmaxp = nullptr;
     int xtr_variant = -1, eta_variant = -1;  // chosen pipeline shapes (-1: not tuned yet)
-    float xtr_tune_ms[kMfmaVariants] = {0, 0, 0}, eta_tune_ms[kMfmaVariants] = {0, 0, 0};
+    float xtr_tune_ms[kMfmaVariants] = {}, eta_tune_ms[kMfmaVariants] = {};
     int geno_state = -1;         // -1 unchecked, 0 counts 0/1/2 only, 1 other values
     int nsplit = 1;
     int64_t split_rows = 0;
@@ -80,9 +85,9 @@ struct cox_ctx {
     int64_t n_events = 0;
     // measurement: event pairs recorded around each phase while timing is on
     bool timing = false;
-    std::vector<hipEvent_t> tev[3];
-    double tms[3] = {0, 0, 0};
-    int64_t tcount[3] = {0, 0, 0};
+    std::vector<hipEvent_t> tev[kPhases];
+    double tms[kPhases] = {};
+    int64_t tcount[kPhases] = {};
 };
 
 namespace {
@@ -133,7 +138,7 @@ bool dalloc(cox_ctx* c, T** out, size_t count)
 
 void timing_clear(cox_ctx* c)
 {
-    for (int ph = 0; ph < 3; ++ph) {
+    for (int ph = 0; ph < kPhases; ++ph) {
         for (hipEvent_t e : c->tev[ph]) (void)hipEventDestroy(e);
         c->tev[ph].clear();
         c->tms[ph] = 0;
@@ -237,15 +242,16 @@ cox_status dense_eta(cox_ctx* c, const double* coef, int B, const double* shift)
 }
 
 // ---- autotuner of the matrix-core pipeline shapes
-// A shape is forced by COXHIP_MFMA_VARIANT, read from the cache file named by
-// COXHIP_TUNE_CACHE (lines "key variant"), or chosen by timing every shape once
-// on the live data and appended to that file.
-int forced_variant()
+// A shape is forced by COXHIP_MFMA_VARIANT (the X~' R pass) or COXHIP_ETA_VARIANT
+// (the eta update), read from the cache file named by COXHIP_TUNE_CACHE (lines
+// "key variant"), or chosen by timing every shape once on the live data and
+// appended to that file.
+int forced_variant(const char* var, int count)
 {
-    const char* v = std::getenv("COXHIP_MFMA_VARIANT");
+    const char* v = std::getenv(var);
     if (!v || !*v) return -1;
     const int k = std::atoi(v);
-    return (k >= 0 && k < kMfmaVariants) ? k : -1;
+    return (k >= 0 && k < count) ? k : -1;
 }
 
 std::string tune_key(const cox_ctx* c, const char* kernel, int bpad)
@@ -255,7 +261,7 @@ std::string tune_key(const cox_ctx* c, const char* kernel, int bpad)
     return os.str();
 }
 
-int tune_cache_lookup(const std::string& key)
+int tune_cache_lookup(const std::string& key, int count)
 {
     const char* path = std::getenv("COXHIP_TUNE_CACHE");
     if (!path) return -1;
@@ -264,7 +270,7 @@ int tune_cache_lookup(const std::string& key)
     int v;
     int found = -1;
     while (f >> k >> v)
-        if (k == key && v >= 0 && v < kMfmaVariants) found = v;
+        if (k == key && v >= 0 && v < count) found = v;
     return found;
 }
 
@@ -276,21 +282,22 @@ void tune_cache_store(const std::string& key, int v)
     f << key << " " << v << "\n";
 }
 
-// Time launch(variant) for every variant with events on the stream; return the fastest.
+// Time launch(variant) for each of count variants with events on the stream;
+// return the fastest.
 template <class F>
-int autotune(cox_ctx* c, F&& launch, float* ms_out)
+int autotune(cox_ctx* c, int count, F&& launch, float* ms_out)
 {
     hipEvent_t e[kMfmaVariants + 1];
     for (auto& ev : e)
         if (hipEventCreate(&ev) != hipSuccess) return 0;
     (void)hipEventRecord(e[0], c->stream);
-    for (int v = 0; v < kMfmaVariants; ++v) {
+    for (int v = 0; v < count; ++v) {
         launch(v);
         (void)hipEventRecord(e[v + 1], c->stream);
     }
-    (void)hipEventSynchronize(e[kMfmaVariants]);
+    (void)hipEventSynchronize(e[count]);
     int best = 0;
-    for (int v = 0; v < kMfmaVariants; ++v) {
+    for (int v = 0; v < count; ++v) {
         float ms = 0;
         (void)hipEventElapsedTime(&ms, e[v], e[v + 1]);
         ms_out[v] = ms;
@@ -392,20 +399,23 @@ cox_status run_gemvt(cox_ctx* c, GemvtArgs g, int B)
                                c->stream),
                "quantise r");
         MfmaArgs m{c->x.X, c->x.xt, c->n, c->p, c->x.ldx, c->limbs, c->rstride, bpad, B, c->qscale, c->part_xtr, 0};
-        const int forced = forced_variant();
+        const int forced = forced_variant("COXHIP_MFMA_VARIANT", kMfmaVariants);
         if (forced >= 0) {
             c->xtr_variant = forced;
         } else if (c->xtr_variant < 0) {
             const std::string key = tune_key(c, "xtr", bpad);
-            c->xtr_variant = tune_cache_lookup(key);
+            c->xtr_variant = tune_cache_lookup(key, kMfmaVariants);
             if (c->xtr_variant < 0) {
                 c->xtr_variant = autotune(
-                    c, [&](int v) { m.variant = v; (void)launch_mfma_xtr(m, c->stream); }, c->xtr_tune_ms);
+                    c, kMfmaVariants, [&](int v) { m.variant = v; (void)launch_mfma_xtr(m, c->stream); },
+                    c->xtr_tune_ms);
                 tune_cache_store(key, c->xtr_variant);
             }
         }
         m.variant = c->xtr_variant;
+        tmark(c, COX_PHASE_XTR_KERNEL);
         HIPCHK(launch_mfma_xtr(m, c->stream), "X' R on matrix cores");
+        tmark(c, COX_PHASE_XTR_KERNEL);
         g.b0 = 0;
         g.nb = B;
         g.nsplit = 1;
@@ -419,7 +429,10 @@ cox_status run_gemvt(cox_ctx* c, GemvtArgs g, int B)
         g.b0 = b0;
         g.nb = std::min(kGroup, B - b0);
         g.first_group = b0 == 0;
-        HIPCHK(launch_gemvt(g, c->stream), "X' r");
+        tmark(c, COX_PHASE_XTR_KERNEL);
+        HIPCHK(launch_gemvt_sums(g, c->stream), "X' r");
+        tmark(c, COX_PHASE_XTR_KERNEL);
+        HIPCHK(launch_gemvt_epilogue(g, c->stream), "X' r epilogue");
     }
     tmark(c, COX_PHASE_XTR);
     return COX_OK;
@@ -812,22 +825,25 @@ cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_
                        "quantise eta update");
                 MfmaEtaArgs m{c->x.X, c->x.xt, c->n, c->p, c->x.ldx, c->sel, c->nsel, c->dlimbs, c->dstride,
                               bpad, B, c->dscale, c->eta, c->active, 0};
-                const int forced = forced_variant();
+                const int forced = forced_variant("COXHIP_ETA_VARIANT", kMfmaEtaVariants);
                 if (forced >= 0) {
                     c->eta_variant = forced;
                 } else if (c->eta_variant < 0) {
                     const std::string key = tune_key(c, "eta", bpad);
-                    c->eta_variant = tune_cache_lookup(key);
+                    c->eta_variant = tune_cache_lookup(key, kMfmaEtaVariants);
                     if (c->eta_variant < 0) {
                         MfmaEtaArgs t = m;
                         t.eta = c->w;  // scratch: the update is in place, so tuning writes elsewhere
                         c->eta_variant = autotune(
-                            c, [&](int v) { t.variant = v; (void)launch_mfma_eta(t, c->stream); }, c->eta_tune_ms);
+                            c, kMfmaEtaVariants, [&](int v) { t.variant = v; (void)launch_mfma_eta(t, c->stream); },
+                            c->eta_tune_ms);
                         tune_cache_store(key, c->eta_variant);
                     }
                 }
                 m.variant = c->eta_variant;
+                tmark(c, COX_PHASE_ETA_KERNEL);
                 HIPCHK(launch_mfma_eta(m, c->stream), "eta update on matrix cores");
+                tmark(c, COX_PHASE_ETA_KERNEL);
                 tmark(c, COX_PHASE_ETA);
             } else if (o.eta_mode == 0) {
                 tmark(c, COX_PHASE_ETA);
@@ -922,7 +938,7 @@ cox_status cox_timing_enable(cox_ctx* c, int32_t enable)
 cox_status cox_timing_read(cox_ctx* c, int32_t phase, double* total_ms, int64_t* count)
 {
     STCHK(check_ctx(c));
-    if (phase < 0 || phase > 2 || !total_ms) return fail(c, COX_ERR_INVALID_ARG, "bad timing_read arguments");
+    if (phase < 0 || phase >= kPhases || !total_ms) return fail(c, COX_ERR_INVALID_ARG, "bad timing_read arguments");
     STCHK(sync(c));
     auto& ev = c->tev[phase];
     for (size_t q = 0; q + 1 < ev.size(); q += 2) {

@@ -317,18 +317,21 @@ hipError_t launch_gemvt_epilogue(const GemvtArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_gemvt(const GemvtArgs& a, hipStream_t s)
+hipError_t launch_gemvt_sums(const GemvtArgs& a, hipStream_t s)
 {
     if (a.nb < 1 || a.nb > 8 || a.nsplit < 1 || a.split_rows % kSplitRows != 0) return hipErrorInvalidValue;
-    hipError_t e;
     switch (a.x.xt) {
-    case XT_F32: e = launch_x<XT_F32>(a, s); break;
-    case XT_FP8: e = launch_x<XT_FP8>(a, s); break;
-    default: e = launch_x<XT_I8>(a, s); break;
+    case XT_F32: return launch_x<XT_F32>(a, s);
+    case XT_FP8: return launch_x<XT_FP8>(a, s);
+    default: return launch_x<XT_I8>(a, s);
     }
+}
+
+hipError_t launch_gemvt(const GemvtArgs& a, hipStream_t s)
+{
+    const hipError_t e = launch_gemvt_sums(a, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(gemvt_epilogue_kernel, dim3((unsigned)((a.x.p + 255) / 256)), dim3(256), 0, s, a);
-    return hipGetLastError();
+    return launch_gemvt_epilogue(a, s);
 }
 
 }  // namespace cox

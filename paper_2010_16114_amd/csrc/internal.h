@@ -120,7 +120,8 @@ struct GemvtArgs {
 
 // Launchers (return hipError_t of the launch).
 hipError_t launch_risk(const RiskArgs& a, hipStream_t s);
-hipError_t launch_gemvt(const GemvtArgs& a, hipStream_t s);
+hipError_t launch_gemvt(const GemvtArgs& a, hipStream_t s);       // sums, then epilogue
+hipError_t launch_gemvt_sums(const GemvtArgs& a, hipStream_t s);  // the row-split column sums alone
 // the epilogue alone, on column sums already in a.part (nb may exceed 8)
 hipError_t launch_gemvt_epilogue(const GemvtArgs& a, hipStream_t s);
 // eta partials: part[cg][b][i] for b in [b0, b0+nb) from the compacted change list

@@ -19,10 +19,12 @@ struct MfmaArgs {
     int B;                  // vectors written (<= bpad)
     const double* qscale;   // [B] quantisation step of each vector
     double* out;            // [B][p] raw sums q_b * sum_i g_ij R_bi
-    int variant;            // pipeline shape: 0 = 128-row stages 3 ahead, 1 = 256-row stages 1 ahead,
-                            // 2 = 128-row stages 4 ahead
+    int variant;            // pipeline shape (waves x M tiles per wave, subjects per stage, stages ahead):
+                            // 0 = 4x3, 64, 10; 1 = 4x3, 128, 4; 2 = 4x2, 128, 6; 3 = 4x2, 64, 12;
+                            // 4 = 4x3, 64, 8
 };
-constexpr int kMfmaVariants = 3;
+constexpr int kMfmaVariants = 5;     // shapes of the X~' R pass
+constexpr int kMfmaEtaVariants = 3;  // shapes of the eta update
 
 // eta_b(i) += q_b * sum_{u < nsel} g(i, sel[u]) D_b(u), D in three int8 limbs.
 struct MfmaEtaArgs {
@@ -37,7 +39,7 @@ struct MfmaEtaArgs {
     const double* dscale;   // [B]
     double* eta;            // [B][n] FP64, updated in place
     const int32_t* active;  // [B] or null
-    int variant;            // prefetch depth in 64-column steps: 0 = 4, 1 = 2, 2 = 6
+    int variant;            // stages (of 64 columns) ahead: 0 = 4, 1 = 3, 2 = 2
 };
 
 int mfma_ntile(int64_t n);

@@ -12,13 +12,14 @@
 // largest entry.  The raw sums q_b * sum_i g_ij R_bi go to the same epilogue
 // as the vector path (centring with sum_i q_b R_bi, proximal step).
 //
-// Tiling: a workgroup of 8 wavefronts (two per SIMD) owns 256 SNP columns (2 M
-// tiles of 16 per wavefront) and all 3 * B limb columns (N tiles of 16), and walks K = n in
-// stages of 256 rows.  X is read once per pass for all B vectors.  A fragments
-// (16 rows of one column per lane, one 16-byte load) stream from global memory
-// one stage ahead; the stage's limb tile (3 * B columns x 256 rows) is staged in
-// LDS, double buffered, laid out so that each MFMA B fragment is one 16-byte
-// LDS read per lane, contiguous across lanes.
+// Tiling: a workgroup of WAVES wavefronts owns 16 * MT * WAVES SNP columns (MT
+// M tiles of 16 per wavefront) and all 3 * B limb columns (N tiles of 16), and
+// walks K = n in stages of 64 * KS subjects.  X is read once per pass for all B
+// vectors.  A fragments (16 subjects of one column per lane, one 16-byte load)
+// stay in registers; the stage's limb tile is staged in LDS.  Memory latency is
+// hidden by a ring of PF stages of loads in flight per wavefront.  Several
+// (WAVES, MT, KS, PF) shapes are compiled; the host times them on the live data
+// and keeps the fastest.
 #include "device_common.h"
 #include "mfma.h"
 
@@ -28,10 +29,6 @@ namespace {
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr int kT = 256;
-constexpr int kTM = 512;         // matrix-core kernels: 8 wavefronts, two per SIMD
-constexpr int kMT = 2;           // M tiles (16 rows each) per wavefront: 8 x 2 x 16 = 256
-constexpr int kKS = 4;           // MFMA k-steps (64 rows each) per stage
-constexpr int kKC = 64 * kKS;    // rows per stage
 constexpr int kLimbs = 3;
 constexpr int kQBits = 22;       // |R| <= 2^22 keeps the top limb within int8
 
@@ -46,122 +43,143 @@ __device__ __forceinline__ uint32_t counts4(uint32_t w)
         return w;
 }
 
-// 16 rows [row, row + 16) of column col as int8 counts; rows >= n and columns
-// >= p read as 0.  Branch-free: one 16-byte load from a clamped address, then
-// byte masks (row is a multiple of 16 and ldx a multiple of 16, so the load
-// never leaves the column's ldx bytes).
-template <int XT>
-__device__ __forceinline__ v4i load_a(const uint8_t* __restrict__ X, int64_t col, int64_t p, int64_t ldx,
-                                      int64_t row, int64_t n)
+// The 16 bytes of column col from row row (row and ldx are multiples of 16, so
+// the load never leaves the column's ldx bytes).  A run outside the matrix
+// loads from X itself; decode_a masks it away.  The load and the decode are
+// separate so that a prefetched run is only waited for where it is used.
+__device__ __forceinline__ v4i load_raw(const uint8_t* __restrict__ X, int64_t col, int64_t p, int64_t ldx,
+                                        int64_t row, int64_t n)
 {
     const bool ok = col < p && row < n;
-    const uint8_t* src = X + (ok ? col * ldx + row : 0);
-    const uint4 u = *reinterpret_cast<const uint4*>(src);
-    const int64_t valid = ok ? n - row : 0;  // bytes of this run that are inside the column
+    return *reinterpret_cast<const v4i*>(X + (ok ? col * ldx + row : 0));
+}
+
+// int8 counts of a raw run of which the first `valid` bytes (0..16) lie inside
+// the matrix; the others read as 0.
+template <int XT>
+__device__ __forceinline__ v4i decode_a(v4i raw, int valid)
+{
     v4i v;
-    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const int64_t keep = valid - 4 * q;  // bytes of dword q to keep
+        const int keep = valid - 4 * q;  // bytes of dword q to keep
         const uint32_t mask = keep >= 4 ? 0xFFFFFFFFu : (keep <= 0 ? 0u : (0xFFFFFFFFu >> (8 * (4 - keep))));
-        v[q] = (int)(counts4<XT>(w[q]) & mask);
+        v[q] = (int)(counts4<XT>((uint32_t)raw[q]) & mask);
     }
     return v;
 }
 
-template <int XT, int NG, int KS, int PF>
-__global__ __launch_bounds__(kTM, 2) void mfma_xtr_kernel(MfmaArgs a)
+__device__ __forceinline__ int clamp16(int64_t x) { return (int)min(max(x, (int64_t)0), (int64_t)16); }
+
+// Software pipeline shared by both matrix-core kernels.  Every global load of a
+// stage (the HBM stream and the small L2-resident operand alike) is issued PF
+// stages before the stage runs, into ring slot t mod PF, and the ring is
+// consumed in issue order.  Vector-memory loads complete in order, so a wait
+// for the oldest slot never waits for a younger one: PF - 1 stages stay in
+// flight.  The loop body has no branches: stages past the end load clamped,
+// masked (all-zero) tiles.
+
+template <int XT, int NG, int WAVES, int MT, int KS, int PF>
+__global__ __launch_bounds__(64 * WAVES, WAVES / 4) void mfma_xtr_kernel(MfmaArgs a)
 {
-    // KS k-steps of 64 rows per stage; loads run PF stages ahead in a register ring.
+    // WAVES wavefronts of MT M tiles (16 SNP columns each); stages of KS k-steps
+    // of 64 subjects.  Stage t's limb tile goes to LDS buffer t & 1 one stage
+    // early, laid out so that an MFMA B fragment is one 16-byte read per lane,
+    // contiguous across lanes.
+    static_assert(PF >= 2, "the ring needs two slots");
+    constexpr int TH = 64 * WAVES;
+    constexpr int WCOLS = 16 * MT * WAVES;  // SNP columns per workgroup
     constexpr int KC = 64 * KS;
     constexpr int NT = kLimbs * NG;  // N tiles, limb-major: tile = limb * NG + b / 16
     constexpr int NCOL = 16 * NT;
-    constexpr int CHUNKS = NCOL * (KC / 16);  // 16-byte chunks of limb data per stage
-    constexpr int CPT = (CHUNKS + kTM - 1) / kTM;
-    __shared__ v4i sR[2][KS * 4 * NCOL];
+    constexpr int QC = KC / 16;             // 16-byte row chunks per limb column per stage
+    constexpr int CHUNKS = NCOL * QC;       // 16-byte chunks of limb data per stage
+    constexpr int CPT = (CHUNKS + TH - 1) / TH;
+    __shared__ v4i sR[2][CHUNKS];           // [q = 4 ks + lane / 16][limb column]
 
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int64_t n = a.n, p = a.p, ldx = a.ldx;
-    const int64_t jw = (int64_t)blockIdx.x * 256 + wid * (16 * kMT);  // first column of this wavefront
+    const int64_t jw = (int64_t)blockIdx.x * WCOLS + wid * (16 * MT);  // first column of this wavefront
     const uint8_t* __restrict__ X = static_cast<const uint8_t*>(a.X);
     const int8_t* __restrict__ limbs = a.limbs;
     const int64_t nstage = (n + KC - 1) / KC;
+    const int64_t nloop = (nstage + PF - 1) / PF * PF;
     const int arow = 16 * (lane >> 4);  // k offset of this lane's 16 bytes within a k-step
     const int acol = lane & 15;
 
-    v4i acc[kMT][NT];
+    // this thread's limb chunks (a chunk index past the end repeats a valid one)
+    const int8_t* rsrc[CPT];
+    int rdst[CPT];
 #pragma unroll
-    for (int mt = 0; mt < kMT; ++mt)
+    for (int u = 0; u < CPT; ++u) {
+        const int c = (threadIdx.x + TH * u) % CHUNKS;
+        const int col = c / QC, q = c % QC;
+        const int limb = col / (16 * NG), b = col % (16 * NG);
+        rsrc[u] = limbs + ((int64_t)limb * a.bpad + b) * a.lstride + 16 * q;
+        rdst[u] = q * NCOL + col;
+    }
+
+    // rows of this lane's runs left in the matrix, before the stage offset (columns >= p: none)
+    int64_t nleft[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) nleft[mt] = jw + mt * 16 + acol < p ? n - arow : 0;
+
+    v4i acc[MT][NT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = v4i{0, 0, 0, 0};
 
-    v4i Ab[PF][kMT][KS];
+    v4i Ab[PF][MT][KS];  // raw runs
     v4i Rb[PF][CPT];
-    auto fetch = [&](int64_t t, v4i (&A)[kMT][KS], v4i (&R)[CPT]) {
-        const int64_t k0 = t * KC;
+    auto fetch = [&](int64_t t, v4i (&A)[MT][KS], v4i (&R)[CPT]) {
+        const int64_t k0 = t * KC;  // rows >= n (stages past the end) read as 0
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-            for (int mt = 0; mt < kMT; ++mt)
-                A[mt][ks] = load_a<XT>(X, jw + mt * 16 + acol, p, ldx, k0 + ks * 64 + arow, n);
+            for (int mt = 0; mt < MT; ++mt)
+                A[mt][ks] = load_raw(X, jw + mt * 16 + acol, p, ldx, k0 + ks * 64 + arow, n);
+        const int64_t kr = min(t, nstage - 1) * KC;
 #pragma unroll
-        for (int u = 0; u < CPT; ++u) {
-            const int c = threadIdx.x + kTM * u;
-            if (c < CHUNKS) {
-                const int col = c / (KC / 16), q = c % (KC / 16);
-                const int limb = col / (16 * NG), b = col % (16 * NG);
-                R[u] = *reinterpret_cast<const v4i*>(limbs + ((int64_t)limb * a.bpad + b) * a.lstride + k0 + 16 * q);
-            }
-        }
+        for (int u = 0; u < CPT; ++u) R[u] = *reinterpret_cast<const v4i*>(rsrc[u] + kr);
     };
     auto store_r = [&](int buf, const v4i (&R)[CPT]) {
 #pragma unroll
-        for (int u = 0; u < CPT; ++u) {
-            const int c = threadIdx.x + kTM * u;
-            if (c < CHUNKS) {
-                const int col = c / (KC / 16), q = c % (KC / 16);
-                sR[buf][(q >> 2) * 4 * NCOL + (q & 3) * NCOL + col] = R[u];
-            }
-        }
+        for (int u = 0; u < CPT; ++u) sR[buf][rdst[u]] = R[u];
     };
 
 #pragma unroll
-    for (int q = 0; q < PF; ++q)
-        if (q < nstage) fetch(q, Ab[q], Rb[q]);
+    for (int q = 0; q < PF; ++q) fetch(q, Ab[q], Rb[q]);
     store_r(0, Rb[0]);
     __syncthreads();
 
-    for (int64_t s0 = 0; s0 < nstage; s0 += PF) {
+    for (int64_t s0 = 0; s0 < nloop; s0 += PF) {
 #pragma unroll
         for (int q = 0; q < PF; ++q) {
             const int64_t t = s0 + q;
-            if (t < nstage) {
-                v4i A[kMT][KS];
+            const int buf = (int)(t & 1);
 #pragma unroll
-                for (int ks = 0; ks < KS; ++ks)
+            for (int ks = 0; ks < KS; ++ks) {
+                v4i A[MT];
 #pragma unroll
-                    for (int mt = 0; mt < kMT; ++mt) A[mt][ks] = Ab[q][mt][ks];
-                if (t + PF < nstage) fetch(t + PF, Ab[q], Rb[q]);
-                const int buf = (int)(t & 1);
+                for (int mt = 0; mt < MT; ++mt) A[mt] = decode_a<XT>(Ab[q][mt][ks], clamp16(nleft[mt] - t * KC - ks * 64));
 #pragma unroll
-                for (int ks = 0; ks < KS; ++ks) {
+                for (int nt = 0; nt < NT; ++nt) {
+                    const v4i bf = sR[buf][(4 * ks + (lane >> 4)) * NCOL + nt * 16 + acol];
 #pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) {
-                        const v4i bf = sR[buf][ks * 4 * NCOL + (lane >> 4) * NCOL + nt * 16 + acol];
-#pragma unroll
-                        for (int mt = 0; mt < kMT; ++mt)
-                            acc[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt][ks], bf, acc[mt][nt], 0, 0, 0);
-                    }
+                    for (int mt = 0; mt < MT; ++mt)
+                        acc[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], bf, acc[mt][nt], 0, 0, 0);
                 }
-                if (t + 1 < nstage) store_r(buf ^ 1, Rb[(q + 1) % PF]);
-                __syncthreads();
             }
+            fetch(t + PF, Ab[q], Rb[q]);
+            store_r(buf ^ 1, Rb[(q + 1) % PF]);
+            __syncthreads();
         }
     }
 
     // C of tile (mt, nt): lane holds rows mfma_c_row(lane, v), column lane & 15.
 #pragma unroll
-    for (int mt = 0; mt < kMT; ++mt)
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int bq = 0; bq < NG; ++bq)
 #pragma unroll
@@ -176,134 +194,192 @@ __global__ __launch_bounds__(kTM, 2) void mfma_xtr_kernel(MfmaArgs a)
             }
 }
 
+// Byte transpose of a 4 x 4 block: d[r] holds bytes (x_r0, x_r1, x_r2, x_r3);
+// o[c] receives (x_0c, x_1c, x_2c, x_3c).  __builtin_amdgcn_perm(hi, lo, sel)
+// picks byte sel_k of the 8-byte value hi:lo for result byte k.
+__device__ __forceinline__ void transpose4x4(const uint32_t (&d)[4], uint32_t (&o)[4])
+{
+    const uint32_t lo01 = __builtin_amdgcn_perm(d[1], d[0], 0x05010400u);  // x00 x10 x01 x11
+    const uint32_t hi01 = __builtin_amdgcn_perm(d[1], d[0], 0x07030602u);  // x02 x12 x03 x13
+    const uint32_t lo23 = __builtin_amdgcn_perm(d[3], d[2], 0x05010400u);  // x20 x30 x21 x31
+    const uint32_t hi23 = __builtin_amdgcn_perm(d[3], d[2], 0x07030602u);  // x22 x32 x23 x33
+    o[0] = __builtin_amdgcn_perm(lo23, lo01, 0x05040100u);                 // x00 x10 x20 x30
+    o[1] = __builtin_amdgcn_perm(lo23, lo01, 0x07060302u);                 // x01 x11 x21 x31
+    o[2] = __builtin_amdgcn_perm(hi23, hi01, 0x05040100u);
+    o[3] = __builtin_amdgcn_perm(hi23, hi01, 0x07060302u);
+}
+
 // eta update on the matrix cores: eta (n x B) += G[:, U] D, contracting over the
 // changed columns U.  M = subjects, N = 3 * B limb columns, K = positions in U.
-// G is stored with subjects contiguous, so a 64-column x 256-row tile is staged
-// in LDS (16-byte chunks, XOR-swizzled by the column's 16-group so that the
-// byte gathers below hit distinct banks) and each A fragment (16 columns of one
-// subject) is gathered byte by byte.  The D limb tile is staged like R above.
-// Each (subject, b) is owned by one lane, so eta is updated in place.
+// A workgroup of 8 wavefronts owns 256 subjects: wavefront w takes subjects
+// [64 (w % 4), 64 (w % 4) + 64) and half of the b's (all three limbs of each),
+// so that its accumulators fit two wavefronts per SIMD.  G is stored with
+// subjects contiguous, so each stage's 64-column x 256-subject tile passes
+// through LDS: a lane reads one dword (4 consecutive subjects of a column) for
+// each of its 16 columns and transposes the four 4 x 4 byte blocks in
+// registers, which yields the A fragments of 4 M tiles (subject 4 r + mt of
+// the wavefront's 64 is row r of tile mt).  Dword positions within a column are
+// XOR-swizzled by the column's 16-group so that the four lane groups of a read
+// hit distinct banks.  The column indices run one ring lap ahead of the G
+// loads they address.  Each (subject, b) is owned by one lane, so eta is
+// updated in place.
 template <int XT, int NG, int PF>
-__global__ __launch_bounds__(kTM, 2) void mfma_eta_kernel(MfmaEtaArgs a)
+__global__ __launch_bounds__(512, 2) void mfma_eta_kernel(MfmaEtaArgs a)
 {
-    // One 64-column k-step per stage; loads run PF stages ahead in a register ring.
+    static_assert(PF >= 2, "the ring needs two slots");
+    constexpr int TH = 512;
+    constexpr int SUB = 256;              // subjects per workgroup
+    constexpr int SW = SUB / 4;           // dwords per column of the G tile
+    constexpr int RB = SUB / 16;          // 16-byte chunks per column of the G tile
     constexpr int NT = kLimbs * NG;
     constexpr int NCOL = 16 * NT;
-    constexpr int DCH = 4 * NCOL;  // 16-byte chunks of D per 64-column step
-    constexpr int DPT = (DCH + kTM - 1) / kTM;
-    constexpr int GPT = 1024 / kTM;  // 16-byte chunks of G per thread per step
-    __shared__ uint4 sG[2][64 * 16];
+    constexpr int NGH = (NG + 1) / 2;     // b groups of 16 per wavefront (the second half repeats one if NG is odd)
+    constexpr int GPT = 64 * RB / TH;     // 16-byte chunks of G per thread per stage (= 2)
+    constexpr int DCH = 4 * NCOL;         // 16-byte chunks of D per stage
+    constexpr int DPT = (DCH + TH - 1) / TH;
+    static_assert(GPT * TH == 64 * RB, "G tile splits evenly");
+    __shared__ uint32_t sG[2][64 * SW];
     __shared__ v4i sD[2][DCH];
     const int nsel = *a.nsel;
     if (nsel == 0) return;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int64_t n = a.n, ldx = a.ldx;
-    const int64_t i0 = (int64_t)blockIdx.x * 256;
+    const int wsub = wid & 3, half = wid >> 2;
+    const int64_t n = a.n, p = a.p, ldx = a.ldx;
+    const int64_t i0 = (int64_t)blockIdx.x * SUB;
     const uint8_t* __restrict__ X = static_cast<const uint8_t*>(a.X);
-    const int nchunk = (nsel + 63) / 64;
+    const int32_t* __restrict__ sel = a.sel;
+    const int64_t nchunk = (nsel + 63) / 64;
+    const int64_t nloop = (nchunk + PF - 1) / PF * PF;
 
-    v4i acc[kMT][NT];
+    // this thread's G chunks: column position gu[k] of the stage, 16 subjects from 16 * grb[k]
+    int gu[GPT], grb[GPT], gdst[GPT];
 #pragma unroll
-    for (int mt = 0; mt < kMT; ++mt)
+    for (int k = 0; k < GPT; ++k) {
+        const int ch = threadIdx.x + TH * k;
+        gu[k] = ch / RB;
+        grb[k] = ch % RB;
+        gdst[k] = gu[k] * SW + ((4 * grb[k]) ^ (((gu[k] >> 4) & 3) << 4));
+    }
+    const int8_t* dsrc[DPT];
+    int ddst[DPT];
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = v4i{0, 0, 0, 0};
+    for (int k = 0; k < DPT; ++k) {
+        const int c = (threadIdx.x + TH * k) % DCH;
+        const int col = c >> 2, kq = c & 3;
+        const int limb = col / (16 * NG), b = col % (16 * NG);
+        dsrc[k] = a.dlimbs + ((int64_t)limb * a.bpad + b) * a.dstride + 16 * kq;
+        ddst[k] = kq * NCOL + col;
+    }
+    // this wavefront's b groups
+    int bqs[NGH];
+#pragma unroll
+    for (int j = 0; j < NGH; ++j) bqs[j] = min(half * NGH + j, NG - 1);
 
-    uint4 gr[PF][GPT];
+    auto load_sel = [&](int64_t t, int32_t (&s)[GPT]) {
+#pragma unroll
+        for (int k = 0; k < GPT; ++k) s[k] = sel[min(t * 64 + gu[k], (int64_t)nsel - 1)];
+    };
+
+    v4i acc[4][kLimbs][NGH];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int l = 0; l < kLimbs; ++l)
+#pragma unroll
+            for (int j = 0; j < NGH; ++j) acc[mt][l][j] = v4i{0, 0, 0, 0};
+
+    v4i gr[PF][GPT];
     v4i dr[PF][DPT];
-    auto fetch = [&](int c, uint4 (&g)[GPT], v4i (&dd)[DPT]) {
+    int32_t sr[PF][GPT];  // column indices of stage t + PF, in slot t mod PF
+    auto fetch = [&](int64_t t, const int32_t (&s)[GPT], v4i (&g)[GPT], v4i (&dd)[DPT]) {
 #pragma unroll
         for (int k = 0; k < GPT; ++k) {
-            const int ch = threadIdx.x + kTM * k;
-            const int u = ch >> 4, rb = ch & 15;
-            const int pos = c * 64 + u;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (pos < nsel) {
-                const v4i t = load_a<XT>(X, a.sel[pos], a.p, ldx, i0 + 16 * rb, n);
-                v = make_uint4((uint32_t)t[0], (uint32_t)t[1], (uint32_t)t[2], (uint32_t)t[3]);
-            }
-            g[k] = v;
+            const int64_t col = t * 64 + gu[k] < nsel ? (int64_t)s[k] : p;  // past the list: reads as 0
+            g[k] = load_raw(X, col, p, ldx, i0 + 16 * grb[k], n);
         }
+        const int64_t kd = min(t, nchunk - 1) * 64;
 #pragma unroll
-        for (int k = 0; k < DPT; ++k) {
-            const int ch = threadIdx.x + kTM * k;
-            if (ch < DCH) {
-                const int col = ch >> 2, kq = ch & 3;
-                const int limb = col / (16 * NG), b = col % (16 * NG);
-                dd[k] = *reinterpret_cast<const v4i*>(a.dlimbs + ((int64_t)limb * a.bpad + b) * a.dstride + c * 64 +
-                                                      16 * kq);
-            }
-        }
+        for (int k = 0; k < DPT; ++k) dd[k] = *reinterpret_cast<const v4i*>(dsrc[k] + kd);
     };
-    auto store = [&](int buf, const uint4 (&g)[GPT], const v4i (&dd)[DPT]) {
+    // subjects of this thread's runs inside the matrix
+    int gvalid[GPT];
 #pragma unroll
-        for (int k = 0; k < GPT; ++k) {
-            const int ch = threadIdx.x + kTM * k;
-            const int u = ch >> 4, rb = ch & 15;
-            sG[buf][u * 16 + (rb ^ (u >> 4))] = g[k];
-        }
+    for (int k = 0; k < GPT; ++k) gvalid[k] = clamp16(n - i0 - 16 * grb[k]);
+    auto store = [&](int64_t t, const v4i (&g)[GPT], const v4i (&dd)[DPT]) {
+        const int buf = (int)(t & 1);
 #pragma unroll
-        for (int k = 0; k < DPT; ++k) {
-            const int ch = threadIdx.x + kTM * k;
-            if (ch < DCH) {
-                const int col = ch >> 2, kq = ch & 3;
-                sD[buf][kq * NCOL + col] = dd[k];
-            }
-        }
+        for (int k = 0; k < GPT; ++k)
+            *reinterpret_cast<v4i*>(&sG[buf][gdst[k]]) = decode_a<XT>(g[k], t * 64 + gu[k] < nsel ? gvalid[k] : 0);
+#pragma unroll
+        for (int k = 0; k < DPT; ++k) sD[buf][ddst[k]] = dd[k];
     };
 
+    {
+        int32_t s0[PF][GPT];
 #pragma unroll
-    for (int q = 0; q < PF; ++q)
-        if (q < nchunk) fetch(q, gr[q], dr[q]);
+        for (int q = 0; q < PF; ++q) load_sel(q, s0[q]);
+#pragma unroll
+        for (int q = 0; q < PF; ++q) load_sel(q + PF, sr[q]);
+#pragma unroll
+        for (int q = 0; q < PF; ++q) fetch(q, s0[q], gr[q], dr[q]);
+    }
     store(0, gr[0], dr[0]);
     __syncthreads();
-    for (int c0 = 0; c0 < nchunk; c0 += PF) {
+
+    const int xr = wsub * 16 + (lane & 15);  // this lane's dword (4 subjects) within a column
+    const int xs = xr ^ ((lane >> 4) << 4);  // its swizzled position (the 16-group of its columns is lane / 16)
+    for (int64_t c0 = 0; c0 < nloop; c0 += PF) {
 #pragma unroll
         for (int q = 0; q < PF; ++q) {
-            const int c = c0 + q;
-            if (c < nchunk) {
-                if (c + PF < nchunk) fetch(c + PF, gr[q], dr[q]);
-                const int buf = c & 1;
-                const uint8_t* g8 = reinterpret_cast<const uint8_t*>(sG[buf]);
-                v4i A[kMT];
+            const int64_t t = c0 + q;
+            const int buf = (int)(t & 1);
+            v4i A[4];
+            {
+                uint32_t f[4][4];  // f[mt][dword of the fragment]
 #pragma unroll
-                for (int mt = 0; mt < kMT; ++mt) {
-                    const int row = wid * (16 * kMT) + mt * 16 + (lane & 15);
-                    uint32_t w[4] = {0, 0, 0, 0};
+                for (int blk = 0; blk < 4; ++blk) {
+                    uint32_t d[4], o[4];
 #pragma unroll
-                    for (int e = 0; e < 16; ++e) {
-                        const int u = 16 * (lane >> 4) + e;
-                        const uint32_t byte = g8[u * 256 + 16 * ((row >> 4) ^ (u >> 4)) + (row & 15)];
-                        w[e >> 2] |= byte << (8 * (e & 3));
-                    }
-                    A[mt] = v4i{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
+                    for (int e = 0; e < 4; ++e) d[e] = sG[buf][(16 * (lane >> 4) + 4 * blk + e) * SW + xs];
+                    transpose4x4(d, o);
+#pragma unroll
+                    for (int mt = 0; mt < 4; ++mt) f[mt][blk] = o[mt];
                 }
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) {
-                    const v4i bf = sD[buf][(lane >> 4) * NCOL + nt * 16 + (lane & 15)];
-#pragma unroll
-                    for (int mt = 0; mt < kMT; ++mt)
-                        acc[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], bf, acc[mt][nt], 0, 0, 0);
-                }
-                if (c + 1 < nchunk) store(buf ^ 1, gr[(q + 1) % PF], dr[(q + 1) % PF]);
-                __syncthreads();
+                for (int mt = 0; mt < 4; ++mt) A[mt] = v4i{(int)f[mt][0], (int)f[mt][1], (int)f[mt][2], (int)f[mt][3]};
             }
+#pragma unroll
+            for (int l = 0; l < kLimbs; ++l)
+#pragma unroll
+                for (int j = 0; j < NGH; ++j) {
+                    const v4i bf = sD[buf][(lane >> 4) * NCOL + (l * NG + bqs[j]) * 16 + (lane & 15)];
+#pragma unroll
+                    for (int mt = 0; mt < 4; ++mt)
+                        acc[mt][l][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], bf, acc[mt][l][j], 0, 0, 0);
+                }
+            fetch(t + PF, sr[q], gr[q], dr[q]);
+            load_sel(t + 2 * PF, sr[q]);
+            store(t + 1, gr[(q + 1) % PF], dr[(q + 1) % PF]);
+            __syncthreads();
         }
     }
 
 #pragma unroll
-    for (int mt = 0; mt < kMT; ++mt)
+    for (int j = 0; j < NGH; ++j) {
+        if (half * NGH + j >= NG) continue;  // the repeated group of an odd NG
+        const int b = bqs[j] * 16 + (lane & 15);
 #pragma unroll
-        for (int bq = 0; bq < NG; ++bq)
+        for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int b = bq * 16 + (lane & 15);
-                const int64_t i = i0 + wid * (16 * kMT) + mt * 16 + mfma_c_row(lane, v);
+                const int64_t i = i0 + 64 * wsub + 4 * mfma_c_row(lane, v) + mt;
                 if (i < n && b < a.B && (a.active == nullptr || a.active[b])) {
-                    const int64_t tot = (int64_t)acc[mt][bq][v] + 256 * (int64_t)acc[mt][NG + bq][v] +
-                                        65536 * (int64_t)acc[mt][2 * NG + bq][v];
+                    const int64_t tot = (int64_t)acc[mt][0][j][v] + 256 * (int64_t)acc[mt][1][j][v] +
+                                        65536 * (int64_t)acc[mt][2][j][v];
                     a.eta[(int64_t)b * n + i] += a.dscale[b] * (double)tot;
                 }
             }
+    }
 }
 
 // Largest |D_b(u)| over a tile of 4096 positions of the change list.
@@ -443,16 +519,21 @@ __global__ __launch_bounds__(kT) void geno_check_kernel(const uint8_t* __restric
     if (__any(b) && (threadIdx.x & 63) == 0) atomicOr(bad, 1);
 }
 
+template <int XT, int NG, int PF>
+hipError_t launch_eta_shape(const MfmaEtaArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL((mfma_eta_kernel<XT, NG, PF>), dim3((unsigned)((a.n + 255) / 256)), dim3(512), 0, s, a);
+    return hipGetLastError();
+}
+
 template <int XT, int NG>
 hipError_t launch_eta_ng(const MfmaEtaArgs& a, hipStream_t s)
 {
-    const dim3 grid((unsigned)((a.n + 255) / 256));
     switch (a.variant) {
-    case 1: hipLaunchKernelGGL((mfma_eta_kernel<XT, NG, 2>), grid, dim3(kTM), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((mfma_eta_kernel<XT, NG, 6>), grid, dim3(kTM), 0, s, a); break;
-    default: hipLaunchKernelGGL((mfma_eta_kernel<XT, NG, 4>), grid, dim3(kTM), 0, s, a); break;
+    case 1: return launch_eta_shape<XT, NG, 3>(a, s);
+    case 2: return launch_eta_shape<XT, NG, 2>(a, s);
+    default: return launch_eta_shape<XT, NG, 4>(a, s);
     }
-    return hipGetLastError();
 }
 
 template <int XT>
@@ -466,16 +547,25 @@ hipError_t launch_eta_xt(const MfmaEtaArgs& a, hipStream_t s)
     }
 }
 
+template <int XT, int NG, int WAVES, int MT, int KS, int PF>
+hipError_t launch_shape(const MfmaArgs& a, hipStream_t s)
+{
+    constexpr int WCOLS = 16 * MT * WAVES;
+    hipLaunchKernelGGL((mfma_xtr_kernel<XT, NG, WAVES, MT, KS, PF>), dim3((unsigned)((a.p + WCOLS - 1) / WCOLS)),
+                       dim3(64 * WAVES), 0, s, a);
+    return hipGetLastError();
+}
+
 template <int XT, int NG>
 hipError_t launch_ng(const MfmaArgs& a, hipStream_t s)
 {
-    const dim3 grid((unsigned)((a.p + 255) / 256));
     switch (a.variant) {
-    case 1: hipLaunchKernelGGL((mfma_xtr_kernel<XT, NG, 4, 1>), grid, dim3(kTM), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((mfma_xtr_kernel<XT, NG, 2, 4>), grid, dim3(kTM), 0, s, a); break;
-    default: hipLaunchKernelGGL((mfma_xtr_kernel<XT, NG, 2, 3>), grid, dim3(kTM), 0, s, a); break;
+    case 1: return launch_shape<XT, NG, 4, 3, 2, 4>(a, s);
+    case 2: return launch_shape<XT, NG, 4, 2, 2, 6>(a, s);
+    case 3: return launch_shape<XT, NG, 4, 2, 1, 12>(a, s);
+    case 4: return launch_shape<XT, NG, 4, 3, 1, 8>(a, s);
+    default: return launch_shape<XT, NG, 4, 3, 1, 10>(a, s);
     }
-    return hipGetLastError();
 }
 
 template <int XT>

@@ -55,3 +55,13 @@ def test_null_context_calls():
     assert L.cox_loss_grad(None, None, 1, None, None) == P.ERR_INVALID_ARG
     assert L.cox_fit_path(None, None, 1, None, None, None, None) == P.ERR_INVALID_ARG
     assert L.cox_nll_forward(None, None, 0, 1, None) == P.ERR_INVALID_ARG
+
+
+def test_header_constants_match_binding():
+    """The binding's enum values and array sizes are the ones include/cox.h declares."""
+    import re
+    text = open(P.HEADER).read()
+    assert int(re.search(r"#define COX_MFMA_VARIANTS (\d+)", text).group(1)) == P.MFMA_VARIANTS
+    assert int(re.search(r"#define COX_MFMA_ETA_VARIANTS (\d+)", text).group(1)) == P.ETA_VARIANTS
+    assert re.search(r"COX_X_FP8_E4M3\s*=\s*(\d+)", text).group(1) == str(P.X_FP8_E4M3)
+    assert re.search(r"COX_X_INT8\s*=\s*(\d+)", text).group(1) == str(P.X_INT8)

@@ -123,10 +123,12 @@ def test_vector_path_switch(prob, monkeypatch):
     np.testing.assert_allclose(oa, ov, rtol=OBJ_TOL)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", range(max(P.MFMA_VARIANTS, P.ETA_VARIANTS)))
 def test_every_pipeline_shape(prob, variant, monkeypatch):
     """Each pipeline shape the autotuner can pick gives the oracle's iterates."""
-    monkeypatch.setenv("COXHIP_MFMA_VARIANT", str(variant))
+    xv, ev = variant % P.MFMA_VARIANTS, variant % P.ETA_VARIANTS
+    monkeypatch.setenv("COXHIP_MFMA_VARIANT", str(xv))
+    monkeypatch.setenv("COXHIP_ETA_VARIANT", str(ev))
     B = 32
     cox, M = _setup(prob, "fp8", B)
     lm = oracle.lambda_max(M, prob.time, prob.event)
@@ -134,7 +136,7 @@ def test_every_pipeline_shape(prob, variant, monkeypatch):
     sigma = 1.0 / (2.0 * oracle.opnorm2(M)[0])
     beta, _, obj, _ = cox.fit_path(lams, max_iter=15, tol=0.0, step=sigma)
     t = cox.mfma_tuning()
-    assert t["xtr_variant"] == variant and t["eta_variant"] == variant
+    assert t["xtr_variant"] == xv and t["eta_variant"] == ev
     for b in (8, 31):
         bo, tr, _, _ = oracle.fit(M, prob.time, prob.event, lams[b], sigma, max_iter=15)
         assert rel_beta_err(beta.cpu().numpy()[b], bo) <= BETA_TOL
@@ -145,18 +147,20 @@ def test_autotuner_picks_and_caches(prob, tmp_path, monkeypatch):
     cache = tmp_path / "tune.txt"
     monkeypatch.setenv("COXHIP_TUNE_CACHE", str(cache))
     monkeypatch.delenv("COXHIP_MFMA_VARIANT", raising=False)
+    monkeypatch.delenv("COXHIP_ETA_VARIANT", raising=False)
     B = 16
     cox, M = _setup(prob, "int8", B)
     lm = cox.lambda_max()
     lams = coxsim.lambda_grid(lm, B, 0.01)
     cox.fit_path(lams, max_iter=3, tol=0.0, step=1.0 / (2.0 * cox.opnorm2()[0]))
     t = cox.mfma_tuning()
-    assert 0 <= t["xtr_variant"] < 3 and 0 <= t["eta_variant"] < 3
+    assert 0 <= t["xtr_variant"] < P.MFMA_VARIANTS and 0 <= t["eta_variant"] < P.ETA_VARIANTS
     assert all(m > 0 for m in t["xtr_ms"])
+    assert all(m > 0 for m in t["eta_ms"][: P.ETA_VARIANTS]) and not any(t["eta_ms"][P.ETA_VARIANTS:])
     lines = cache.read_text().split()
     assert "xtr:xt2:n3001:p700:b16" in lines and "eta:xt2:n3001:p700:b16" in lines
     # a new context reads the cache instead of timing again
     cox2, _ = _setup(prob, "int8", B)
     cox2.fit_path(lams, max_iter=3, tol=0.0, step=1.0 / (2.0 * cox.opnorm2()[0]))
     t2 = cox2.mfma_tuning()
-    assert t2["xtr_variant"] == t["xtr_variant"] and t2["xtr_ms"] == [0.0, 0.0, 0.0]
+    assert t2["xtr_variant"] == t["xtr_variant"] and t2["xtr_ms"] == [0.0] * P.MFMA_VARIANTS
