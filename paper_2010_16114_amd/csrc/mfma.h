@@ -20,8 +20,8 @@ struct MfmaArgs {
     const double* qscale;   // [B] quantisation step of each vector
     double* out;            // [B][p] raw sums q_b * sum_i g_ij R_bi
     int variant;            // pipeline shape (waves x M tiles per wave, subjects per stage, stages ahead):
-                            // 0 = 4x3, 64, 10; 1 = 4x3, 128, 4; 2 = 4x2, 128, 6; 3 = 4x2, 64, 12;
-                            // 4 = 4x3, 64, 8
+                            // 0 = 4x3, 64, 8; 1 = 8x2, 64, 5; 2 = 8x2, 64, 6; 3 = 8x2, 128, 4;
+                            // 4 = 8x2, 128, 3
 };
 constexpr int kMfmaVariants = 5;     // shapes of the X~' R pass
 constexpr int kMfmaEtaVariants = 3;  // shapes of the eta update

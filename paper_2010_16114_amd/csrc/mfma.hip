@@ -44,9 +44,11 @@ __device__ __forceinline__ uint32_t counts4(uint32_t w)
 }
 
 // The 16 bytes of column col from row row (row and ldx are multiples of 16, so
-// the load never leaves the column's ldx bytes).  A run outside the matrix
-// loads from X itself; decode_a masks it away.  The load and the decode are
-// separate so that a prefetched run is only waited for where it is used.
+// the load never leaves the column's ldx bytes).  A run that starts outside
+// the matrix loads from X itself.  The bytes of rows >= n are whatever the
+// padding holds: the kernels make them harmless (zero limbs, or outputs that
+// are never written).  The load and the decode are separate so that a
+// prefetched run is only waited for where it is used.
 __device__ __forceinline__ v4i load_raw(const uint8_t* __restrict__ X, int64_t col, int64_t p, int64_t ldx,
                                         int64_t row, int64_t n)
 {
@@ -54,22 +56,15 @@ __device__ __forceinline__ v4i load_raw(const uint8_t* __restrict__ X, int64_t c
     return *reinterpret_cast<const v4i*>(X + (ok ? col * ldx + row : 0));
 }
 
-// int8 counts of a raw run of which the first `valid` bytes (0..16) lie inside
-// the matrix; the others read as 0.
+// int8 counts of a raw run.
 template <int XT>
-__device__ __forceinline__ v4i decode_a(v4i raw, int valid)
+__device__ __forceinline__ v4i decode_a(v4i raw)
 {
     v4i v;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int keep = valid - 4 * q;  // bytes of dword q to keep
-        const uint32_t mask = keep >= 4 ? 0xFFFFFFFFu : (keep <= 0 ? 0u : (0xFFFFFFFFu >> (8 * (4 - keep))));
-        v[q] = (int)(counts4<XT>((uint32_t)raw[q]) & mask);
-    }
+    for (int q = 0; q < 4; ++q) v[q] = (int)counts4<XT>((uint32_t)raw[q]);
     return v;
 }
-
-__device__ __forceinline__ int clamp16(int64_t x) { return (int)min(max(x, (int64_t)0), (int64_t)16); }
 
 // Software pipeline shared by both matrix-core kernels.  Every global load of a
 // stage (the HBM stream and the small L2-resident operand alike) is issued PF
@@ -85,7 +80,10 @@ __global__ __launch_bounds__(64 * WAVES, WAVES / 4) void mfma_xtr_kernel(MfmaArg
     // WAVES wavefronts of MT M tiles (16 SNP columns each); stages of KS k-steps
     // of 64 subjects.  Stage t's limb tile goes to LDS buffer t & 1 one stage
     // early, laid out so that an MFMA B fragment is one 16-byte read per lane,
-    // contiguous across lanes.
+    // contiguous across lanes.  The limb rows of subjects >= n are zero (the
+    // limb buffer is cleared at setup and only rows < n are ever written), so
+    // the padding bytes of X that meet them add nothing; the stages past the
+    // last one (the ring runs in whole laps) skip their products.
     static_assert(PF >= 2, "the ring needs two slots");
     constexpr int TH = 64 * WAVES;
     constexpr int WCOLS = 16 * MT * WAVES;  // SNP columns per workgroup
@@ -118,11 +116,6 @@ __global__ __launch_bounds__(64 * WAVES, WAVES / 4) void mfma_xtr_kernel(MfmaArg
         rsrc[u] = limbs + ((int64_t)limb * a.bpad + b) * a.lstride + 16 * q;
         rdst[u] = q * NCOL + col;
     }
-
-    // rows of this lane's runs left in the matrix, before the stage offset (columns >= p: none)
-    int64_t nleft[MT];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) nleft[mt] = jw + mt * 16 + acol < p ? n - arow : 0;
 
     v4i acc[MT][NT];
 #pragma unroll
@@ -158,17 +151,25 @@ __global__ __launch_bounds__(64 * WAVES, WAVES / 4) void mfma_xtr_kernel(MfmaArg
         for (int q = 0; q < PF; ++q) {
             const int64_t t = s0 + q;
             const int buf = (int)(t & 1);
+            if (t < nstage) {
+                // B fragments in (ks, nt) order, each read one fragment ahead of its MFMAs
+                const v4i* sb = &sR[buf][(lane >> 4) * NCOL + acol];
+                v4i bcur = sb[0];
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                v4i A[MT];
+                for (int ks = 0; ks < KS; ++ks) {
+                    v4i A[MT];
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt) A[mt] = decode_a<XT>(Ab[q][mt][ks], clamp16(nleft[mt] - t * KC - ks * 64));
+                    for (int mt = 0; mt < MT; ++mt) A[mt] = decode_a<XT>(Ab[q][mt][ks]);
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) {
-                    const v4i bf = sR[buf][(4 * ks + (lane >> 4)) * NCOL + nt * 16 + acol];
+                    for (int nt = 0; nt < NT; ++nt) {
+                        const int f = ks * NT + nt + 1;  // next fragment
+                        v4i bnext = bcur;
+                        if (f < KS * NT) bnext = sb[(f / NT) * 4 * NCOL + (f % NT) * 16];
 #pragma unroll
-                    for (int mt = 0; mt < MT; ++mt)
-                        acc[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], bf, acc[mt][nt], 0, 0, 0);
+                        for (int mt = 0; mt < MT; ++mt)
+                            acc[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], bcur, acc[mt][nt], 0, 0, 0);
+                        bcur = bnext;
+                    }
                 }
             }
             fetch(t + PF, Ab[q], Rb[q]);
@@ -301,15 +302,14 @@ __global__ __launch_bounds__(512, 2) void mfma_eta_kernel(MfmaEtaArgs a)
 #pragma unroll
         for (int k = 0; k < DPT; ++k) dd[k] = *reinterpret_cast<const v4i*>(dsrc[k] + kd);
     };
-    // subjects of this thread's runs inside the matrix
-    int gvalid[GPT];
-#pragma unroll
-    for (int k = 0; k < GPT; ++k) gvalid[k] = clamp16(n - i0 - 16 * grb[k]);
+    // positions past the change list read as 0 (subjects >= n only reach
+    // outputs that are never written)
     auto store = [&](int64_t t, const v4i (&g)[GPT], const v4i (&dd)[DPT]) {
         const int buf = (int)(t & 1);
 #pragma unroll
         for (int k = 0; k < GPT; ++k)
-            *reinterpret_cast<v4i*>(&sG[buf][gdst[k]]) = decode_a<XT>(g[k], t * 64 + gu[k] < nsel ? gvalid[k] : 0);
+            *reinterpret_cast<v4i*>(&sG[buf][gdst[k]]) =
+                t * 64 + gu[k] < nsel ? decode_a<XT>(g[k]) : v4i{0, 0, 0, 0};
 #pragma unroll
         for (int k = 0; k < DPT; ++k) sD[buf][ddst[k]] = dd[k];
     };
@@ -348,15 +348,22 @@ __global__ __launch_bounds__(512, 2) void mfma_eta_kernel(MfmaEtaArgs a)
 #pragma unroll
                 for (int mt = 0; mt < 4; ++mt) A[mt] = v4i{(int)f[mt][0], (int)f[mt][1], (int)f[mt][2], (int)f[mt][3]};
             }
+            {
+                const v4i* sb = &sD[buf][(lane >> 4) * NCOL + (lane & 15)];
+                v4i bcur = sb[bqs[0] * 16];
 #pragma unroll
-            for (int l = 0; l < kLimbs; ++l)
+                for (int l = 0; l < kLimbs; ++l)
 #pragma unroll
-                for (int j = 0; j < NGH; ++j) {
-                    const v4i bf = sD[buf][(lane >> 4) * NCOL + (l * NG + bqs[j]) * 16 + (lane & 15)];
+                    for (int j = 0; j < NGH; ++j) {
+                        const int f = l * NGH + j + 1;  // next fragment
+                        v4i bnext = bcur;
+                        if (f < kLimbs * NGH) bnext = sb[((f / NGH) * NG + bqs[f % NGH]) * 16];
 #pragma unroll
-                    for (int mt = 0; mt < 4; ++mt)
-                        acc[mt][l][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], bf, acc[mt][l][j], 0, 0, 0);
-                }
+                        for (int mt = 0; mt < 4; ++mt)
+                            acc[mt][l][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], bcur, acc[mt][l][j], 0, 0, 0);
+                        bcur = bnext;
+                    }
+            }
             fetch(t + PF, sr[q], gr[q], dr[q]);
             load_sel(t + 2 * PF, sr[q]);
             store(t + 1, gr[(q + 1) % PF], dr[(q + 1) % PF]);
@@ -560,11 +567,11 @@ template <int XT, int NG>
 hipError_t launch_ng(const MfmaArgs& a, hipStream_t s)
 {
     switch (a.variant) {
-    case 1: return launch_shape<XT, NG, 4, 3, 2, 4>(a, s);
-    case 2: return launch_shape<XT, NG, 4, 2, 2, 6>(a, s);
-    case 3: return launch_shape<XT, NG, 4, 2, 1, 12>(a, s);
-    case 4: return launch_shape<XT, NG, 4, 3, 1, 8>(a, s);
-    default: return launch_shape<XT, NG, 4, 3, 1, 10>(a, s);
+    case 1: return launch_shape<XT, NG, 8, 2, 1, 5>(a, s);
+    case 2: return launch_shape<XT, NG, 8, 2, 1, 6>(a, s);
+    case 3: return launch_shape<XT, NG, 8, 2, 2, 4>(a, s);
+    case 4: return launch_shape<XT, NG, 8, 2, 2, 3>(a, s);
+    default: return launch_shape<XT, NG, 4, 3, 1, 8>(a, s);
     }
 }
 

@@ -1,0 +1,81 @@
+"""Precision of the FP8 path at full size: the 200,000 x 200,000 genotype
+problem (FP8 E4M3 allele counts, standardised on the fly) solved at
+lambda = 0.2 lambda_max until the relative objective change over the lag
+falls below 1e-8, then checked against the FP64 oracle at the solution.
+
+The oracle cannot run ISTA over 40 GB in seconds, but at a sparse solution it
+needs only the support: eta = X~_S beta_S, then L, r and g_j for any column j
+it regenerates from the counter hash.  What is stated:
+  * the objective f = -L + lambda ||beta||_1 recomputed in FP64 by the oracle
+    at the GPU's beta, against the GPU's own;
+  * the KKT conditions of the l1 problem in FP64 (Section 5.3's objective is
+    convex): g_j = lambda sign(beta_j) on the support, |g_j| <= lambda on the
+    columns outside it (a random sample plus those the GPU ranks largest);
+  * the distance to the oracle's own FP64 solution of the problem restricted to
+    the support, started from the GPU's beta and run to a far tighter tolerance.
+"""
+import numpy as np
+import pytest
+
+import coxsim
+import oracle
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+import paper_2010_16114_amd as P  # noqa: E402
+
+
+def test_fp8_200k_solution_against_fp64_oracle():
+    d = coxsim.config3()
+    ldx = (d.n + 15) // 16 * 16
+    G, c1, c2 = coxsim.genotype_device(d.n, d.p, d.seed, d.thresholds, fmt=1, ldx=ldx)
+    mu, s = coxsim.standardisation(c1, c2, d.n)
+    cox = P.Cox(G, d.time, d.event, xtype=P.X_FP8_E4M3, n=d.n, center=torch.from_numpy(mu).cuda(),
+                scale=torch.from_numpy(s).cuda())
+    lam = 0.2 * cox.lambda_max()
+    s2, _ = cox.opnorm2()
+    sigma = 1.0 / (2.0 * s2)
+    beta, iters, obj, status = cox.fit_path([lam], max_iter=4000, tol=1e-8, step=sigma)
+    assert status == P.OK, (status, iters)
+    b = beta.cpu().numpy()[0].astype(np.float64)
+    S = np.flatnonzero(b)
+    assert 0 < S.size < 5000
+    _, grad = cox.loss_grad(beta)  # gradient of -L at the solution, every column
+    g_gpu = -grad.cpu().numpy()[0].astype(np.float64)
+    del G
+    torch.cuda.empty_cache()
+
+    rng = np.random.default_rng(7)
+    off = np.setdiff1d(np.arange(d.p), S)
+    top = off[np.argsort(-np.abs(g_gpu[off]))[:64]]
+    Z = np.union1d(rng.choice(off, 256, replace=False), top)
+    cols = np.concatenate([S, Z])
+    Gh = coxsim.genotype_columns(d.n, cols, d.seed, d.thresholds[cols])
+    MS = oracle.Matrix.genotype(Gh[: S.size], mu[S], s[S])
+    MZ = oracle.Matrix.genotype(Gh[S.size:], mu[Z], s[Z])
+
+    eta = oracle.xbeta(MS, b[S])
+    L, r = oracle.loglik(eta, d.time, d.event)
+    f_oracle = -L + lam * np.abs(b).sum()
+    rel_f = abs(obj[0] - f_oracle) / abs(f_oracle)
+    gS = oracle.xtr(MS, r)
+    gZ = oracle.xtr(MZ, r)
+    kkt_support = np.abs(gS - lam * np.sign(b[S])).max() / lam
+    kkt_outside = max(0.0, (np.abs(gZ) - lam).max()) / lam
+
+    bo, trace, k, conv = oracle.fit(MS, d.time, d.event, lam, sigma, max_iter=3000, tol=1e-13, beta0=b[S])
+    rel_beta = np.abs(b[S] - bo).max() / np.abs(bo).max()
+    print(f"\nFP8 200k x 200k, lambda = 0.2 lambda_max: {iters[0]} steps to rel. change < 1e-8, "
+          f"|S| = {S.size}\n  objective: GPU {obj[0]:.12g}, FP64 oracle at the GPU's beta {f_oracle:.12g} "
+          f"(rel. diff {rel_f:.2e})\n  KKT (FP64): support max|g - lambda sign| / lambda = {kkt_support:.2e}, "
+          f"outside max(|g| - lambda)+ / lambda = {kkt_outside:.2e}\n  FP64 restricted solution ({k} more "
+          f"steps): max|beta - beta_oracle| / max|beta_oracle| = {rel_beta:.2e}")
+    assert rel_f <= 1e-9
+    # the GPU's gradient at the solution agrees with the oracle's
+    assert np.abs(g_gpu[S] - gS).max() <= 5e-6 * lam
+    assert np.abs(g_gpu[Z] - gZ).max() <= 5e-6 * lam
+    assert kkt_support <= 1e-2 and kkt_outside <= 1e-2
+    assert rel_beta <= 1e-2
