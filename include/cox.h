@@ -210,7 +210,7 @@ typedef enum {
  * [COX_MFMA_VARIANTS] each, nullable; entries past a pass's shape count and
  * entries of a pass that was not timed are 0). */
 #define COX_MFMA_VARIANTS 5
-#define COX_MFMA_ETA_VARIANTS 3
+#define COX_MFMA_ETA_VARIANTS 5
 cox_status cox_mfma_tuning(cox_ctx *ctx, int32_t *xtr_variant, int32_t *eta_variant, float *xtr_ms, float *eta_ms);
 cox_status cox_timing_enable(cox_ctx *ctx, int32_t enable);
 cox_status cox_timing_read(cox_ctx *ctx, int32_t phase, double *total_ms, int64_t *count);

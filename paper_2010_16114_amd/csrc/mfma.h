@@ -13,8 +13,9 @@ struct MfmaArgs {
     const void* X;          // column-major allele counts (int8 or FP8 E4M3 codes)
     int xt;                 // XT_I8 or XT_FP8
     int64_t n, p, ldx;      // ldx % 16 == 0, X 16-byte aligned
-    const int8_t* limbs;    // [3][bpad][lstride] residual limbs, zero beyond n
-    int64_t lstride;        // multiple of 256
+    const int8_t* limbs;    // [lstride / 16][3 * bpad][16] residual limbs by 16-subject chunk, limb-major
+                            // within a chunk (column limb * bpad + b); rows n .. round_up(n, 256) zero
+    int64_t lstride;        // subject rows the limb buffer holds: a multiple of 256, >= n
     int bpad;               // 16, 32, 48 or 64
     int B;                  // vectors written (<= bpad)
     const double* qscale;   // [B] quantisation step of each vector
@@ -24,7 +25,7 @@ struct MfmaArgs {
                             // 4 = 8x2, 128, 3
 };
 constexpr int kMfmaVariants = 5;     // shapes of the X~' R pass
-constexpr int kMfmaEtaVariants = 3;  // shapes of the eta update
+constexpr int kMfmaEtaVariants = 5;  // shapes of the eta update
 
 // eta_b(i) += q_b * sum_{u < nsel} g(i, sel[u]) D_b(u), D in three int8 limbs.
 struct MfmaEtaArgs {
@@ -33,13 +34,15 @@ struct MfmaEtaArgs {
     int64_t n, p, ldx;      // ldx % 16 == 0, X 16-byte aligned
     const int32_t* sel;     // [nsel] changed columns, ascending
     const int32_t* nsel;    // device count
-    const int8_t* dlimbs;   // [3][bpad][dstride] limbs of D by position in sel, zero past nsel
-    int64_t dstride;        // multiple of 64, >= p
+    const int8_t* dlimbs;   // [dstride / 16][3 * bpad][16] limbs of D by 16-position chunk of sel;
+                            // positions nsel .. round_up(nsel, 64) zero
+    int64_t dstride;        // positions the buffer holds: a multiple of 64, >= p
     int bpad, B;
     const double* dscale;   // [B]
     double* eta;            // [B][n] FP64, updated in place
     const int32_t* active;  // [B] or null
-    int variant;            // stages (of 64 columns) ahead: 0 = 4, 1 = 3, 2 = 2
+    int variant;            // (wavefronts, stages of 64 columns ahead): 0 = 8, 4; 1 = 8, 3; 2 = 8, 2;
+                            // 3 = 4, 4; 4 = 4, 3
 };
 
 int mfma_ntile(int64_t n);

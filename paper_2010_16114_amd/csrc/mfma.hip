@@ -93,7 +93,8 @@ __global__ __launch_bounds__(64 * WAVES, WAVES / 4) void mfma_xtr_kernel(MfmaArg
     constexpr int QC = KC / 16;             // 16-byte row chunks per limb column per stage
     constexpr int CHUNKS = NCOL * QC;       // 16-byte chunks of limb data per stage
     constexpr int CPT = (CHUNKS + TH - 1) / TH;
-    __shared__ v4i sR[2][CHUNKS];           // [q = 4 ks + lane / 16][limb column]
+    constexpr int RS = NCOL + 8;            // LDS row stride (16-byte units), padded against bank conflicts
+    __shared__ v4i sR[2][QC * RS];          // [q = 4 ks + lane / 16][limb column]
 
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int64_t n = a.n, p = a.p, ldx = a.ldx;
@@ -105,16 +106,17 @@ __global__ __launch_bounds__(64 * WAVES, WAVES / 4) void mfma_xtr_kernel(MfmaArg
     const int arow = 16 * (lane >> 4);  // k offset of this lane's 16 bytes within a k-step
     const int acol = lane & 15;
 
-    // this thread's limb chunks (a chunk index past the end repeats a valid one)
+    // This thread's limb chunks (a chunk index past the end repeats a valid
+    // one).  A stage's limb tile is one contiguous block of CHUNKS 16-byte
+    // chunks ([16-subject row q][limb column]), so consecutive lanes read
+    // consecutive chunks and store them to consecutive LDS slots.
     const int8_t* rsrc[CPT];
     int rdst[CPT];
 #pragma unroll
     for (int u = 0; u < CPT; ++u) {
         const int c = (threadIdx.x + TH * u) % CHUNKS;
-        const int col = c / QC, q = c % QC;
-        const int limb = col / (16 * NG), b = col % (16 * NG);
-        rsrc[u] = limbs + ((int64_t)limb * a.bpad + b) * a.lstride + 16 * q;
-        rdst[u] = q * NCOL + col;
+        rsrc[u] = limbs + 16 * c;
+        rdst[u] = (c / NCOL) * RS + c % NCOL;
     }
 
     v4i acc[MT][NT];
@@ -132,7 +134,7 @@ __global__ __launch_bounds__(64 * WAVES, WAVES / 4) void mfma_xtr_kernel(MfmaArg
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
                 A[mt][ks] = load_raw(X, jw + mt * 16 + acol, p, ldx, k0 + ks * 64 + arow, n);
-        const int64_t kr = min(t, nstage - 1) * KC;
+        const int64_t kr = min(t, nstage - 1) * (int64_t)(16 * CHUNKS);
 #pragma unroll
         for (int u = 0; u < CPT; ++u) R[u] = *reinterpret_cast<const v4i*>(rsrc[u] + kr);
     };
@@ -153,7 +155,7 @@ __global__ __launch_bounds__(64 * WAVES, WAVES / 4) void mfma_xtr_kernel(MfmaArg
             const int buf = (int)(t & 1);
             if (t < nstage) {
                 // B fragments in (ks, nt) order, each read one fragment ahead of its MFMAs
-                const v4i* sb = &sR[buf][(lane >> 4) * NCOL + acol];
+                const v4i* sb = &sR[buf][(lane >> 4) * RS + acol];
                 v4i bcur = sb[0];
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks) {
@@ -164,7 +166,7 @@ __global__ __launch_bounds__(64 * WAVES, WAVES / 4) void mfma_xtr_kernel(MfmaArg
                     for (int nt = 0; nt < NT; ++nt) {
                         const int f = ks * NT + nt + 1;  // next fragment
                         v4i bnext = bcur;
-                        if (f < KS * NT) bnext = sb[(f / NT) * 4 * NCOL + (f % NT) * 16];
+                        if (f < KS * NT) bnext = sb[(f / NT) * 4 * RS + (f % NT) * 16];
 #pragma unroll
                         for (int mt = 0; mt < MT; ++mt)
                             acc[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], bcur, acc[mt][nt], 0, 0, 0);
@@ -212,9 +214,11 @@ __device__ __forceinline__ void transpose4x4(const uint32_t (&d)[4], uint32_t (&
 
 // eta update on the matrix cores: eta (n x B) += G[:, U] D, contracting over the
 // changed columns U.  M = subjects, N = 3 * B limb columns, K = positions in U.
-// A workgroup of 8 wavefronts owns 256 subjects: wavefront w takes subjects
-// [64 (w % 4), 64 (w % 4) + 64) and half of the b's (all three limbs of each),
-// so that its accumulators fit two wavefronts per SIMD.  G is stored with
+// A workgroup of 4 * NSPLIT wavefronts owns 256 subjects: wavefront w takes
+// subjects [64 (w % 4), 64 (w % 4) + 64) and one NSPLIT-th of the b's (all
+// three limbs of each).  NSPLIT = 2 fits the accumulators two wavefronts per
+// SIMD; NSPLIT = 1 keeps one wavefront per SIMD with the accumulators in the
+// accumulation registers, which leaves room for a deeper load ring.  G is stored with
 // subjects contiguous, so each stage's 64-column x 256-subject tile passes
 // through LDS: a lane reads one dword (4 consecutive subjects of a column) for
 // each of its 16 columns and transposes the four 4 x 4 byte blocks in
@@ -224,23 +228,25 @@ __device__ __forceinline__ void transpose4x4(const uint32_t (&d)[4], uint32_t (&
 // hit distinct banks.  The column indices run one ring lap ahead of the G
 // loads they address.  Each (subject, b) is owned by one lane, so eta is
 // updated in place.
-template <int XT, int NG, int PF>
-__global__ __launch_bounds__(512, 2) void mfma_eta_kernel(MfmaEtaArgs a)
+template <int XT, int NG, int NSPLIT, int PF>
+__global__ __launch_bounds__(256 * NSPLIT, NSPLIT) void mfma_eta_kernel(MfmaEtaArgs a)
 {
     static_assert(PF >= 2, "the ring needs two slots");
-    constexpr int TH = 512;
+    static_assert(NSPLIT == 1 || NSPLIT == 2, "one or two b groups per subject block");
+    constexpr int TH = 256 * NSPLIT;
     constexpr int SUB = 256;              // subjects per workgroup
     constexpr int SW = SUB / 4;           // dwords per column of the G tile
     constexpr int RB = SUB / 16;          // 16-byte chunks per column of the G tile
     constexpr int NT = kLimbs * NG;
     constexpr int NCOL = 16 * NT;
-    constexpr int NGH = (NG + 1) / 2;     // b groups of 16 per wavefront (the second half repeats one if NG is odd)
-    constexpr int GPT = 64 * RB / TH;     // 16-byte chunks of G per thread per stage (= 2)
+    constexpr int NGH = (NG + NSPLIT - 1) / NSPLIT;  // b groups of 16 per wavefront (a split of an odd NG repeats one)
+    constexpr int GPT = 64 * RB / TH;     // 16-byte chunks of G per thread per stage
     constexpr int DCH = 4 * NCOL;         // 16-byte chunks of D per stage
     constexpr int DPT = (DCH + TH - 1) / TH;
+    constexpr int DS = NCOL + 8;          // LDS row stride of the D tile (16-byte units)
     static_assert(GPT * TH == 64 * RB, "G tile splits evenly");
     __shared__ uint32_t sG[2][64 * SW];
-    __shared__ v4i sD[2][DCH];
+    __shared__ v4i sD[2][4 * DS];
     const int nsel = *a.nsel;
     if (nsel == 0) return;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -261,15 +267,15 @@ __global__ __launch_bounds__(512, 2) void mfma_eta_kernel(MfmaEtaArgs a)
         grb[k] = ch % RB;
         gdst[k] = gu[k] * SW + ((4 * grb[k]) ^ (((gu[k] >> 4) & 3) << 4));
     }
+    // D chunks: a stage's D tile is one contiguous block of DCH chunks
+    // ([16-position quarter kq][limb column])
     const int8_t* dsrc[DPT];
     int ddst[DPT];
 #pragma unroll
     for (int k = 0; k < DPT; ++k) {
         const int c = (threadIdx.x + TH * k) % DCH;
-        const int col = c >> 2, kq = c & 3;
-        const int limb = col / (16 * NG), b = col % (16 * NG);
-        dsrc[k] = a.dlimbs + ((int64_t)limb * a.bpad + b) * a.dstride + 16 * kq;
-        ddst[k] = kq * NCOL + col;
+        dsrc[k] = a.dlimbs + 16 * c;
+        ddst[k] = (c / NCOL) * DS + c % NCOL;
     }
     // this wavefront's b groups
     int bqs[NGH];
@@ -298,7 +304,7 @@ __global__ __launch_bounds__(512, 2) void mfma_eta_kernel(MfmaEtaArgs a)
             const int64_t col = t * 64 + gu[k] < nsel ? (int64_t)s[k] : p;  // past the list: reads as 0
             g[k] = load_raw(X, col, p, ldx, i0 + 16 * grb[k], n);
         }
-        const int64_t kd = min(t, nchunk - 1) * 64;
+        const int64_t kd = min(t, nchunk - 1) * (int64_t)(16 * DCH);
 #pragma unroll
         for (int k = 0; k < DPT; ++k) dd[k] = *reinterpret_cast<const v4i*>(dsrc[k] + kd);
     };
@@ -349,7 +355,7 @@ __global__ __launch_bounds__(512, 2) void mfma_eta_kernel(MfmaEtaArgs a)
                 for (int mt = 0; mt < 4; ++mt) A[mt] = v4i{(int)f[mt][0], (int)f[mt][1], (int)f[mt][2], (int)f[mt][3]};
             }
             {
-                const v4i* sb = &sD[buf][(lane >> 4) * NCOL + (lane & 15)];
+                const v4i* sb = &sD[buf][(lane >> 4) * DS + (lane & 15)];
                 v4i bcur = sb[bqs[0] * 16];
 #pragma unroll
                 for (int l = 0; l < kLimbs; ++l)
@@ -408,10 +414,11 @@ __global__ __launch_bounds__(kT) void dmax_kernel(const double* __restrict__ dco
 }
 
 // D limbs by position; positions nsel .. round_up(nsel, 64) - 1 are zeroed.
+// Limb layout as for the residual: [u / 16][limb * bpad + b][u % 16].
 __global__ __launch_bounds__(kT) void dquant_kernel(const double* __restrict__ dcoef, int64_t p,
                                                     const int32_t* __restrict__ sel, const int32_t* __restrict__ nsel,
                                                     const double* __restrict__ dmaxp, int ntile,
-                                                    int8_t* __restrict__ dlimbs, int64_t dstride, int bpad,
+                                                    int8_t* __restrict__ dlimbs, int bpad,
                                                     double* __restrict__ dscale)
 {
     const int b = blockIdx.y;
@@ -432,9 +439,10 @@ __global__ __launch_bounds__(kT) void dquant_kernel(const double* __restrict__ d
             d1 = ((R1 + 128) & 255) - 128;
             d2 = (R1 - d1) >> 8;
         }
-        dlimbs[((int64_t)0 * bpad + b) * dstride + u] = (int8_t)d0;
-        dlimbs[((int64_t)1 * bpad + b) * dstride + u] = (int8_t)d1;
-        dlimbs[((int64_t)2 * bpad + b) * dstride + u] = (int8_t)d2;
+        int8_t* dst = dlimbs + ((u >> 4) * (3 * bpad) + b) * 16 + (u & 15);
+        dst[0] = (int8_t)d0;
+        dst[16 * bpad] = (int8_t)d1;
+        dst[32 * bpad] = (int8_t)d2;
     }
 }
 
@@ -454,10 +462,15 @@ __global__ __launch_bounds__(kT) void rmax_kernel(const double* __restrict__ r, 
     if (threadIdx.x == 0) part[(int64_t)b * ntile + blockIdx.x] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
 }
 
-// Quantise r to three int8 limbs per vector; exact partial sums of R.
+// Quantise r to three int8 limbs per vector; exact partial sums of R.  Limb
+// layout: 16-subject chunks, [i / 16][limb * bpad + b][i % 16], so that a
+// stage's tile (all 3 * bpad limb columns of KC subjects) is one contiguous
+// block.  Rows n .. round_up(n, 256) - 1 are written as zeros: the X~' R
+// kernel reads whole 64- or 128-subject stages, and the layout changes with
+// bpad, so stale limbs from an earlier batch size must not survive there.
 __global__ __launch_bounds__(kT) void quantize_kernel(const double* __restrict__ r, int64_t n,
                                                       const double* __restrict__ rmaxp, int ntile,
-                                                      int8_t* __restrict__ limbs, int64_t lstride, int bpad,
+                                                      int8_t* __restrict__ limbs, int bpad,
                                                       double* __restrict__ qscale, long long* __restrict__ rsump)
 {
     __shared__ long long sh[kT / 64];
@@ -467,16 +480,18 @@ __global__ __launch_bounds__(kT) void quantize_kernel(const double* __restrict__
     const double q = mx > 0.0 ? mx / (double)(1 << kQBits) : 1.0;
     if (blockIdx.x == 0 && threadIdx.x == 0) qscale[b] = q;
     long long sum = 0;
-    for (int64_t i = (int64_t)blockIdx.x * 4096 + threadIdx.x; i < min(n, (int64_t)(blockIdx.x + 1) * 4096);
+    const int64_t npad = (n + 255) / 256 * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 4096 + threadIdx.x; i < min(npad, (int64_t)(blockIdx.x + 1) * 4096);
          i += kT) {
-        const int R = (int)llrint(r[(int64_t)b * n + i] / q);
+        const int R = i < n ? (int)llrint(r[(int64_t)b * n + i] / q) : 0;
         const int d0 = ((R + 128) & 255) - 128;
         const int R1 = (R - d0) >> 8;
         const int d1 = ((R1 + 128) & 255) - 128;
         const int d2 = (R1 - d1) >> 8;
-        limbs[((int64_t)0 * bpad + b) * lstride + i] = (int8_t)d0;
-        limbs[((int64_t)1 * bpad + b) * lstride + i] = (int8_t)d1;
-        limbs[((int64_t)2 * bpad + b) * lstride + i] = (int8_t)d2;
+        int8_t* dst = limbs + ((i >> 4) * (3 * bpad) + b) * 16 + (i & 15);
+        dst[0] = (int8_t)d0;
+        dst[16 * bpad] = (int8_t)d1;
+        dst[32 * bpad] = (int8_t)d2;
         sum += R;
     }
     for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
@@ -526,10 +541,11 @@ __global__ __launch_bounds__(kT) void geno_check_kernel(const uint8_t* __restric
     if (__any(b) && (threadIdx.x & 63) == 0) atomicOr(bad, 1);
 }
 
-template <int XT, int NG, int PF>
+template <int XT, int NG, int NSPLIT, int PF>
 hipError_t launch_eta_shape(const MfmaEtaArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL((mfma_eta_kernel<XT, NG, PF>), dim3((unsigned)((a.n + 255) / 256)), dim3(512), 0, s, a);
+    hipLaunchKernelGGL((mfma_eta_kernel<XT, NG, NSPLIT, PF>), dim3((unsigned)((a.n + 255) / 256)), dim3(256 * NSPLIT),
+                       0, s, a);
     return hipGetLastError();
 }
 
@@ -537,9 +553,11 @@ template <int XT, int NG>
 hipError_t launch_eta_ng(const MfmaEtaArgs& a, hipStream_t s)
 {
     switch (a.variant) {
-    case 1: return launch_eta_shape<XT, NG, 3>(a, s);
-    case 2: return launch_eta_shape<XT, NG, 2>(a, s);
-    default: return launch_eta_shape<XT, NG, 4>(a, s);
+    case 1: return launch_eta_shape<XT, NG, 2, 3>(a, s);
+    case 2: return launch_eta_shape<XT, NG, 2, 2>(a, s);
+    case 3: return launch_eta_shape<XT, NG, 1, 4>(a, s);
+    case 4: return launch_eta_shape<XT, NG, 1, 3>(a, s);
+    default: return launch_eta_shape<XT, NG, 2, 4>(a, s);
     }
 }
 
@@ -593,10 +611,10 @@ int mfma_ntile(int64_t n) { return (int)((n + 4095) / 4096); }
 hipError_t launch_quantize(const double* r64, int64_t n, int B, double* rmaxp, long long* rsump, int8_t* limbs,
                            int64_t lstride, int bpad, double* qscale, double* sumr, hipStream_t s)
 {
+    if (lstride % 256 || lstride < n || bpad < B || bpad % 16) return hipErrorInvalidValue;
     const int nt = mfma_ntile(n);
     hipLaunchKernelGGL(rmax_kernel, dim3(nt, B), dim3(kT), 0, s, r64, n, rmaxp, nt);
-    hipLaunchKernelGGL(quantize_kernel, dim3(nt, B), dim3(kT), 0, s, r64, n, rmaxp, nt, limbs, lstride, bpad, qscale,
-                       rsump);
+    hipLaunchKernelGGL(quantize_kernel, dim3(nt, B), dim3(kT), 0, s, r64, n, rmaxp, nt, limbs, bpad, qscale, rsump);
     hipLaunchKernelGGL(rsum_kernel, dim3(1), dim3(64), 0, s, rsump, nt, qscale, sumr, B);
     return hipGetLastError();
 }
@@ -605,22 +623,25 @@ hipError_t launch_quantize_d(const double* dcoef, int64_t p, const int32_t* sel,
                              double* dmaxp, int8_t* dlimbs, int64_t dstride, int bpad, double* dscale,
                              hipStream_t s)
 {
+    if (dstride % 64 || dstride < p || bpad < B || bpad % 16) return hipErrorInvalidValue;
     const int nt = (int)((p + 63) / 64 * 64 + 4095) / 4096;
     hipLaunchKernelGGL(dmax_kernel, dim3(nt, B), dim3(kT), 0, s, dcoef, p, sel, nsel, dmaxp, nt);
-    hipLaunchKernelGGL(dquant_kernel, dim3(nt, B), dim3(kT), 0, s, dcoef, p, sel, nsel, dmaxp, nt, dlimbs, dstride,
-                       bpad, dscale);
+    hipLaunchKernelGGL(dquant_kernel, dim3(nt, B), dim3(kT), 0, s, dcoef, p, sel, nsel, dmaxp, nt, dlimbs, bpad,
+                       dscale);
     return hipGetLastError();
 }
 
 hipError_t launch_mfma_eta(const MfmaEtaArgs& a, hipStream_t s)
 {
-    if (a.bpad < 16 || a.bpad > 64 || a.bpad % 16 || a.B > a.bpad || a.dstride % 64) return hipErrorInvalidValue;
+    if (a.bpad < 16 || a.bpad > 64 || a.bpad % 16 || a.B > a.bpad || a.dstride % 64 || a.dstride < a.p)
+        return hipErrorInvalidValue;
     return a.xt == XT_FP8 ? launch_eta_xt<XT_FP8>(a, s) : launch_eta_xt<XT_I8>(a, s);
 }
 
 hipError_t launch_mfma_xtr(const MfmaArgs& a, hipStream_t s)
 {
-    if (a.bpad < 16 || a.bpad > 64 || a.bpad % 16 || a.B > a.bpad || a.lstride % 256) return hipErrorInvalidValue;
+    if (a.bpad < 16 || a.bpad > 64 || a.bpad % 16 || a.B > a.bpad || a.lstride % 256 || a.lstride < a.n)
+        return hipErrorInvalidValue;
     return a.xt == XT_FP8 ? launch_xt<XT_FP8>(a, s) : launch_xt<XT_I8>(a, s);
 }
 
