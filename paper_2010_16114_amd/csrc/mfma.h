@@ -20,9 +20,9 @@ struct MfmaArgs {
     int B;                  // vectors written (<= bpad)
     const double* qscale;   // [B] quantisation step of each vector
     double* out;            // [B][p] raw sums q_b * sum_i g_ij R_bi
-    int variant;            // pipeline shape (waves x M tiles per wave, subjects per stage, stages ahead):
-                            // 0 = 4x3, 64, 8; 1 = 8x2, 64, 5; 2 = 8x2, 64, 6; 3 = 8x2, 128, 4;
-                            // 4 = 8x2, 128, 3
+    int variant;            // pipeline shape (compute + loader wavefronts, M tiles per wavefront, subjects
+                            // per stage, stages ahead): 0 = 6+2, 2, 128, 6; 1 = 6+2, 2, 128, 4;
+                            // 2 = 6+2, 2, 64, 8; 3 = 8 mixed, 2, 128, 4; 4 = 8 mixed, 2, 128, 3
 };
 constexpr int kMfmaVariants = 5;     // shapes of the X~' R pass
 constexpr int kMfmaEtaVariants = 5;  // shapes of the eta update

@@ -197,6 +197,134 @@ __global__ __launch_bounds__(64 * WAVES, WAVES / 4) void mfma_xtr_kernel(MfmaArg
             }
 }
 
+// The same pass with the two operand streams in different wavefronts: CW
+// compute wavefronts keep a ring of A runs only (HBM), LW loader wavefronts
+// move the stage's limb tile (mostly L2 hits) into LDS two stages ahead.
+// Loads complete in issue order per wavefront, so with one mixed ring every
+// limb load waits behind the A loads issued before it; split, each stream
+// drains at its own pace.  Both roles meet at one barrier per stage.
+template <int XT, int NG, int CW, int LW, int MT, int KS, int PF>
+__global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_split_kernel(MfmaArgs a)
+{
+    static_assert(PF >= 2 && PF % 2 == 0, "the loaders' two-slot ring indexes statically");
+    constexpr int WCOLS = 16 * MT * CW;  // SNP columns per workgroup
+    constexpr int KC = 64 * KS;
+    constexpr int NT = kLimbs * NG;
+    constexpr int NCOL = 16 * NT;
+    constexpr int QC = KC / 16;
+    constexpr int CHUNKS = NCOL * QC;
+    constexpr int LTH = 64 * LW;
+    constexpr int CPL = (CHUNKS + LTH - 1) / LTH;
+    constexpr int RS = NCOL + 8;
+    __shared__ v4i sR[2][QC * RS];
+
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int64_t n = a.n, p = a.p, ldx = a.ldx;
+    const uint8_t* __restrict__ X = static_cast<const uint8_t*>(a.X);
+    const int64_t nstage = (n + KC - 1) / KC;
+    const int64_t nloop = (nstage + PF - 1) / PF * PF;
+
+    if (wid < CW) {
+        const int arow = 16 * (lane >> 4);
+        const int acol = lane & 15;
+        const int64_t jw = (int64_t)blockIdx.x * WCOLS + wid * (16 * MT);
+        v4i acc[MT][NT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = v4i{0, 0, 0, 0};
+        v4i Ab[PF][MT][KS];  // raw runs
+        auto fetch = [&](int64_t t, v4i (&A)[MT][KS]) {
+            const int64_t k0 = t * KC;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    A[mt][ks] = load_raw(X, jw + mt * 16 + acol, p, ldx, k0 + ks * 64 + arow, n);
+        };
+#pragma unroll
+        for (int q = 0; q < PF; ++q) fetch(q, Ab[q]);
+        __syncthreads();
+        for (int64_t s0 = 0; s0 < nloop; s0 += PF) {
+#pragma unroll
+            for (int q = 0; q < PF; ++q) {
+                const int64_t t = s0 + q;
+                const int buf = (int)(t & 1);
+                if (t < nstage) {
+                    const v4i* sb = &sR[buf][(lane >> 4) * RS + acol];
+                    v4i bcur = sb[0];
+#pragma unroll
+                    for (int ks = 0; ks < KS; ++ks) {
+                        v4i A[MT];
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt) A[mt] = decode_a<XT>(Ab[q][mt][ks]);
+#pragma unroll
+                        for (int nt = 0; nt < NT; ++nt) {
+                            const int f = ks * NT + nt + 1;  // next fragment
+                            v4i bnext = bcur;
+                            if (f < KS * NT) bnext = sb[(f / NT) * 4 * RS + (f % NT) * 16];
+#pragma unroll
+                            for (int mt = 0; mt < MT; ++mt)
+                                acc[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], bcur, acc[mt][nt], 0, 0, 0);
+                            bcur = bnext;
+                        }
+                    }
+                }
+                fetch(t + PF, Ab[q]);
+                __syncthreads();
+            }
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int bq = 0; bq < NG; ++bq)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int b = bq * 16 + acol;
+                    const int64_t j = jw + mt * 16 + mfma_c_row(lane, v);
+                    if (j < p && b < a.B) {
+                        const int64_t tot = (int64_t)acc[mt][bq][v] + 256 * (int64_t)acc[mt][NG + bq][v] +
+                                            65536 * (int64_t)acc[mt][2 * NG + bq][v];
+                        a.out[(int64_t)b * p + j] = a.qscale[b] * (double)tot;
+                    }
+                }
+    } else {
+        // loader: chunk c of a stage's contiguous limb tile goes to LDS slot (c / NCOL, c % NCOL)
+        const int lt = threadIdx.x - 64 * CW;
+        const int8_t* rsrc[CPL];
+        int rdst[CPL];
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) {
+            const int c = (lt + LTH * u) % CHUNKS;  // a chunk index past the end repeats a valid one
+            rsrc[u] = a.limbs + 16 * c;
+            rdst[u] = (c / NCOL) * RS + c % NCOL;
+        }
+        v4i Rb[2][CPL];
+        auto fetch_r = [&](int64_t t, v4i (&R)[CPL]) {
+            const int64_t kr = min(t, nstage - 1) * (int64_t)(16 * CHUNKS);
+#pragma unroll
+            for (int u = 0; u < CPL; ++u) R[u] = *reinterpret_cast<const v4i*>(rsrc[u] + kr);
+        };
+        auto store_r = [&](int buf, const v4i (&R)[CPL]) {
+#pragma unroll
+            for (int u = 0; u < CPL; ++u) sR[buf][rdst[u]] = R[u];
+        };
+        fetch_r(0, Rb[0]);
+        fetch_r(1, Rb[1]);
+        store_r(0, Rb[0]);
+        __syncthreads();
+        for (int64_t s0 = 0; s0 < nloop; s0 += PF) {
+#pragma unroll
+            for (int q = 0; q < PF; ++q) {
+                const int64_t t = s0 + q;
+                fetch_r(t + 2, Rb[q % 2]);
+                store_r((int)(t & 1) ^ 1, Rb[(q + 1) % 2]);
+                __syncthreads();
+            }
+        }
+    }
+}
+
 // Byte transpose of a 4 x 4 block: d[r] holds bytes (x_r0, x_r1, x_r2, x_r3);
 // o[c] receives (x_0c, x_1c, x_2c, x_3c).  __builtin_amdgcn_perm(hi, lo, sel)
 // picks byte sel_k of the 8-byte value hi:lo for result byte k.
@@ -581,15 +709,24 @@ hipError_t launch_shape(const MfmaArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int XT, int NG, int CW, int LW, int MT, int KS, int PF>
+hipError_t launch_split(const MfmaArgs& a, hipStream_t s)
+{
+    constexpr int WCOLS = 16 * MT * CW;
+    hipLaunchKernelGGL((mfma_xtr_split_kernel<XT, NG, CW, LW, MT, KS, PF>),
+                       dim3((unsigned)((a.p + WCOLS - 1) / WCOLS)), dim3(64 * (CW + LW)), 0, s, a);
+    return hipGetLastError();
+}
+
 template <int XT, int NG>
 hipError_t launch_ng(const MfmaArgs& a, hipStream_t s)
 {
     switch (a.variant) {
-    case 1: return launch_shape<XT, NG, 8, 2, 1, 5>(a, s);
-    case 2: return launch_shape<XT, NG, 8, 2, 1, 6>(a, s);
+    case 1: return launch_split<XT, NG, 6, 2, 2, 2, 4>(a, s);
+    case 2: return launch_split<XT, NG, 6, 2, 2, 1, 8>(a, s);
     case 3: return launch_shape<XT, NG, 8, 2, 2, 4>(a, s);
     case 4: return launch_shape<XT, NG, 8, 2, 2, 3>(a, s);
-    default: return launch_shape<XT, NG, 4, 3, 1, 8>(a, s);
+    default: return launch_split<XT, NG, 6, 2, 2, 2, 6>(a, s);
     }
 }
 
