@@ -20,9 +20,9 @@ struct MfmaArgs {
     int B;                  // vectors written (<= bpad)
     const double* qscale;   // [B] quantisation step of each vector
     double* out;            // [B][p] raw sums q_b * sum_i g_ij R_bi
-    int variant;            // pipeline shape (compute + loader wavefronts, M tiles per wavefront, subjects
-                            // per stage, stages ahead): 0 = 6+2, 2, 128, 6; 1 = 6+2, 2, 128, 4;
-                            // 2 = 6+2, 2, 64, 8; 3 = 8 mixed, 2, 128, 4; 4 = 8 mixed, 2, 128, 3
+    int variant;            // pipeline shape, 6 compute + 2 loader wavefronts (M tiles per wavefront,
+                            // subjects per stage, stages ahead): 0 = 2, 128, 6; 1 = 2, 128, 4;
+                            // 2 = 3, 64, 6; 3 = 3, 64, 4; 4 = 3, 128, 2
 };
 constexpr int kMfmaVariants = 5;     // shapes of the X~' R pass
 constexpr int kMfmaEtaVariants = 5;  // shapes of the eta update
@@ -41,8 +41,8 @@ struct MfmaEtaArgs {
     const double* dscale;   // [B]
     double* eta;            // [B][n] FP64, updated in place
     const int32_t* active;  // [B] or null
-    int variant;            // (wavefronts, stages of 64 columns ahead): 0 = 8, 4; 1 = 8, 3; 2 = 8, 2;
-                            // 3 = 4, 4; 4 = 4, 3
+    int variant;            // stages of 64 columns ahead: 0, 1 = 6, 4 with 6 compute + 2 loader
+                            // wavefronts; 2, 3, 4 = 4, 3, 2 with 8 wavefronts that load both operands
 };
 
 int mfma_ntile(int64_t n);

@@ -12,14 +12,13 @@
 // largest entry.  The raw sums q_b * sum_i g_ij R_bi go to the same epilogue
 // as the vector path (centring with sum_i q_b R_bi, proximal step).
 //
-// Tiling: a workgroup of WAVES wavefronts owns 16 * MT * WAVES SNP columns (MT
-// M tiles of 16 per wavefront) and all 3 * B limb columns (N tiles of 16), and
-// walks K = n in stages of 64 * KS subjects.  X is read once per pass for all B
-// vectors.  A fragments (16 subjects of one column per lane, one 16-byte load)
-// stay in registers; the stage's limb tile is staged in LDS.  Memory latency is
-// hidden by a ring of PF stages of loads in flight per wavefront.  Several
-// (WAVES, MT, KS, PF) shapes are compiled; the host times them on the live data
-// and keeps the fastest.
+// Tiling: a workgroup of CW compute wavefronts owns 16 * MT * CW SNP columns
+// (MT M tiles of 16 per wavefront) and all 3 * B limb columns (N tiles of
+// 16), and walks K = n in stages of 64 * KS subjects; LW more wavefronts stage
+// the limb tiles.  X is read once per pass for all B vectors.  A fragments (16
+// subjects of one column per lane, one 16-byte load) stay in registers; the
+// stage's limb tile is staged in LDS.  Several (MT, KS, PF) shapes are
+// compiled; the host times them on the live data and keeps the fastest.
 #include "device_common.h"
 #include "mfma.h"
 
@@ -66,143 +65,20 @@ __device__ __forceinline__ v4i decode_a(v4i raw)
     return v;
 }
 
-// Software pipeline shared by both matrix-core kernels.  Every global load of a
-// stage (the HBM stream and the small L2-resident operand alike) is issued PF
-// stages before the stage runs, into ring slot t mod PF, and the ring is
-// consumed in issue order.  Vector-memory loads complete in order, so a wait
-// for the oldest slot never waits for a younger one: PF - 1 stages stay in
-// flight.  The loop body has no branches: stages past the end load clamped,
-// masked (all-zero) tiles.
-
-template <int XT, int NG, int WAVES, int MT, int KS, int PF>
-__global__ __launch_bounds__(64 * WAVES, WAVES / 4) void mfma_xtr_kernel(MfmaArgs a)
-{
-    // WAVES wavefronts of MT M tiles (16 SNP columns each); stages of KS k-steps
-    // of 64 subjects.  Stage t's limb tile goes to LDS buffer t & 1 one stage
-    // early, laid out so that an MFMA B fragment is one 16-byte read per lane,
-    // contiguous across lanes.  The limb rows of subjects >= n are zero (the
-    // limb buffer is cleared at setup and only rows < n are ever written), so
-    // the padding bytes of X that meet them add nothing; the stages past the
-    // last one (the ring runs in whole laps) skip their products.
-    static_assert(PF >= 2, "the ring needs two slots");
-    constexpr int TH = 64 * WAVES;
-    constexpr int WCOLS = 16 * MT * WAVES;  // SNP columns per workgroup
-    constexpr int KC = 64 * KS;
-    constexpr int NT = kLimbs * NG;  // N tiles, limb-major: tile = limb * NG + b / 16
-    constexpr int NCOL = 16 * NT;
-    constexpr int QC = KC / 16;             // 16-byte row chunks per limb column per stage
-    constexpr int CHUNKS = NCOL * QC;       // 16-byte chunks of limb data per stage
-    constexpr int CPT = (CHUNKS + TH - 1) / TH;
-    constexpr int RS = NCOL + 8;            // LDS row stride (16-byte units), padded against bank conflicts
-    __shared__ v4i sR[2][QC * RS];          // [q = 4 ks + lane / 16][limb column]
-
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int64_t n = a.n, p = a.p, ldx = a.ldx;
-    const int64_t jw = (int64_t)blockIdx.x * WCOLS + wid * (16 * MT);  // first column of this wavefront
-    const uint8_t* __restrict__ X = static_cast<const uint8_t*>(a.X);
-    const int8_t* __restrict__ limbs = a.limbs;
-    const int64_t nstage = (n + KC - 1) / KC;
-    const int64_t nloop = (nstage + PF - 1) / PF * PF;
-    const int arow = 16 * (lane >> 4);  // k offset of this lane's 16 bytes within a k-step
-    const int acol = lane & 15;
-
-    // This thread's limb chunks (a chunk index past the end repeats a valid
-    // one).  A stage's limb tile is one contiguous block of CHUNKS 16-byte
-    // chunks ([16-subject row q][limb column]), so consecutive lanes read
-    // consecutive chunks and store them to consecutive LDS slots.
-    const int8_t* rsrc[CPT];
-    int rdst[CPT];
-#pragma unroll
-    for (int u = 0; u < CPT; ++u) {
-        const int c = (threadIdx.x + TH * u) % CHUNKS;
-        rsrc[u] = limbs + 16 * c;
-        rdst[u] = (c / NCOL) * RS + c % NCOL;
-    }
-
-    v4i acc[MT][NT];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = v4i{0, 0, 0, 0};
-
-    v4i Ab[PF][MT][KS];  // raw runs
-    v4i Rb[PF][CPT];
-    auto fetch = [&](int64_t t, v4i (&A)[MT][KS], v4i (&R)[CPT]) {
-        const int64_t k0 = t * KC;  // rows >= n (stages past the end) read as 0
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-                A[mt][ks] = load_raw(X, jw + mt * 16 + acol, p, ldx, k0 + ks * 64 + arow, n);
-        const int64_t kr = min(t, nstage - 1) * (int64_t)(16 * CHUNKS);
-#pragma unroll
-        for (int u = 0; u < CPT; ++u) R[u] = *reinterpret_cast<const v4i*>(rsrc[u] + kr);
-    };
-    auto store_r = [&](int buf, const v4i (&R)[CPT]) {
-#pragma unroll
-        for (int u = 0; u < CPT; ++u) sR[buf][rdst[u]] = R[u];
-    };
-
-#pragma unroll
-    for (int q = 0; q < PF; ++q) fetch(q, Ab[q], Rb[q]);
-    store_r(0, Rb[0]);
-    __syncthreads();
-
-    for (int64_t s0 = 0; s0 < nloop; s0 += PF) {
-#pragma unroll
-        for (int q = 0; q < PF; ++q) {
-            const int64_t t = s0 + q;
-            const int buf = (int)(t & 1);
-            if (t < nstage) {
-                // B fragments in (ks, nt) order, each read one fragment ahead of its MFMAs
-                const v4i* sb = &sR[buf][(lane >> 4) * RS + acol];
-                v4i bcur = sb[0];
-#pragma unroll
-                for (int ks = 0; ks < KS; ++ks) {
-                    v4i A[MT];
-#pragma unroll
-                    for (int mt = 0; mt < MT; ++mt) A[mt] = decode_a<XT>(Ab[q][mt][ks]);
-#pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) {
-                        const int f = ks * NT + nt + 1;  // next fragment
-                        v4i bnext = bcur;
-                        if (f < KS * NT) bnext = sb[(f / NT) * 4 * RS + (f % NT) * 16];
-#pragma unroll
-                        for (int mt = 0; mt < MT; ++mt)
-                            acc[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], bcur, acc[mt][nt], 0, 0, 0);
-                        bcur = bnext;
-                    }
-                }
-            }
-            fetch(t + PF, Ab[q], Rb[q]);
-            store_r(buf ^ 1, Rb[(q + 1) % PF]);
-            __syncthreads();
-        }
-    }
-
-    // C of tile (mt, nt): lane holds rows mfma_c_row(lane, v), column lane & 15.
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int bq = 0; bq < NG; ++bq)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int b = bq * 16 + acol;
-                const int64_t j = jw + mt * 16 + mfma_c_row(lane, v);
-                if (j < p && b < a.B) {
-                    const int64_t tot = (int64_t)acc[mt][bq][v] + 256 * (int64_t)acc[mt][NG + bq][v] +
-                                        65536 * (int64_t)acc[mt][2 * NG + bq][v];
-                    a.out[(int64_t)b * p + j] = a.qscale[b] * (double)tot;
-                }
-            }
-}
-
-// The same pass with the two operand streams in different wavefronts: CW
-// compute wavefronts keep a ring of A runs only (HBM), LW loader wavefronts
-// move the stage's limb tile (mostly L2 hits) into LDS two stages ahead.
-// Loads complete in issue order per wavefront, so with one mixed ring every
-// limb load waits behind the A loads issued before it; split, each stream
-// drains at its own pace.  Both roles meet at one barrier per stage.
+// Software pipelines.  Vector-memory loads complete in issue order per
+// wavefront, so a wait for one load is a wait for every older one.  Every
+// global load of a stage is therefore issued PF stages before the stage runs,
+// into ring slot t mod PF, and each ring is consumed in issue order: PF - 1
+// stages stay in flight.  The loop bodies have no branches on data: stages
+// past the end load clamped tiles whose products are skipped or zero.
+//
+// X~' R: the two operand streams run in different wavefronts.  CW compute
+// wavefronts keep a ring of A runs only (X, from HBM); LW loader wavefronts
+// move each stage's limb tile (mostly L2 hits) into LDS two stages ahead.  In
+// one mixed ring every limb load waits behind the A loads issued before it;
+// split, each stream drains at its own pace.  Both roles meet at one barrier
+// per stage.  The limb rows of subjects >= n are zero (the quantiser writes
+// them so), so the padding bytes of X that meet them add nothing.
 template <int XT, int NG, int CW, int LW, int MT, int KS, int PF>
 __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_split_kernel(MfmaArgs a)
 {
@@ -523,6 +399,191 @@ __global__ __launch_bounds__(256 * NSPLIT, NSPLIT) void mfma_eta_kernel(MfmaEtaA
     }
 }
 
+// The eta update with split roles, as for X~' R: 6 compute wavefronts (3
+// subject blocks of 64 x 2 halves of the b's) stream G and the change-list
+// indices in one ring; 2 loader wavefronts stage the D tiles (L2 hits) into
+// LDS two stages ahead.  A workgroup owns 192 subjects; the G tile's columns
+// keep 64 dword slots (48 used) so the swizzle stays within a column.
+template <int XT, int NG, int PF>
+__global__ __launch_bounds__(512, 2) void mfma_eta_split_kernel(MfmaEtaArgs a)
+{
+    static_assert(PF >= 2 && PF % 2 == 0, "the loaders' two-slot ring indexes statically");
+    constexpr int CTH = 384;              // compute threads
+    constexpr int LTH = 128;              // loader threads
+    constexpr int SUB = 192;              // subjects per workgroup
+    constexpr int SW = 64;                // dword slots per column of the G tile
+    constexpr int RB = SUB / 16;          // 16-byte chunks per column of the G tile
+    constexpr int NT = kLimbs * NG;
+    constexpr int NCOL = 16 * NT;
+    constexpr int NGH = (NG + 1) / 2;
+    constexpr int GPT = 64 * RB / CTH;    // 16-byte chunks of G per compute thread per stage (= 2)
+    constexpr int DCH = 4 * NCOL;         // 16-byte chunks of D per stage
+    constexpr int DPL = (DCH + LTH - 1) / LTH;
+    constexpr int DS = NCOL + 8;
+    static_assert(GPT * CTH == 64 * RB, "G tile splits evenly");
+    __shared__ uint32_t sG[2][64 * SW];
+    __shared__ v4i sD[2][4 * DS];
+    const int nsel = *a.nsel;
+    if (nsel == 0) return;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int64_t n = a.n, p = a.p, ldx = a.ldx;
+    const int64_t i0 = (int64_t)blockIdx.x * SUB;
+    const int64_t nchunk = (nsel + 63) / 64;
+    const int64_t nloop = (nchunk + PF - 1) / PF * PF;
+
+    if (wid < 6) {
+        const int wsub = wid % 3, half = wid / 3;
+        const uint8_t* __restrict__ X = static_cast<const uint8_t*>(a.X);
+        const int32_t* __restrict__ sel = a.sel;
+        int gu[GPT], grb[GPT], gdst[GPT];
+#pragma unroll
+        for (int k = 0; k < GPT; ++k) {
+            const int ch = threadIdx.x + CTH * k;
+            gu[k] = ch / RB;
+            grb[k] = ch % RB;
+            gdst[k] = gu[k] * SW + ((4 * grb[k]) ^ (((gu[k] >> 4) & 3) << 4));
+        }
+        int bqs[NGH];
+#pragma unroll
+        for (int j = 0; j < NGH; ++j) bqs[j] = min(half * NGH + j, NG - 1);
+        auto load_sel = [&](int64_t t, int32_t (&s)[GPT]) {
+#pragma unroll
+            for (int k = 0; k < GPT; ++k) s[k] = sel[min(t * 64 + gu[k], (int64_t)nsel - 1)];
+        };
+        v4i acc[4][kLimbs][NGH];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int l = 0; l < kLimbs; ++l)
+#pragma unroll
+                for (int j = 0; j < NGH; ++j) acc[mt][l][j] = v4i{0, 0, 0, 0};
+        v4i gr[PF][GPT];
+        int32_t sr[PF][GPT];  // column indices of stage t + PF, in slot t mod PF
+        auto fetch = [&](int64_t t, const int32_t (&s)[GPT], v4i (&g)[GPT]) {
+#pragma unroll
+            for (int k = 0; k < GPT; ++k) {
+                const int64_t col = t * 64 + gu[k] < nsel ? (int64_t)s[k] : p;  // past the list: reads as 0
+                g[k] = load_raw(X, col, p, ldx, i0 + 16 * grb[k], n);
+            }
+        };
+        auto store = [&](int64_t t, const v4i (&g)[GPT]) {
+            const int buf = (int)(t & 1);
+#pragma unroll
+            for (int k = 0; k < GPT; ++k)
+                *reinterpret_cast<v4i*>(&sG[buf][gdst[k]]) =
+                    t * 64 + gu[k] < nsel ? decode_a<XT>(g[k]) : v4i{0, 0, 0, 0};
+        };
+        {
+            int32_t s0[PF][GPT];
+#pragma unroll
+            for (int q = 0; q < PF; ++q) load_sel(q, s0[q]);
+#pragma unroll
+            for (int q = 0; q < PF; ++q) load_sel(q + PF, sr[q]);
+#pragma unroll
+            for (int q = 0; q < PF; ++q) fetch(q, s0[q], gr[q]);
+        }
+        store(0, gr[0]);
+        __syncthreads();
+
+        const int xr = wsub * 16 + (lane & 15);  // this lane's dword (4 subjects) within a column
+        const int xs = xr ^ ((lane >> 4) << 4);
+        for (int64_t c0 = 0; c0 < nloop; c0 += PF) {
+#pragma unroll
+            for (int q = 0; q < PF; ++q) {
+                const int64_t t = c0 + q;
+                const int buf = (int)(t & 1);
+                v4i A[4];
+                {
+                    uint32_t f[4][4];
+#pragma unroll
+                    for (int blk = 0; blk < 4; ++blk) {
+                        uint32_t d[4], o[4];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) d[e] = sG[buf][(16 * (lane >> 4) + 4 * blk + e) * SW + xs];
+                        transpose4x4(d, o);
+#pragma unroll
+                        for (int mt = 0; mt < 4; ++mt) f[mt][blk] = o[mt];
+                    }
+#pragma unroll
+                    for (int mt = 0; mt < 4; ++mt)
+                        A[mt] = v4i{(int)f[mt][0], (int)f[mt][1], (int)f[mt][2], (int)f[mt][3]};
+                }
+                {
+                    const v4i* sb = &sD[buf][(lane >> 4) * DS + (lane & 15)];
+                    v4i bcur = sb[bqs[0] * 16];
+#pragma unroll
+                    for (int l = 0; l < kLimbs; ++l)
+#pragma unroll
+                        for (int j = 0; j < NGH; ++j) {
+                            const int f = l * NGH + j + 1;  // next fragment
+                            v4i bnext = bcur;
+                            if (f < kLimbs * NGH) bnext = sb[((f / NGH) * NG + bqs[f % NGH]) * 16];
+#pragma unroll
+                            for (int mt = 0; mt < 4; ++mt)
+                                acc[mt][l][j] =
+                                    __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], bcur, acc[mt][l][j], 0, 0, 0);
+                            bcur = bnext;
+                        }
+                }
+                fetch(t + PF, sr[q], gr[q]);
+                load_sel(t + 2 * PF, sr[q]);
+                store(t + 1, gr[(q + 1) % PF]);
+                __syncthreads();
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NGH; ++j) {
+            if (half * NGH + j >= NG) continue;  // the repeated group of an odd NG
+            const int b = bqs[j] * 16 + (lane & 15);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t i = i0 + 64 * wsub + 4 * mfma_c_row(lane, v) + mt;
+                    if (i < n && b < a.B && (a.active == nullptr || a.active[b])) {
+                        const int64_t tot = (int64_t)acc[mt][0][j][v] + 256 * (int64_t)acc[mt][1][j][v] +
+                                            65536 * (int64_t)acc[mt][2][j][v];
+                        a.eta[(int64_t)b * n + i] += a.dscale[b] * (double)tot;
+                    }
+                }
+        }
+    } else {
+        // loader: chunk c of a stage's contiguous D tile goes to LDS slot (c / NCOL, c % NCOL)
+        const int lt = threadIdx.x - CTH;
+        const int8_t* dsrc[DPL];
+        int ddst[DPL];
+#pragma unroll
+        for (int k = 0; k < DPL; ++k) {
+            const int c = (lt + LTH * k) % DCH;  // a chunk index past the end repeats a valid one
+            dsrc[k] = a.dlimbs + 16 * c;
+            ddst[k] = (c / NCOL) * DS + c % NCOL;
+        }
+        v4i dr[2][DPL];
+        auto fetch_d = [&](int64_t t, v4i (&dd)[DPL]) {
+            const int64_t kd = min(t, nchunk - 1) * (int64_t)(16 * DCH);
+#pragma unroll
+            for (int k = 0; k < DPL; ++k) dd[k] = *reinterpret_cast<const v4i*>(dsrc[k] + kd);
+        };
+        auto store_d = [&](int buf, const v4i (&dd)[DPL]) {
+#pragma unroll
+            for (int k = 0; k < DPL; ++k) sD[buf][ddst[k]] = dd[k];
+        };
+        fetch_d(0, dr[0]);
+        fetch_d(1, dr[1]);
+        store_d(0, dr[0]);
+        __syncthreads();
+        for (int64_t c0 = 0; c0 < nloop; c0 += PF) {
+#pragma unroll
+            for (int q = 0; q < PF; ++q) {
+                const int64_t t = c0 + q;
+                fetch_d(t + 2, dr[q % 2]);
+                store_d((int)(t & 1) ^ 1, dr[(q + 1) % 2]);
+                __syncthreads();
+            }
+        }
+    }
+}
+
 // Largest |D_b(u)| over a tile of 4096 positions of the change list.
 __global__ __launch_bounds__(kT) void dmax_kernel(const double* __restrict__ dcoef, int64_t p,
                                                   const int32_t* __restrict__ sel, const int32_t* __restrict__ nsel,
@@ -677,15 +738,22 @@ hipError_t launch_eta_shape(const MfmaEtaArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int XT, int NG, int PF>
+hipError_t launch_eta_split(const MfmaEtaArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL((mfma_eta_split_kernel<XT, NG, PF>), dim3((unsigned)((a.n + 191) / 192)), dim3(512), 0, s, a);
+    return hipGetLastError();
+}
+
 template <int XT, int NG>
 hipError_t launch_eta_ng(const MfmaEtaArgs& a, hipStream_t s)
 {
     switch (a.variant) {
-    case 1: return launch_eta_shape<XT, NG, 2, 3>(a, s);
-    case 2: return launch_eta_shape<XT, NG, 2, 2>(a, s);
-    case 3: return launch_eta_shape<XT, NG, 1, 4>(a, s);
-    case 4: return launch_eta_shape<XT, NG, 1, 3>(a, s);
-    default: return launch_eta_shape<XT, NG, 2, 4>(a, s);
+    case 1: return launch_eta_split<XT, NG, 4>(a, s);
+    case 2: return launch_eta_shape<XT, NG, 2, 4>(a, s);
+    case 3: return launch_eta_shape<XT, NG, 2, 3>(a, s);
+    case 4: return launch_eta_shape<XT, NG, 2, 2>(a, s);
+    default: return launch_eta_split<XT, NG, 6>(a, s);
     }
 }
 
@@ -698,15 +766,6 @@ hipError_t launch_eta_xt(const MfmaEtaArgs& a, hipStream_t s)
     case 3: return launch_eta_ng<XT, 3>(a, s);
     default: return launch_eta_ng<XT, 4>(a, s);
     }
-}
-
-template <int XT, int NG, int WAVES, int MT, int KS, int PF>
-hipError_t launch_shape(const MfmaArgs& a, hipStream_t s)
-{
-    constexpr int WCOLS = 16 * MT * WAVES;
-    hipLaunchKernelGGL((mfma_xtr_kernel<XT, NG, WAVES, MT, KS, PF>), dim3((unsigned)((a.p + WCOLS - 1) / WCOLS)),
-                       dim3(64 * WAVES), 0, s, a);
-    return hipGetLastError();
 }
 
 template <int XT, int NG, int CW, int LW, int MT, int KS, int PF>
@@ -723,9 +782,9 @@ hipError_t launch_ng(const MfmaArgs& a, hipStream_t s)
 {
     switch (a.variant) {
     case 1: return launch_split<XT, NG, 6, 2, 2, 2, 4>(a, s);
-    case 2: return launch_split<XT, NG, 6, 2, 2, 1, 8>(a, s);
-    case 3: return launch_shape<XT, NG, 8, 2, 2, 4>(a, s);
-    case 4: return launch_shape<XT, NG, 8, 2, 2, 3>(a, s);
+    case 2: return launch_split<XT, NG, 6, 2, 3, 1, 6>(a, s);
+    case 3: return launch_split<XT, NG, 6, 2, 3, 1, 4>(a, s);
+    case 4: return launch_split<XT, NG, 6, 2, 3, 2, 2>(a, s);
     default: return launch_split<XT, NG, 6, 2, 2, 2, 6>(a, s);
     }
 }
