@@ -20,9 +20,9 @@ struct MfmaArgs {
     int B;                  // vectors written (<= bpad)
     const double* qscale;   // [B] quantisation step of each vector
     double* out;            // [B][p] raw sums q_b * sum_i g_ij R_bi
-    int variant;            // pipeline shape, 6 compute + 2 loader wavefronts (M tiles per wavefront,
-                            // subjects per stage, stages ahead): 0 = 2, 128, 6; 1 = 2, 128, 4;
-                            // 2 = 3, 64, 6; 3 = 3, 64, 4; 4 = 3, 128, 2
+    int variant;            // pipeline shape (compute + loader wavefronts, M tiles per compute
+                            // wavefront, subjects per stage, stages ahead): 0 = 7+1, 3, 64, 6;
+                            // 1 = 7+1, 3, 64, 4; 2 = 6+2, 3, 64, 6; 3 = 6+2, 3, 64, 4; 4 = 6+2, 3, 128, 2
 };
 constexpr int kMfmaVariants = 5;     // shapes of the X~' R pass
 constexpr int kMfmaEtaVariants = 5;  // shapes of the eta update

@@ -781,11 +781,11 @@ template <int XT, int NG>
 hipError_t launch_ng(const MfmaArgs& a, hipStream_t s)
 {
     switch (a.variant) {
-    case 1: return launch_split<XT, NG, 6, 2, 2, 2, 4>(a, s);
+    case 1: return launch_split<XT, NG, 7, 1, 3, 1, 4>(a, s);
     case 2: return launch_split<XT, NG, 6, 2, 3, 1, 6>(a, s);
     case 3: return launch_split<XT, NG, 6, 2, 3, 1, 4>(a, s);
     case 4: return launch_split<XT, NG, 6, 2, 3, 2, 2>(a, s);
-    default: return launch_split<XT, NG, 6, 2, 2, 2, 6>(a, s);
+    default: return launch_split<XT, NG, 7, 1, 3, 1, 6>(a, s);
     }
 }
 
