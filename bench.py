@@ -50,11 +50,12 @@ def kernel_source_hash(files) -> str:
     return h.hexdigest()
 
 
-def stored_traffic(summary: str, sources) -> float | None:
+def stored_traffic(summary: str, sources, shape="all") -> float | None:
     """HBM bytes per launch of a kernel, from a committed counter summary under
     profiles/ (FETCH_SIZE + WRITE_SIZE per dispatch, each scaled by what the
     same counter reads for a plain copy of known size), or None when there is
-    none or the kernel's sources changed since it was taken."""
+    none, the kernel's sources changed since it was taken, or it holds no
+    figure for the pipeline shape that ran."""
     path = os.path.join(ROOT, "profiles", summary)
     try:
         text = open(path).read()
@@ -62,12 +63,14 @@ def stored_traffic(summary: str, sources) -> float | None:
         return None
     vals = {}
     for line in text.splitlines():
-        if ":" in line and line.strip().startswith(("traffic_bytes_per_launch", "source_sha256")):
-            k, v = line.strip().strip("`").split(":", 1)
-            vals[k.strip()] = v.strip().strip("`")
-    if vals.get("source_sha256") != kernel_source_hash(sources) or "traffic_bytes_per_launch" not in vals:
+        line = line.strip().lstrip("- ")
+        if line.startswith(("traffic_bytes_per_launch_", "source_sha256")) and ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_sha256") != kernel_source_hash(sources):
         return None
-    return float(vals["traffic_bytes_per_launch"])
+    v = vals.get(f"traffic_bytes_per_launch_{shape}")
+    return float(v) if v is not None else None
 
 
 MFMA_SOURCES = ("paper_2010_16114_amd/csrc/mfma.hip", "paper_2010_16114_amd/csrc/mfma.h")
@@ -171,7 +174,7 @@ def cpu_baseline_gauss(d, lam, sigma, budget_s: float = 15.0):
     t0 = time.perf_counter()
     oracle.fit(M, d.time, d.event, lam, sigma, max_iter=1)
     one = time.perf_counter() - t0
-    k = int(max(2, min(100, budget_s / max(one / 2, 1e-6))))
+    k = int(max(2, min(600, budget_s / max(one / 2, 1e-6))))
     log(f"oracle: one step ~{one / 2:.2f} s; timing {k} steps")
     t0 = time.perf_counter()
     oracle.fit(M, d.time, d.event, lam, sigma, max_iter=k)
@@ -220,6 +223,7 @@ def bench_geno_batched(args):
     nnz = (beta != 0).sum(dim=1).cpu().numpy()
     log(f"{args.steps} steps x {B} lambdas in {elapsed:.3f} s; nnz per lambda {nnz.min()}..{nnz.max()}")
     bpad = (B + 15) // 16 * 16
+    tuning = cox.mfma_tuning()
     # Algorithmic bytes of one launch of the matrix-core X~' R kernel: X once,
     # the residual limbs once, the raw column sums written once.
     xtr_bytes = n * p + 3 * bpad * n + B * p * 8
@@ -247,14 +251,15 @@ def bench_geno_batched(args):
         "iters_per_s": args.steps / elapsed,
         "phases_ms_per_step": {"xtr_prox": xtr_ms / max(xtr_n, 1), "risk": risk_ms / max(risk_n, 1),
                                "eta_update": eta_ms / max(eta_n, 1)},
-        "kernels_ms_per_launch": {"mfma_xtr_kernel": xk_ms / max(xk_n, 1), "mfma_eta_kernel": ek_ms / max(ek_n, 1)},
-        "roofline": {"bound": "hbm", "kernel": "mfma_xtr_kernel (X~' R for B lambdas)",
+        "kernels_ms_per_launch": {"mfma_xtr_split_kernel": xk_ms / max(xk_n, 1), "mfma_eta_kernel": ek_ms / max(ek_n, 1)},
+        "roofline": {"bound": "hbm", "kernel": "mfma_xtr_split_kernel (X~' R for B lambdas)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": stored_traffic(f"mfma_xtr_kernel_geno_fp8_{n}x{p}_b{B}_traffic.md", MFMA_SOURCES),
+                     "traffic": stored_traffic(f"mfma_xtr_kernel_geno_fp8_{n}x{p}_b{B}_traffic.md", MFMA_SOURCES,
+                                               f"shape{tuning['xtr_variant']}"),
                      "algorithmic_bytes_per_launch": xtr_bytes, "kernel_ms": 1e3 * xtr_avg, "launches_timed": xk_n,
                      "mfma_tops": tops, "mfma_frac_int8": tops / INT8_MFMA_PEAK_TOPS},
         "nnz_range": [int(nnz.min()), int(nnz.max())],
-        "autotune": cox.mfma_tuning(),
+        "autotune": tuning,
     }
     if args.fp32_slice > 0:
         res["fp32_comparator"] = fp32_comparator(args, d, G, mu_d, sc_d, lams, sigma, n, p)
@@ -306,7 +311,7 @@ def fp32_comparator(args, d, G, mu_d, sc_d, lams, sigma, n, p):
                       f"{args.steps} steps from beta=0 at lambda_max and 0.01*lambda_max; rate scaled by {ps}/{p}"}
 
 
-def cpu_baseline_geno(d, lam, sigma, p_full, p_sample: int = 1000, budget_s: float = 15.0):
+def cpu_baseline_geno(d, lam, sigma, p_full, p_sample: int = 8000, budget_s: float = 15.0):
     """The FP64 oracle on a column sample of the genotype workload: its steps
     from beta = 0 at the smallest lambda, timed on the host cores and scaled to
     the full column count (the oracle's step cost is linear in p)."""
@@ -321,7 +326,8 @@ def cpu_baseline_geno(d, lam, sigma, p_full, p_sample: int = 1000, budget_s: flo
     t0 = time.perf_counter()
     oracle.fit(M, d.time, d.event, lam, sigma, max_iter=1)
     one = time.perf_counter() - t0
-    k = int(max(2, min(50, budget_s / max(one / 2, 1e-6))))
+    k = int(max(2, min(200, budget_s / max(one / 2, 1e-6))))
+    log(f"oracle: one step on {p_sample} columns ~{one / 2:.2f} s; timing {k} steps")
     t0 = time.perf_counter()
     oracle.fit(M, d.time, d.event, lam, sigma, max_iter=k)
     dt = time.perf_counter() - t0
