@@ -85,3 +85,54 @@ def test_batched_400k_x_500k_first_step(release):
     # the objective decreased for every lambda
     assert np.all(f1 <= f0)
     assert np.allclose(f0, f0[0], rtol=1e-12)
+
+
+def test_fp32_gaussian_20k_x_50k_iterates(release):
+    """The plain FP32 method at its full size (20,000 x 50,000 Gaussian X,
+    lambda = 0.3 lambda_max, the power-iteration step): GPU and FP64 oracle
+    iterates after 20 steps from beta = 0, element by element."""
+    d = coxsim.config1()
+    X = torch.from_numpy(d.X32).cuda()
+    cox = P.Cox(X, d.time, d.event)
+    M = oracle.Matrix.dense(d.X32)
+    lam = 0.3 * oracle.lambda_max(M, d.time, d.event)
+    s2, _ = cox.opnorm2()
+    sigma = 1.0 / (2.0 * s2)
+    K = 20
+    beta, _, obj, _ = cox.fit_path([lam], max_iter=K, tol=0.0, step=sigma)
+    bo, tr, _, _ = oracle.fit(M, d.time, d.event, lam, sigma, max_iter=K)
+    b = beta.cpu().numpy()[0].astype(np.float64)
+    rel = np.abs(b - bo).max() / np.abs(bo).max()
+    print(f"\nFP32 20,000 x 50,000 after {K} steps: max|beta - beta_oracle| / max|beta_oracle| = {rel:.2e}, "
+          f"objective rel. diff {abs(obj[0] - tr[-1]) / abs(tr[-1]):.2e}, nnz {np.count_nonzero(bo)}")
+    assert rel <= 1e-5
+    assert obj[0] == pytest.approx(tr[-1], rel=1e-6)
+
+
+def test_batched_iterates_at_n_400k(release):
+    """The batched matrix-core path at the real n: 400,000 x 2,000 FP8
+    genotypes (same generator), 64 lambdas from lambda_max to 0.01 lambda_max,
+    10 steps from beta = 0; GPU iterates against the FP64 oracle's at three
+    lambdas across the path."""
+    d = coxsim.genotype_problem(400000, 2000, 40, 0.80, 4711)
+    G, mu, s = _device_problem(d, fmt=1)
+    B = 64
+    cox = P.Cox(G, d.time, d.event, xtype=P.X_FP8_E4M3, n=d.n, center=torch.from_numpy(mu).cuda(),
+                scale=torch.from_numpy(s).cuda(), max_batch=B)
+    M = oracle.Matrix.genotype(d.G, d.mu, d.s)
+    lams = coxsim.lambda_grid(oracle.lambda_max(M, d.time, d.event), B, 0.01)
+    lams[0] *= 1 + 1e-6
+    sigma = 1.0 / (2.0 * cox.opnorm2()[0])  # an input to both sides
+    K = 10
+    beta, _, obj, _ = cox.fit_path(lams, max_iter=K, tol=0.0, step=sigma)
+    beta = beta.cpu().numpy()
+    assert cox.mfma_tuning()["xtr_variant"] >= 0  # the matrix-core pass ran
+    worst = 0.0
+    for b in (5, 32, 63):
+        bo, tr, _, _ = oracle.fit(M, d.time, d.event, lams[b], sigma, max_iter=K)
+        e = np.abs(beta[b] - bo).max() / np.abs(bo).max()
+        worst = max(worst, e)
+        assert e <= 1e-5, (b, e)
+        assert obj[b] == pytest.approx(tr[-1], rel=1e-6), b
+    print(f"\nbatched FP8 400,000 x 2,000, B = 64, {K} steps: worst max|beta - beta_oracle| / max|beta_oracle| "
+          f"over sampled lambdas = {worst:.2e}")
