@@ -204,13 +204,14 @@ def bench_geno_batched(args):
     sigma = 1.0 / (2.0 * s2)
     lams = coxsim.lambda_grid(lmax, B, 0.01)
     log(f"lambda_max={lmax:.6g} ||X~||^2~{s2:.6g} ({pit} power steps) sigma={sigma:.4g}")
-    log(f"warmup {args.warmup} steps (B={B})")
-    cox.fit_path(lams, max_iter=args.warmup, tol=0.0, step=sigma)
+    log(f"warmup {args.warmup} steps (B={B}, residual in {args.residual_bits}-bit integers)")
+    cox.fit_path(lams, max_iter=args.warmup, tol=0.0, step=sigma, residual_bits=args.residual_bits)
     torch.cuda.synchronize()
     log(f"timing {args.steps} steps")
     cox.timing(True)
     t0 = time.perf_counter()
-    beta, iters, obj, _ = cox.fit_path(lams, max_iter=args.steps, tol=0.0, step=sigma)
+    beta, iters, obj, _ = cox.fit_path(lams, max_iter=args.steps, tol=0.0, step=sigma,
+                                       residual_bits=args.residual_bits)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     xtr_ms, xtr_n = cox.timing_read("xtr")
@@ -226,10 +227,11 @@ def bench_geno_batched(args):
     tuning = cox.mfma_tuning()
     # Algorithmic bytes of one launch of the matrix-core X~' R kernel: X once,
     # the residual limbs once, the raw column sums written once.
-    xtr_bytes = n * p + 3 * bpad * n + B * p * 8
+    limbs = 3 if args.residual_bits == 22 else 2
+    xtr_bytes = n * p + limbs * bpad * n + B * p * 8
     xtr_avg = xk_ms / max(xk_n, 1) / 1e3
     achieved = xtr_bytes / xtr_avg / 1e9
-    tops = 2.0 * n * p * 3 * bpad / xtr_avg / 1e12
+    tops = 2.0 * n * p * limbs * bpad / xtr_avg / 1e12
     res = {
         "metric": METRIC,
         "value": args.steps * B / elapsed,
@@ -246,7 +248,9 @@ def bench_geno_batched(args):
         "config": {"workload": f"l1-Cox ISTA path, FP8 E4M3 genotype X n={n} p={p} (standardised on the fly), "
                                f"B={B} lambdas log-spaced lambda_max..0.01*lambda_max, {args.steps} steps from beta=0",
                    "n": n, "p": p, "B": B, "x_storage": "fp8_e4m3 allele counts", "x_bytes": n * p,
-                   "gradient": "int8 MFMA, residual in 3 exact int8 limbs, int32 accumulation",
+                   "gradient": f"int8 MFMA, residual rounded to {args.residual_bits}-bit integers in {limbs} "
+                               f"int8 limbs, exact int32 accumulation",
+                   "residual_bits": args.residual_bits,
                    "eta": "int8 MFMA over the changed columns, FP64 accumulator"},
         "iters_per_s": args.steps / elapsed,
         "phases_ms_per_step": {"xtr_prox": xtr_ms / max(xtr_n, 1), "risk": risk_ms / max(risk_n, 1),
@@ -255,7 +259,7 @@ def bench_geno_batched(args):
         "roofline": {"bound": "hbm", "kernel": "mfma_xtr_split_kernel (X~' R for B lambdas)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": stored_traffic(f"mfma_xtr_kernel_geno_fp8_{n}x{p}_b{B}_traffic.md", MFMA_SOURCES,
-                                               f"shape{tuning['xtr_variant']}"),
+                                               f"shape{tuning['xtr_variant']}" + ("" if limbs == 3 else "_limbs2")),
                      "algorithmic_bytes_per_launch": xtr_bytes, "kernel_ms": 1e3 * xtr_avg, "launches_timed": xk_n,
                      "mfma_tops": tops, "mfma_frac_int8": tops / INT8_MFMA_PEAK_TOPS},
         "nnz_range": [int(nnz.min()), int(nnz.max())],
@@ -344,6 +348,9 @@ def main():
     ap.add_argument("--workload", default="geno-fp8-batched", choices=["geno-fp8-batched", "gauss-fp32"])
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--power-steps", type=int, default=20)
+    ap.add_argument("--residual-bits", type=int, default=22, choices=[22, 14],
+                    help="batched workload: residual rounding of the matrix-core gradient pass "
+                         "(22: three int8 limbs, the default; 14: two limbs)")
     ap.add_argument("--fp32-slice", type=int, default=31250,
                     help="columns of the FP32 comparator of the batched workload (0: skip)")
     ap.add_argument("--calibrate-copy-gb", type=float, default=0.0,

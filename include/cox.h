@@ -137,6 +137,12 @@ typedef struct {
     int32_t eta_mode;   /* 0: eta updated from the columns whose beta changed (FP64 accumulator);
                            1: eta recomputed by a dense pass over X every step (two X passes) */
     int32_t poll;       /* steps between host checks of the convergence flags; <= 0: 16 */
+    int32_t residual_bits; /* batched matrix-core gradient pass only (allele counts, B > 8): the
+                              residual r_b is rounded to integers |R| <= 2^bits relative to
+                              max |r_b| before the exact int8 contraction.  0 or 22: three
+                              limbs (default); 14: two limbs, a third less limb traffic and
+                              matrix-core work at about 2^-15 relative rounding of r.  Other
+                              values are INVALID_ARG. */
 } cox_fit_opts;
 
 /* Solve B problems (one per lambda_b) by ISTA, all sharing each pass over X.

@@ -41,7 +41,7 @@ class _Matrix(ctypes.Structure):
 class FitOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("lag", ctypes.c_int32),
                 ("step", ctypes.c_double), ("warm_start", ctypes.c_int32), ("eta_mode", ctypes.c_int32),
-                ("poll", ctypes.c_int32)]
+                ("poll", ctypes.c_int32), ("residual_bits", ctypes.c_int32)]
 
 
 _lib = None
@@ -179,7 +179,7 @@ class Cox:
         self._check(st, "cox_prox_apply")
 
     def fit_path(self, lambdas, max_iter: int = 1000, tol: float = 1e-5, lag: int = 10, step: float = 0.0,
-                 beta=None, eta_mode: int = 0, poll: int = 16):
+                 beta=None, eta_mode: int = 0, poll: int = 16, residual_bits: int = 0):
         """ISTA for each lambda.  Returns (beta (B, p) tensor, iters, obj, status)."""
         torch = self._torch
         lam = np.ascontiguousarray(np.asarray(lambdas, np.float64).reshape(-1))
@@ -191,7 +191,8 @@ class Cox:
         assert Bb == B
         iters = np.zeros(B, np.int32)
         obj = np.zeros(B, np.float64)
-        o = FitOpts(int(max_iter), float(tol), int(lag), float(step), int(warm), int(eta_mode), int(poll))
+        o = FitOpts(int(max_iter), float(tol), int(lag), float(step), int(warm), int(eta_mode), int(poll),
+                    int(residual_bits))
         st = lib().cox_fit_path(self._h, _np_ptr(lam), B, ctypes.byref(o), beta2.data_ptr(), _np_ptr(iters),
                                 _np_ptr(obj))
         self._check(st, "cox_fit_path", allow=(OK, ERR_NOT_CONVERGED))

@@ -70,8 +70,10 @@ struct cox_ctx {
     int8_t* dlimbs = nullptr;    // [3][Bmax16][dstride] eta-update limbs
     int64_t dstride = 0;
     double *dscale = nullptr, *dmaxp = nullptr;
-    int xtr_variant = -1, eta_variant = -1;  // chosen pipeline shapes (-1: not tuned yet)
+    int xtr_variant = -1, eta_variant = -1;  // pipeline shapes last used (-1: not tuned yet)
     float xtr_tune_ms[kMfmaVariants] = {}, eta_tune_ms[kMfmaVariants] = {};
+    int xtr_by_limbs[4] = {-1, -1, -1, -1};  // X~' R shape chosen for 2 and 3 residual limbs
+    float xtr_ms_by_limbs[4][kMfmaVariants] = {};
     int geno_state = -1;         // -1 unchecked, 0 counts 0/1/2 only, 1 other values
     int nsplit = 1;
     int64_t split_rows = 0;
@@ -390,29 +392,35 @@ GemvtArgs gemvt_args(cox_ctx* c, int mode)
     return g;
 }
 
-cox_status run_gemvt(cox_ctx* c, GemvtArgs g, int B)
+// X~' r for B vectors: the matrix-core pass (residual in rlimbs int8 limbs)
+// when X holds allele counts and B > kGroup, else the vector pass.
+cox_status run_gemvt(cox_ctx* c, GemvtArgs g, int B, int rlimbs = 3)
 {
     if (use_mfma(c, B)) {
         tmark(c, COX_PHASE_XTR);
         const int bpad = (int)round_up(B, 16);
-        HIPCHK(launch_quantize(c->r64, c->n, B, c->rmaxp, c->rsump, c->limbs, c->rstride, bpad, c->qscale, c->sumr,
-                               c->stream),
+        HIPCHK(launch_quantize(c->r64, c->n, B, c->rmaxp, c->rsump, c->limbs, c->rstride, bpad, rlimbs, c->qscale,
+                               c->sumr, c->stream),
                "quantise r");
-        MfmaArgs m{c->x.X, c->x.xt, c->n, c->p, c->x.ldx, c->limbs, c->rstride, bpad, B, c->qscale, c->part_xtr, 0};
+        MfmaArgs m{c->x.X,   c->x.xt, c->n, c->p,      c->x.ldx,     c->limbs, c->rstride,
+                   bpad,     rlimbs,  B,    c->qscale, c->part_xtr, 0};
+        int& chosen = c->xtr_by_limbs[rlimbs];
         const int forced = forced_variant("COXHIP_MFMA_VARIANT", kMfmaVariants);
         if (forced >= 0) {
-            c->xtr_variant = forced;
-        } else if (c->xtr_variant < 0) {
-            const std::string key = tune_key(c, "xtr", bpad);
-            c->xtr_variant = tune_cache_lookup(key, kMfmaVariants);
-            if (c->xtr_variant < 0) {
-                c->xtr_variant = autotune(
+            chosen = forced;
+        } else if (chosen < 0) {
+            const std::string key = tune_key(c, rlimbs == 3 ? "xtr" : "xtr2", bpad);
+            chosen = tune_cache_lookup(key, kMfmaVariants);
+            if (chosen < 0) {
+                chosen = autotune(
                     c, kMfmaVariants, [&](int v) { m.variant = v; (void)launch_mfma_xtr(m, c->stream); },
-                    c->xtr_tune_ms);
-                tune_cache_store(key, c->xtr_variant);
+                    c->xtr_ms_by_limbs[rlimbs]);
+                tune_cache_store(key, chosen);
             }
         }
-        m.variant = c->xtr_variant;
+        c->xtr_variant = chosen;
+        std::copy(c->xtr_ms_by_limbs[rlimbs], c->xtr_ms_by_limbs[rlimbs] + kMfmaVariants, c->xtr_tune_ms);
+        m.variant = chosen;
         tmark(c, COX_PHASE_XTR_KERNEL);
         HIPCHK(launch_mfma_xtr(m, c->stream), "X' R on matrix cores");
         tmark(c, COX_PHASE_XTR_KERNEL);
@@ -770,11 +778,13 @@ cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_
     if (!beta) return fail(c, COX_ERR_INVALID_ARG, "beta is NULL");
     STCHK(check_batch(c, B));
     STCHK(check_lambdas(c, lambdas, B));
-    cox_fit_opts o{1000, 1e-5, 10, 0.0, 0, 0, 16};
+    cox_fit_opts o{1000, 1e-5, 10, 0.0, 0, 0, 16, 0};
     if (opts_in) o = *opts_in;
     if (o.max_iter < 0 || !(o.tol >= 0) || o.lag < 1 || o.lag > kMaxHist - 1 || !std::isfinite(o.step) ||
-        (o.warm_start != 0 && o.warm_start != 1) || (o.eta_mode != 0 && o.eta_mode != 1))
+        (o.warm_start != 0 && o.warm_start != 1) || (o.eta_mode != 0 && o.eta_mode != 1) ||
+        (o.residual_bits != 0 && o.residual_bits != 22 && o.residual_bits != 14))
         return fail(c, COX_ERR_INVALID_ARG, "bad cox_fit_opts");
+    const int rlimbs = o.residual_bits == 14 ? 2 : 3;
     const int poll = o.poll > 0 ? o.poll : 16;
     double step = o.step;
     if (step <= 0) {
@@ -861,7 +871,7 @@ cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_
         HIPCHK(launch_risk(ra, c->stream), "risk-set sums");
         tmark(c, COX_PHASE_RISK);
         if (it < o.max_iter) {
-            STCHK(run_gemvt(c, g, B));
+            STCHK(run_gemvt(c, g, B, rlimbs));
             if (o.eta_mode == 0) HIPCHK(launch_compact(c->chg_cnt, c->chg_idx, c->nblk, c->sel, c->nsel, c->stream), "compact");
         }
         if ((it + 1) % poll == 0 && it < o.max_iter) {

@@ -13,10 +13,12 @@ struct MfmaArgs {
     const void* X;          // column-major allele counts (int8 or FP8 E4M3 codes)
     int xt;                 // XT_I8 or XT_FP8
     int64_t n, p, ldx;      // ldx % 16 == 0, X 16-byte aligned
-    const int8_t* limbs;    // [lstride / 16][3 * bpad][16] residual limbs by 16-subject chunk, limb-major
-                            // within a chunk (column limb * bpad + b); rows n .. round_up(n, 256) zero
+    const int8_t* limbs;    // [lstride / 16][limbs_n * bpad][16] residual limbs by 16-subject chunk,
+                            // limb-major within a chunk (column limb * bpad + b); rows n .. round_up(n, 256)
+                            // zero
     int64_t lstride;        // subject rows the limb buffer holds: a multiple of 256, >= n
     int bpad;               // 16, 32, 48 or 64
+    int limbs_n;            // residual limbs: 3 (|R| <= 2^22) or 2 (|R| <= 2^14)
     int B;                  // vectors written (<= bpad)
     const double* qscale;   // [B] quantisation step of each vector
     double* out;            // [B][p] raw sums q_b * sum_i g_ij R_bi
@@ -53,7 +55,7 @@ hipError_t launch_quantize_d(const double* dcoef, int64_t p, const int32_t* sel,
 hipError_t launch_mfma_eta(const MfmaEtaArgs& a, hipStream_t s);
 // r64 [B][n] -> limbs, qscale [B], sumr [B] = q_b * sum_i R_bi
 hipError_t launch_quantize(const double* r64, int64_t n, int B, double* rmaxp, long long* rsump, int8_t* limbs,
-                           int64_t lstride, int bpad, double* qscale, double* sumr, hipStream_t s);
+                           int64_t lstride, int bpad, int nlimb, double* qscale, double* sumr, hipStream_t s);
 hipError_t launch_mfma_xtr(const MfmaArgs& a, hipStream_t s);
 hipError_t launch_geno_check(const void* X, int xt, int64_t n, int64_t p, int64_t ldx, int* bad, hipStream_t s);
 

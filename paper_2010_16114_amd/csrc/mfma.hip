@@ -30,6 +30,7 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 constexpr int kT = 256;
 constexpr int kLimbs = 3;
 constexpr int kQBits = 22;       // |R| <= 2^22 keeps the top limb within int8
+constexpr int kQBits2 = 14;      // the same for two limbs (the residual's faster, coarser form)
 
 // Allele-count bytes -> int8 counts.  FP8 E4M3 codes of 0, 1, 2 are 0x00, 0x38,
 // 0x40: bit 3 marks 1 and bit 6 marks 2 (other codes are rejected beforehand).
@@ -79,13 +80,14 @@ __device__ __forceinline__ v4i decode_a(v4i raw)
 // split, each stream drains at its own pace.  Both roles meet at one barrier
 // per stage.  The limb rows of subjects >= n are zero (the quantiser writes
 // them so), so the padding bytes of X that meet them add nothing.
-template <int XT, int NG, int CW, int LW, int MT, int KS, int PF>
+template <int XT, int NG, int RL, int CW, int LW, int MT, int KS, int PF>
 __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_split_kernel(MfmaArgs a)
 {
     static_assert(PF >= 2 && PF % 2 == 0, "the loaders' two-slot ring indexes statically");
+    static_assert(RL == 2 || RL == 3, "the residual comes in 2 or 3 limbs");
     constexpr int WCOLS = 16 * MT * CW;  // SNP columns per workgroup
     constexpr int KC = 64 * KS;
-    constexpr int NT = kLimbs * NG;
+    constexpr int NT = RL * NG;         // N tiles, limb-major: tile = limb * NG + b / 16
     constexpr int NCOL = 16 * NT;
     constexpr int QC = KC / 16;
     constexpr int CHUNKS = NCOL * QC;
@@ -159,8 +161,8 @@ __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_split_
                     const int b = bq * 16 + acol;
                     const int64_t j = jw + mt * 16 + mfma_c_row(lane, v);
                     if (j < p && b < a.B) {
-                        const int64_t tot = (int64_t)acc[mt][bq][v] + 256 * (int64_t)acc[mt][NG + bq][v] +
-                                            65536 * (int64_t)acc[mt][2 * NG + bq][v];
+                        int64_t tot = (int64_t)acc[mt][bq][v] + 256 * (int64_t)acc[mt][NG + bq][v];
+                        if constexpr (RL == 3) tot += 65536 * (int64_t)acc[mt][2 * NG + bq][v];
                         a.out[(int64_t)b * p + j] = a.qscale[b] * (double)tot;
                     }
                 }
@@ -651,22 +653,24 @@ __global__ __launch_bounds__(kT) void rmax_kernel(const double* __restrict__ r, 
     if (threadIdx.x == 0) part[(int64_t)b * ntile + blockIdx.x] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
 }
 
-// Quantise r to three int8 limbs per vector; exact partial sums of R.  Limb
+// Quantise r to nlimb int8 limbs per vector (3: |R| <= 2^22; 2: |R| <= 2^14,
+// the top limb within int8 either way); exact partial sums of R.  Limb
 // layout: 16-subject chunks, [i / 16][limb * bpad + b][i % 16], so that a
-// stage's tile (all 3 * bpad limb columns of KC subjects) is one contiguous
-// block.  Rows n .. round_up(n, 256) - 1 are written as zeros: the X~' R
+// stage's tile (all nlimb * bpad limb columns of KC subjects) is one
+// contiguous block.  Rows n .. round_up(n, 256) - 1 are written as zeros: the X~' R
 // kernel reads whole 64- or 128-subject stages, and the layout changes with
 // bpad, so stale limbs from an earlier batch size must not survive there.
 __global__ __launch_bounds__(kT) void quantize_kernel(const double* __restrict__ r, int64_t n,
                                                       const double* __restrict__ rmaxp, int ntile,
-                                                      int8_t* __restrict__ limbs, int bpad,
+                                                      int8_t* __restrict__ limbs, int bpad, int nlimb,
                                                       double* __restrict__ qscale, long long* __restrict__ rsump)
 {
     __shared__ long long sh[kT / 64];
     const int b = blockIdx.y;
     double mx = 0.0;
     for (int t = 0; t < ntile; ++t) mx = fmax(mx, rmaxp[(int64_t)b * ntile + t]);
-    const double q = mx > 0.0 ? mx / (double)(1 << kQBits) : 1.0;
+    const int bits = nlimb == 2 ? kQBits2 : kQBits;
+    const double q = mx > 0.0 ? mx / (double)(1 << bits) : 1.0;
     if (blockIdx.x == 0 && threadIdx.x == 0) qscale[b] = q;
     long long sum = 0;
     const int64_t npad = (n + 255) / 256 * 256;
@@ -675,12 +679,15 @@ __global__ __launch_bounds__(kT) void quantize_kernel(const double* __restrict__
         const int R = i < n ? (int)llrint(r[(int64_t)b * n + i] / q) : 0;
         const int d0 = ((R + 128) & 255) - 128;
         const int R1 = (R - d0) >> 8;
-        const int d1 = ((R1 + 128) & 255) - 128;
-        const int d2 = (R1 - d1) >> 8;
-        int8_t* dst = limbs + ((i >> 4) * (3 * bpad) + b) * 16 + (i & 15);
+        int8_t* dst = limbs + ((i >> 4) * (nlimb * bpad) + b) * 16 + (i & 15);
         dst[0] = (int8_t)d0;
-        dst[16 * bpad] = (int8_t)d1;
-        dst[32 * bpad] = (int8_t)d2;
+        if (nlimb == 2) {
+            dst[16 * bpad] = (int8_t)R1;  // |R1| <= 64 when |R| <= 2^14
+        } else {
+            const int d1 = ((R1 + 128) & 255) - 128;
+            dst[16 * bpad] = (int8_t)d1;
+            dst[32 * bpad] = (int8_t)((R1 - d1) >> 8);
+        }
         sum += R;
     }
     for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
@@ -768,36 +775,42 @@ hipError_t launch_eta_xt(const MfmaEtaArgs& a, hipStream_t s)
     }
 }
 
-template <int XT, int NG, int CW, int LW, int MT, int KS, int PF>
+template <int XT, int NG, int RL, int CW, int LW, int MT, int KS, int PF>
 hipError_t launch_split(const MfmaArgs& a, hipStream_t s)
 {
     constexpr int WCOLS = 16 * MT * CW;
-    hipLaunchKernelGGL((mfma_xtr_split_kernel<XT, NG, CW, LW, MT, KS, PF>),
+    hipLaunchKernelGGL((mfma_xtr_split_kernel<XT, NG, RL, CW, LW, MT, KS, PF>),
                        dim3((unsigned)((a.p + WCOLS - 1) / WCOLS)), dim3(64 * (CW + LW)), 0, s, a);
     return hipGetLastError();
 }
 
-template <int XT, int NG>
+template <int XT, int NG, int RL>
 hipError_t launch_ng(const MfmaArgs& a, hipStream_t s)
 {
     switch (a.variant) {
-    case 1: return launch_split<XT, NG, 7, 1, 3, 1, 4>(a, s);
-    case 2: return launch_split<XT, NG, 6, 2, 3, 1, 6>(a, s);
-    case 3: return launch_split<XT, NG, 6, 2, 3, 1, 4>(a, s);
-    case 4: return launch_split<XT, NG, 6, 2, 3, 2, 2>(a, s);
-    default: return launch_split<XT, NG, 7, 1, 3, 1, 6>(a, s);
+    case 1: return launch_split<XT, NG, RL, 7, 1, 3, 1, 4>(a, s);
+    case 2: return launch_split<XT, NG, RL, 6, 2, 3, 1, 6>(a, s);
+    case 3: return launch_split<XT, NG, RL, 6, 2, 3, 1, 4>(a, s);
+    case 4: return launch_split<XT, NG, RL, 6, 2, 3, 2, 2>(a, s);
+    default: return launch_split<XT, NG, RL, 7, 1, 3, 1, 6>(a, s);
+    }
+}
+
+template <int XT, int RL>
+hipError_t launch_rl(const MfmaArgs& a, hipStream_t s)
+{
+    switch (a.bpad / 16) {
+    case 1: return launch_ng<XT, 1, RL>(a, s);
+    case 2: return launch_ng<XT, 2, RL>(a, s);
+    case 3: return launch_ng<XT, 3, RL>(a, s);
+    default: return launch_ng<XT, 4, RL>(a, s);
     }
 }
 
 template <int XT>
 hipError_t launch_xt(const MfmaArgs& a, hipStream_t s)
 {
-    switch (a.bpad / 16) {
-    case 1: return launch_ng<XT, 1>(a, s);
-    case 2: return launch_ng<XT, 2>(a, s);
-    case 3: return launch_ng<XT, 3>(a, s);
-    default: return launch_ng<XT, 4>(a, s);
-    }
+    return a.limbs_n == 2 ? launch_rl<XT, 2>(a, s) : launch_rl<XT, 3>(a, s);
 }
 
 }  // namespace
@@ -805,12 +818,14 @@ hipError_t launch_xt(const MfmaArgs& a, hipStream_t s)
 int mfma_ntile(int64_t n) { return (int)((n + 4095) / 4096); }
 
 hipError_t launch_quantize(const double* r64, int64_t n, int B, double* rmaxp, long long* rsump, int8_t* limbs,
-                           int64_t lstride, int bpad, double* qscale, double* sumr, hipStream_t s)
+                           int64_t lstride, int bpad, int nlimb, double* qscale, double* sumr, hipStream_t s)
 {
-    if (lstride % 256 || lstride < n || bpad < B || bpad % 16) return hipErrorInvalidValue;
+    if (lstride % 256 || lstride < n || bpad < B || bpad % 16 || (nlimb != 2 && nlimb != 3))
+        return hipErrorInvalidValue;
     const int nt = mfma_ntile(n);
     hipLaunchKernelGGL(rmax_kernel, dim3(nt, B), dim3(kT), 0, s, r64, n, rmaxp, nt);
-    hipLaunchKernelGGL(quantize_kernel, dim3(nt, B), dim3(kT), 0, s, r64, n, rmaxp, nt, limbs, bpad, qscale, rsump);
+    hipLaunchKernelGGL(quantize_kernel, dim3(nt, B), dim3(kT), 0, s, r64, n, rmaxp, nt, limbs, bpad, nlimb, qscale,
+                       rsump);
     hipLaunchKernelGGL(rsum_kernel, dim3(1), dim3(64), 0, s, rsump, nt, qscale, sumr, B);
     return hipGetLastError();
 }
@@ -836,7 +851,8 @@ hipError_t launch_mfma_eta(const MfmaEtaArgs& a, hipStream_t s)
 
 hipError_t launch_mfma_xtr(const MfmaArgs& a, hipStream_t s)
 {
-    if (a.bpad < 16 || a.bpad > 64 || a.bpad % 16 || a.B > a.bpad || a.lstride % 256 || a.lstride < a.n)
+    if (a.bpad < 16 || a.bpad > 64 || a.bpad % 16 || a.B > a.bpad || a.lstride % 256 || a.lstride < a.n ||
+        (a.limbs_n != 2 && a.limbs_n != 3))
         return hipErrorInvalidValue;
     return a.xt == XT_FP8 ? launch_xt<XT_FP8>(a, s) : launch_xt<XT_I8>(a, s);
 }

@@ -65,3 +65,13 @@ def test_header_constants_match_binding():
     assert int(re.search(r"#define COX_MFMA_ETA_VARIANTS (\d+)", text).group(1)) == P.ETA_VARIANTS
     assert re.search(r"COX_X_FP8_E4M3\s*=\s*(\d+)", text).group(1) == str(P.X_FP8_E4M3)
     assert re.search(r"COX_X_INT8\s*=\s*(\d+)", text).group(1) == str(P.X_INT8)
+
+
+def test_fit_opts_layout_matches_header():
+    """The binding's cox_fit_opts has the header's fields, in order."""
+    import re
+    text = open(P.HEADER).read()
+    body = text.split("} cox_fit_opts;")[0].rsplit("typedef struct {", 1)[1]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"\b(?:int32_t|double)\s+(\w+);", body)
+    assert fields == [f[0] for f in P.FitOpts._fields_]

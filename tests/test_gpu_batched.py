@@ -164,3 +164,31 @@ def test_autotuner_picks_and_caches(prob, tmp_path, monkeypatch):
     cox2.fit_path(lams, max_iter=3, tol=0.0, step=1.0 / (2.0 * cox.opnorm2()[0]))
     t2 = cox2.mfma_tuning()
     assert t2["xtr_variant"] == t["xtr_variant"] and t2["xtr_ms"] == [0.0] * P.MFMA_VARIANTS
+
+
+def test_residual_in_two_limbs(prob):
+    """residual_bits = 14 (two limbs) stays within the oracle tolerances; 22
+    (the default) is the three-limb pass; other values are rejected."""
+    B = 64
+    cox, M = _setup(prob, "fp8", B)
+    lm = oracle.lambda_max(M, prob.time, prob.event)
+    lams = coxsim.lambda_grid(lm, B, 0.01)
+    lams[0] *= 1 + 1e-6
+    sigma = 1.0 / (2.0 * oracle.opnorm2(M)[0])
+    K = 30
+    b14, _, o14, _ = cox.fit_path(lams, max_iter=K, tol=0.0, step=sigma, residual_bits=14)
+    b22, _, o22, _ = cox.fit_path(lams, max_iter=K, tol=0.0, step=sigma, residual_bits=22)
+    b00, _, o00, _ = cox.fit_path(lams, max_iter=K, tol=0.0, step=sigma)
+    np.testing.assert_array_equal(b22.cpu().numpy(), b00.cpu().numpy())
+    b14 = b14.cpu().numpy()
+    worst = 0.0
+    for b in (2, 21, 42, 63):
+        bo, tr, _, _ = oracle.fit(M, prob.time, prob.event, lams[b], sigma, max_iter=K)
+        e = rel_beta_err(b14[b], bo)
+        worst = max(worst, e)
+        assert e <= BETA_TOL, (b, e)
+        assert o14[b] == pytest.approx(tr[-1], rel=OBJ_TOL), b
+    print(f"two-limb residual: worst relative beta error over sampled b: {worst:.2e}")
+    with pytest.raises(P.CoxError) as ei:
+        cox.fit_path(lams, max_iter=1, tol=0.0, step=sigma, residual_bits=16)
+    assert ei.value.status == P.ERR_INVALID_ARG
