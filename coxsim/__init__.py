@@ -270,6 +270,35 @@ def genotype_problem(n: int, p: int, k: int, censor_frac: float, seed: int, days
     return CoxData(name, n, p, "genotype", y, d, beta, causal, seed, G=G, mu=mu, s=s, thresholds=thr)
 
 
+def covariate_block(n: int, q: int, seed: int) -> np.ndarray:
+    """(q, n) FP32 covariates shaped like the application's unpenalised ones:
+    row 0 a sex indicator (0/1, probability 1/2), rows 1.. standard normal
+    stand-ins for principal components."""
+    rng = np.random.Generator(np.random.PCG64(seed + 7))
+    Z = np.empty((q, n), np.float32)
+    if q > 0:
+        Z[0] = (rng.random(n) < 0.5).astype(np.float32)
+    if q > 1:
+        Z[1:] = rng.standard_normal((q - 1, n), dtype=np.float32)
+    return Z
+
+
+def genotype_problem_with_covariates(n: int, p: int, k: int, q: int, censor_frac: float, seed: int,
+                                     days: bool = False) -> tuple[CoxData, np.ndarray, np.ndarray]:
+    """A genotype problem whose survival times also depend on q covariates
+    (covariate_block) with effects gamma (sex 0.3, the others N(0, 0.2^2)).
+    Returns (data, Z (q, n) FP32, gamma)."""
+    d = genotype_problem(n, p, k, censor_frac, seed, days=days)
+    Z = covariate_block(n, q, seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 11))
+    gamma = np.concatenate([[0.3], rng.normal(0.0, 0.2, size=max(0, q - 1))])[:q]
+    Gc = d.G[d.causal]
+    Xc = (Gc.astype(np.float64) - d.mu[d.causal, None].astype(np.float64)) * d.s[d.causal, None].astype(np.float64)
+    eta = Xc.T @ d.beta_true[d.causal] + Z.astype(np.float64).T @ gamma
+    d.time, d.event = survival_times(eta, censor_frac, rng, days=days)
+    return d, Z, gamma
+
+
 def gaussian_problem(n: int, p: int, k: int, censor_frac: float, seed: int, name: str = "gaussian") -> CoxData:
     """X ~ N(0,1) i.i.d. FP32, not standardised."""
     rng = np.random.Generator(np.random.PCG64(seed + 1))

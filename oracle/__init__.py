@@ -54,6 +54,9 @@ def _load():
     lib.cox_oracle_lambda_max.argtypes = mat + [vp, vp, vp]
     lib.cox_oracle_opnorm2.argtypes = mat + [dbl, i32, u64, vp, vp]
     lib.cox_oracle_fit.argtypes = mat + [vp, vp, dbl, dbl, i32, dbl, i32, vp, vp, vp]
+    lib.cox_oracle_fit_pf.argtypes = mat + [vp, vp, dbl, vp, dbl, i32, dbl, i32, vp, vp, vp]
+    lib.cox_oracle_newton.argtypes = mat + [vp, vp, vp, i64, vp, vp, i32, dbl, vp, vp]
+    lib.cox_oracle_lambda_max_pf.argtypes = mat + [vp, vp, vp, dbl, vp, vp]
     _lib = lib
     return lib
 
@@ -192,18 +195,61 @@ def opnorm2(X: Matrix, tol: float = 1e-6, maxiter: int = 1000, seed: int = 95376
 
 
 def fit(X: Matrix, time, event, lam: float, sigma: float, max_iter: int, tol: float = 0.0, lag: int = 10,
-        beta0=None):
-    """ISTA for min -L + lam ||beta||_1.  Returns (beta, objective trace f_0..f_K,
-    K = steps taken, converged flag)."""
+        beta0=None, pf=None):
+    """ISTA for min -L + lam sum_j pf_j |beta_j| (pf None: every pf_j = 1).
+    Returns (beta, objective trace f_0..f_K, K = steps taken, converged flag)."""
     t, ev = _f64(time, X.n), _ev(event, X.n)
     beta = np.zeros(X.p, np.float64) if beta0 is None else _f64(beta0, X.p).copy()
     trace = np.full(max_iter + 1, np.nan)
     it = ctypes.c_int32()
-    rc = _load().cox_oracle_fit(*X.args(), _ptr(t), _ptr(ev), float(lam), float(sigma), int(max_iter),
+    lib = _load()
+    if pf is None:
+        rc = lib.cox_oracle_fit(*X.args(), _ptr(t), _ptr(ev), float(lam), float(sigma), int(max_iter),
                                 float(tol), int(lag), _ptr(beta), _ptr(trace), ctypes.byref(it))
+    else:
+        w = _f64(pf, X.p)
+        rc = lib.cox_oracle_fit_pf(*X.args(), _ptr(t), _ptr(ev), float(lam), _ptr(w), float(sigma),
+                                   int(max_iter), float(tol), int(lag), _ptr(beta), _ptr(trace), ctypes.byref(it))
     if rc == -1:
         raise ValueError("bad input")
     if rc == -2:
         raise FloatingPointError("objective became non-finite")
     k = it.value
     return beta, trace[: k + 1], k, rc == 0
+
+
+def newton(X: Matrix, time, event, cols, beta_fixed=None, beta_start=None, maxit: int = 100, gtol: float = 1e-10):
+    """Unpenalised maximum partial likelihood over the columns ``cols`` (every
+    other coefficient held at ``beta_fixed``, default 0) by Newton's method.
+    Returns (beta over cols, inverse of -Hessian at it, Newton steps, converged)."""
+    t, ev = _f64(time, X.n), _ev(event, X.n)
+    c = np.ascontiguousarray(cols, dtype=np.int64)
+    m = c.shape[0]
+    bs = np.zeros(m, np.float64) if beta_start is None else _f64(beta_start, m).copy()
+    bf = None if beta_fixed is None else _f64(beta_fixed, X.p)
+    cov = np.empty((m, m), np.float64)
+    it = ctypes.c_int32()
+    rc = _load().cox_oracle_newton(*X.args(), _ptr(t), _ptr(ev), _ptr(c), m, None if bf is None else _ptr(bf),
+                                   _ptr(bs), int(maxit), float(gtol), _ptr(cov), ctypes.byref(it))
+    if rc == -1:
+        raise ValueError("bad input")
+    if rc == -2:
+        raise np.linalg.LinAlgError("the negative Hessian is not positive definite")
+    return bs, cov, it.value, rc == 0
+
+
+def lambda_max_pf(X: Matrix, time, event, pf, gtol: float = 1e-10):
+    """(lambda_max, beta over the unpenalised columns in increasing order) with
+    penalty factors pf: the largest |g_j| / pf_j over penalised j at the
+    unpenalised optimum over {j : pf_j = 0}."""
+    t, ev = _f64(time, X.n), _ev(event, X.n)
+    w = _f64(pf, X.p)
+    out = ctypes.c_double()
+    bu = np.zeros(max(1, int(np.count_nonzero(w == 0))), np.float64)
+    rc = _load().cox_oracle_lambda_max_pf(*X.args(), _ptr(t), _ptr(ev), _ptr(w), float(gtol), ctypes.byref(out),
+                                          _ptr(bu))
+    if rc == -1:
+        raise ValueError("bad input")
+    if rc == -2:
+        raise np.linalg.LinAlgError("the unpenalised fit failed")
+    return out.value, bu[: int(np.count_nonzero(w == 0))]

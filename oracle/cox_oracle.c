@@ -21,7 +21,14 @@
  *   - the soft-thresholding operator of Section 4.2 ("Dot syntax");
  *   - opnorm(., 2) by power iteration with tol 1e-6, maxiter 1000 (Section 4.3);
  *   - the lag-10 relative-objective stopping rule of Section 6;
- *   - Breslow's convention for tied times (Section 6).
+ *   - Breslow's convention for tied times (Section 6);
+ *   - Section 6's application, where sex and the top principal components
+ *     enter the model unpenalised: a penalty factor pf_j >= 0 per column, the
+ *     objective -L + lambda sum_j pf_j |beta_j| and the threshold
+ *     sigma lambda pf_j (pf_j = 0: the column is unpenalised);
+ *   - the unpenalised Cox fit on a chosen set of columns that the same section
+ *     uses for its significance tests, here by Newton's method on L with its
+ *     exact Hessian (the textbook maximiser; the paper names no method).
  *
  * Readings taken where the paper is silent or inconsistent:
  *   - the threshold of the prox is sigma*lambda (standard ISTA for the stated
@@ -30,11 +37,16 @@
  *     subjects are all in each other's risk sets and tied events share W;
  *   - w is computed as exp(eta - max eta); every quantity that the iteration
  *     uses is invariant to this shift in exact arithmetic;
- *   - no normalisation of L by n or by the number of events.
+ *   - no normalisation of L by n or by the number of events;
+ *   - with unpenalised columns U = {j : pf_j = 0}, lambda_max is the smallest
+ *     lambda at which every penalised coefficient is zero at the optimum:
+ *     max over penalised j of |g_j| / pf_j, with g the gradient of L at
+ *     beta_U = the unpenalised maximiser over U and every other beta_j = 0.
  *
  * Parity status: every function here is pinned by the CPU tests (brute-force
  * risk sets, hand-derived closed forms, finite differences, a closed-form
- * minimiser, an independent quasi-Newton solver, an SVD).  None is unpinned.
+ * minimiser, an independent quasi-Newton solver, an SVD, a finite-difference
+ * Hessian).  None is unpinned.
  *
  * All arithmetic is IEEE double precision, evaluated in natural index order
  * except where OpenMP splits a loop over independent outputs.
@@ -340,26 +352,29 @@ int cox_oracle_opnorm2(int kind, const void *data, int64_t n, int64_t p, int64_t
 
 /* ------------------------------------------------------------------- ISTA */
 
-/* Proximal gradient (ISTA) for min f(beta) = -L(beta) + lambda ||beta||_1
- * (Section 5.3), from the start point in beta[] (in/out).
+/* Proximal gradient (ISTA) for min f(beta) = -L(beta) + lambda sum_j pf_j
+ * |beta_j| (Section 5.3; pf = NULL means pf_j = 1 for every j, the plain l1
+ * penalty), from the start point in beta[] (in/out).
  *
  * At iterate k (k = 0, 1, ...): eta = X beta_k; the risk-set sums give L and
- * r; f_k = -L + lambda ||beta_k||_1 is recorded in obj_trace[k] (if given);
- * then
+ * r; f_k = -L + lambda sum_j pf_j |beta_kj| is recorded in obj_trace[k] (if
+ * given); then
  *   - if k >= lag and |f_k - f_{k-lag}| / (|f_k| + 1) < tol, stop (Section 6's
  *     rule) with beta_k;
  *   - if k == max_iter, stop with beta_k;
- *   - otherwise beta_{k+1} = S_{sigma lambda}(beta_k + sigma X'r).
+ *   - otherwise beta_{k+1,j} = S_{sigma lambda pf_j}(beta_kj + sigma (X'r)_j).
  * *iters_out = k at the stop (the number of steps taken).  Returns 0 when the
  * rule fired, 1 when max_iter was reached, -1 on bad input or no memory, -2
  * when the objective became non-finite. */
-int cox_oracle_fit(int kind, const void *data, int64_t n, int64_t p, int64_t ldx, const double *mu,
-                   const double *s, const double *time, const int32_t *event, double lambda, double sigma,
-                   int32_t max_iter, double tol, int32_t lag, double *beta, double *obj_trace,
-                   int32_t *iters_out)
+int cox_oracle_fit_pf(int kind, const void *data, int64_t n, int64_t p, int64_t ldx, const double *mu,
+                      const double *s, const double *time, const int32_t *event, double lambda,
+                      const double *pf, double sigma, int32_t max_iter, double tol, int32_t lag, double *beta,
+                      double *obj_trace, int32_t *iters_out)
 {
     oracle_matrix X;
     if (make_matrix(&X, kind, data, n, p, ldx, mu, s) || lag < 1 || max_iter < 0) return -1;
+    for (int64_t j = 0; pf && j < p; ++j)
+        if (!(pf[j] >= 0.0) || !isfinite(pf[j])) return -1;
     int64_t *order = malloc(sizeof(int64_t) * (size_t)(3 * n + 1));
     double *work = malloc(sizeof(double) * (size_t)(3 * n + 1));
     double *eta = malloc(sizeof(double) * (size_t)(n + 1));
@@ -375,7 +390,7 @@ int cox_oracle_fit(int kind, const void *data, int64_t n, int64_t p, int64_t ldx
         xbeta(&X, beta, eta);
         double L = loglik_resid_sorted(n, eta, event, order, gstart, gend, r, work);
         double l1 = 0.0;
-        for (int64_t j = 0; j < p; ++j) l1 += fabs(beta[j]);
+        for (int64_t j = 0; j < p; ++j) l1 += (pf ? pf[j] : 1.0) * fabs(beta[j]);
         double f = -L + lambda * l1;
         hist[k] = f;
         if (obj_trace) obj_trace[k] = f;
@@ -384,9 +399,237 @@ int cox_oracle_fit(int kind, const void *data, int64_t n, int64_t p, int64_t ldx
         if (k == max_iter) { rc = 1; *iters_out = k; break; }
         xtr(&X, r, g);
         for (int64_t j = 0; j < p; ++j)
-            beta[j] = cox_oracle_soft_threshold(beta[j] + sigma * g[j], sigma * lambda);
+            beta[j] = cox_oracle_soft_threshold(beta[j] + sigma * g[j], sigma * lambda * (pf ? pf[j] : 1.0));
     }
 out:
     free(order); free(work); free(eta); free(r); free(g); free(hist);
+    return rc;
+}
+
+/* The plain l1 problem: cox_oracle_fit_pf with every pf_j = 1. */
+int cox_oracle_fit(int kind, const void *data, int64_t n, int64_t p, int64_t ldx, const double *mu,
+                   const double *s, const double *time, const int32_t *event, double lambda, double sigma,
+                   int32_t max_iter, double tol, int32_t lag, double *beta, double *obj_trace,
+                   int32_t *iters_out)
+{
+    return cox_oracle_fit_pf(kind, data, n, p, ldx, mu, s, time, event, lambda, NULL, sigma, max_iter, tol, lag,
+                             beta, obj_trace, iters_out);
+}
+
+/* ------------------------------------------------- unpenalised Newton fit */
+
+/* Gradient and Hessian of L with respect to the coefficients of the m columns
+ * cols[0..m-1], at linear predictor eta (Breslow ties).  With the risk set
+ * R_i = {j : y_j >= y_i}, w_j = exp(eta_j - max eta), and for each event i
+ *   W_i   = sum_{j in R_i} w_j,
+ *   S1_i  = sum_{j in R_i} w_j x_j          (m-vector over the chosen columns),
+ *   S2_i  = sum_{j in R_i} w_j x_j x_j'     (m x m),
+ * L's gradient is sum_i delta_i (x_i - S1_i / W_i) and its Hessian is
+ * -sum_i delta_i (S2_i / W_i - S1_i S1_i' / W_i^2).  In sorted order the sums
+ * over R_i are running sums, complete at the end of i's tie group: a tie
+ * group is accumulated whole, then its events are added.  grad [m], hess
+ * [m*m] row-major.  Returns L. */
+static double loglik_grad_hess(const oracle_matrix *X, const int64_t *cols, int64_t m, const double *eta,
+                               const int32_t *event, const int64_t *order, const int64_t *gend, double *grad,
+                               double *hess, double *S1 /* m */, double *S2 /* m*m */, double *xk /* m */)
+{
+    const int64_t n = X->n;
+    double mx = -INFINITY;
+    for (int64_t i = 0; i < n; ++i)
+        if (eta[i] > mx) mx = eta[i];
+    double W = 0.0, L = 0.0;
+    for (int64_t a = 0; a < m; ++a) S1[a] = grad[a] = 0.0;
+    for (int64_t a = 0; a < m * m; ++a) S2[a] = hess[a] = 0.0;
+    int64_t k = 0;
+    while (k < n) {
+        const int64_t e = gend[k];
+        for (int64_t q = k; q <= e; ++q) { /* the tie group joins the running sums */
+            const int64_t i = order[q];
+            const double w = exp(eta[i] - mx);
+            for (int64_t a = 0; a < m; ++a) xk[a] = xval(X, i, cols[a]);
+            W += w;
+            for (int64_t a = 0; a < m; ++a) {
+                S1[a] += w * xk[a];
+                for (int64_t b = 0; b < m; ++b) S2[a * m + b] += w * xk[a] * xk[b];
+            }
+        }
+        for (int64_t q = k; q <= e; ++q) { /* its events see the whole risk set */
+            const int64_t i = order[q];
+            if (!event[i]) continue;
+            L += eta[i] - mx - log(W);
+            for (int64_t a = 0; a < m; ++a) {
+                grad[a] += xval(X, i, cols[a]) - S1[a] / W;
+                for (int64_t b = 0; b < m; ++b) hess[a * m + b] -= S2[a * m + b] / W - S1[a] * S1[b] / (W * W);
+            }
+        }
+        k = e + 1;
+    }
+    return L;
+}
+
+/* Solve A x = b for a symmetric positive definite m x m matrix A (row-major) by
+ * Cholesky factorisation; A is overwritten by its factor.  Returns 0, or -1 when
+ * A is not numerically positive definite. */
+static int cholesky_solve(double *A, int64_t m, double *x)
+{
+    for (int64_t j = 0; j < m; ++j) {
+        double d = A[j * m + j];
+        for (int64_t k = 0; k < j; ++k) d -= A[j * m + k] * A[j * m + k];
+        if (!(d > 0.0)) return -1;
+        d = sqrt(d);
+        A[j * m + j] = d;
+        for (int64_t i = j + 1; i < m; ++i) {
+            double v = A[i * m + j];
+            for (int64_t k = 0; k < j; ++k) v -= A[i * m + k] * A[j * m + k];
+            A[i * m + j] = v / d;
+        }
+    }
+    for (int64_t i = 0; i < m; ++i) { /* forward: L y = b */
+        double v = x[i];
+        for (int64_t k = 0; k < i; ++k) v -= A[i * m + k] * x[k];
+        x[i] = v / A[i * m + i];
+    }
+    for (int64_t i = m - 1; i >= 0; --i) { /* back: L' x = y */
+        double v = x[i];
+        for (int64_t k = i + 1; k < m; ++k) v -= A[k * m + i] * x[k];
+        x[i] = v / A[i * m + i];
+    }
+    return 0;
+}
+
+/* Unpenalised maximum partial likelihood over the m columns cols[] with every
+ * other coefficient fixed at beta_fixed (NULL: zero), by Newton's method with
+ * step halving: from beta_sub (in/out, length m), each step solves
+ * (-H) d = g and takes the largest of d, d/2, d/4, ... that does not lower L;
+ * it stops when max_a |g_a| <= gtol (after the step), or after maxit steps.
+ * On return, if cov is not NULL it holds the inverse of -H at the result
+ * (m x m, row-major: the estimated covariance of beta_sub, whose diagonal gives
+ * the standard errors of Wald tests).  *iters_out = Newton steps taken.
+ * Returns 0 when converged, 1 at maxit, -1 on bad input or no memory, -2 when
+ * -H is not positive definite. */
+int cox_oracle_newton(int kind, const void *data, int64_t n, int64_t p, int64_t ldx, const double *mu,
+                      const double *s, const double *time, const int32_t *event, const int64_t *cols, int64_t m,
+                      const double *beta_fixed, double *beta_sub, int32_t maxit, double gtol, double *cov,
+                      int32_t *iters_out)
+{
+    oracle_matrix X;
+    if (make_matrix(&X, kind, data, n, p, ldx, mu, s) || m < 1 || m > 256 || maxit < 0 || n < 1) return -1;
+    for (int64_t a = 0; a < m; ++a)
+        if (cols[a] < 0 || cols[a] >= p) return -1;
+    int64_t *order = malloc(sizeof(int64_t) * (size_t)(3 * n));
+    double *beta = malloc(sizeof(double) * (size_t)p);
+    double *eta = malloc(sizeof(double) * (size_t)n);
+    double *grad = malloc(sizeof(double) * (size_t)m), *hess = malloc(sizeof(double) * (size_t)(m * m));
+    double *fac = malloc(sizeof(double) * (size_t)(m * m)), *d = malloc(sizeof(double) * (size_t)m);
+    double *S1 = malloc(sizeof(double) * (size_t)m), *S2 = malloc(sizeof(double) * (size_t)(m * m));
+    double *xk = malloc(sizeof(double) * (size_t)m), *trial = malloc(sizeof(double) * (size_t)m);
+    int rc = -1;
+    int32_t it = 0;
+    if (!order || !beta || !eta || !grad || !hess || !fac || !d || !S1 || !S2 || !xk || !trial) goto out;
+    int64_t *gstart = order + n, *gend = order + 2 * n;
+    if (cox_oracle_order(n, time, order, gstart, gend)) goto out;
+    for (int64_t j = 0; j < p; ++j) beta[j] = beta_fixed ? beta_fixed[j] : 0.0;
+    for (int64_t a = 0; a < m; ++a) beta[cols[a]] = beta_sub[a];
+    xbeta(&X, beta, eta);
+    double L = loglik_grad_hess(&X, cols, m, eta, event, order, gend, grad, hess, S1, S2, xk);
+    rc = 1;
+    for (;;) {
+        double gmax = 0.0;
+        for (int64_t a = 0; a < m; ++a)
+            if (fabs(grad[a]) > gmax) gmax = fabs(grad[a]);
+        if (gmax <= gtol) { rc = 0; break; }
+        if (it >= maxit) { rc = 1; break; }
+        for (int64_t a = 0; a < m * m; ++a) fac[a] = -hess[a];
+        memcpy(d, grad, sizeof(double) * (size_t)m);
+        if (cholesky_solve(fac, m, d)) { rc = -2; break; }
+        /* predicted gain of the full step, g'd; once it is at the rounding level
+         * of L the full step is taken unchecked (the quadratic model is exact
+         * to that order there), else the step is halved until L does not fall */
+        double gain = 0.0;
+        for (int64_t a = 0; a < m; ++a) gain += grad[a] * d[a];
+        const int pure = gain <= 1e-12 * (1.0 + fabs(L));
+        double t = 1.0, Lt = -INFINITY;
+        for (int half = 0; half < 60; ++half, t *= 0.5) {
+            for (int64_t a = 0; a < m; ++a) {
+                trial[a] = beta_sub[a] + t * d[a];
+                beta[cols[a]] = trial[a];
+            }
+            xbeta(&X, beta, eta);
+            Lt = loglik_grad_hess(&X, cols, m, eta, event, order, gend, grad, hess, S1, S2, xk);
+            if (Lt >= L || pure) break;
+        }
+        ++it;
+        if (pure && isfinite(Lt)) {
+            memcpy(beta_sub, trial, sizeof(double) * (size_t)m);
+            L = Lt;
+            continue;
+        }
+        if (!(Lt >= L)) { /* no ascent along the Newton direction (rounding level): stay at beta_sub */
+            for (int64_t a = 0; a < m; ++a) beta[cols[a]] = beta_sub[a];
+            xbeta(&X, beta, eta);
+            loglik_grad_hess(&X, cols, m, eta, event, order, gend, grad, hess, S1, S2, xk);
+            rc = 1;
+            break;
+        }
+        memcpy(beta_sub, trial, sizeof(double) * (size_t)m);
+        L = Lt;
+    }
+    if (cov && rc >= 0) {
+        /* inverse of -H, column by column */
+        for (int64_t b = 0; b < m; ++b) {
+            for (int64_t a = 0; a < m * m; ++a) fac[a] = -hess[a];
+            for (int64_t a = 0; a < m; ++a) d[a] = (a == b) ? 1.0 : 0.0;
+            if (cholesky_solve(fac, m, d)) { rc = -2; break; }
+            for (int64_t a = 0; a < m; ++a) cov[a * m + b] = d[a];
+        }
+    }
+out:
+    if (iters_out) *iters_out = it;
+    free(order); free(beta); free(eta); free(grad); free(hess); free(fac); free(d); free(S1); free(S2);
+    free(xk); free(trial);
+    return rc;
+}
+
+/* lambda_max with penalty factors: with U = {j : pf_j = 0} (pf = NULL: none),
+ * beta_U = the unpenalised maximiser over U (Newton, gradient below gtol) and
+ * every other coefficient zero, the largest |g_j| / pf_j over penalised j of
+ * the gradient g of L there.  beta_u_out (nullable) receives beta_U in
+ * increasing column order.  Returns 0, -1 on bad input, -2 when the Newton
+ * fit fails. */
+int cox_oracle_lambda_max_pf(int kind, const void *data, int64_t n, int64_t p, int64_t ldx, const double *mu,
+                             const double *s, const double *time, const int32_t *event, const double *pf,
+                             double gtol, double *lambda_max, double *beta_u_out)
+{
+    oracle_matrix X;
+    if (make_matrix(&X, kind, data, n, p, ldx, mu, s)) return -1;
+    int64_t m = 0;
+    int64_t *cols = malloc(sizeof(int64_t) * (size_t)(p + 1));
+    double *beta = calloc((size_t)(p + 1), sizeof(double));
+    double *bu = calloc((size_t)(p + 1), sizeof(double));
+    double *g = malloc(sizeof(double) * (size_t)(p + 1));
+    int rc = -1;
+    if (!cols || !beta || !bu || !g) goto out;
+    for (int64_t j = 0; j < p; ++j) {
+        if (pf && (!(pf[j] >= 0.0) || !isfinite(pf[j]))) goto out;
+        if (pf && pf[j] == 0.0) cols[m++] = j;
+    }
+    if (m > 0) {
+        int32_t it;
+        int nr = cox_oracle_newton(kind, data, n, p, ldx, mu, s, time, event, cols, m, NULL, bu, 200, gtol, NULL,
+                                   &it);
+        if (nr != 0) { rc = -2; goto out; }
+        for (int64_t a = 0; a < m; ++a) beta[cols[a]] = bu[a];
+    }
+    double negL;
+    rc = cox_oracle_loss_grad(kind, data, n, p, ldx, mu, s, time, event, beta, &negL, g);
+    double mx = 0.0;
+    for (int64_t j = 0; rc == 0 && j < p; ++j) {
+        const double f = pf ? pf[j] : 1.0;
+        if (f > 0.0 && fabs(g[j]) / f > mx) mx = fabs(g[j]) / f;
+    }
+    *lambda_max = mx;
+    if (beta_u_out) memcpy(beta_u_out, bu, sizeof(double) * (size_t)m);
+out:
+    free(cols); free(beta); free(bu); free(g);
     return rc;
 }
