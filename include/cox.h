@@ -18,12 +18,24 @@
  * (The paper writes the threshold as lambda; the threshold of the proximal map
  * of sigma * lambda ||.||_1 is sigma * lambda, which is what is used here.)
  *
+ * Covariates and penalty factors (Section 6's application, where sex and the
+ * top principal components enter the model unpenalised beside the SNPs).  A
+ * dense FP32 block Z of q covariates may be attached (cox_set_covariates); the
+ * model matrix is then [X~ | Z] and every coefficient vector has
+ * ptot = p + q entries, the covariates last.  Each column j has a penalty
+ * factor pf_j >= 0 (cox_set_penalty_factors; by default 1 for the columns of
+ * X and 0 for the covariates): the objective is
+ *     f_lambda(beta) = -L(beta) + lambda sum_j pf_j |beta_j|
+ * and the step's threshold for column j is sigma * lambda * pf_j, so a column
+ * with pf_j = 0 is unpenalised.
+ *
  * Data layout.  X is dense, column-major (each SNP column contiguous), n rows
  * by p columns with leading dimension ldx >= n, the column split of Section
  * 4.1.  X~ is X itself for COX_X_F32.  For the 1-byte genotype types X holds
  * allele counts g and X~_ij = (g_ij - col_center[j]) * col_scale[j] is formed
  * on the fly (NULL center = 0, NULL scale = 1).  Vectors for B coefficient
- * vectors are stored b-major: beta[b*p + j], eta[b*n + i].
+ * vectors are stored b-major: beta[b*ptot + j] (ptot = p without covariates),
+ * eta[b*n + i].
  *
  * Conventions shared by every entry point.
  *  - Return value: a cox_status.  No C++ exception or abort crosses the ABI.
@@ -105,15 +117,15 @@ cox_status cox_last_error(const cox_ctx *ctx, char *buf, size_t len);
 
 /* Value and gradient of the NEGATIVE log partial likelihood, -L(beta_b), for B
  * coefficient vectors (Section 5.3: the gradient of L is X~'(I - P) delta).
- *   beta  dev [B][p] float
+ *   beta  dev [B][ptot] float
  *   loss  host [B] double: -L(beta_b)
- *   grad  dev [B][p] float, or NULL for the loss only: -X~' r_b
+ *   grad  dev [B][ptot] float, or NULL for the loss only: -[X~ Z]' r_b
  * NUMERIC if a loss is non-finite (e.g. NaN in beta). Synchronises. */
 cox_status cox_loss_grad(cox_ctx *ctx, const float *beta, int32_t B, double *loss, float *grad);
 
 /* One proximal-gradient (ISTA) step in place for each b (Section 5.3):
- *   beta_b <- S_{step*lambda_b}(beta_b + step * X~' r_b)
- *   beta        dev [B][p] float, in/out
+ *   beta_bj <- S_{step*lambda_b*pf_j}(beta_bj + step * ([X~ Z]' r_b)_j)
+ *   beta        dev [B][ptot] float, in/out
  *   lambdas     host [B], each >= 0 and finite
  *   step        sigma > 0
  *   obj_before  host [B] or NULL: f_lambda_b(beta_b) before the step.
@@ -123,8 +135,8 @@ cox_status cox_prox_step(cox_ctx *ctx, float *beta, int32_t B, const double *lam
 
 /* Apply the soft-threshold update alone (the elementwise kernel), given a
  * gradient of the negative log likelihood:
- *   beta_b <- S_{step*lambda_b}(beta_b - step * grad_b)
- *   beta dev [B][p] in/out; grad dev [B][p]; lambdas host [B] >= 0; step > 0. */
+ *   beta_bj <- S_{step*lambda_b*pf_j}(beta_bj - step * grad_bj)
+ *   beta dev [B][ptot] in/out; grad dev [B][ptot]; lambdas host [B] >= 0; step > 0. */
 cox_status cox_prox_apply(cox_ctx *ctx, float *beta, const float *grad, int32_t B, const double *lambdas,
                           double step);
 
@@ -149,10 +161,10 @@ typedef struct {
  * For each b, from beta_0 (0, or the input when warm_start): at step k the
  * objective f_k = f_lambda_b(beta_k) is evaluated; b stops at the first k with
  * k >= lag and |f_k - f_{k-lag}| / (|f_k| + 1) < tol, or at k = max_iter; else
- * beta_{k+1} = S_{sigma lambda_b}(beta_k + sigma X~' r).
+ * beta_{k+1,j} = S_{sigma lambda_b pf_j}(beta_kj + sigma ([X~ Z]' r)_j).
  *   lambdas host [B] >= 0; opts host (NULL: max_iter 1000, tol 1e-5, lag 10,
  *           step from cox_opnorm2, cold start, eta_mode 0, poll 16)
- *   beta  dev [B][p] float: the start if warm_start, and the result beta_{k_b}
+ *   beta  dev [B][ptot] float: the start if warm_start, and the result beta_{k_b}
  *   iters host [B] or NULL: k_b, the number of steps taken
  *   obj   host [B] or NULL: f_lambda_b(beta_{k_b})
  * Returns OK when every b met the tolerance, NOT_CONVERGED (outputs valid) when
@@ -160,18 +172,59 @@ typedef struct {
 cox_status cox_fit_path(cox_ctx *ctx, const double *lambdas, int32_t B, const cox_fit_opts *opts, float *beta,
                         int32_t *iters, double *obj);
 
-/* lambda_max = ||X~' r(0)||_inf, the smallest lambda for which beta = 0 is a
- * fixed point of the iteration.  At beta = 0 every w_i = 1 and r is delta minus
- * the Breslow cumulative hazard.  host [1].  Synchronises. */
+/* lambda_max: the smallest lambda at which every penalised coefficient is zero
+ * at the optimum.  With no unpenalised column it is max_j |(X~' r(0))_j| / pf_j,
+ * where at beta = 0 every w_i = 1 and r is delta minus the Breslow cumulative
+ * hazard.  When some covariates have pf = 0 it is the same maximum over the
+ * penalised columns at the unpenalised optimum over those covariates (every
+ * other coefficient zero); that optimum is found by ISTA over Z alone with step
+ * 1/(2 ||Z||_2^2) until the largest free-covariate gradient is below 1e-10 of
+ * its value at zero (at most 100000 steps: NOT_CONVERGED, value still written).
+ * An unpenalised column of X (pf_j = 0, j < p) is UNSUPPORTED here (it would
+ * need a pass over X per step); fits with one are fine.
+ *   lambda_max host [1].  Synchronises. */
 cox_status cox_lambda_max(cox_ctx *ctx, double *lambda_max);
 
-/* ||X~||_2^2 by power iteration on X~'X~ (Section 4.3, opnorm(X, 2;
- * method = "power"); the paper's defaults are tol 1e-6, maxiter 1000, seed
- * 95376).  Start vector: entries uniform on [-1, 1) from SplitMix64 seeded
- * with `seed` (top 53 bits of each output), normalised.  Stops when the
+/* ||[X~ Z]||_2^2 (||X~||_2^2 without covariates) by power iteration on
+ * [X~ Z]'[X~ Z] (Section 4.3, opnorm(X, 2; method = "power"); the paper's
+ * defaults are tol 1e-6, maxiter 1000, seed 95376).  Start vector: ptot
+ * entries uniform on [-1, 1) from SplitMix64 seeded with `seed` (top 53 bits
+ * of each output), normalised.  Stops when the
  * estimate changes by less than tol relative to itself.  Centring is exact.
  *   s2 host [1]; iters host [1] or NULL.  Synchronises. */
 cox_status cox_opnorm2(cox_ctx *ctx, double tol, int32_t maxiter, uint64_t seed, double *s2, int32_t *iters);
+
+/* The paper's sequential protocol (Section 6): one lambda after another, each
+ * solved to the stopping rule from the previous lambda's solution.
+ *   lambdas   host [L] >= 0, in the order solved (typically decreasing)
+ *   opts      as cox_fit_path (NULL: its defaults); a step <= 0 is computed once
+ *             for the whole sequence.  warm_start applies to the first lambda.
+ *   beta_path dev [L][ptot] float: row l is the solution at lambdas[l] (row 0 is
+ *             also the start when warm_start)
+ *   iters, obj host [L] or NULL: steps taken and final objective per lambda
+ * Returns OK, NOT_CONVERGED (every row valid) when some lambda reached max_iter,
+ * or the first other error.  Synchronises. */
+cox_status cox_fit_sequence(cox_ctx *ctx, const double *lambdas, int32_t L, const cox_fit_opts *opts,
+                            float *beta_path, int32_t *iters, double *obj);
+
+/* Attach the dense block Z of q unpenalised covariates (Section 6's
+ * application) beside X: dev float, column-major n x q, element (i, k) at
+ * Z[k*ldz + i], ldz >= n; BORROWED (valid and unchanged while the context
+ * uses it).  From then on every coefficient and gradient argument has
+ * ptot = p + q entries per vector, the covariates last, and the covariates'
+ * penalty factors are 0 until cox_set_penalty_factors says otherwise.  q = 0
+ * (Z may be NULL) removes the block.  The workspace is sized at cox_setup, so
+ * this allocates nothing.  INVALID_ARG for q outside 0..COX_MAX_COVARIATES, a
+ * NULL Z with q > 0, or ldz < n.  Synchronises. */
+#define COX_MAX_COVARIATES 64
+cox_status cox_set_covariates(cox_ctx *ctx, const float *Z, int64_t q, int64_t ldz);
+
+/* Penalty factors of the ptot columns (host [ptot], copied; each finite and
+ * >= 0): the objective becomes -L + lambda sum_j pf_j |beta_j| and the threshold
+ * of column j sigma * lambda * pf_j.  NULL restores the defaults (1 for the
+ * columns of X, 0 for the covariates).  Attaching or removing covariates
+ * resets the covariates' factors to 0 and keeps those of X.  Synchronises. */
+cox_status cox_set_penalty_factors(cox_ctx *ctx, const double *pf);
 
 /* Negative log partial likelihood as a function of the linear predictor, for
  * automatic differentiation (the adjoint of the risk-set sums).

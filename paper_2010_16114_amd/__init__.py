@@ -6,8 +6,9 @@ PyTorch provides device memory and the stream.  There is no CPU fallback: if
 the library is not built, importing the binding's entry points raises.
 
 Matrices are column-major n x p: a torch tensor of shape (p, ldx) whose row j
-is SNP column j (first n entries used).  Coefficients are (B, p) float32,
-linear predictors (B, n).
+is SNP column j (first n entries used).  Coefficients are (B, ptot) float32 with
+ptot = p + q when q covariates are attached (the covariates last), linear
+predictors (B, n).
 """
 from __future__ import annotations
 
@@ -24,6 +25,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "cox.h")
 X_F32, X_FP8_E4M3, X_INT8 = 0, 1, 2
 MFMA_VARIANTS = 5  # COX_MFMA_VARIANTS: pipeline shapes of the X~' R pass (and the tuning arrays' length)
 ETA_VARIANTS = 5  # COX_MFMA_ETA_VARIANTS: pipeline shapes of the eta update
+MAX_COVARIATES = 64  # COX_MAX_COVARIATES
 OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NUMERIC, ERR_NOT_CONVERGED, ERR_UNSUPPORTED = range(7)
 
 
@@ -70,6 +72,9 @@ def lib():
         "cox_prox_step": [vp, vp, i32, vp, dbl, vp],
         "cox_prox_apply": [vp, vp, vp, i32, vp, dbl],
         "cox_fit_path": [vp, vp, i32, ctypes.POINTER(FitOpts), vp, vp, vp],
+        "cox_fit_sequence": [vp, vp, i32, ctypes.POINTER(FitOpts), vp, vp, vp],
+        "cox_set_covariates": [vp, vp, i64, i64],
+        "cox_set_penalty_factors": [vp, vp],
         "cox_lambda_max": [vp, ctypes.POINTER(dbl)],
         "cox_opnorm2": [vp, dbl, i32, u64, ctypes.POINTER(dbl), ctypes.POINTER(i32)],
         "cox_nll_forward": [vp, vp, i32, i32, vp],
@@ -126,6 +131,7 @@ class Cox:
             raise CoxError(st, f"cox_setup: {lib().cox_status_string(st).decode()}")
         self._h = h
         self.last_forward_key = None
+        self.Z, self.q = None, 0
 
     # -- helpers
     def _check(self, st, what, allow=(OK,)):
@@ -138,8 +144,13 @@ class Cox:
     def _beta(self, beta):
         torch = self._torch
         assert beta.dtype == torch.float32 and beta.is_cuda and beta.is_contiguous()
-        beta2 = beta.view(-1, self.p)
+        beta2 = beta.view(-1, self.ptot)
         return beta2, beta2.shape[0]
+
+    @property
+    def ptot(self) -> int:
+        """Coefficients per vector: p, plus the attached covariates."""
+        return self.p + self.q
 
     def close(self):
         if getattr(self, "_h", None):
@@ -153,8 +164,31 @@ class Cox:
             pass
 
     # -- entry points
+    def set_covariates(self, Z):
+        """Attach unpenalised covariates: Z a float32 device tensor of shape (q, ldz)
+        whose row k is covariate k over the n subjects (None or q = 0 removes
+        them).  Z is borrowed: this object keeps a reference."""
+        if Z is None or Z.shape[0] == 0:
+            self._check(lib().cox_set_covariates(self._h, None, 0, 0), "cox_set_covariates")
+            self.Z, self.q = None, 0
+            return
+        torch = self._torch
+        assert Z.dtype == torch.float32 and Z.is_cuda and Z.dim() == 2 and Z.stride(1) == 1
+        self._check(lib().cox_set_covariates(self._h, Z.data_ptr(), Z.shape[0], Z.stride(0)), "cox_set_covariates")
+        self.Z, self.q = Z, Z.shape[0]
+
+    def set_penalty_factors(self, pf=None):
+        """Penalty factors of the ptot columns (None: 1 for X's columns, 0 for covariates)."""
+        if pf is None:
+            self._check(lib().cox_set_penalty_factors(self._h, None), "cox_set_penalty_factors")
+            return
+        w = np.ascontiguousarray(np.asarray(pf, np.float64).reshape(-1))
+        if w.shape != (self.ptot,):
+            raise ValueError(f"pf must have ptot = {self.ptot} entries")
+        self._check(lib().cox_set_penalty_factors(self._h, _np_ptr(w)), "cox_set_penalty_factors")
+
     def loss_grad(self, beta, want_grad: bool = True):
-        """(-L(beta_b) for each b as numpy, gradient of -L as a (B, p) tensor or None)."""
+        """(-L(beta_b) for each b as numpy, gradient of -L as a (B, ptot) tensor or None)."""
         beta2, B = self._beta(beta)
         loss = np.empty(B, np.float64)
         grad = self._torch.empty_like(beta2) if want_grad else None
@@ -180,13 +214,13 @@ class Cox:
 
     def fit_path(self, lambdas, max_iter: int = 1000, tol: float = 1e-5, lag: int = 10, step: float = 0.0,
                  beta=None, eta_mode: int = 0, poll: int = 16, residual_bits: int = 0):
-        """ISTA for each lambda.  Returns (beta (B, p) tensor, iters, obj, status)."""
+        """ISTA for each lambda.  Returns (beta (B, ptot) tensor, iters, obj, status)."""
         torch = self._torch
         lam = np.ascontiguousarray(np.asarray(lambdas, np.float64).reshape(-1))
         B = lam.shape[0]
         warm = beta is not None
         if beta is None:
-            beta = torch.zeros((B, self.p), dtype=torch.float32, device=self.device)
+            beta = torch.zeros((B, self.ptot), dtype=torch.float32, device=self.device)
         beta2, Bb = self._beta(beta)
         assert Bb == B
         iters = np.zeros(B, np.int32)
@@ -197,6 +231,25 @@ class Cox:
                                 _np_ptr(obj))
         self._check(st, "cox_fit_path", allow=(OK, ERR_NOT_CONVERGED))
         return beta2, iters, obj, st
+
+    def fit_sequence(self, lambdas, max_iter: int = 1000, tol: float = 1e-5, lag: int = 10, step: float = 0.0,
+                     beta0=None, eta_mode: int = 0, poll: int = 16):
+        """The sequential protocol: each lambda in turn, warm-started from the
+        previous solution.  Returns (path (L, ptot) tensor, iters, obj, status)."""
+        torch = self._torch
+        lam = np.ascontiguousarray(np.asarray(lambdas, np.float64).reshape(-1))
+        L = lam.shape[0]
+        path = torch.zeros((L, self.ptot), dtype=torch.float32, device=self.device)
+        if beta0 is not None:
+            path[0] = beta0.reshape(-1)
+        iters = np.zeros(L, np.int32)
+        obj = np.zeros(L, np.float64)
+        o = FitOpts(int(max_iter), float(tol), int(lag), float(step), int(beta0 is not None), int(eta_mode),
+                    int(poll), 0)
+        st = lib().cox_fit_sequence(self._h, _np_ptr(lam), L, ctypes.byref(o), path.data_ptr(), _np_ptr(iters),
+                                    _np_ptr(obj))
+        self._check(st, "cox_fit_sequence", allow=(OK, ERR_NOT_CONVERGED))
+        return path, iters, obj, st
 
     def lambda_max(self) -> float:
         out = ctypes.c_double()

@@ -15,6 +15,7 @@
 #include <sstream>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <new>
 #include <numeric>
 #include <string>
@@ -30,11 +31,14 @@ constexpr int kPhases = 5;  // cox_phase values
 
 static_assert(kMfmaVariants == COX_MFMA_VARIANTS && kMfmaEtaVariants == COX_MFMA_ETA_VARIANTS,
               "pipeline shape counts differ from the header");
+static_assert(kMaxCov == COX_MAX_COVARIATES, "covariate limit differs from the header");
 
 namespace {
 
 constexpr int kMaxBatch = 64;
 constexpr int kGroup = 8;  // coefficient vectors per VALU pass over X
+constexpr int kFreeCovMaxIter = 100000;  // steps of the unpenalised covariate fit inside cox_lambda_max
+constexpr double kFreeCovGtol = 1e-10;   // its stop: max |g_k| below this fraction of its value at zero
 
 int64_t round_up(int64_t a, int64_t m) { return (a + m - 1) / m * m; }
 
@@ -85,6 +89,15 @@ struct cox_ctx {
     int32_t *kit = nullptr, *active = nullptr, *iters = nullptr, *status = nullptr;
     int fwd_B = 0, fwd_f64 = 0;
     int64_t n_events = 0;
+    // the dense covariate block Z beside X, and the penalty factors
+    const float* Z = nullptr;
+    int64_t q = 0, ldz = 0;
+    int nrb = 0;
+    double *cov_part = nullptr, *betaZ = nullptr, *dZ = nullptr, *gZ = nullptr;
+    double *l1c_old = nullptr, *l1c_new = nullptr;
+    double* pf = nullptr;         // device [p + kMaxCov]: factors of X's columns, then of the covariates
+    std::vector<double> pf_host;  // [p + q]
+    bool pf_x_custom = false;     // some factor of X's columns differs from 1
     // measurement: event pairs recorded around each phase while timing is on
     bool timing = false;
     std::vector<hipEvent_t> tev[kPhases];
@@ -230,6 +243,68 @@ cox_status h2d(cox_ctx* c, void* dev, const void* host, size_t m)
 }
 
 const float* geno_scale(const cox_ctx* c) { return c->x.xt == XT_F32 ? nullptr : c->x.scale; }
+
+// Coefficients per vector: X's p columns, then the q covariates.
+int64_t ptot(const cox_ctx* c) { return c->p + c->q; }
+
+// Penalty factors of X's columns as the kernels take them (null: all 1).
+const double* pf_x(const cox_ctx* c) { return c->pf_x_custom ? c->pf : nullptr; }
+
+CovArgs cov_args(cox_ctx* c) { return CovArgs{c->Z, c->n, c->ldz, (int)c->q, c->nrb, c->cov_part}; }
+
+// Caller's [B][ptot] FP32 coefficients -> the FP64 iterate of X's columns (and the covariates').
+cox_status load_beta(cox_ctx* c, const float* beta, int B)
+{
+    if (c->q)
+        HIPCHK(launch_split_coef(beta, c->p, c->q, B, c->beta64, c->betaZ, c->stream), "split coefficients");
+    else
+        HIPCHK(launch_f32_to_f64(beta, c->beta64, (int64_t)B * c->p, c->stream), "beta to FP64");
+    return COX_OK;
+}
+
+cox_status store_beta(cox_ctx* c, float* beta, int B)
+{
+    if (c->q)
+        HIPCHK(launch_merge_coef(c->beta64, c->betaZ, c->p, c->q, B, beta, c->stream), "merge coefficients");
+    else
+        HIPCHK(launch_f64_to_f32(c->beta64, beta, (int64_t)B * c->p, c->stream), "beta to FP32");
+    return COX_OK;
+}
+
+// eta_b += Z coef_b (no covariates: nothing)
+cox_status cov_eta(cox_ctx* c, const double* coef, int B, const int32_t* active)
+{
+    if (!c->q) return COX_OK;
+    HIPCHK(launch_cov_eta(cov_args(c), coef, B, c->eta, active, c->stream), "Z beta");
+    return COX_OK;
+}
+
+// g_Z = Z' r from the residual the risk pass stored (FP64 when it kept one),
+// then the epilogue of st (no covariates: nothing).
+cox_status cov_grad(cox_ctx* c, const RiskArgs& ra, int B, const int32_t* active, const CovStep& st)
+{
+    if (!c->q) return COX_OK;
+    const CovArgs ca = cov_args(c);
+    HIPCHK(launch_cov_xtr(ca, ra.r64 ? nullptr : ra.r32, c->rstride, ra.r64, B, active, c->stream), "Z' r");
+    HIPCHK(launch_cov_epilogue(ca, st, B, c->stream), "Z' r epilogue");
+    return COX_OK;
+}
+
+CovStep cov_prox(cox_ctx* c, double step, const int32_t* active)
+{
+    CovStep st{};
+    st.mode = GT_PROX;
+    st.beta = c->betaZ;
+    st.dbeta = c->dZ;
+    st.lam = c->lam;
+    st.pf = c->pf + c->p;
+    st.step = step;
+    st.active = active;
+    st.l1old = c->l1c_old;
+    st.l1new = c->l1c_new;
+    st.ostride = c->q;
+    return st;
+}
 
 // eta[b] = X~ coef[b] (no centring) for b < B; coef is b-major [B][p].
 cox_status dense_eta(cox_ctx* c, const double* coef, int B, const double* shift)
@@ -382,6 +457,8 @@ GemvtArgs gemvt_args(cox_ctx* c, int mode)
     g.part_sstride = (int64_t)c->Bmax * c->p;
     g.sumr = c->sumr;
     g.mode = mode;
+    g.ostride = c->p;
+    g.pf = pf_x(c);
     g.nblk = c->nblk;
     g.dcoef = c->dcoef;
     g.chg_flag = c->chg_flag;
@@ -464,6 +541,81 @@ void splitmix_start(uint64_t seed, std::vector<double>& v)
     for (double& x : v) x /= nv;
 }
 
+// ||Z||_2^2 of the covariate block by power iteration (tol 1e-6, at most 1000
+// steps, the SplitMix64 start of seed 95376).  Uses eta, betaZ, dZ and gZ.
+cox_status opnorm2_cov(cox_ctx* c, double* s2)
+{
+    const int q = (int)c->q;
+    std::vector<double> v(q);
+    splitmix_start(95376, v);
+    STCHK(h2d(c, c->betaZ, v.data(), sizeof(double) * q));
+    CovStep raw{};
+    raw.mode = GT_RAW;
+    raw.out64 = c->gZ;
+    raw.ostride = q;
+    const CovArgs ca = cov_args(c);
+    double est = 0.0, prev = 0.0;
+    for (int it = 0; it < 1000; ++it) {
+        HIPCHK(launch_fill_f64(c->eta, 0.0, c->n, c->stream), "zero");
+        HIPCHK(launch_cov_eta(ca, c->betaZ, 1, c->eta, nullptr, c->stream), "Z v");
+        HIPCHK(launch_dot(c->eta, c->eta, c->n, c->scal + 1, c->stream), "norm of Z v");
+        HIPCHK(launch_cov_xtr(ca, nullptr, 0, c->eta, 1, nullptr, c->stream), "Z' u");
+        HIPCHK(launch_cov_epilogue(ca, raw, 1, c->stream), "Z' u");
+        HIPCHK(launch_fill_f64(c->scal + 2, 0.0, 1, c->stream), "zero");
+        HIPCHK(launch_sqnorm_add(c->gZ, q, c->scal + 2, c->stream), "norm of Z' u");
+        double h[2];
+        STCHK(d2h(c, h, c->scal + 1, sizeof(h)));
+        prev = est;
+        est = h[0];
+        if (!std::isfinite(est) || !std::isfinite(h[1])) return fail(c, COX_ERR_NUMERIC, "non-finite power iteration");
+        if (h[1] == 0.0) break;
+        HIPCHK(launch_normalize(c->gZ, c->scal + 2, nullptr, c->betaZ, c->dZ, q, c->stream), "normalise");
+        if (it > 0 && std::fabs(est - prev) < 1e-6 * est) break;
+    }
+    *s2 = est;
+    return COX_OK;
+}
+
+// The unpenalised optimum over the covariates whose penalty factor is 0, with
+// every other coefficient zero: ISTA on Z alone (a penalised covariate gets an
+// infinite threshold and stays at zero) with step 1/(2 ||Z||^2), until
+// max_k |g_k| over the free covariates falls below kFreeCovGtol times its value
+// at zero.  Leaves betaZ, eta and the risk-set state (residual ra stores) at
+// that point.  eta must be zero on entry.
+cox_status fit_free_covariates(cox_ctx* c, const RiskArgs& ra)
+{
+    const int q = (int)c->q;
+    double s2 = 0.0;
+    STCHK(opnorm2_cov(c, &s2));
+    if (!(s2 > 0)) return fail(c, COX_ERR_NUMERIC, "the covariate block is zero");
+    const double step = 1.0 / (2.0 * s2), inf = std::numeric_limits<double>::infinity();
+    STCHK(h2d(c, c->lam, &inf, sizeof(double)));
+    HIPCHK(launch_fill_f64(c->betaZ, 0.0, q, c->stream), "zero");
+    HIPCHK(launch_fill_f64(c->eta, 0.0, c->n, c->stream), "zero");
+    CovStep st = cov_prox(c, step, nullptr);
+    st.out64 = c->gZ;
+    std::vector<double> gz(q);
+    double g0 = -1.0;
+    bool done = false;
+    for (int it = 0; it < kFreeCovMaxIter && !done; ++it) {
+        HIPCHK(launch_risk(ra, c->stream), "risk-set sums");
+        STCHK(cov_grad(c, ra, 1, nullptr, st));  // g at beta_it, then beta_{it+1}
+        STCHK(cov_eta(c, c->dZ, 1, nullptr));
+        if (it % 4 == 0) {
+            STCHK(d2h(c, gz.data(), c->gZ, sizeof(double) * q));
+            double gm = 0.0;
+            for (int k = 0; k < q; ++k)
+                if (c->pf_host[c->p + k] == 0.0) gm = std::max(gm, std::fabs(gz[k]));
+            if (!std::isfinite(gm)) return fail(c, COX_ERR_NUMERIC, "non-finite covariate gradient");
+            if (g0 < 0) g0 = gm;
+            done = gm <= kFreeCovGtol * g0;
+        }
+    }
+    HIPCHK(launch_risk(ra, c->stream), "risk-set sums");
+    if (!done) return fail(c, COX_ERR_NOT_CONVERGED, "the unpenalised covariate fit did not converge");
+    return COX_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -535,6 +687,8 @@ cox_status cox_setup(cox_ctx** out, const cox_matrix* X, const double* time, con
     c->tile = 1024 * std::max<int64_t>(1, (n + 1024LL * kMaxTiles - 1) / (1024LL * kMaxTiles));
     c->ntile = (int)((n + c->tile - 1) / c->tile);
     c->nfin = (int)((n + kFinElems - 1) / kFinElems);
+    c->nrb = cov_row_blocks(n);
+    c->pf_host.assign(p, 1.0);
     {   // row splits of X' r: enough workgroups for several even rounds over the chip
         const int64_t cols_wg = X->xtype == COX_X_F32 ? 16 : 64;
         const int64_t wgs = (p + cols_wg - 1) / cols_wg;
@@ -579,7 +733,11 @@ cox_status cox_setup(cox_ctx** out, const cox_matrix* X, const double* time, con
               dalloc(c, &c->mshift, max_batch) && dalloc(c, &c->stot, (size_t)max_batch * c->ntile) &&
               dalloc(c, &c->qtot, (size_t)max_batch * c->ntile) && dalloc(c, &c->Lpart, (size_t)max_batch * c->ntile) &&
               dalloc(c, &c->rpart, (size_t)max_batch * c->ntile) &&
-              dalloc(c, &c->part_xtr, (size_t)c->nsplit * Bp);
+              dalloc(c, &c->part_xtr, (size_t)c->nsplit * Bp) &&
+              dalloc(c, &c->cov_part, (size_t)max_batch * cov_row_blocks(n) * kMaxCov) &&
+              dalloc(c, &c->betaZ, (size_t)max_batch * kMaxCov) && dalloc(c, &c->dZ, (size_t)max_batch * kMaxCov) &&
+              dalloc(c, &c->gZ, (size_t)max_batch * kMaxCov) && dalloc(c, &c->l1c_old, max_batch) &&
+              dalloc(c, &c->l1c_new, max_batch) && dalloc(c, &c->pf, p + kMaxCov);
     const bool mfma_able = X->xtype != COX_X_F32 && c->x.vec16 && max_batch > kGroup;
     if (ok && mfma_able) {
         c->bpad_max = (int)round_up(max_batch, 16);
@@ -618,6 +776,8 @@ cox_status cox_setup(cox_ctx** out, const cox_matrix* X, const double* time, con
     chk(launch_fill_i32(c->chg_flag, 0, p, c->stream));
     chk(launch_fill_i32(c->nsel, 0, 1, c->stream));
     chk(launch_fill_f64(c->eta, 0.0, Bn, c->stream));
+    chk(launch_fill_f64(c->pf, 1.0, p, c->stream));
+    chk(launch_fill_f64(c->pf + p, 0.0, kMaxCov, c->stream));
     if (c->limbs)
         chk(launch_fill_f64(reinterpret_cast<double*>(c->limbs), 0.0, (int64_t)3 * c->bpad_max * c->rstride / 8,
                             c->stream));
@@ -647,17 +807,23 @@ cox_status cox_loss_grad(cox_ctx* c, const float* beta, int32_t B, double* loss,
     STCHK(check_ctx(c));
     if (!beta || !loss) return fail(c, COX_ERR_INVALID_ARG, "beta and loss must not be NULL");
     STCHK(check_batch(c, B));
-    const int64_t Bp = (int64_t)B * c->p;
-    HIPCHK(launch_f32_to_f64(beta, c->beta64, Bp, c->stream), "beta to FP64");
+    STCHK(load_beta(c, beta, B));
     HIPCHK(launch_scale_coef(c->beta64, geno_scale(c), c->coef, c->p, B, c->stream), "coefficients");
     STCHK(dense_eta(c, c->coef, B, nullptr));
+    STCHK(cov_eta(c, c->betaZ, B, nullptr));
     RiskArgs ra = risk_args(c, B);
     if (!grad) ra.r32 = nullptr;
     HIPCHK(launch_risk(ra, c->stream), "risk-set sums");
     if (grad) {
         GemvtArgs g = gemvt_args(c, GT_GRAD);
         g.out32 = grad;
+        g.ostride = ptot(c);
         STCHK(run_gemvt(c, g, B));
+        CovStep st{};
+        st.mode = GT_GRAD;
+        st.out32 = grad + c->p;
+        st.ostride = ptot(c);
+        STCHK(cov_grad(c, ra, B, nullptr, st));
     }
     std::vector<double> L(B);
     STCHK(d2h(c, L.data(), c->L, sizeof(double) * B));
@@ -678,26 +844,29 @@ cox_status cox_prox_step(cox_ctx* c, float* beta, int32_t B, const double* lambd
     STCHK(check_lambdas(c, lambdas, B));
     if (!(step > 0) || !std::isfinite(step)) return fail(c, COX_ERR_INVALID_ARG, "step must be finite and > 0");
     STCHK(h2d(c, c->lam, lambdas, sizeof(double) * B));
-    const int64_t Bp = (int64_t)B * c->p;
-    HIPCHK(launch_f32_to_f64(beta, c->beta64, Bp, c->stream), "beta to FP64");
+    STCHK(load_beta(c, beta, B));
     HIPCHK(launch_scale_coef(c->beta64, geno_scale(c), c->coef, c->p, B, c->stream), "coefficients");
     STCHK(dense_eta(c, c->coef, B, nullptr));
-    HIPCHK(launch_risk(risk_args(c, B), c->stream), "risk-set sums");
+    STCHK(cov_eta(c, c->betaZ, B, nullptr));
+    const RiskArgs ra = risk_args(c, B);
+    HIPCHK(launch_risk(ra, c->stream), "risk-set sums");
     GemvtArgs g = gemvt_args(c, GT_PROX);
     g.beta = c->beta64;
     g.lam = c->lam;
     g.step = step;
     g.active = nullptr;
     STCHK(run_gemvt(c, g, B));
-    HIPCHK(launch_f64_to_f32(c->beta64, beta, Bp, c->stream), "beta to FP32");
+    STCHK(cov_grad(c, ra, B, nullptr, cov_prox(c, step, nullptr)));
+    STCHK(store_beta(c, beta, B));
     if (obj_before) {
         HIPCHK(launch_rowsum(c->l1old, c->nblk, B, 1.0, c->scal, c->stream), "l1 norm");
-        std::vector<double> v(2 * B);
+        std::vector<double> v(3 * B, 0.0);
         STCHK(d2h(c, v.data(), c->L, sizeof(double) * B));
         STCHK(d2h(c, v.data() + B, c->scal, sizeof(double) * B));
+        if (c->q) STCHK(d2h(c, v.data() + 2 * B, c->l1c_old, sizeof(double) * B));
         bool finite = true;
         for (int b = 0; b < B; ++b) {
-            obj_before[b] = -v[b] + lambdas[b] * v[B + b];
+            obj_before[b] = -v[b] + lambdas[b] * (v[B + b] + v[2 * B + b]);
             finite = finite && std::isfinite(obj_before[b]);
         }
         if (!finite) return fail(c, COX_ERR_NUMERIC, "non-finite objective");
@@ -713,7 +882,9 @@ cox_status cox_prox_apply(cox_ctx* c, float* beta, const float* grad, int32_t B,
     STCHK(check_lambdas(c, lambdas, B));
     if (!(step > 0) || !std::isfinite(step)) return fail(c, COX_ERR_INVALID_ARG, "step must be finite and > 0");
     STCHK(h2d(c, c->lam, lambdas, sizeof(double) * B));
-    HIPCHK(launch_prox_apply(beta, grad, c->lam, step, c->p, B, c->stream), "soft threshold");
+    HIPCHK(launch_prox_apply(beta, grad, c->lam, (c->pf_x_custom || c->q) ? c->pf : nullptr, step, ptot(c), B,
+                             c->stream),
+           "soft threshold");
     return COX_OK;
 }
 
@@ -721,27 +892,56 @@ cox_status cox_lambda_max(cox_ctx* c, double* lambda_max)
 {
     STCHK(check_ctx(c));
     if (!lambda_max) return fail(c, COX_ERR_INVALID_ARG, "lambda_max is NULL");
+    const int64_t p = c->p, q = c->q;
+    for (int64_t j = 0; j < p; ++j)
+        if (c->pf_host[j] == 0.0)
+            return fail(c, COX_ERR_UNSUPPORTED, "lambda_max: only covariates may have a zero penalty factor");
+    bool free_cov = false;
+    for (int64_t k = 0; k < q; ++k) free_cov = free_cov || c->pf_host[p + k] == 0.0;
     HIPCHK(launch_fill_f64(c->eta, 0.0, c->n, c->stream), "zero eta");
-    HIPCHK(launch_risk(risk_args(c, 1), c->stream), "risk-set sums");
+    RiskArgs ra = risk_args(c, 1);
+    ra.r64 = c->r64;
+    cox_status conv = COX_OK;
+    if (free_cov) {
+        conv = fit_free_covariates(c, ra);
+        if (conv != COX_OK && conv != COX_ERR_NOT_CONVERGED) return conv;
+    } else {
+        HIPCHK(launch_risk(ra, c->stream), "risk-set sums");
+    }
     GemvtArgs g = gemvt_args(c, GT_RAW);
     g.out64 = c->g64;
     STCHK(run_gemvt(c, g, 1));
-    std::vector<double> gh(c->p);
-    STCHK(d2h(c, gh.data(), c->g64, sizeof(double) * c->p));
+    std::vector<double> gh(p + q);
+    if (q) {
+        CovStep st{};
+        st.mode = GT_RAW;
+        st.out64 = c->gZ;
+        st.ostride = q;
+        STCHK(cov_grad(c, ra, 1, nullptr, st));
+        STCHK(d2h(c, gh.data() + p, c->gZ, sizeof(double) * q));
+    }
+    STCHK(d2h(c, gh.data(), c->g64, sizeof(double) * p));
     double mx = 0.0;
-    for (double v : gh) mx = std::max(mx, std::fabs(v));
+    for (int64_t j = 0; j < p + q; ++j)
+        if (c->pf_host[j] > 0.0) mx = std::max(mx, std::fabs(gh[j]) / c->pf_host[j]);
     if (!std::isfinite(mx)) return fail(c, COX_ERR_NUMERIC, "non-finite gradient");
     *lambda_max = mx;
-    return COX_OK;
+    return conv == COX_OK ? COX_OK : fail(c, conv, "the unpenalised covariate fit did not converge");
 }
 
 cox_status cox_opnorm2(cox_ctx* c, double tol, int32_t maxiter, uint64_t seed, double* s2, int32_t* iters)
 {
     STCHK(check_ctx(c));
     if (!s2 || !(tol >= 0) || maxiter < 1) return fail(c, COX_ERR_INVALID_ARG, "bad opnorm2 arguments");
-    std::vector<double> v(c->p);
+    const int q = (int)c->q;
+    std::vector<double> v(ptot(c));
     splitmix_start(seed, v);
     STCHK(h2d(c, c->beta64, v.data(), sizeof(double) * c->p));
+    if (q) STCHK(h2d(c, c->betaZ, v.data() + c->p, sizeof(double) * q));
+    CovStep raw{};
+    raw.mode = GT_RAW;
+    raw.out64 = c->gZ;
+    raw.ostride = q;
     const float* scale = geno_scale(c);
     const bool centred = c->x.xt != XT_F32 && c->x.center;
     HIPCHK(launch_scale_coef(c->beta64, scale, c->coef, c->p, 1, c->stream), "coefficients");
@@ -750,12 +950,19 @@ cox_status cox_opnorm2(cox_ctx* c, double tol, int32_t maxiter, uint64_t seed, d
     while (it < maxiter) {
         if (centred) HIPCHK(launch_center_shift(c->x.center, scale, c->beta64, c->p, c->scal + 0, c->stream), "shift");
         STCHK(dense_eta(c, c->coef, 1, centred ? c->scal + 0 : nullptr));
+        STCHK(cov_eta(c, c->betaZ, 1, nullptr));
         HIPCHK(launch_dot(c->eta, c->eta, c->n, c->scal + 1, c->stream), "norm of X v");
         HIPCHK(launch_to_r32(c->eta, nullptr, c->r32, c->sumr, c->n, c->stream), "u to FP32");
         GemvtArgs g = gemvt_args(c, GT_RAW);
         g.out64 = c->g64;
         STCHK(run_gemvt(c, g, 1));
         HIPCHK(launch_dot(c->g64, c->g64, c->p, c->scal + 2, c->stream), "norm of X' u");
+        if (q) {
+            RiskArgs ru{};
+            ru.r32 = c->r32;
+            STCHK(cov_grad(c, ru, 1, nullptr, raw));
+            HIPCHK(launch_sqnorm_add(c->gZ, q, c->scal + 2, c->stream), "norm of Z' u");
+        }
         double h[2];
         STCHK(d2h(c, h, c->scal + 1, sizeof(h)));
         ++it;
@@ -764,6 +971,7 @@ cox_status cox_opnorm2(cox_ctx* c, double tol, int32_t maxiter, uint64_t seed, d
         if (!std::isfinite(est) || !std::isfinite(h[1])) return fail(c, COX_ERR_NUMERIC, "non-finite power iteration");
         if (h[1] == 0.0) break;
         HIPCHK(launch_normalize(c->g64, c->scal + 2, scale, c->beta64, c->coef, c->p, c->stream), "normalise");
+        if (q) HIPCHK(launch_normalize(c->gZ, c->scal + 2, nullptr, c->betaZ, c->dZ, q, c->stream), "normalise");
         if (it > 1 && std::fabs(est - prev) < tol * est) break;
     }
     *s2 = est;
@@ -795,15 +1003,22 @@ cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_
     }
     STCHK(h2d(c, c->lam, lambdas, sizeof(double) * B));
     const int64_t Bp = (int64_t)B * c->p, Bn = (int64_t)B * c->n;
+    const int q = (int)c->q;
     if (o.warm_start) {
-        HIPCHK(launch_f32_to_f64(beta, c->beta64, Bp, c->stream), "beta to FP64");
+        STCHK(load_beta(c, beta, B));
         HIPCHK(launch_scale_coef(c->beta64, geno_scale(c), c->coef, c->p, B, c->stream), "coefficients");
         STCHK(dense_eta(c, c->coef, B, nullptr));
-        HIPCHK(launch_l1_blocks(c->beta64, c->p, B, c->nblk, c->l1new, c->stream), "l1 blocks");
+        STCHK(cov_eta(c, c->betaZ, B, nullptr));
+        HIPCHK(launch_l1_blocks(c->beta64, pf_x(c), c->p, B, c->nblk, c->l1new, c->stream), "l1 blocks");
+        if (q) HIPCHK(launch_cov_l1(c->betaZ, c->pf + c->p, q, B, c->l1c_new, c->stream), "covariate l1");
     } else {
         HIPCHK(launch_fill_f64(c->beta64, 0.0, Bp, c->stream), "zero beta");
         HIPCHK(launch_fill_f64(c->eta, 0.0, Bn, c->stream), "zero eta");
         HIPCHK(launch_fill_f64(c->l1new, 0.0, (int64_t)B * c->nblk, c->stream), "zero l1");
+        if (q) {
+            HIPCHK(launch_fill_f64(c->betaZ, 0.0, (int64_t)B * q, c->stream), "zero beta");
+            HIPCHK(launch_fill_f64(c->l1c_new, 0.0, B, c->stream), "zero l1");
+        }
     }
     HIPCHK(launch_fill_i32(c->nsel, 0, 1, c->stream), "reset");
     HIPCHK(launch_fill_i32(c->kit, 0, B, c->stream), "reset");
@@ -817,7 +1032,8 @@ cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_
     ra.part = (o.eta_mode == 0 && !mfma) ? c->part_upd : nullptr;
     ra.use_ctl = 1;
     ra.ctl = FitCtl{c->lam, c->l1new, c->nblk, c->hist, c->kit, c->active, c->iters, c->status, c->fobj,
-                    o.max_iter, o.lag, o.tol};
+                    q ? c->l1c_new : nullptr, o.max_iter, o.lag, o.tol};
+    const CovStep cst = cov_prox(c, step, c->active);
     GemvtArgs g = gemvt_args(c, GT_PROX);
     g.beta = c->beta64;
     g.lam = c->lam;
@@ -866,12 +1082,15 @@ cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_
                 HIPCHK(launch_scale_coef(c->beta64, geno_scale(c), c->coef, c->p, B, c->stream), "coefficients");
                 STCHK(dense_eta(c, c->coef, B, nullptr));
             }
+            // the covariates' share: a fresh eta needs all of Z beta_Z, an updated one the change
+            STCHK(cov_eta(c, o.eta_mode == 1 ? c->betaZ : c->dZ, B, o.eta_mode == 1 ? nullptr : c->active));
         }
         tmark(c, COX_PHASE_RISK);
         HIPCHK(launch_risk(ra, c->stream), "risk-set sums");
         tmark(c, COX_PHASE_RISK);
         if (it < o.max_iter) {
             STCHK(run_gemvt(c, g, B, rlimbs));
+            STCHK(cov_grad(c, ra, B, c->active, cst));
             if (o.eta_mode == 0) HIPCHK(launch_compact(c->chg_cnt, c->chg_idx, c->nblk, c->sel, c->nsel, c->stream), "compact");
         }
         if ((it + 1) % poll == 0 && it < o.max_iter) {
@@ -880,7 +1099,7 @@ cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_
             if (std::all_of(act.begin(), act.end(), [](int32_t a) { return a == 0; })) break;
         }
     }
-    HIPCHK(launch_f64_to_f32(c->beta64, beta, Bp, c->stream), "beta to FP32");
+    STCHK(store_beta(c, beta, B));
     std::vector<int32_t> st(B), itv(B);
     std::vector<double> fo(B);
     STCHK(d2h(c, st.data(), c->status, sizeof(int32_t) * B));
@@ -895,6 +1114,85 @@ cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_
     }
     if (numeric) return fail(c, COX_ERR_NUMERIC, "non-finite objective");
     if (notconv) return fail(c, COX_ERR_NOT_CONVERGED, "max_iter reached");
+    return COX_OK;
+}
+
+cox_status cox_fit_sequence(cox_ctx* c, const double* lambdas, int32_t L, const cox_fit_opts* opts_in,
+                            float* beta_path, int32_t* iters, double* obj)
+{
+    STCHK(check_ctx(c));
+    if (!beta_path || L < 1) return fail(c, COX_ERR_INVALID_ARG, "beta_path is NULL or L < 1");
+    STCHK(check_lambdas(c, lambdas, L));
+    cox_fit_opts o{1000, 1e-5, 10, 0.0, 0, 0, 16, 0};
+    if (opts_in) o = *opts_in;
+    if (o.step <= 0) {  // one step size for the whole sequence
+        double s2 = 0;
+        STCHK(cox_opnorm2(c, 1e-6, 1000, 95376, &s2, nullptr));
+        if (!(s2 > 0)) return fail(c, COX_ERR_NUMERIC, "||X||_2 is zero; no step size");
+        o.step = 1.0 / (2.0 * s2);
+    }
+    const int64_t pt = ptot(c);
+    bool notconv = false;
+    for (int32_t l = 0; l < L; ++l) {
+        float* bl = beta_path + (int64_t)l * pt;
+        cox_fit_opts ol = o;
+        if (l > 0) {
+            HIPCHK(hipMemcpyAsync(bl, bl - pt, sizeof(float) * pt, hipMemcpyDeviceToDevice, c->stream),
+                   "previous solution");
+            ol.warm_start = 1;
+        }
+        int32_t it = 0;
+        double f = 0;
+        const cox_status st = cox_fit_path(c, lambdas + l, 1, &ol, bl, &it, &f);
+        if (iters) iters[l] = it;
+        if (obj) obj[l] = f;
+        if (st == COX_ERR_NOT_CONVERGED)
+            notconv = true;
+        else if (st != COX_OK)
+            return st;
+    }
+    if (notconv) return fail(c, COX_ERR_NOT_CONVERGED, "max_iter reached for some lambda");
+    return COX_OK;
+}
+
+cox_status cox_set_covariates(cox_ctx* c, const float* Z, int64_t q, int64_t ldz)
+{
+    STCHK(check_ctx(c));
+    if (q < 0 || q > kMaxCov) return fail(c, COX_ERR_INVALID_ARG, "q must be in 0..COX_MAX_COVARIATES");
+    if (q > 0 && (!Z || ldz < c->n || ldz > (int64_t(1) << 40)))
+        return fail(c, COX_ERR_INVALID_ARG, "Z is NULL or ldz < n");
+    STCHK(sync(c));  // work already enqueued may still read the previous block
+    c->Z = q ? Z : nullptr;
+    c->q = q;
+    c->ldz = q ? ldz : 0;
+    c->pf_host.resize(c->p + q);
+    std::fill(c->pf_host.begin() + c->p, c->pf_host.end(), 0.0);
+    HIPCHK(launch_fill_f64(c->pf + c->p, 0.0, kMaxCov, c->stream), "covariate penalty factors");
+    STCHK(sync(c));
+    return COX_OK;
+}
+
+cox_status cox_set_penalty_factors(cox_ctx* c, const double* pf)
+{
+    STCHK(check_ctx(c));
+    const int64_t pt = ptot(c);
+    std::vector<double> v(pt);
+    if (pf) {
+        for (int64_t j = 0; j < pt; ++j) {
+            if (!std::isfinite(pf[j]) || pf[j] < 0)
+                return fail(c, COX_ERR_INVALID_ARG, "penalty factors must be finite and >= 0");
+            v[j] = pf[j];
+        }
+    } else {
+        std::fill(v.begin(), v.begin() + c->p, 1.0);
+        std::fill(v.begin() + c->p, v.end(), 0.0);
+    }
+    STCHK(sync(c));  // work already enqueued may still read the previous factors
+    HIPCHK(hipMemcpyAsync(c->pf, v.data(), sizeof(double) * pt, hipMemcpyHostToDevice, c->stream),
+           "penalty factors");
+    STCHK(sync(c));
+    c->pf_host = v;
+    c->pf_x_custom = std::any_of(v.begin(), v.begin() + c->p, [](double f) { return f != 1.0; });
     return COX_OK;
 }
 

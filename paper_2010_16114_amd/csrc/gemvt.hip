@@ -18,8 +18,9 @@
 //    order, genotype columns are standardised, g_j = s_j (sum_i g_ij r_i -
 //    mu_j sum_i r_i), and the mode's output is written: RAW (g, FP64), GRAD
 //    (-g, FP32: the gradient of -L) or PROX (the soft-threshold step on the FP64
-//    iterate, the list of columns whose coefficient changed and partial sums of
-//    |beta| before and after, for the next eta update and the objective).
+//    iterate with threshold sigma lambda pf_j, pf_j the column's penalty factor,
+//    the list of columns whose coefficient changed and partial sums of
+//    pf_j |beta_j| before and after, for the next eta update and the objective).
 //
 // Arithmetic: FP32 X is multiplied in FP64 (exact products, FP64 sums).  One-
 // byte X (allele counts) is decoded to FP32 and accumulated in FP32 within an
@@ -245,19 +246,21 @@ __global__ __launch_bounds__(256) void gemvt_epilogue_kernel(GemvtArgs a)
             for (int s = 0; s < a.nsplit; ++s) g += a.part[(int64_t)s * a.part_sstride + at];
             if (geno) g = sc * (g - mu * a.sumr[bb]);
             if (a.mode == GT_RAW) {
-                a.out64[at] = g;
+                a.out64[(int64_t)bb * a.ostride + j] = g;
             } else if (a.mode == GT_GRAD) {
-                a.out32[at] = (float)(-g);
+                a.out32[(int64_t)bb * a.ostride + j] = (float)(-g);
             } else {
+                const double f = a.pf ? a.pf[j] : 1.0;  // penalty factor: 0 leaves the column unpenalised
                 const double old = a.beta[at];
                 double nw = old;
-                if (a.active == nullptr || a.active[bb]) nw = soft_threshold(old + a.step * g, a.step * a.lam[bb]);
+                if (a.active == nullptr || a.active[bb])
+                    nw = soft_threshold(old + a.step * g, f == 0.0 ? 0.0 : a.step * a.lam[bb] * f);
                 a.beta[at] = nw;
                 const double d = nw - old;
                 a.dcoef[at] = d * (geno ? sc : 1.0);
                 changed |= d != 0.0;
-                l1o = fabs(old);
-                l1n = fabs(nw);
+                l1o = f * fabs(old);
+                l1n = f * fabs(nw);
             }
         }
         if (a.mode == GT_PROX) {

@@ -18,6 +18,8 @@ constexpr int kUpdThreads = 256;                    // eta update: 4 rows per th
 constexpr int kUpdRows = 4 * kUpdThreads;
 constexpr int kGemvThreads = 256;                   // dense GEMV
 constexpr int kMaxHist = 33;                        // lag <= 32
+constexpr int kCovRows = 8192;                      // rows per workgroup of Z' r
+constexpr int kMaxCov = 64;                         // covariates in the dense block beside X
 
 // Read-only description of X as the kernels see it.
 struct XDesc {
@@ -49,6 +51,7 @@ struct FitCtl {
     int32_t* iters;        // [B] steps taken at the stop
     int32_t* status;       // [B] 0 running, 1 converged, 2 max_iter, 3 non-finite
     double* fobj;          // [B] latest objective
+    const double* l1cov;   // [B] penalised l1 of the covariate coefficients, or null
     int max_iter, lag;
     double tol;
 };
@@ -101,11 +104,13 @@ struct GemvtArgs {
     const double* sumr;    // [B] (centring of genotype columns)
     int b0, nb;            // this launch covers b0 .. b0+nb-1 (nb <= template NB)
     int mode;
-    double* out64;         // GT_RAW: [B][p]  X~' r
-    float* out32;          // GT_GRAD: [B][p]  -X~' r
+    double* out64;         // GT_RAW: [B][ostride]  X~' r (first p entries of each row)
+    float* out32;          // GT_GRAD: [B][ostride]  -X~' r
+    int64_t ostride;       // >= p
     // GT_PROX
     double* beta;          // [B][p] in/out
     const double* lam;     // [B]
+    const double* pf;      // [p] penalty factors (threshold step * lam * pf_j), or null: all 1
     double step;
     const int32_t* active; // [B] or null (all active)
     double* dcoef;         // [B][p] (beta_new - beta_old) * scale_j
@@ -138,9 +143,12 @@ hipError_t launch_f32_to_f64(const float* in, double* out, int64_t m, hipStream_
 hipError_t launch_f64_to_f32(const double* in, float* out, int64_t m, hipStream_t s);
 hipError_t launch_scale_coef(const double* beta, const float* scale, double* coef, int64_t p, int B,
                              hipStream_t s);
-hipError_t launch_l1_blocks(const double* beta, int64_t p, int B, int nblk, double* l1, hipStream_t s);
-hipError_t launch_prox_apply(float* beta, const float* grad, const double* lam, double step, int64_t p, int B,
-                             hipStream_t s);
+// l1[b][blk] = sum over the block's columns of pf_j |beta_bj| (pf null: 1)
+hipError_t launch_l1_blocks(const double* beta, const double* pf, int64_t p, int B, int nblk, double* l1,
+                            hipStream_t s);
+// beta <- S_{step lam_b pf_j}(beta - step grad), pf null: 1
+hipError_t launch_prox_apply(float* beta, const float* grad, const double* lam, const double* pf, double step,
+                             int64_t p, int B, hipStream_t s);
 hipError_t launch_nll_backward(const double* r64, const double* gl, int64_t n, int B, void* out, int out_f64,
                                hipStream_t s);
 // out[0] = sum_i a_i * (b ? b_i : 1) over m entries, one workgroup, fixed order
@@ -158,5 +166,46 @@ hipError_t launch_to_r32(const double* u, const double* shift, float* r32, doubl
 hipError_t launch_rowsum(const double* in, int64_t m, int B, double a, double* out, hipStream_t s);
 hipError_t launch_fill_f64(double* p, double v, int64_t m, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t m, hipStream_t s);
+
+// ---- the dense covariate block Z beside X (covar.hip)
+struct CovArgs {
+    const float* Z;        // column-major n x q, column k at Z + k * ldz
+    int64_t n, ldz;
+    int q;                 // 1 .. kMaxCov
+    int nrb;               // cov_row_blocks(n)
+    double* part;          // [B][nrb][q] partial sums of Z' r
+};
+
+struct CovStep {
+    int mode;              // GemvtMode
+    double* out64;         // [B][ostride] g_Z, or null
+    float* out32;          // GT_GRAD: [B][ostride] -g_Z
+    int64_t ostride;
+    // GT_PROX
+    double* beta;          // [B][q] in/out
+    double* dbeta;         // [B][q] new - old
+    const double* lam;     // [B]
+    const double* pf;      // [q]
+    double step;
+    const int32_t* active; // [B] or null
+    double* l1old;         // [B] sum_k pf_k |beta_k| before
+    double* l1new;         // [B] and after
+};
+
+int cov_row_blocks(int64_t n);
+// partial sums of Z' r for b < B; the residual is r32 ([B][rstride]) or r64 ([B][n])
+hipError_t launch_cov_xtr(const CovArgs& c, const float* r32, int64_t rstride, const double* r64, int B,
+                          const int32_t* active, hipStream_t s);
+hipError_t launch_cov_epilogue(const CovArgs& c, const CovStep& st, int B, hipStream_t s);
+// eta_b += Z coef_b for b < B (coef [B][q]) unless active[b] == 0
+hipError_t launch_cov_eta(const CovArgs& c, const double* coef, int B, double* eta, const int32_t* active,
+                          hipStream_t s);
+hipError_t launch_cov_l1(const double* beta, const double* pf, int q, int B, double* l1, hipStream_t s);
+// [B][p + q] FP32 <-> [B][p] and [B][q] FP64
+hipError_t launch_split_coef(const float* in, int64_t p, int64_t q, int B, double* x64, double* z64, hipStream_t s);
+hipError_t launch_merge_coef(const double* x64, const double* z64, int64_t p, int64_t q, int B, float* out,
+                             hipStream_t s);
+// acc[0] += sum_k v_k^2
+hipError_t launch_sqnorm_add(const double* v, int q, double* acc, hipStream_t s);
 
 }  // namespace cox

@@ -1,8 +1,8 @@
 // misc.hip -- small elementwise kernels and fixed-order reductions.
 //
 // prox_apply is the standalone fused elementwise step of Section 5.3,
-// beta <- S_{sigma lambda}(beta - sigma grad), with S the soft-thresholding of
-// Section 4.2; nll_backward is the adjoint of the negative log partial
+// beta <- S_{sigma lambda pf_j}(beta - sigma grad), with S the soft-thresholding
+// of Section 4.2 and pf_j the column's penalty factor; nll_backward is the adjoint of the negative log partial
 // likelihood with respect to eta (-(I - P) delta scaled by the incoming
 // gradient).  Reductions run in one workgroup in a fixed order, so results are
 // reproducible bit for bit.
@@ -34,9 +34,9 @@ __global__ void scale_coef_kernel(const double* __restrict__ beta, const float* 
         coef[i] = scale ? beta[i] * (double)scale[i % p] : beta[i];
 }
 
-// l1[b][blk] = sum over the 16 columns of GEMV^T workgroup blk of |beta_bj|, in column order.
-__global__ void l1_blocks_kernel(const double* __restrict__ beta, int64_t p, int B, int nblk,
-                                 double* __restrict__ l1)
+// l1[b][blk] = sum over the 16 columns of GEMV^T workgroup blk of pf_j |beta_bj|, in column order.
+__global__ void l1_blocks_kernel(const double* __restrict__ beta, const double* __restrict__ pf, int64_t p, int B,
+                                 int nblk, double* __restrict__ l1)
 {
     const int64_t m = (int64_t)nblk * B;
     for (int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x; t < m; t += (int64_t)gridDim.x * kT) {
@@ -44,18 +44,20 @@ __global__ void l1_blocks_kernel(const double* __restrict__ beta, int64_t p, int
         double s = 0.0;
         for (int c = 0; c < kGemvtCols; ++c) {
             const int64_t j = blk * kGemvtCols + c;
-            if (j < p) s += fabs(beta[b * p + j]);
+            if (j < p) s += (pf ? pf[j] : 1.0) * fabs(beta[b * p + j]);
         }
         l1[t] = s;
     }
 }
 
 __global__ void prox_apply_kernel(float* __restrict__ beta, const float* __restrict__ grad,
-                                  const double* __restrict__ lam, double step, int64_t p, int B)
+                                  const double* __restrict__ lam, const double* __restrict__ pf, double step,
+                                  int64_t p, int B)
 {
     const int64_t m = p * B;
     for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < m; i += (int64_t)gridDim.x * kT) {
-        const double t = step * lam[i / p];
+        const double f = pf ? pf[i % p] : 1.0;
+        const double t = f == 0.0 ? 0.0 : step * lam[i / p] * f;
         beta[i] = (float)soft_threshold((double)beta[i] - step * (double)grad[i], t);
     }
 }
@@ -172,14 +174,15 @@ hipError_t launch_scale_coef(const double* beta, const float* scale, double* coe
 {
     COX_LAUNCH(scale_coef_kernel, grid_for(p * B), beta, scale, coef, p, B);
 }
-hipError_t launch_l1_blocks(const double* beta, int64_t p, int B, int nblk, double* l1, hipStream_t s)
+hipError_t launch_l1_blocks(const double* beta, const double* pf, int64_t p, int B, int nblk, double* l1,
+                            hipStream_t s)
 {
-    COX_LAUNCH(l1_blocks_kernel, grid_for((int64_t)nblk * B), beta, p, B, nblk, l1);
+    COX_LAUNCH(l1_blocks_kernel, grid_for((int64_t)nblk * B), beta, pf, p, B, nblk, l1);
 }
-hipError_t launch_prox_apply(float* beta, const float* grad, const double* lam, double step, int64_t p, int B,
-                             hipStream_t s)
+hipError_t launch_prox_apply(float* beta, const float* grad, const double* lam, const double* pf, double step,
+                             int64_t p, int B, hipStream_t s)
 {
-    COX_LAUNCH(prox_apply_kernel, grid_for(p * B), beta, grad, lam, step, p, B);
+    COX_LAUNCH(prox_apply_kernel, grid_for(p * B), beta, grad, lam, pf, step, p, B);
 }
 hipError_t launch_nll_backward(const double* r64, const double* gl, int64_t n, int B, void* out, int out_f64,
                                hipStream_t s)

@@ -280,6 +280,7 @@ __global__ __launch_bounds__(kT) void risk_finish_kernel(RiskArgs a)
     for (int q = threadIdx.x; q < c.nblk; q += kT) l1 += c.l1[(int64_t)b * c.nblk + q];
     l1 = block_sum(l1, sh);
     if (threadIdx.x == 0) {
+        if (c.l1cov) l1 += c.l1cov[b];
         const double f = -L + c.lam[b] * l1;
         const int k = c.kit[b];
         double* h = c.hist + (int64_t)b * kMaxHist;

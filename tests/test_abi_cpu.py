@@ -55,6 +55,9 @@ def test_null_context_calls():
     assert L.cox_loss_grad(None, None, 1, None, None) == P.ERR_INVALID_ARG
     assert L.cox_fit_path(None, None, 1, None, None, None, None) == P.ERR_INVALID_ARG
     assert L.cox_nll_forward(None, None, 0, 1, None) == P.ERR_INVALID_ARG
+    assert L.cox_fit_sequence(None, None, 1, None, None, None, None) == P.ERR_INVALID_ARG
+    assert L.cox_set_covariates(None, None, 0, 0) == P.ERR_INVALID_ARG
+    assert L.cox_set_penalty_factors(None, None) == P.ERR_INVALID_ARG
 
 
 def test_header_constants_match_binding():
@@ -63,6 +66,7 @@ def test_header_constants_match_binding():
     text = open(P.HEADER).read()
     assert int(re.search(r"#define COX_MFMA_VARIANTS (\d+)", text).group(1)) == P.MFMA_VARIANTS
     assert int(re.search(r"#define COX_MFMA_ETA_VARIANTS (\d+)", text).group(1)) == P.ETA_VARIANTS
+    assert int(re.search(r"#define COX_MAX_COVARIATES (\d+)", text).group(1)) == P.MAX_COVARIATES
     assert re.search(r"COX_X_FP8_E4M3\s*=\s*(\d+)", text).group(1) == str(P.X_FP8_E4M3)
     assert re.search(r"COX_X_INT8\s*=\s*(\d+)", text).group(1) == str(P.X_INT8)
 
