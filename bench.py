@@ -199,6 +199,11 @@ def bench_geno_batched(args):
     mu_d, sc_d = torch.from_numpy(mu).cuda(), torch.from_numpy(sc).cuda()
     torch.cuda.synchronize()
     cox = P.Cox(G, d.time, d.event, xtype=P.X_FP8_E4M3, n=n, center=mu_d, scale=sc_d, max_batch=B)
+    if args.covariates:
+        # Section 6's unpenalised covariates (sex and principal components) beside the SNPs
+        log(f"attaching {args.covariates} unpenalised covariates")
+        Z = torch.from_numpy(coxsim.covariate_block(n, args.covariates, d.seed)).cuda()
+        cox.set_covariates(Z)
     lmax = cox.lambda_max()
     s2, pit = cox.opnorm2(tol=1e-6, maxiter=args.power_steps)
     sigma = 1.0 / (2.0 * s2)
@@ -219,6 +224,7 @@ def bench_geno_batched(args):
     eta_ms, eta_n = cox.timing_read("eta")
     xk_ms, xk_n = cox.timing_read("xtr_kernel")
     ek_ms, ek_n = cox.timing_read("eta_kernel")
+    cov_ms, cov_n = cox.timing_read("cov")
     cox.timing(False)
     elapsed = t1 - t0
     nnz = (beta != 0).sum(dim=1).cpu().numpy()
@@ -251,10 +257,12 @@ def bench_geno_batched(args):
                    "gradient": f"int8 MFMA, residual rounded to {args.residual_bits}-bit integers in {limbs} "
                                f"int8 limbs, exact int32 accumulation",
                    "residual_bits": args.residual_bits,
-                   "eta": "int8 MFMA over the changed columns, FP64 accumulator"},
+                   "eta": "int8 MFMA over the changed columns, FP64 accumulator",
+                   "covariates": args.covariates},
         "iters_per_s": args.steps / elapsed,
         "phases_ms_per_step": {"xtr_prox": xtr_ms / max(xtr_n, 1), "risk": risk_ms / max(risk_n, 1),
-                               "eta_update": eta_ms / max(eta_n, 1)},
+                               "eta_update": eta_ms / max(eta_n, 1),
+                               "covariates": cov_ms / args.steps if args.covariates else 0.0},
         "kernels_ms_per_launch": {"mfma_xtr_split_kernel": xk_ms / max(xk_n, 1), "mfma_eta_kernel": ek_ms / max(ek_n, 1)},
         "roofline": {"bound": "hbm", "kernel": "mfma_xtr_split_kernel (X~' R for B lambdas)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -356,6 +364,8 @@ def main():
     ap.add_argument("--calibrate-copy-gb", type=float, default=0.0,
                     help="first copy a buffer of this many GB with torch (a plain copy kernel of known size, "
                          "for scaling the HBM counters)")
+    ap.add_argument("--covariates", type=int, default=0,
+                    help="batched workload: attach this many unpenalised covariates (sex + principal components)")
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--p", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")

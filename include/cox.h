@@ -247,7 +247,8 @@ cox_status cox_nll_backward(cox_ctx *ctx, const double *grad_loss, int32_t B, vo
  * pass), COX_PHASE_XTR_KERNEL (each launch of the column-sum kernel alone:
  * the matrix-core X~' R kernel, or one vector X~' r launch per group of up to
  * 8 vectors), COX_PHASE_ETA_KERNEL (each launch of the matrix-core eta kernel
- * alone).
+ * alone), COX_PHASE_COV (the covariate block's Z' r with its proximal step, and
+ * its eta update; nothing without covariates).
  * cox_timing_enable(ctx, 1) starts recording and clears the totals; 0 stops.
  * cox_timing_read returns the summed milliseconds and the number of timed
  * launches of a phase since the last enable.  Synchronises. */
@@ -256,7 +257,8 @@ typedef enum {
     COX_PHASE_RISK = 1,
     COX_PHASE_ETA = 2,
     COX_PHASE_XTR_KERNEL = 3,
-    COX_PHASE_ETA_KERNEL = 4
+    COX_PHASE_ETA_KERNEL = 4,
+    COX_PHASE_COV = 5
 } cox_phase;
 
 /* The batched matrix-core passes (X~' R and the eta update, used when X holds

@@ -276,7 +276,7 @@ class Cox:
         self.last_forward_key = self.forward_key(eta)
         return loss
 
-    PHASES = {"xtr": 0, "risk": 1, "eta": 2, "xtr_kernel": 3, "eta_kernel": 4}
+    PHASES = {"xtr": 0, "risk": 1, "eta": 2, "xtr_kernel": 3, "eta_kernel": 4, "cov": 5}
 
     def mfma_tuning(self):
         """Pipeline shapes chosen by the autotuner and their tuning times (ms)."""

@@ -27,7 +27,7 @@
 
 using namespace cox;
 
-constexpr int kPhases = 5;  // cox_phase values
+constexpr int kPhases = 6;  // cox_phase values
 
 static_assert(kMfmaVariants == COX_MFMA_VARIANTS && kMfmaEtaVariants == COX_MFMA_ETA_VARIANTS,
               "pipeline shape counts differ from the header");
@@ -275,7 +275,9 @@ cox_status store_beta(cox_ctx* c, float* beta, int B)
 cox_status cov_eta(cox_ctx* c, const double* coef, int B, const int32_t* active)
 {
     if (!c->q) return COX_OK;
+    tmark(c, COX_PHASE_COV);
     HIPCHK(launch_cov_eta(cov_args(c), coef, B, c->eta, active, c->stream), "Z beta");
+    tmark(c, COX_PHASE_COV);
     return COX_OK;
 }
 
@@ -285,8 +287,10 @@ cox_status cov_grad(cox_ctx* c, const RiskArgs& ra, int B, const int32_t* active
 {
     if (!c->q) return COX_OK;
     const CovArgs ca = cov_args(c);
+    tmark(c, COX_PHASE_COV);
     HIPCHK(launch_cov_xtr(ca, ra.r64 ? nullptr : ra.r32, c->rstride, ra.r64, B, active, c->stream), "Z' r");
     HIPCHK(launch_cov_epilogue(ca, st, B, c->stream), "Z' r epilogue");
+    tmark(c, COX_PHASE_COV);
     return COX_OK;
 }
 
