@@ -513,7 +513,7 @@ int cox_oracle_newton(int kind, const void *data, int64_t n, int64_t p, int64_t 
                       int32_t *iters_out)
 {
     oracle_matrix X;
-    if (make_matrix(&X, kind, data, n, p, ldx, mu, s) || m < 1 || m > 256 || maxit < 0 || n < 1) return -1;
+    if (make_matrix(&X, kind, data, n, p, ldx, mu, s) || m < 1 || m > 1024 || maxit < 0 || n < 1) return -1;
     for (int64_t a = 0; a < m; ++a)
         if (cols[a] < 0 || cols[a] >= p) return -1;
     int64_t *order = malloc(sizeof(int64_t) * (size_t)(3 * n));
