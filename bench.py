@@ -16,6 +16,10 @@ Workloads (synthetic, seeded; they stand in for the UK Biobank genotypes):
   gauss-fp32 : n = 20,000 subjects x p = 50,000 covariates, X ~ N(0,1) FP32,
                50 true effects, ~30% censored, lambda = 0.3 lambda_max,
                step 1/(2 ||X||^2) by power iteration, 500 steps.
+  refit      : Section 6's post-selection refit: n = 400,000 subjects, 333 SNP
+               columns of an FP8 genotype matrix plus 11 unpenalised covariates,
+               Newton's method with the exact Breslow Hessian to max |g| <= 1e-6
+               (timed in Newton steps per second).
 
 The oracle (plain FP64 C) is timed on the host cores on a bounded sample of
 the same workload as the CPU baseline.
@@ -348,12 +352,101 @@ def cpu_baseline_geno(d, lam, sigma, p_full, p_sample: int = 8000, budget_s: flo
                       f"{p_full} columns (n={d.n}), scaled by {p_sample}/{p_full}"}
 
 
+FP64_VALU_PEAK_TFLOPS = 78.6
+
+
+def bench_refit(args):
+    """Section 6's post-selection refit at its size: n subjects, m SNPs of an FP8
+    genotype matrix (standardised on the fly) plus q unpenalised covariates,
+    Newton's method with the exact Breslow Hessian until max |g| <= gtol."""
+    import torch
+
+    import coxsim
+    import paper_2010_16114_amd as P
+
+    n, p, m, q = args.n or 400000, args.p or 4000, args.refit_cols, args.covariates or 11
+    ldx = (n + 15) // 16 * 16
+    log(f"drawing survival times (n={n}, p={p})")
+    d = coxsim.genotype_problem(n, p, 40, 0.8, coxsim.SEED_BASE + 6, materialize=False)
+    G, c1, c2 = coxsim.genotype_device(n, p, d.seed, d.thresholds, fmt=1, ldx=ldx)
+    mu, sc = coxsim.standardisation(c1, c2, n)
+    mu_d, sc_d = torch.from_numpy(mu).cuda(), torch.from_numpy(sc).cuda()
+    cox = P.Cox(G, d.time, d.event, xtype=P.X_FP8_E4M3, n=n, center=mu_d, scale=sc_d)
+    Z = torch.from_numpy(coxsim.covariate_block(n, q, d.seed)).cuda()
+    cox.set_covariates(Z)
+    rng = np.random.default_rng(d.seed)
+    extra = rng.choice(np.setdiff1d(np.arange(p), d.causal), m - d.causal.size, replace=False)
+    cols = np.sort(np.concatenate([d.causal, extra]))
+    log(f"refit on {m} SNPs + {q} covariates: warm-up")
+    cox.refit(cols, max_iter=1)
+    torch.cuda.synchronize()
+    cox.timing(True)
+    t0 = time.perf_counter()
+    coef, se, pv, L, it, st = cox.refit(cols, gtol=args.refit_gtol)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    h_ms, h_n = cox.timing_read("refit_hessian")
+    s_ms, s_n = cox.timing_read("refit_solve")
+    cox.timing(False)
+    elapsed = t1 - t0
+    M = m + q
+    log(f"{it} Newton steps in {elapsed:.3f} s (status {st}); {h_n} Hessians, {h_ms / max(h_n, 1):.2f} ms each")
+    # the two Gram matrices of the information: n (M + 1) M / 2 products each, 2 flops
+    flops = 2 * n * M * (M + 1)
+    hess_s = h_ms / max(h_n, 1) / 1e3
+    res = {
+        "metric": "unpenalised Cox refit, Newton steps/s",
+        "value": it / elapsed,
+        "unit": "newton-steps/s",
+        "n_gpus": 1,
+        "steps": int(it),
+        "warmup": 1,
+        "ms_per_step": 1e3 * elapsed / max(it, 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"post-selection refit: n={n}, {m} SNPs (FP8 counts, standardised, gathered to "
+                               f"FP32) + {q} covariates, Newton to max|g| <= {args.refit_gtol}",
+                   "n": n, "columns": M, "status": int(st), "loglik": L},
+        "phases_ms_per_step": {"hessian": h_ms / max(h_n, 1), "factor_solve": s_ms / max(it, 1)},
+        "roofline": {"bound": "alu", "kernel": "gram_kernel (the information matrix's two Gram terms)",
+                     "achieved": flops / hess_s / 1e12, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": flops / hess_s / 1e12 / FP64_VALU_PEAK_TFLOPS, "traffic": None,
+                     "flops_per_hessian": flops},
+        "min_pval": float(pv.min()),
+    }
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline_refit(d, cols, mu, sc, Z.cpu().numpy(), n)
+    return res
+
+
+def cpu_baseline_refit(d, cols, mu, sc, Z, n, ns: int = 20000):
+    """The FP64 oracle's Newton fit, as it stands, on the first ns subjects of the
+    same columns: one Newton step timed on the host, scaled by ns / n."""
+    import coxsim
+    import oracle
+
+    G = coxsim.genotype_columns(ns, cols, d.seed, d.thresholds[cols])
+    X = np.vstack([(G.astype(np.float64) - mu[cols, None].astype(np.float64)) * sc[cols, None].astype(np.float64),
+                   Z[:, :ns].astype(np.float64)])
+    Mo = oracle.Matrix.dense(X)
+    t0 = time.perf_counter()
+    oracle.newton(Mo, d.time[:ns], d.event[:ns], np.arange(Mo.p), maxit=1, gtol=0.0)
+    dt = time.perf_counter() - t0
+    return {"value": ns / n / dt, "unit": "newton-steps/s", "cores": cpu_threads(), "kind": "oracle",
+            "sample": f"one Newton step of the oracle on the first {ns} of {n} subjects, scaled by {ns}/{n}"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=0, help="default: 10 (batched) or 500 (gauss-fp32)")
     ap.add_argument("--warmup", type=int, default=-1, help="default: 2 (batched) or 20 (gauss-fp32)")
-    ap.add_argument("--workload", default="geno-fp8-batched", choices=["geno-fp8-batched", "gauss-fp32"])
+    ap.add_argument("--workload", default="geno-fp8-batched", choices=["geno-fp8-batched", "gauss-fp32", "refit"])
+    ap.add_argument("--refit-cols", type=int, default=333, help="refit workload: SNP columns refitted")
+    ap.add_argument("--refit-gtol", type=float, default=1e-6, help="refit workload: Newton stop, max |gradient|")
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--power-steps", type=int, default=20)
     ap.add_argument("--residual-bits", type=int, default=22, choices=[22, 14],
@@ -391,7 +484,8 @@ def main():
         args.steps = 10 if batched else 500
     if args.warmup < 0:
         args.warmup = 2 if batched else 20
-    res = {"gauss-fp32": bench_gauss_fp32, "geno-fp8-batched": bench_geno_batched}[args.workload](args)
+    res = {"gauss-fp32": bench_gauss_fp32, "geno-fp8-batched": bench_geno_batched,
+           "refit": bench_refit}[args.workload](args)
     print(json.dumps(res), flush=True)
 
 

@@ -226,6 +226,47 @@ cox_status cox_set_covariates(cox_ctx *ctx, const float *Z, int64_t q, int64_t l
  * resets the covariates' factors to 0 and keeps those of X.  Synchronises. */
 cox_status cox_set_penalty_factors(cox_ctx *ctx, const double *pf);
 
+/* Post-selection (Section 6): rank the columns a lasso path selects, refit the
+ * unpenalised model on them with the covariates, and test each by Wald's test.
+ *
+ * cox_rank_path: for a path of L solutions (dev [L][ptot] float, row l at the
+ * l-th lambda of a decreasing sequence, e.g. from cox_fit_sequence), each
+ * column j < p of X gets entry[j] = the first row where it is nonzero (-1:
+ * never) and entry_coef[j] = |beta| there (host [p] each; entry_coef
+ * nullable).  order (host [p], nullable) receives the entered columns ranked as
+ * in Section 6: by entry (the largest lambda first), ties by |coef| at entry
+ * (larger first), then by index; *n_entered (nullable) their number.
+ * Synchronises. */
+cox_status cox_rank_path(cox_ctx *ctx, const float *path, int32_t L, int32_t *entry, float *entry_coef,
+                         int64_t *order, int64_t *n_entered);
+
+/* cox_refit: maximum partial likelihood (no penalty) over the m chosen columns
+ * of X (cols host [m], distinct, each < p; X~ standardised as everywhere) and
+ * all q attached covariates, every other coefficient zero, by Newton's method
+ * with the exact Breslow Hessian: each step solves (-H) d = g and halves d
+ * until L does not fall (the full step is taken once its predicted gain g'd is
+ * at the rounding level of L); it stops when max |g| <= gtol.  The M = m + q
+ * columns are gathered once into a dense FP32 block (allocated for the call).
+ *   coef  host [M] double: the start (e.g. zeros, or the lasso's values) and the
+ *         result, the chosen columns first in the order given, then the
+ *         covariates
+ *   se    host [M] or NULL: standard errors sqrt(diag((-H)^{-1})) at the result
+ *   pval  host [M] or NULL: two-sided Wald p-values erfc(|coef / se| / sqrt 2);
+ *         Section 6 keeps a column when pval < alpha / (number tested)
+ *   loglik host [1] or NULL: L at the result; iters host [1] or NULL: steps
+ *   opts  NULL: 50 steps, gtol 1e-8
+ * INVALID_ARG for M outside 1..COX_MAX_REFIT, repeated or out-of-range columns,
+ * a non-finite start; NUMERIC when -H is not positive definite (e.g. a constant
+ * or repeated column) or L is not finite; NOT_CONVERGED (outputs valid) when
+ * max_iter steps end with max |g| > gtol.  Synchronises. */
+#define COX_MAX_REFIT 1024
+typedef struct {
+    int32_t max_iter; /* >= 0 */
+    double gtol;      /* >= 0 */
+} cox_refit_opts;
+cox_status cox_refit(cox_ctx *ctx, const int64_t *cols, int32_t m, const cox_refit_opts *opts, double *coef,
+                     double *se, double *pval, double *loglik, int32_t *iters);
+
 /* Negative log partial likelihood as a function of the linear predictor, for
  * automatic differentiation (the adjoint of the risk-set sums).
  * forward:  loss_b = -L(eta_b)   for eta dev [B][n] (float when eta_f64 = 0,
@@ -248,7 +289,9 @@ cox_status cox_nll_backward(cox_ctx *ctx, const double *grad_loss, int32_t B, vo
  * the matrix-core X~' R kernel, or one vector X~' r launch per group of up to
  * 8 vectors), COX_PHASE_ETA_KERNEL (each launch of the matrix-core eta kernel
  * alone), COX_PHASE_COV (the covariate block's Z' r with its proximal step, and
- * its eta update; nothing without covariates).
+ * its eta update; nothing without covariates), COX_PHASE_REFIT_HESSIAN (each
+ * evaluation of the refit's information matrix) and COX_PHASE_REFIT_SOLVE (each
+ * Cholesky factorisation and Newton solve of the refit).
  * cox_timing_enable(ctx, 1) starts recording and clears the totals; 0 stops.
  * cox_timing_read returns the summed milliseconds and the number of timed
  * launches of a phase since the last enable.  Synchronises. */
@@ -258,7 +301,9 @@ typedef enum {
     COX_PHASE_ETA = 2,
     COX_PHASE_XTR_KERNEL = 3,
     COX_PHASE_ETA_KERNEL = 4,
-    COX_PHASE_COV = 5
+    COX_PHASE_COV = 5,
+    COX_PHASE_REFIT_HESSIAN = 6,
+    COX_PHASE_REFIT_SOLVE = 7
 } cox_phase;
 
 /* The batched matrix-core passes (X~' R and the eta update, used when X holds

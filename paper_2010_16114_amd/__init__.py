@@ -26,6 +26,7 @@ X_F32, X_FP8_E4M3, X_INT8 = 0, 1, 2
 MFMA_VARIANTS = 5  # COX_MFMA_VARIANTS: pipeline shapes of the X~' R pass (and the tuning arrays' length)
 ETA_VARIANTS = 5  # COX_MFMA_ETA_VARIANTS: pipeline shapes of the eta update
 MAX_COVARIATES = 64  # COX_MAX_COVARIATES
+MAX_REFIT = 1024  # COX_MAX_REFIT
 OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NUMERIC, ERR_NOT_CONVERGED, ERR_UNSUPPORTED = range(7)
 
 
@@ -38,6 +39,10 @@ class CoxError(RuntimeError):
 class _Matrix(ctypes.Structure):
     _fields_ = [("X", ctypes.c_void_p), ("xtype", ctypes.c_int32), ("n", ctypes.c_int64), ("p", ctypes.c_int64),
                 ("ldx", ctypes.c_int64), ("col_center", ctypes.c_void_p), ("col_scale", ctypes.c_void_p)]
+
+
+class RefitOpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("gtol", ctypes.c_double)]
 
 
 class FitOpts(ctypes.Structure):
@@ -75,6 +80,9 @@ def lib():
         "cox_fit_sequence": [vp, vp, i32, ctypes.POINTER(FitOpts), vp, vp, vp],
         "cox_set_covariates": [vp, vp, i64, i64],
         "cox_set_penalty_factors": [vp, vp],
+        "cox_rank_path": [vp, vp, i32, vp, vp, vp, ctypes.POINTER(i64)],
+        "cox_refit": [vp, vp, i32, ctypes.POINTER(RefitOpts), vp, vp, vp, ctypes.POINTER(dbl),
+                      ctypes.POINTER(i32)],
         "cox_lambda_max": [vp, ctypes.POINTER(dbl)],
         "cox_opnorm2": [vp, dbl, i32, u64, ctypes.POINTER(dbl), ctypes.POINTER(i32)],
         "cox_nll_forward": [vp, vp, i32, i32, vp],
@@ -251,6 +259,34 @@ class Cox:
         self._check(st, "cox_fit_sequence", allow=(OK, ERR_NOT_CONVERGED))
         return path, iters, obj, st
 
+    def rank_path(self, path):
+        """Section 6's ranking of a decreasing-lambda path (L, ptot): (entry row
+        per column of X or -1, |coef| at entry, the entered columns in rank order)."""
+        path2 = path.contiguous().view(-1, self.ptot)
+        entry = np.zeros(self.p, np.int32)
+        coef = np.zeros(self.p, np.float32)
+        order = np.zeros(self.p, np.int64)
+        ne = ctypes.c_int64()
+        self._check(lib().cox_rank_path(self._h, path2.data_ptr(), path2.shape[0], _np_ptr(entry), _np_ptr(coef),
+                                        _np_ptr(order), ctypes.byref(ne)), "cox_rank_path")
+        return entry, coef, order[: ne.value]
+
+    def refit(self, cols, coef0=None, max_iter: int = 50, gtol: float = 1e-8):
+        """Unpenalised Newton refit on columns `cols` of X plus the covariates.
+        Returns (coef, se, pval, loglik, iters, status) over cols then covariates."""
+        c = np.ascontiguousarray(np.asarray(cols, np.int64).reshape(-1))
+        M = c.shape[0] + self.q
+        coef = np.zeros(M, np.float64) if coef0 is None else np.ascontiguousarray(coef0, np.float64).copy()
+        se = np.zeros(M, np.float64)
+        pv = np.zeros(M, np.float64)
+        L = ctypes.c_double()
+        it = ctypes.c_int32()
+        o = RefitOpts(int(max_iter), float(gtol))
+        st = lib().cox_refit(self._h, _np_ptr(c) if c.size else None, c.shape[0], ctypes.byref(o), _np_ptr(coef),
+                             _np_ptr(se), _np_ptr(pv), ctypes.byref(L), ctypes.byref(it))
+        self._check(st, "cox_refit", allow=(OK, ERR_NOT_CONVERGED))
+        return coef, se, pv, L.value, it.value, st
+
     def lambda_max(self) -> float:
         out = ctypes.c_double()
         self._check(lib().cox_lambda_max(self._h, ctypes.byref(out)), "cox_lambda_max")
@@ -276,7 +312,8 @@ class Cox:
         self.last_forward_key = self.forward_key(eta)
         return loss
 
-    PHASES = {"xtr": 0, "risk": 1, "eta": 2, "xtr_kernel": 3, "eta_kernel": 4, "cov": 5}
+    PHASES = {"xtr": 0, "risk": 1, "eta": 2, "xtr_kernel": 3, "eta_kernel": 4, "cov": 5, "refit_hessian": 6,
+              "refit_solve": 7}
 
     def mfma_tuning(self):
         """Pipeline shapes chosen by the autotuner and their tuning times (ms)."""

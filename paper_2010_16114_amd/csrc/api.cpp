@@ -27,11 +27,12 @@
 
 using namespace cox;
 
-constexpr int kPhases = 6;  // cox_phase values
+constexpr int kPhases = 8;  // cox_phase values
 
 static_assert(kMfmaVariants == COX_MFMA_VARIANTS && kMfmaEtaVariants == COX_MFMA_ETA_VARIANTS,
               "pipeline shape counts differ from the header");
 static_assert(kMaxCov == COX_MAX_COVARIATES, "covariate limit differs from the header");
+static_assert(kMaxRefit == COX_MAX_REFIT, "refit column limit differs from the header");
 
 namespace {
 
@@ -1197,6 +1198,192 @@ cox_status cox_set_penalty_factors(cox_ctx* c, const double* pf)
     STCHK(sync(c));
     c->pf_host = v;
     c->pf_x_custom = std::any_of(v.begin(), v.begin() + c->p, [](double f) { return f != 1.0; });
+    return COX_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Device buffers of one call, freed when the call returns.
+struct Scratch {
+    std::vector<void*> ptrs;
+    ~Scratch()
+    {
+        for (void* p : ptrs) (void)hipFree(p);
+    }
+    template <class T>
+    bool get(T** out, size_t count)
+    {
+        *out = nullptr;
+        if (fault_injected("alloc")) return false;
+        void* p = nullptr;
+        if (hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        ptrs.push_back(p);
+        *out = static_cast<T*>(p);
+        return true;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+cox_status cox_refit(cox_ctx* c, const int64_t* cols, int32_t m, const cox_refit_opts* opts_in, double* coef,
+                     double* se, double* pval, double* loglik, int32_t* iters)
+{
+    STCHK(check_ctx(c));
+    const int q = (int)c->q, M = m + q;
+    const int64_t n = c->n;
+    if (m < 0 || M < 1 || M > kMaxRefit || (m > 0 && !cols) || !coef)
+        return fail(c, COX_ERR_INVALID_ARG, "refit needs 1..COX_MAX_REFIT columns (chosen + covariates) and coef");
+    std::vector<int32_t> cols32(std::max(m, 1));
+    for (int a = 0; a < m; ++a) {
+        if (cols[a] < 0 || cols[a] >= c->p) return fail(c, COX_ERR_INVALID_ARG, "refit column out of range");
+        cols32[a] = (int32_t)cols[a];
+    }
+    {
+        std::vector<int32_t> sorted(cols32.begin(), cols32.begin() + m);
+        std::sort(sorted.begin(), sorted.end());
+        if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+            return fail(c, COX_ERR_INVALID_ARG, "refit columns must be distinct");
+    }
+    cox_refit_opts o{50, 1e-8};
+    if (opts_in) o = *opts_in;
+    if (o.max_iter < 0 || !(o.gtol >= 0) || !std::isfinite(o.gtol))
+        return fail(c, COX_ERR_INVALID_ARG, "bad cox_refit_opts");
+    for (int a = 0; a < M; ++a)
+        if (!std::isfinite(coef[a])) return fail(c, COX_ERR_INVALID_ARG, "coef must be finite");
+
+    const int nc = gram_chunks(n), nrb = refit_row_blocks(n);
+    const size_t MM = (size_t)M * M;
+    Scratch w;
+    float* D;
+    double *S, *wt, *p1, *p2, *H, *scr, *g, *d, *b, *bt, *gpart, *sed, *pvd;
+    int32_t* colsd;
+    int* okd;
+    if (!(w.get(&D, (size_t)M * n) && w.get(&S, (size_t)(M + 1) * n) && w.get(&wt, n) && w.get(&p1, nc * MM) &&
+          w.get(&p2, nc * MM) && w.get(&H, MM) && w.get(&scr, MM) && w.get(&g, M) && w.get(&d, M) && w.get(&b, M) &&
+          w.get(&bt, M) && w.get(&gpart, (size_t)nrb * M) && w.get(&sed, M) && w.get(&pvd, M) &&
+          w.get(&colsd, std::max(m, 1)) && w.get(&okd, 1)))
+        return fail(c, COX_ERR_OUT_OF_MEMORY, "refit workspace");
+
+    if (m > 0) {
+        STCHK(h2d(c, colsd, cols32.data(), sizeof(int32_t) * m));
+        HIPCHK(launch_gather_cols(c->x, colsd, m, D, n, c->stream), "gather columns");
+    }
+    if (q)
+        HIPCHK(hipMemcpy2DAsync(D + (size_t)m * n, sizeof(float) * n, c->Z, sizeof(float) * c->ldz,
+                                sizeof(float) * n, q, hipMemcpyDeviceToDevice, c->stream),
+               "copy covariates");
+    STCHK(h2d(c, b, coef, sizeof(double) * M));
+
+    RiskArgs ra = risk_args(c, 1);
+    ra.r32 = nullptr;
+    ra.r64 = c->r64;
+    auto eval = [&](const double* bb, double* Lout) -> cox_status {
+        HIPCHK(launch_refit_eta(D, n, n, M, bb, c->eta, c->stream), "D b");
+        HIPCHK(launch_risk(ra, c->stream), "risk-set sums");
+        STCHK(d2h(c, Lout, c->L, sizeof(double)));
+        if (!std::isfinite(*Lout)) return fail(c, COX_ERR_NUMERIC, "non-finite log likelihood");
+        return COX_OK;
+    };
+    auto hessian = [&]() -> cox_status {
+        tmark(c, COX_PHASE_REFIT_HESSIAN);
+        HIPCHK(launch_refit_hessian(D, n, n, M, c->perm, c->gstart, c->gend, c->ev, c->w, c->r64, wt, S, p1, p2, H,
+                                    c->stream),
+               "Hessian");
+        tmark(c, COX_PHASE_REFIT_HESSIAN);
+        tmark(c, COX_PHASE_REFIT_SOLVE);
+        HIPCHK(launch_chol(H, M, okd, c->stream), "Cholesky");
+        tmark(c, COX_PHASE_REFIT_SOLVE);
+        int ok = 0;
+        STCHK(d2h(c, &ok, okd, sizeof(int)));
+        if (!ok) return fail(c, COX_ERR_NUMERIC, "the information matrix is not positive definite");
+        return COX_OK;
+    };
+
+    double L = 0.0;
+    STCHK(eval(b, &L));
+    std::vector<double> gh(M), dh(M);
+    bool converged = false;
+    int it = 0;
+    for (;; ++it) {
+        HIPCHK(launch_refit_grad(D, n, n, M, c->r64, gpart, g, c->stream), "D' r");
+        STCHK(d2h(c, gh.data(), g, sizeof(double) * M));
+        double gmax = 0.0;
+        for (double v : gh) gmax = std::max(gmax, std::fabs(v));
+        if (!std::isfinite(gmax)) return fail(c, COX_ERR_NUMERIC, "non-finite gradient");
+        if (gmax <= o.gtol) {
+            converged = true;
+            break;
+        }
+        if (it >= o.max_iter) break;
+        STCHK(hessian());
+        tmark(c, COX_PHASE_REFIT_SOLVE);
+        HIPCHK(launch_chol_solve(H, M, g, d, c->stream), "Newton direction");
+        tmark(c, COX_PHASE_REFIT_SOLVE);
+        STCHK(d2h(c, dh.data(), d, sizeof(double) * M));
+        double gain = 0.0;
+        for (int a = 0; a < M; ++a) gain += gh[a] * dh[a];
+        // once the predicted gain is at the rounding level of L the full step is
+        // taken unchecked; otherwise it is halved until L does not fall
+        const bool pure = gain <= 1e-12 * (1.0 + std::fabs(L));
+        double t = 1.0, Lt = -std::numeric_limits<double>::infinity();
+        for (int half = 0; half < 60; ++half, t *= 0.5) {
+            HIPCHK(launch_axpy(b, d, t, M, bt, c->stream), "trial step");
+            const cox_status st = eval(bt, &Lt);
+            if (st != COX_OK && st != COX_ERR_NUMERIC) return st;
+            if (st == COX_OK && (Lt >= L || pure)) break;
+        }
+        if (!(Lt >= L) && !pure) {  // no ascent at the rounding level of L: stay
+            STCHK(eval(b, &L));
+            break;
+        }
+        std::swap(b, bt);
+        L = Lt;
+    }
+    STCHK(hessian());
+    HIPCHK(launch_wald(H, M, b, scr, sed, pvd, c->stream), "Wald statistics");
+    STCHK(d2h(c, coef, b, sizeof(double) * M));
+    if (se) STCHK(d2h(c, se, sed, sizeof(double) * M));
+    if (pval) STCHK(d2h(c, pval, pvd, sizeof(double) * M));
+    if (loglik) *loglik = L;
+    if (iters) *iters = it;
+    if (!converged) return fail(c, COX_ERR_NOT_CONVERGED, "refit: gradient above gtol at the stop");
+    return COX_OK;
+}
+
+cox_status cox_rank_path(cox_ctx* c, const float* path, int32_t L, int32_t* entry, float* entry_coef, int64_t* order,
+                         int64_t* n_entered)
+{
+    STCHK(check_ctx(c));
+    if (!path || L < 1 || !entry) return fail(c, COX_ERR_INVALID_ARG, "rank_path needs path, L >= 1 and entry");
+    const int64_t p = c->p;
+    Scratch w;
+    int32_t* ed;
+    float* cd;
+    if (!(w.get(&ed, p) && w.get(&cd, p))) return fail(c, COX_ERR_OUT_OF_MEMORY, "rank workspace");
+    HIPCHK(launch_entry(path, L, ptot(c), p, ed, cd, c->stream), "entry points");
+    std::vector<float> coefv(p);
+    STCHK(d2h(c, entry, ed, sizeof(int32_t) * p));
+    STCHK(d2h(c, coefv.data(), cd, sizeof(float) * p));
+    if (entry_coef) std::copy(coefv.begin(), coefv.end(), entry_coef);
+    std::vector<int64_t> idx;
+    for (int64_t j = 0; j < p; ++j)
+        if (entry[j] >= 0) idx.push_back(j);
+    // Section 6's ranking: the largest lambda at which the column is nonzero
+    // (the earliest position on a decreasing path), ties by |coef| on entry
+    std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+        if (entry[a] != entry[b]) return entry[a] < entry[b];
+        if (coefv[a] != coefv[b]) return coefv[a] > coefv[b];
+        return a < b;
+    });
+    if (order) std::copy(idx.begin(), idx.end(), order);
+    if (n_entered) *n_entered = (int64_t)idx.size();
     return COX_OK;
 }
 

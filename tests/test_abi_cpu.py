@@ -58,6 +58,8 @@ def test_null_context_calls():
     assert L.cox_fit_sequence(None, None, 1, None, None, None, None) == P.ERR_INVALID_ARG
     assert L.cox_set_covariates(None, None, 0, 0) == P.ERR_INVALID_ARG
     assert L.cox_set_penalty_factors(None, None) == P.ERR_INVALID_ARG
+    assert L.cox_rank_path(None, None, 1, None, None, None, None) == P.ERR_INVALID_ARG
+    assert L.cox_refit(None, None, 1, None, None, None, None, None, None) == P.ERR_INVALID_ARG
 
 
 def test_header_constants_match_binding():
@@ -67,6 +69,7 @@ def test_header_constants_match_binding():
     assert int(re.search(r"#define COX_MFMA_VARIANTS (\d+)", text).group(1)) == P.MFMA_VARIANTS
     assert int(re.search(r"#define COX_MFMA_ETA_VARIANTS (\d+)", text).group(1)) == P.ETA_VARIANTS
     assert int(re.search(r"#define COX_MAX_COVARIATES (\d+)", text).group(1)) == P.MAX_COVARIATES
+    assert int(re.search(r"#define COX_MAX_REFIT (\d+)", text).group(1)) == P.MAX_REFIT
     assert re.search(r"COX_X_FP8_E4M3\s*=\s*(\d+)", text).group(1) == str(P.X_FP8_E4M3)
     assert re.search(r"COX_X_INT8\s*=\s*(\d+)", text).group(1) == str(P.X_INT8)
 
