@@ -43,8 +43,9 @@ struct MfmaEtaArgs {
     const double* dscale;   // [B]
     double* eta;            // [B][n] FP64, updated in place
     const int32_t* active;  // [B] or null
-    int variant;            // stages of 64 columns ahead: 0, 1 = 6, 4 with 6 compute + 2 loader
-                            // wavefronts; 2, 3, 4 = 4, 3, 2 with 8 wavefronts that load both operands
+    int variant;            // stages of 64 columns ahead (8 wavefronts load both operands): 0, 1 = 2, 3
+                            // with the D tile moved in 8-byte pieces when bpad = 64 (16-byte chunks
+                            // otherwise); 2, 3, 4 = 4, 3, 2 with 16-byte chunks
 };
 
 int mfma_ntile(int64_t n);

@@ -19,6 +19,8 @@
 // subjects of one column per lane, one 16-byte load) stay in registers; the
 // stage's limb tile is staged in LDS.  Several (MT, KS, PF) shapes are
 // compiled; the host times them on the live data and keeps the fastest.
+#include <type_traits>
+
 #include "device_common.h"
 #include "mfma.h"
 
@@ -234,7 +236,7 @@ __device__ __forceinline__ void transpose4x4(const uint32_t (&d)[4], uint32_t (&
 // hit distinct banks.  The column indices run one ring lap ahead of the G
 // loads they address.  Each (subject, b) is owned by one lane, so eta is
 // updated in place.
-template <int XT, int NG, int NSPLIT, int PF>
+template <int XT, int NG, int NSPLIT, int PF, bool D8 = false>
 __global__ __launch_bounds__(256 * NSPLIT, NSPLIT) void mfma_eta_kernel(MfmaEtaArgs a)
 {
     static_assert(PF >= 2, "the ring needs two slots");
@@ -248,9 +250,13 @@ __global__ __launch_bounds__(256 * NSPLIT, NSPLIT) void mfma_eta_kernel(MfmaEtaA
     constexpr int NGH = (NG + NSPLIT - 1) / NSPLIT;  // b groups of 16 per wavefront (a split of an odd NG repeats one)
     constexpr int GPT = 64 * RB / TH;     // 16-byte chunks of G per thread per stage
     constexpr int DCH = 4 * NCOL;         // 16-byte chunks of D per stage
-    constexpr int DPT = (DCH + TH - 1) / TH;
+    // D8: the D tile moves as 8-byte pieces, 2 DCH / TH per thread (3 at B = 64 over
+    // 512 threads, where 16-byte chunks would leave half of a second chunk idle)
+    constexpr int DPT = D8 ? 2 * DCH / TH : (DCH + TH - 1) / TH;
     constexpr int DS = NCOL + 8;          // LDS row stride of the D tile (16-byte units)
     static_assert(GPT * TH == 64 * RB, "G tile splits evenly");
+    static_assert(!D8 || DPT * TH == 2 * DCH, "8-byte D pieces split evenly");
+    using dchunk = typename std::conditional<D8, uint2, v4i>::type;
     __shared__ uint32_t sG[2][64 * SW];
     __shared__ v4i sD[2][4 * DS];
     const int nsel = *a.nsel;
@@ -276,12 +282,18 @@ __global__ __launch_bounds__(256 * NSPLIT, NSPLIT) void mfma_eta_kernel(MfmaEtaA
     // D chunks: a stage's D tile is one contiguous block of DCH chunks
     // ([16-position quarter kq][limb column])
     const int8_t* dsrc[DPT];
-    int ddst[DPT];
+    int ddst[DPT];  // byte offset in a D buffer
 #pragma unroll
     for (int k = 0; k < DPT; ++k) {
-        const int c = (threadIdx.x + TH * k) % DCH;
-        dsrc[k] = a.dlimbs + 16 * c;
-        ddst[k] = (c / NCOL) * DS + c % NCOL;
+        if constexpr (D8) {
+            const int c8 = threadIdx.x + TH * k, c = c8 >> 1;
+            dsrc[k] = a.dlimbs + 8 * c8;
+            ddst[k] = ((c / NCOL) * DS + c % NCOL) * 16 + 8 * (c8 & 1);
+        } else {
+            const int c = (threadIdx.x + TH * k) % DCH;
+            dsrc[k] = a.dlimbs + 16 * c;
+            ddst[k] = ((c / NCOL) * DS + c % NCOL) * 16;
+        }
     }
     // this wavefront's b groups
     int bqs[NGH];
@@ -302,9 +314,9 @@ __global__ __launch_bounds__(256 * NSPLIT, NSPLIT) void mfma_eta_kernel(MfmaEtaA
             for (int j = 0; j < NGH; ++j) acc[mt][l][j] = v4i{0, 0, 0, 0};
 
     v4i gr[PF][GPT];
-    v4i dr[PF][DPT];
+    dchunk dr[PF][DPT];
     int32_t sr[PF][GPT];  // column indices of stage t + PF, in slot t mod PF
-    auto fetch = [&](int64_t t, const int32_t (&s)[GPT], v4i (&g)[GPT], v4i (&dd)[DPT]) {
+    auto fetch = [&](int64_t t, const int32_t (&s)[GPT], v4i (&g)[GPT], dchunk (&dd)[DPT]) {
 #pragma unroll
         for (int k = 0; k < GPT; ++k) {
             const int64_t col = t * 64 + gu[k] < nsel ? (int64_t)s[k] : p;  // past the list: reads as 0
@@ -312,18 +324,19 @@ __global__ __launch_bounds__(256 * NSPLIT, NSPLIT) void mfma_eta_kernel(MfmaEtaA
         }
         const int64_t kd = min(t, nchunk - 1) * (int64_t)(16 * DCH);
 #pragma unroll
-        for (int k = 0; k < DPT; ++k) dd[k] = *reinterpret_cast<const v4i*>(dsrc[k] + kd);
+        for (int k = 0; k < DPT; ++k) dd[k] = *reinterpret_cast<const dchunk*>(dsrc[k] + kd);
     };
     // positions past the change list read as 0 (subjects >= n only reach
     // outputs that are never written)
-    auto store = [&](int64_t t, const v4i (&g)[GPT], const v4i (&dd)[DPT]) {
+    auto store = [&](int64_t t, const v4i (&g)[GPT], const dchunk (&dd)[DPT]) {
         const int buf = (int)(t & 1);
 #pragma unroll
         for (int k = 0; k < GPT; ++k)
             *reinterpret_cast<v4i*>(&sG[buf][gdst[k]]) =
                 t * 64 + gu[k] < nsel ? decode_a<XT>(g[k]) : v4i{0, 0, 0, 0};
+        char* sd = reinterpret_cast<char*>(sD[buf]);
 #pragma unroll
-        for (int k = 0; k < DPT; ++k) sD[buf][ddst[k]] = dd[k];
+        for (int k = 0; k < DPT; ++k) *reinterpret_cast<dchunk*>(sd + ddst[k]) = dd[k];
     };
 
     {
@@ -398,191 +411,6 @@ __global__ __launch_bounds__(256 * NSPLIT, NSPLIT) void mfma_eta_kernel(MfmaEtaA
                     a.eta[(int64_t)b * n + i] += a.dscale[b] * (double)tot;
                 }
             }
-    }
-}
-
-// The eta update with split roles, as for X~' R: 6 compute wavefronts (3
-// subject blocks of 64 x 2 halves of the b's) stream G and the change-list
-// indices in one ring; 2 loader wavefronts stage the D tiles (L2 hits) into
-// LDS two stages ahead.  A workgroup owns 192 subjects; the G tile's columns
-// keep 64 dword slots (48 used) so the swizzle stays within a column.
-template <int XT, int NG, int PF>
-__global__ __launch_bounds__(512, 2) void mfma_eta_split_kernel(MfmaEtaArgs a)
-{
-    static_assert(PF >= 2 && PF % 2 == 0, "the loaders' two-slot ring indexes statically");
-    constexpr int CTH = 384;              // compute threads
-    constexpr int LTH = 128;              // loader threads
-    constexpr int SUB = 192;              // subjects per workgroup
-    constexpr int SW = 64;                // dword slots per column of the G tile
-    constexpr int RB = SUB / 16;          // 16-byte chunks per column of the G tile
-    constexpr int NT = kLimbs * NG;
-    constexpr int NCOL = 16 * NT;
-    constexpr int NGH = (NG + 1) / 2;
-    constexpr int GPT = 64 * RB / CTH;    // 16-byte chunks of G per compute thread per stage (= 2)
-    constexpr int DCH = 4 * NCOL;         // 16-byte chunks of D per stage
-    constexpr int DPL = (DCH + LTH - 1) / LTH;
-    constexpr int DS = NCOL + 8;
-    static_assert(GPT * CTH == 64 * RB, "G tile splits evenly");
-    __shared__ uint32_t sG[2][64 * SW];
-    __shared__ v4i sD[2][4 * DS];
-    const int nsel = *a.nsel;
-    if (nsel == 0) return;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int64_t n = a.n, p = a.p, ldx = a.ldx;
-    const int64_t i0 = (int64_t)blockIdx.x * SUB;
-    const int64_t nchunk = (nsel + 63) / 64;
-    const int64_t nloop = (nchunk + PF - 1) / PF * PF;
-
-    if (wid < 6) {
-        const int wsub = wid % 3, half = wid / 3;
-        const uint8_t* __restrict__ X = static_cast<const uint8_t*>(a.X);
-        const int32_t* __restrict__ sel = a.sel;
-        int gu[GPT], grb[GPT], gdst[GPT];
-#pragma unroll
-        for (int k = 0; k < GPT; ++k) {
-            const int ch = threadIdx.x + CTH * k;
-            gu[k] = ch / RB;
-            grb[k] = ch % RB;
-            gdst[k] = gu[k] * SW + ((4 * grb[k]) ^ (((gu[k] >> 4) & 3) << 4));
-        }
-        int bqs[NGH];
-#pragma unroll
-        for (int j = 0; j < NGH; ++j) bqs[j] = min(half * NGH + j, NG - 1);
-        auto load_sel = [&](int64_t t, int32_t (&s)[GPT]) {
-#pragma unroll
-            for (int k = 0; k < GPT; ++k) s[k] = sel[min(t * 64 + gu[k], (int64_t)nsel - 1)];
-        };
-        v4i acc[4][kLimbs][NGH];
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-            for (int l = 0; l < kLimbs; ++l)
-#pragma unroll
-                for (int j = 0; j < NGH; ++j) acc[mt][l][j] = v4i{0, 0, 0, 0};
-        v4i gr[PF][GPT];
-        int32_t sr[PF][GPT];  // column indices of stage t + PF, in slot t mod PF
-        auto fetch = [&](int64_t t, const int32_t (&s)[GPT], v4i (&g)[GPT]) {
-#pragma unroll
-            for (int k = 0; k < GPT; ++k) {
-                const int64_t col = t * 64 + gu[k] < nsel ? (int64_t)s[k] : p;  // past the list: reads as 0
-                g[k] = load_raw(X, col, p, ldx, i0 + 16 * grb[k], n);
-            }
-        };
-        auto store = [&](int64_t t, const v4i (&g)[GPT]) {
-            const int buf = (int)(t & 1);
-#pragma unroll
-            for (int k = 0; k < GPT; ++k)
-                *reinterpret_cast<v4i*>(&sG[buf][gdst[k]]) =
-                    t * 64 + gu[k] < nsel ? decode_a<XT>(g[k]) : v4i{0, 0, 0, 0};
-        };
-        {
-            int32_t s0[PF][GPT];
-#pragma unroll
-            for (int q = 0; q < PF; ++q) load_sel(q, s0[q]);
-#pragma unroll
-            for (int q = 0; q < PF; ++q) load_sel(q + PF, sr[q]);
-#pragma unroll
-            for (int q = 0; q < PF; ++q) fetch(q, s0[q], gr[q]);
-        }
-        store(0, gr[0]);
-        __syncthreads();
-
-        const int xr = wsub * 16 + (lane & 15);  // this lane's dword (4 subjects) within a column
-        const int xs = xr ^ ((lane >> 4) << 4);
-        for (int64_t c0 = 0; c0 < nloop; c0 += PF) {
-#pragma unroll
-            for (int q = 0; q < PF; ++q) {
-                const int64_t t = c0 + q;
-                const int buf = (int)(t & 1);
-                v4i A[4];
-                {
-                    uint32_t f[4][4];
-#pragma unroll
-                    for (int blk = 0; blk < 4; ++blk) {
-                        uint32_t d[4], o[4];
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) d[e] = sG[buf][(16 * (lane >> 4) + 4 * blk + e) * SW + xs];
-                        transpose4x4(d, o);
-#pragma unroll
-                        for (int mt = 0; mt < 4; ++mt) f[mt][blk] = o[mt];
-                    }
-#pragma unroll
-                    for (int mt = 0; mt < 4; ++mt)
-                        A[mt] = v4i{(int)f[mt][0], (int)f[mt][1], (int)f[mt][2], (int)f[mt][3]};
-                }
-                {
-                    const v4i* sb = &sD[buf][(lane >> 4) * DS + (lane & 15)];
-                    v4i bcur = sb[bqs[0] * 16];
-#pragma unroll
-                    for (int l = 0; l < kLimbs; ++l)
-#pragma unroll
-                        for (int j = 0; j < NGH; ++j) {
-                            const int f = l * NGH + j + 1;  // next fragment
-                            v4i bnext = bcur;
-                            if (f < kLimbs * NGH) bnext = sb[((f / NGH) * NG + bqs[f % NGH]) * 16];
-#pragma unroll
-                            for (int mt = 0; mt < 4; ++mt)
-                                acc[mt][l][j] =
-                                    __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], bcur, acc[mt][l][j], 0, 0, 0);
-                            bcur = bnext;
-                        }
-                }
-                fetch(t + PF, sr[q], gr[q]);
-                load_sel(t + 2 * PF, sr[q]);
-                store(t + 1, gr[(q + 1) % PF]);
-                __syncthreads();
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < NGH; ++j) {
-            if (half * NGH + j >= NG) continue;  // the repeated group of an odd NG
-            const int b = bqs[j] * 16 + (lane & 15);
-#pragma unroll
-            for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int64_t i = i0 + 64 * wsub + 4 * mfma_c_row(lane, v) + mt;
-                    if (i < n && b < a.B && (a.active == nullptr || a.active[b])) {
-                        const int64_t tot = (int64_t)acc[mt][0][j][v] + 256 * (int64_t)acc[mt][1][j][v] +
-                                            65536 * (int64_t)acc[mt][2][j][v];
-                        a.eta[(int64_t)b * n + i] += a.dscale[b] * (double)tot;
-                    }
-                }
-        }
-    } else {
-        // loader: chunk c of a stage's contiguous D tile goes to LDS slot (c / NCOL, c % NCOL)
-        const int lt = threadIdx.x - CTH;
-        const int8_t* dsrc[DPL];
-        int ddst[DPL];
-#pragma unroll
-        for (int k = 0; k < DPL; ++k) {
-            const int c = (lt + LTH * k) % DCH;  // a chunk index past the end repeats a valid one
-            dsrc[k] = a.dlimbs + 16 * c;
-            ddst[k] = (c / NCOL) * DS + c % NCOL;
-        }
-        v4i dr[2][DPL];
-        auto fetch_d = [&](int64_t t, v4i (&dd)[DPL]) {
-            const int64_t kd = min(t, nchunk - 1) * (int64_t)(16 * DCH);
-#pragma unroll
-            for (int k = 0; k < DPL; ++k) dd[k] = *reinterpret_cast<const v4i*>(dsrc[k] + kd);
-        };
-        auto store_d = [&](int buf, const v4i (&dd)[DPL]) {
-#pragma unroll
-            for (int k = 0; k < DPL; ++k) sD[buf][ddst[k]] = dd[k];
-        };
-        fetch_d(0, dr[0]);
-        fetch_d(1, dr[1]);
-        store_d(0, dr[0]);
-        __syncthreads();
-        for (int64_t c0 = 0; c0 < nloop; c0 += PF) {
-#pragma unroll
-            for (int q = 0; q < PF; ++q) {
-                const int64_t t = c0 + q;
-                fetch_d(t + 2, dr[q % 2]);
-                store_d((int)(t & 1) ^ 1, dr[(q + 1) % 2]);
-                __syncthreads();
-            }
-        }
     }
 }
 
@@ -737,30 +565,24 @@ __global__ __launch_bounds__(kT) void geno_check_kernel(const uint8_t* __restric
     if (__any(b) && (threadIdx.x & 63) == 0) atomicOr(bad, 1);
 }
 
-template <int XT, int NG, int NSPLIT, int PF>
+template <int XT, int NG, int NSPLIT, int PF, bool D8 = false>
 hipError_t launch_eta_shape(const MfmaEtaArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL((mfma_eta_kernel<XT, NG, NSPLIT, PF>), dim3((unsigned)((a.n + 255) / 256)), dim3(256 * NSPLIT),
-                       0, s, a);
-    return hipGetLastError();
-}
-
-template <int XT, int NG, int PF>
-hipError_t launch_eta_split(const MfmaEtaArgs& a, hipStream_t s)
-{
-    hipLaunchKernelGGL((mfma_eta_split_kernel<XT, NG, PF>), dim3((unsigned)((a.n + 191) / 192)), dim3(512), 0, s, a);
+    hipLaunchKernelGGL((mfma_eta_kernel<XT, NG, NSPLIT, PF, D8>), dim3((unsigned)((a.n + 255) / 256)),
+                       dim3(256 * NSPLIT), 0, s, a);
     return hipGetLastError();
 }
 
 template <int XT, int NG>
 hipError_t launch_eta_ng(const MfmaEtaArgs& a, hipStream_t s)
 {
+    // the 8-byte D pieces divide evenly over 512 threads at NG = 4 only
     switch (a.variant) {
-    case 1: return launch_eta_split<XT, NG, 4>(a, s);
+    case 1: return launch_eta_shape<XT, NG, 2, 3, NG == 4>(a, s);
     case 2: return launch_eta_shape<XT, NG, 2, 4>(a, s);
     case 3: return launch_eta_shape<XT, NG, 2, 3>(a, s);
     case 4: return launch_eta_shape<XT, NG, 2, 2>(a, s);
-    default: return launch_eta_split<XT, NG, 6>(a, s);
+    default: return launch_eta_shape<XT, NG, 2, 2, NG == 4>(a, s);
     }
 }
 
