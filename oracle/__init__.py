@@ -20,6 +20,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "cox_oracle.c")
+_SRC_NMF = os.path.join(_HERE, "nmf_oracle.c")
 _LIB = os.path.join(_HERE, "libcoxoracle.so")
 
 KIND_F64, KIND_F32, KIND_GENO = 0, 1, 2
@@ -27,7 +28,7 @@ KIND_F64, KIND_F32, KIND_GENO = 0, 1, 2
 
 def build() -> str:
     """Compile the oracle with gcc (IEEE semantics: no fast-math)."""
-    cmd = ["gcc", "-O2", "-fopenmp", "-Wall", "-shared", "-fPIC", "-o", _LIB, _SRC, "-lm"]
+    cmd = ["gcc", "-O2", "-fopenmp", "-Wall", "-shared", "-fPIC", "-o", _LIB, _SRC, _SRC_NMF, "-lm"]
     subprocess.run(cmd, check=True)
     return _LIB
 
@@ -39,7 +40,7 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC), os.path.getmtime(_SRC_NMF)):
         build()
     lib = ctypes.CDLL(_LIB)
     i64, i32, dbl, u64, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64, ctypes.c_void_p
@@ -57,6 +58,9 @@ def _load():
     lib.cox_oracle_fit_pf.argtypes = mat + [vp, vp, dbl, vp, dbl, i32, dbl, i32, vp, vp, vp]
     lib.cox_oracle_newton.argtypes = mat + [vp, vp, vp, i64, vp, vp, i32, dbl, vp, vp]
     lib.cox_oracle_lambda_max_pf.argtypes = mat + [vp, vp, vp, dbl, vp, vp]
+    lib.nmf_oracle_objective.argtypes = [vp, i64, i64, i64, i32, vp, vp]
+    lib.nmf_oracle_objective.restype = dbl
+    lib.nmf_oracle_run.argtypes = [vp, i64, i64, i64, i32, i32, dbl, i32, vp, vp, vp]
     _lib = lib
     return lib
 
@@ -253,3 +257,35 @@ def lambda_max_pf(X: Matrix, time, event, pf, gtol: float = 1e-10):
     if rc == -2:
         raise np.linalg.LinAlgError("the unpenalised fit failed")
     return out.value, bu[: int(np.count_nonzero(w == 0))]
+
+
+# ---- nonnegative matrix factorisation (Section 5.1), nmf_oracle.c
+
+NMF_MU, NMF_APG = 0, 1
+
+
+def _nmf_args(X, Vt, W):
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    m, n = X.shape
+    Vt = np.ascontiguousarray(Vt, dtype=np.float64).copy()
+    W = np.ascontiguousarray(W, dtype=np.float64).copy()
+    r = Vt.shape[0]
+    assert Vt.shape == (r, m) and W.shape == (r, n)
+    return X, m, n, r, Vt, W
+
+
+def nmf_objective(X, Vt, W) -> float:
+    """||X - V W||_F^2 evaluated directly (X: (m, n) float32, Vt: (r, m), W: (r, n))."""
+    X, m, n, r, Vt, W = _nmf_args(X, Vt, W)
+    return _load().nmf_oracle_objective(_ptr(X), m, n, n, r, _ptr(Vt), _ptr(W))
+
+
+def nmf_run(X, Vt0, W0, algo: int, iters: int, eps: float = 1e-10):
+    """iters iterations of the multiplicative (algo 0) or APG (algo 1) update.
+    Returns (Vt, W, objective before and after each iteration)."""
+    X, m, n, r, Vt, W = _nmf_args(X, Vt0, W0)
+    trace = np.empty(iters + 1, np.float64)
+    if _load().nmf_oracle_run(_ptr(X), m, n, n, r, int(algo), float(eps), int(iters), _ptr(Vt), _ptr(W),
+                              _ptr(trace)):
+        raise ValueError("bad input")
+    return Vt, W, trace
