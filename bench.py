@@ -20,6 +20,9 @@ Workloads (synthetic, seeded; they stand in for the UK Biobank genotypes):
                columns of an FP8 genotype matrix plus 11 unpenalised covariates,
                Newton's method with the exact Breslow Hessian to max |g| <= 1e-6
                (timed in Newton steps per second).
+  nmf        : Section 5.1's NMF on its GPU shape, X 10,000 x 10,000 uniform
+               FP32, rank 20 (--nmf-rank), multiplicative update (--nmf-algo 1:
+               APG), 1000 iterations timed.
 
 The oracle (plain FP64 C) is timed on the host cores on a bounded sample of
 the same workload as the CPU baseline.
@@ -439,12 +442,99 @@ def cpu_baseline_refit(d, cols, mu, sc, Z, n, ns: int = 20000):
             "sample": f"one Newton step of the oracle on the first {ns} of {n} subjects, scaled by {ns}/{n}"}
 
 
+# Section 5.1's single-GPU runtimes for 10,000 iterations at 10,000 x 10,000
+# (the paper's own hardware; context only): seconds by (algorithm, r)
+NMF_PAPER_1GPU_S = {(0, 20): 62, (0, 40): 72, (0, 60): 83, (1, 20): 61, (1, 40): 80, (1, 60): 85}
+
+
+def bench_nmf(args):
+    """Section 5.1's NMF on its GPU shape: X 10,000 x 10,000 uniform FP32, rank
+    r, the multiplicative (0) or APG (1) update, K iterations timed."""
+    import torch
+
+    import paper_2010_16114_amd as P
+
+    m = args.n or 10000
+    n = args.p or 10000
+    r, algo = args.nmf_rank, args.nmf_algo
+    rng = np.random.default_rng(16114 + 7)
+    Xh = rng.random((m, n), dtype=np.float32)
+    X = torch.from_numpy(Xh).cuda()
+    Vt0, W0 = rng.random((r, m)), rng.random((r, n))
+    Vt, W = torch.from_numpy(Vt0).cuda(), torch.from_numpy(W0).cuda()
+    nmf = P.NMF(X, r)
+    log(f"NMF {m} x {n}, r = {r}, algorithm {algo}: {args.warmup} warm-up, {args.steps} timed iterations")
+    nmf.run(Vt, W, algo, args.warmup, want_obj=False)
+    torch.cuda.synchronize()
+    nmf.timing(True)
+    t0 = time.perf_counter()
+    nmf.run(Vt, W, algo, args.steps, want_obj=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    w_ms, w_n = nmf.timing_read(0)
+    v_ms, v_n = nmf.timing_read(1)
+    nmf.timing(False)
+    f = nmf.run(Vt, W, algo, 0)
+    elapsed = t1 - t0
+    # per pass over X: X once (4mn bytes), the factor tile reads and the split partials
+    kms = max(w_ms / max(w_n, 1), v_ms / max(v_n, 1))
+    kname = "nmf_wxt_kernel (W X')" if w_ms / max(w_n, 1) >= v_ms / max(v_n, 1) else "nmf_vtx_kernel (V' X)"
+    nbytes = 4.0 * m * n
+    flops = 2.0 * m * n * r
+    gbs = nbytes / (kms / 1e3) / 1e9
+    tfs = flops / (kms / 1e3) / 1e12
+    hbm = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+    alu = {"bound": "alu", "achieved": tfs, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+           "frac": tfs / FP64_VALU_PEAK_TFLOPS}
+    roof = dict(hbm if hbm["frac"] >= alu["frac"] else alu)
+    roof.update({"kernel": kname, "traffic": None, "kernel_ms": kms, "bytes_per_launch": nbytes,
+                 "flops_per_launch": flops, "other_bound": alu if roof["bound"] == "hbm" else hbm})
+    paper_s = NMF_PAPER_1GPU_S.get((algo, r))
+    res = {
+        "metric": "NMF iterations/s",
+        "value": args.steps / elapsed,
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"NMF {m} x {n} uniform FP32 X, r = {r}, "
+                               f"{'multiplicative' if algo == 0 else 'APG'} update, factors FP64",
+                   "m": m, "n": n, "r": r, "algorithm": algo},
+        "phases_ms_per_step": {"wxt": w_ms / max(w_n, 1), "vtx": v_ms / max(v_n, 1)},
+        "roofline": roof,
+        "objective": f,
+        "paper_context": None if paper_s is None else {"iters_per_s_on_the_papers_gpu": 10000 / paper_s},
+    }
+    if not args.no_cpu:
+        import oracle
+        t0 = time.perf_counter()
+        oracle.nmf_run(Xh, Vt0, W0, algo, 1)
+        dt = time.perf_counter() - t0
+        k = max(1, min(10, int(15.0 / max(dt, 1e-3))))
+        t0 = time.perf_counter()
+        oracle.nmf_run(Xh, Vt0, W0, algo, k)
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": k / dt, "unit": "iters/s", "cores": cpu_threads(), "kind": "oracle",
+                               "sample": f"{k} iterations of the oracle on the same X (the objective is evaluated "
+                                         f"after each, as the oracle does)"}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=0, help="default: 10 (batched) or 500 (gauss-fp32)")
     ap.add_argument("--warmup", type=int, default=-1, help="default: 2 (batched) or 20 (gauss-fp32)")
-    ap.add_argument("--workload", default="geno-fp8-batched", choices=["geno-fp8-batched", "gauss-fp32", "refit"])
+    ap.add_argument("--workload", default="geno-fp8-batched",
+                    choices=["geno-fp8-batched", "gauss-fp32", "refit", "nmf"])
+    ap.add_argument("--nmf-rank", type=int, default=20, help="nmf workload: rank r")
+    ap.add_argument("--nmf-algo", type=int, default=0, choices=[0, 1], help="nmf workload: 0 multiplicative, 1 APG")
     ap.add_argument("--refit-cols", type=int, default=333, help="refit workload: SNP columns refitted")
     ap.add_argument("--refit-gtol", type=float, default=1e-6, help="refit workload: Newton stop, max |gradient|")
     ap.add_argument("--batch", type=int, default=64)
@@ -481,11 +571,11 @@ def main():
         torch.cuda.empty_cache()
     batched = args.workload == "geno-fp8-batched"
     if args.steps <= 0:
-        args.steps = 10 if batched else 500
+        args.steps = {"geno-fp8-batched": 10, "nmf": 1000}.get(args.workload, 500)
     if args.warmup < 0:
         args.warmup = 2 if batched else 20
     res = {"gauss-fp32": bench_gauss_fp32, "geno-fp8-batched": bench_geno_batched,
-           "refit": bench_refit}[args.workload](args)
+           "refit": bench_refit, "nmf": bench_nmf}[args.workload](args)
     print(json.dumps(res), flush=True)
 
 

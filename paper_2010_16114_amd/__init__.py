@@ -21,6 +21,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcoxhip.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "cox.h")
+NMF_HEADER = os.path.join(os.path.dirname(_HERE), "include", "nmf.h")
 
 X_F32, X_FP8_E4M3, X_INT8 = 0, 1, 2
 MFMA_VARIANTS = 5  # COX_MFMA_VARIANTS: pipeline shapes of the X~' R pass (and the tuning arrays' length)
@@ -55,9 +56,9 @@ _lib = None
 
 
 def declared_symbols() -> list[str]:
-    """Function names declared by include/cox.h."""
-    src = open(HEADER).read()
-    return re.findall(r"^(?:cox_status|const char \*)\s*(cox_\w+)\s*\(", src, flags=re.M)
+    """Function names declared by include/cox.h and include/nmf.h."""
+    src = open(HEADER).read() + open(NMF_HEADER).read()
+    return re.findall(r"^(?:cox_status|const char \*)\s*((?:cox|nmf)_\w+)\s*\(", src, flags=re.M)
 
 
 def lib():
@@ -90,6 +91,12 @@ def lib():
         "cox_timing_enable": [vp, i32],
         "cox_mfma_tuning": [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), vp, vp],
         "cox_timing_read": [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64)],
+        "nmf_setup": [ctypes.POINTER(vp), vp, i64, i64, i64, i32, vp],
+        "nmf_destroy": [vp],
+        "nmf_last_error": [vp, ctypes.c_char_p, ctypes.c_size_t],
+        "nmf_run": [vp, i32, i32, dbl, vp, vp, vp],
+        "nmf_timing_enable": [vp, i32],
+        "nmf_timing_read": [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -347,6 +354,70 @@ class Cox:
         st = lib().cox_nll_backward(self._h, gl.data_ptr(), gl.shape[0], out.data_ptr())
         self._check(st, "cox_nll_backward")
         return out
+
+
+NMF_MULTIPLICATIVE, NMF_APG = 0, 1
+NMF_MAX_RANK = 64  # NMF_MAX_RANK
+
+
+class NMF:
+    """Nonnegative matrix factorisation of one X on the GPU (nmf_setup, Section
+    5.1).  X: float32 device tensor (m, ldx), row i of X in its first n entries;
+    borrowed.  Factors are float64 device tensors Vt (r, m) and W (r, n)."""
+
+    def __init__(self, X, r: int, n: int | None = None, stream=None):
+        import torch
+        self._torch = torch
+        assert X.is_cuda and X.dtype == torch.float32 and X.dim() == 2 and X.stride(1) == 1
+        self.X, self.m, self.ldx = X, X.shape[0], X.stride(0)
+        self.n = X.shape[1] if n is None else int(n)
+        self.r = int(r)
+        self.stream = torch.cuda.current_stream(X.device) if stream is None else stream
+        h = ctypes.c_void_p()
+        st = lib().nmf_setup(ctypes.byref(h), X.data_ptr(), self.m, self.n, self.ldx, self.r,
+                             self.stream.cuda_stream)
+        if st != OK:
+            raise CoxError(st, f"nmf_setup: {lib().cox_status_string(st).decode()}")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().nmf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, Vt, W, algo: int, iters: int, eps: float = 1e-10, want_obj: bool = True):
+        """iters iterations in place on Vt (r, m) and W (r, n); returns f at the end (or None)."""
+        torch = self._torch
+        for t, shape in ((Vt, (self.r, self.m)), (W, (self.r, self.n))):
+            assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and tuple(t.shape) == shape
+        obj = ctypes.c_double()
+        st = lib().nmf_run(self._h, int(algo), int(iters), float(eps), Vt.data_ptr(), W.data_ptr(),
+                           ctypes.byref(obj) if want_obj else None)
+        if st != OK:
+            buf = ctypes.create_string_buffer(512)
+            lib().nmf_last_error(self._h, buf, 512)
+            raise CoxError(st, f"nmf_run: {lib().cox_status_string(st).decode()} ({buf.value.decode()})")
+        return obj.value if want_obj else None
+
+    def timing(self, enable: bool):
+        st = lib().nmf_timing_enable(self._h, int(enable))
+        if st != OK:
+            raise CoxError(st, "nmf_timing_enable")
+
+    def timing_read(self, phase: int):
+        """(total ms, launches) of the W X' pass (0) or the V' X pass (1) since timing(True)."""
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        st = lib().nmf_timing_read(self._h, int(phase), ctypes.byref(ms), ctypes.byref(cnt))
+        if st != OK:
+            raise CoxError(st, "nmf_timing_read")
+        return ms.value, cnt.value
 
 
 from .autograd import BreslowNLL, CoxLinearNLL  # noqa: E402
