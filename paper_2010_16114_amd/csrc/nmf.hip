@@ -7,19 +7,21 @@
 // formed and summed in FP64, so the only rounding is in the order of the sums.
 //
 // One iteration (Section 5.1, the loop's order):
-//   W X'   (r x m)  nmf_wxt_kernel: workgroups over (256 rows of X, a split of
-//                   the columns); each thread owns a row, the 256 x 32 X tile and
-//                   the r x 32 W tile of a step pass through LDS, r FMAs per X
-//                   element; split partials are added in the update.
+//   W X'   (r x m)  nmf_wxt_*_kernel: workgroups over (256 rows of X, a split
+//                   of the columns); the 256 x 32 X tile and the r x 32 W tile
+//                   of a step pass through LDS.  Up to r = 32 each thread owns a
+//                   row and does r FMAs per X element (VALU); above, the tiles
+//                   feed FP64 matrix-core tiles.  The split partials are added
+//                   by nmf_reduce_kernel.
 //   W W'   (r x r)  nmf_gram_kernel, one workgroup per entry of the upper
 //                   triangle, fixed-order reduction.
 //   V' <- update    nmf_update_kernel, one thread per column of V': the r x r
 //                   product with W W', then the multiplicative update
 //                   V .* (X W') ./ (V W W' + eps) or the projected step
 //                   max(0, V - sigma (V W W' - X W')), sigma = 1/(2||W W'||_F^2 + eps).
-//   V' X   (r x n)  nmf_vtx_kernel: workgroups over (256 columns of X, a split
-//                   of the rows); each thread owns a column, reads X coalesced
-//                   row by row and takes V'[:, i] from an LDS tile.
+//   V' X   (r x n)  nmf_vtx_*_kernel: workgroups over (256 or 512 columns of
+//                   X, a split of the rows); VALU up to r = 32 (two columns per
+//                   thread, V' from LDS), matrix cores above (a 32 x 256 X tile).
 //   V' V   (r x r), then the W update the same way with tau = 1/(2||V'V||_F^2 + eps).
 // Both passes over X read it once each; the r x r products and the updates
 // are O(r^2 (m + n)).
@@ -62,10 +64,10 @@ __device__ double block_sum256(double v, double* sh)
 template <int R>
 constexpr int per_thread() { return R <= 32 ? 2 : 1; }
 
-// part[split][a][i] = sum over the split's columns j of W[a][j] X[i][j]; a
-// workgroup owns kT rows, one per thread
+// VALU form of the W X' pass (ranks up to 32): part[split][a][i] = sum over the
+// split's columns j of W[a][j] X[i][j]; a workgroup owns kT rows, one per thread
 template <int R>
-__global__ __launch_bounds__(kT) void nmf_wxt_kernel(const float* __restrict__ X, int64_t m, int64_t n, int64_t ldx,
+__global__ __launch_bounds__(kT) void nmf_wxt_valu_kernel(const float* __restrict__ X, int64_t m, int64_t n, int64_t ldx,
                                                      int r, const double* __restrict__ W, int64_t cols,
                                                      double* __restrict__ part)
 {
@@ -124,10 +126,11 @@ __global__ __launch_bounds__(kT) void nmf_wxt_kernel(const float* __restrict__ X
     }
 }
 
-// part[split][a][j] = sum over the split's rows i of Vt[a][i] X[i][j]; a
-// workgroup owns kT * per_thread columns (thread t: columns t, t + kT, ...)
+// VALU form of the V' X pass (ranks up to 32): part[split][a][j] = sum over the
+// split's rows i of Vt[a][i] X[i][j]; a workgroup owns kT * per_thread columns
+// (thread t: columns t, t + kT, ...)
 template <int R>
-__global__ __launch_bounds__(kT) void nmf_vtx_kernel(const float* __restrict__ X, int64_t m, int64_t n, int64_t ldx,
+__global__ __launch_bounds__(kT) void nmf_vtx_valu_kernel(const float* __restrict__ X, int64_t m, int64_t n, int64_t ldx,
                                                      int r, const double* __restrict__ Vt, int64_t rows,
                                                      double* __restrict__ part)
 {
@@ -173,6 +176,142 @@ __global__ __launch_bounds__(kT) void nmf_vtx_kernel(const float* __restrict__ X
                 if (a < r) part[((int64_t)blockIdx.y * r + a) * n + j] = acc[u][a];
         }
     }
+}
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// Both passes run on the FP64 matrix cores (v_mfma_f64_16x16x4f64: D = A B + C
+// with A 16 x 4, B 4 x 16, FP64 operands and accumulation).  Per lane: A holds
+// (row lane % 16, k lane / 16), B holds (k lane / 16, column lane % 16), and D
+// holds rows lane / 16 + 4 v, v < 4, of column lane % 16 (interleaved, unlike
+// the int8 instruction's 4 (lane / 16) + v; checked on the device).  The rank
+// is padded to MT tiles of 16; a wavefront owns 64 rows (or columns) of X, 4 N
+// tiles.
+__device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Matrix-core form of the W X' pass (ranks above 32): part[split][a][i] = sum
+// over the split's columns j of W[a][j] X[i][j]: M = a (the rank), N = i (256 rows of X per workgroup), K = j
+template <int MT>
+__global__ __launch_bounds__(kT) void nmf_wxt_mfma_kernel(const float* __restrict__ X, int64_t m, int64_t n, int64_t ldx,
+                                                     int r, const double* __restrict__ W, int64_t cols,
+                                                     double* __restrict__ part)
+{
+    constexpr int R = 16 * MT;
+    __shared__ float Xs[kT][kTJ + 1];
+    __shared__ double Ws[R][kTJ + 1];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int64_t i0 = (int64_t)blockIdx.x * kT;
+    const int64_t j0 = (int64_t)blockIdx.y * cols, j1 = min(n, j0 + cols);
+    v4d acc[MT][4];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int64_t js = j0; js < j1; js += kTJ) {
+        // X tile: 8 threads per row, 4 columns each
+#pragma unroll
+        for (int e = 0; e < kT * kTJ / (4 * kT); ++e) {
+            const int li = threadIdx.x + kT * e;
+            const int row = li / (kTJ / 4), c4 = (li % (kTJ / 4)) * 4;
+            const int64_t i = i0 + row;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t j = js + c4 + q;
+                Xs[row][c4 + q] = (i < m && j < j1) ? X[i * ldx + j] : 0.0f;
+            }
+        }
+        for (int li = threadIdx.x; li < R * kTJ; li += kT) {
+            const int a = li / kTJ, jj = li % kTJ;
+            const int64_t j = js + jj;
+            Ws[a][jj] = (a < r && j < j1) ? W[(int64_t)a * n + j] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kTJ; kk += 4) {
+            const int k = kk + (lane >> 4);
+            double av[MT], bv[4];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) av[mt] = Ws[mt * 16 + (lane & 15)][k];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) bv[nt] = (double)Xs[wid * 64 + nt * 16 + (lane & 15)][k];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = mfma_f64(av[mt], bv[nt], acc[mt][nt]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int a = mt * 16 + (lane >> 4) + 4 * v;
+                const int64_t i = i0 + wid * 64 + nt * 16 + (lane & 15);
+                if (a < r && i < m) part[((int64_t)blockIdx.y * r + a) * m + i] = acc[mt][nt][v];
+            }
+}
+
+// Matrix-core form of the V' X pass (ranks above 32): part[split][a][j] = sum
+// over the split's rows i of Vt[a][i] X[i][j]: M = a, N = j (256 columns of X per workgroup), K = i
+template <int MT>
+__global__ __launch_bounds__(kT) void nmf_vtx_mfma_kernel(const float* __restrict__ X, int64_t m, int64_t n, int64_t ldx,
+                                                     int r, const double* __restrict__ Vt, int64_t rows,
+                                                     double* __restrict__ part)
+{
+    constexpr int R = 16 * MT;
+    __shared__ float Xs[kTI][kT + 4];
+    __shared__ double Vs[R][kTI + 1];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int64_t jb = (int64_t)blockIdx.x * kT;
+    const int64_t i0 = (int64_t)blockIdx.y * rows, i1 = min(m, i0 + rows);
+    v4d acc[MT][4];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int64_t is = i0; is < i1; is += kTI) {
+        // X tile: kTI rows x 256 columns, one column per thread
+#pragma unroll
+        for (int ii = 0; ii < kTI; ++ii) {
+            const int64_t i = is + ii, j = jb + threadIdx.x;
+            Xs[ii][threadIdx.x] = (i < i1 && j < n) ? X[i * ldx + j] : 0.0f;
+        }
+        for (int li = threadIdx.x; li < R * kTI; li += kT) {
+            const int a = li / kTI, ii = li % kTI;
+            const int64_t i = is + ii;
+            Vs[a][ii] = (a < r && i < i1) ? Vt[(int64_t)a * m + i] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kTI; kk += 4) {
+            const int k = kk + (lane >> 4);
+            double av[MT], bv[4];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) av[mt] = Vs[mt * 16 + (lane & 15)][k];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) bv[nt] = (double)Xs[k][wid * 64 + nt * 16 + (lane & 15)];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = mfma_f64(av[mt], bv[nt], acc[mt][nt]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int a = mt * 16 + (lane >> 4) + 4 * v;
+                const int64_t j = jb + wid * 64 + nt * 16 + (lane & 15);
+                if (a < r && j < n) part[((int64_t)blockIdx.y * r + a) * n + j] = acc[mt][nt][v];
+            }
 }
 
 // num[t] = sum over splits of part[split][t], t < r * len, in split order
@@ -291,7 +430,11 @@ __global__ void nmf_objective_kernel(const double* __restrict__ scal, const doub
     f[0] = scal[0] - 2.0 * scal[1] + c;
 }
 
-int rpad(int r) { return (r + 7) / 8 * 8; }
+// Accumulator width of the dispatched kernels: ranks up to 32 run the VALU
+// passes, padded to a multiple of 8; larger ranks the matrix-core passes,
+// padded to a multiple of 16.
+int rpad(int r) { return r <= 32 ? (r + 7) / 8 * 8 : (r + 15) / 16 * 16; }
+constexpr bool use_mfma(int R) { return R > 32; }
 
 inline unsigned grid_for(int64_t m) { return (unsigned)min((int64_t)8192, max((int64_t)1, (m + kT - 1) / kT)); }
 
@@ -371,10 +514,16 @@ template <int R>
 void nmf_vtx_gram(nmf_ctx* c, const double* Vt)
 {
     const int r = c->r;
-    const unsigned gn = (unsigned)((c->n + kT * per_thread<R>() - 1) / (kT * per_thread<R>()));
     nmark(c, 1);
-    hipLaunchKernelGGL((nmf_vtx_kernel<R>), dim3(gn, c->ns_vtx), dim3(kT), 0, c->stream, c->X, c->m, c->n, c->ldx,
-                       r, Vt, c->rows, c->part);
+    if constexpr (use_mfma(R)) {
+        const unsigned gn = (unsigned)((c->n + kT - 1) / kT);
+        hipLaunchKernelGGL((nmf_vtx_mfma_kernel<R / 16>), dim3(gn, c->ns_vtx), dim3(kT), 0, c->stream, c->X, c->m,
+                           c->n, c->ldx, r, Vt, c->rows, c->part);
+    } else {
+        const unsigned gn = (unsigned)((c->n + kT * per_thread<R>() - 1) / (kT * per_thread<R>()));
+        hipLaunchKernelGGL((nmf_vtx_valu_kernel<R>), dim3(gn, c->ns_vtx), dim3(kT), 0, c->stream, c->X, c->m, c->n,
+                           c->ldx, r, Vt, c->rows, c->part);
+    }
     nmark(c, 1);
     hipLaunchKernelGGL(nmf_reduce_kernel, dim3(grid_for((int64_t)r * c->n)), dim3(kT), 0, c->stream, c->part,
                        c->ns_vtx, (int64_t)r * c->n, c->num);
@@ -387,10 +536,13 @@ hipError_t nmf_iteration(nmf_ctx* c, int algo, double eps, double* Vt, double* W
 {
     const int r = c->r;
     const unsigned gm = (unsigned)((c->m + kT - 1) / kT), gn = (unsigned)((c->n + kT - 1) / kT);
-    const unsigned gx = gm;
     nmark(c, 0);
-    hipLaunchKernelGGL((nmf_wxt_kernel<R>), dim3(gx, c->ns_wxt), dim3(kT), 0, c->stream, c->X, c->m, c->n, c->ldx,
-                       r, W, c->cols, c->part);
+    if constexpr (use_mfma(R))
+        hipLaunchKernelGGL((nmf_wxt_mfma_kernel<R / 16>), dim3(gm, c->ns_wxt), dim3(kT), 0, c->stream, c->X, c->m,
+                           c->n, c->ldx, r, W, c->cols, c->part);
+    else
+        hipLaunchKernelGGL((nmf_wxt_valu_kernel<R>), dim3(gm, c->ns_wxt), dim3(kT), 0, c->stream, c->X, c->m, c->n,
+                           c->ldx, r, W, c->cols, c->part);
     nmark(c, 0);
     hipLaunchKernelGGL(nmf_reduce_kernel, dim3(grid_for((int64_t)r * c->m)), dim3(kT), 0, c->stream, c->part,
                        c->ns_wxt, (int64_t)r * c->m, c->num);
@@ -425,9 +577,7 @@ hipError_t nmf_dispatch_r(nmf_ctx* c, int algo, double eps, double* Vt, double* 
     case 16: return nmf_dispatch<16>(c, algo, eps, Vt, W, iters, vtx_only);
     case 24: return nmf_dispatch<24>(c, algo, eps, Vt, W, iters, vtx_only);
     case 32: return nmf_dispatch<32>(c, algo, eps, Vt, W, iters, vtx_only);
-    case 40: return nmf_dispatch<40>(c, algo, eps, Vt, W, iters, vtx_only);
     case 48: return nmf_dispatch<48>(c, algo, eps, Vt, W, iters, vtx_only);
-    case 56: return nmf_dispatch<56>(c, algo, eps, Vt, W, iters, vtx_only);
     default: return nmf_dispatch<64>(c, algo, eps, Vt, W, iters, vtx_only);
     }
 }
@@ -456,7 +606,7 @@ cox_status nmf_setup(nmf_ctx** out, const float* X, int64_t m, int64_t n, int64_
     c->ldx = ldx;
     c->r = r;
     // split the inner dimension so each pass has several workgroups per CU
-    const int pt = rpad(r) <= 32 ? 2 : 1;  // columns per thread of the dispatched V' X pass
+    const int pt = r <= 32 && rpad(r) <= 32 ? 2 : 1;  // columns per thread of the dispatched V' X pass
     const int64_t gm = (m + kT - 1) / kT, gn = (n + kT * pt - 1) / (kT * pt);
     c->ns_wxt = (int)std::max<int64_t>(1, std::min<int64_t>((n + kTJ - 1) / kTJ, (1024 + gm - 1) / gm));
     c->ns_vtx = (int)std::max<int64_t>(1, std::min<int64_t>((m + kTI - 1) / kTI, (1024 + gn - 1) / gn));
