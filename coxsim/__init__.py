@@ -80,7 +80,7 @@ def _device_lib():
     global _hlib
     if _hlib is None:
         if not os.path.exists(_HIP_LIB):
-            raise RuntimeError(f"{_HIP_LIB} is not built; run __graft_entry__.build()")
+            raise RuntimeError(f"{_HIP_LIB} is not built; run coxsim.build_device()")
         lib = ctypes.CDLL(_HIP_LIB)
         vp, i64, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64
         lib.coxsim_genotype_device.argtypes = [vp, i64, i64, i64, u64, vp, ctypes.c_int, vp, vp, vp]

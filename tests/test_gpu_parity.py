@@ -128,7 +128,7 @@ def test_lambda_max_and_opnorm(c0, storage):
 @pytest.mark.parametrize("storage", ["f32", "int8", "fp8"])
 @pytest.mark.parametrize("eta_mode", [0, 1])
 def test_fit_iterates_match_oracle(c0, storage, eta_mode):
-    """configs[0] shape: lambda = 0.5 lambda_max, 200 steps from beta = 0,
+    """The 1,000 x 2,000 oracle-sized problem: lambda = 0.5 lambda_max, 200 steps from beta = 0,
     compared at k = 1, 10, 100, 200."""
     cox, M = device_problem(c0, storage)
     lm = oracle.lambda_max(M, c0.time, c0.event)
