@@ -213,3 +213,26 @@ def test_covariate_argument_checks(prob):
     big = torch.zeros((P.MAX_COVARIATES + 1, d.n), dtype=torch.float32, device="cuda")
     with pytest.raises(P.CoxError):
         cox.set_covariates(big)
+
+
+@pytest.mark.parametrize("storage,B", [("int8", 6), ("fp8", 40)])
+def test_early_stopping_lambdas_with_covariates(prob, storage, B):
+    """Lambdas that meet the lag-10 rule at different steps stop while the rest
+    go on: each one's steps, objective and beta match the oracle's own run
+    under the same rule (the covariate block must leave a stopped lambda
+    untouched)."""
+    d, Z = prob
+    cox, Mo = _setup(prob, storage, B)
+    pf = np.concatenate([np.ones(d.p), np.zeros(Q)])
+    lm, _ = oracle.lambda_max_pf(Mo, d.time, d.event, pf)
+    lams = coxsim.lambda_grid(lm, B, 0.05)
+    sigma = 1.0 / (2.0 * oracle.opnorm2(Mo)[0])
+    beta, iters, obj, st = cox.fit_path(lams, max_iter=400, tol=1e-6, lag=10, step=sigma)
+    beta = beta.cpu().numpy()
+    assert len(set(iters.tolist())) > 1  # they did stop at different steps
+    for b in sorted({0, B // 3, B - 1}):
+        bo, tr, k, conv = oracle.fit(Mo, d.time, d.event, lams[b], sigma, max_iter=400, tol=1e-6, lag=10, pf=pf)
+        assert abs(int(iters[b]) - k) <= 1, (b, iters[b], k)
+        if int(iters[b]) == k:
+            assert rel_beta_err(beta[b], bo) <= BETA_TOL, b
+            assert obj[b] == pytest.approx(tr[-1], rel=OBJ_TOL), b
