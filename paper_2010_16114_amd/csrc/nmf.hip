@@ -7,21 +7,20 @@
 // formed and summed in FP64, so the only rounding is in the order of the sums.
 //
 // One iteration (Section 5.1, the loop's order):
-//   W X'   (r x m)  nmf_wxt_*_kernel: workgroups over (256 rows of X, a split
-//                   of the columns); the 256 x 32 X tile and the r x 32 W tile
-//                   of a step pass through LDS.  Up to r = 32 each thread owns a
-//                   row and does r FMAs per X element (VALU); above, the tiles
-//                   feed FP64 matrix-core tiles.  The split partials are added
-//                   by nmf_reduce_kernel.
+//   W X'   (r x m)  nmf_wxt_kernel: workgroups over (256 rows of X, a split of
+//                   the columns); the 256 x 32 X tile and the r x 32 W tile of a
+//                   step pass through LDS into FP64 matrix-core tiles, the next
+//                   step's tiles loading into registers meanwhile.  The split
+//                   partials are added by nmf_reduce_kernel.
 //   W W'   (r x r)  nmf_gram_kernel, one workgroup per entry of the upper
 //                   triangle, fixed-order reduction.
 //   V' <- update    nmf_update_kernel, one thread per column of V': the r x r
 //                   product with W W', then the multiplicative update
 //                   V .* (X W') ./ (V W W' + eps) or the projected step
 //                   max(0, V - sigma (V W W' - X W')), sigma = 1/(2||W W'||_F^2 + eps).
-//   V' X   (r x n)  nmf_vtx_*_kernel: workgroups over (256 or 512 columns of
-//                   X, a split of the rows); VALU up to r = 32 (two columns per
-//                   thread, V' from LDS), matrix cores above (a 32 x 256 X tile).
+//   V' X   (r x n)  nmf_vtx_kernel: workgroups over (256 columns of X, a split
+//                   of the rows); a 32 x 256 X tile and the r x 32 V' tile, the
+//                   same way.
 //   V' V   (r x r), then the W update the same way with tau = 1/(2||V'V||_F^2 + eps).
 // Both passes over X read it once each; the r x r products and the updates
 // are O(r^2 (m + n)).
@@ -57,127 +56,6 @@ __device__ double block_sum256(double v, double* sh)
     return s;
 }
 
-// Columns of X per thread in the V' X pass: two while the accumulators fit, so
-// that each factor value read from LDS feeds two FMAs.  (The W X' pass keeps
-// one row per thread: with two, its 512-row X tile and the accumulators cut
-// the occupancy and it ran slower.)
-template <int R>
-constexpr int per_thread() { return R <= 32 ? 2 : 1; }
-
-// VALU form of the W X' pass (ranks up to 32): part[split][a][i] = sum over the
-// split's columns j of W[a][j] X[i][j]; a workgroup owns kT rows, one per thread
-template <int R>
-__global__ __launch_bounds__(kT) void nmf_wxt_valu_kernel(const float* __restrict__ X, int64_t m, int64_t n, int64_t ldx,
-                                                     int r, const double* __restrict__ W, int64_t cols,
-                                                     double* __restrict__ part)
-{
-    constexpr int PT = 1;
-    constexpr int ROWS = kT * PT;
-    __shared__ float Xs[ROWS][kTJ + 1];
-    __shared__ double Ws[R][kTJ];
-    const int64_t i0 = (int64_t)blockIdx.x * ROWS;
-    const int64_t j0 = (int64_t)blockIdx.y * cols, j1 = min(n, j0 + cols);
-    double acc[PT][R];
-#pragma unroll
-    for (int u = 0; u < PT; ++u)
-#pragma unroll
-        for (int a = 0; a < R; ++a) acc[u][a] = 0.0;
-    for (int64_t js = j0; js < j1; js += kTJ) {
-        // X tile: 8 threads per row, 4 columns each
-#pragma unroll
-        for (int e = 0; e < ROWS * kTJ / (4 * kT); ++e) {
-            const int li = threadIdx.x + kT * e;
-            const int row = li / (kTJ / 4), c4 = (li % (kTJ / 4)) * 4;
-            const int64_t i = i0 + row;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t j = js + c4 + q;
-                Xs[row][c4 + q] = (i < m && j < j1) ? X[i * ldx + j] : 0.0f;
-            }
-        }
-        for (int li = threadIdx.x; li < R * kTJ; li += kT) {
-            const int a = li / kTJ, jj = li % kTJ;
-            const int64_t j = js + jj;
-            Ws[a][jj] = (a < r && j < j1) ? W[(int64_t)a * n + j] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll 2
-        for (int jj = 0; jj < kTJ; ++jj) {
-            double x[PT];
-#pragma unroll
-            for (int u = 0; u < PT; ++u) x[u] = (double)Xs[threadIdx.x + kT * u][jj];
-#pragma unroll
-            for (int a = 0; a < R; ++a) {
-                const double wv = Ws[a][jj];
-#pragma unroll
-                for (int u = 0; u < PT; ++u) acc[u][a] += wv * x[u];
-            }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int u = 0; u < PT; ++u) {
-        const int64_t i = i0 + threadIdx.x + kT * u;
-        if (i < m) {
-#pragma unroll
-            for (int a = 0; a < R; ++a)
-                if (a < r) part[((int64_t)blockIdx.y * r + a) * m + i] = acc[u][a];
-        }
-    }
-}
-
-// VALU form of the V' X pass (ranks up to 32): part[split][a][j] = sum over the
-// split's rows i of Vt[a][i] X[i][j]; a workgroup owns kT * per_thread columns
-// (thread t: columns t, t + kT, ...)
-template <int R>
-__global__ __launch_bounds__(kT) void nmf_vtx_valu_kernel(const float* __restrict__ X, int64_t m, int64_t n, int64_t ldx,
-                                                     int r, const double* __restrict__ Vt, int64_t rows,
-                                                     double* __restrict__ part)
-{
-    constexpr int PT = per_thread<R>();
-    __shared__ double Vs[R][kTI];
-    const int64_t jb = (int64_t)blockIdx.x * kT * PT + threadIdx.x;
-    const int64_t i0 = (int64_t)blockIdx.y * rows, i1 = min(m, i0 + rows);
-    double acc[PT][R];
-#pragma unroll
-    for (int u = 0; u < PT; ++u)
-#pragma unroll
-        for (int a = 0; a < R; ++a) acc[u][a] = 0.0;
-    for (int64_t is = i0; is < i1; is += kTI) {
-        for (int li = threadIdx.x; li < R * kTI; li += kT) {
-            const int a = li / kTI, ii = li % kTI;
-            const int64_t i = is + ii;
-            Vs[a][ii] = (a < r && i < i1) ? Vt[(int64_t)a * m + i] : 0.0;
-        }
-        __syncthreads();
-        const int nr = (int)min((int64_t)kTI, i1 - is);
-        for (int ii = 0; ii < nr; ++ii) {
-            double x[PT];
-#pragma unroll
-            for (int u = 0; u < PT; ++u) {
-                const int64_t j = jb + kT * u;
-                x[u] = j < n ? (double)X[(is + ii) * ldx + j] : 0.0;
-            }
-#pragma unroll
-            for (int a = 0; a < R; ++a) {
-                const double vv = Vs[a][ii];
-#pragma unroll
-                for (int u = 0; u < PT; ++u) acc[u][a] += vv * x[u];
-            }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int u = 0; u < PT; ++u) {
-        const int64_t j = jb + kT * u;
-        if (j < n) {
-#pragma unroll
-            for (int a = 0; a < R; ++a)
-                if (a < r) part[((int64_t)blockIdx.y * r + a) * n + j] = acc[u][a];
-        }
-    }
-}
-
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 // Both passes run on the FP64 matrix cores (v_mfma_f64_16x16x4f64: D = A B + C
@@ -192,10 +70,10 @@ __device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Matrix-core form of the W X' pass (ranks above 32): part[split][a][i] = sum
-// over the split's columns j of W[a][j] X[i][j]: M = a (the rank), N = i (256 rows of X per workgroup), K = j
+// part[split][a][i] = sum over the split's columns j of W[a][j] X[i][j]:
+// M = a (the rank), N = i (256 rows of X per workgroup), K = j
 template <int MT>
-__global__ __launch_bounds__(kT) void nmf_wxt_mfma_kernel(const float* __restrict__ X, int64_t m, int64_t n, int64_t ldx,
+__global__ __launch_bounds__(kT) void nmf_wxt_kernel(const float* __restrict__ X, int64_t m, int64_t n, int64_t ldx,
                                                      int r, const double* __restrict__ W, int64_t cols,
                                                      double* __restrict__ part)
 {
@@ -210,25 +88,48 @@ __global__ __launch_bounds__(kT) void nmf_wxt_mfma_kernel(const float* __restric
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = v4d{0.0, 0.0, 0.0, 0.0};
-    for (int64_t js = j0; js < j1; js += kTJ) {
-        // X tile: 8 threads per row, 4 columns each
+    // the next step's tiles are loaded into registers while the current one is
+    // multiplied out of LDS
+    constexpr int XE = kT * kTJ / (4 * kT);
+    constexpr int WE = (R * kTJ + kT - 1) / kT;
+    float xr[XE][4];
+    double wr[WE];
+    auto fetch = [&](int64_t js) {
 #pragma unroll
-        for (int e = 0; e < kT * kTJ / (4 * kT); ++e) {
+        for (int e = 0; e < XE; ++e) {
             const int li = threadIdx.x + kT * e;
             const int row = li / (kTJ / 4), c4 = (li % (kTJ / 4)) * 4;
             const int64_t i = i0 + row;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int64_t j = js + c4 + q;
-                Xs[row][c4 + q] = (i < m && j < j1) ? X[i * ldx + j] : 0.0f;
+                xr[e][q] = (i < m && j < j1) ? X[i * ldx + j] : 0.0f;
             }
         }
-        for (int li = threadIdx.x; li < R * kTJ; li += kT) {
+#pragma unroll
+        for (int e = 0; e < WE; ++e) {
+            const int li = threadIdx.x + kT * e;
             const int a = li / kTJ, jj = li % kTJ;
             const int64_t j = js + jj;
-            Ws[a][jj] = (a < r && j < j1) ? W[(int64_t)a * n + j] : 0.0;
+            wr[e] = (li < R * kTJ && a < r && j < j1) ? W[(int64_t)a * n + j] : 0.0;
+        }
+    };
+    if (j0 < j1) fetch(j0);
+    for (int64_t js = j0; js < j1; js += kTJ) {
+#pragma unroll
+        for (int e = 0; e < XE; ++e) {
+            const int li = threadIdx.x + kT * e;
+            const int row = li / (kTJ / 4), c4 = (li % (kTJ / 4)) * 4;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Xs[row][c4 + q] = xr[e][q];
+        }
+#pragma unroll
+        for (int e = 0; e < WE; ++e) {
+            const int li = threadIdx.x + kT * e;
+            if (li < R * kTJ) Ws[li / kTJ][li % kTJ] = wr[e];
         }
         __syncthreads();
+        if (js + kTJ < j1) fetch(js + kTJ);
 #pragma unroll
         for (int kk = 0; kk < kTJ; kk += 4) {
             const int k = kk + (lane >> 4);
@@ -256,10 +157,10 @@ __global__ __launch_bounds__(kT) void nmf_wxt_mfma_kernel(const float* __restric
             }
 }
 
-// Matrix-core form of the V' X pass (ranks above 32): part[split][a][j] = sum
-// over the split's rows i of Vt[a][i] X[i][j]: M = a, N = j (256 columns of X per workgroup), K = i
+// part[split][a][j] = sum over the split's rows i of Vt[a][i] X[i][j]:
+// M = a, N = j (256 columns of X per workgroup), K = i
 template <int MT>
-__global__ __launch_bounds__(kT) void nmf_vtx_mfma_kernel(const float* __restrict__ X, int64_t m, int64_t n, int64_t ldx,
+__global__ __launch_bounds__(kT) void nmf_vtx_kernel(const float* __restrict__ X, int64_t m, int64_t n, int64_t ldx,
                                                      int r, const double* __restrict__ Vt, int64_t rows,
                                                      double* __restrict__ part)
 {
@@ -274,19 +175,36 @@ __global__ __launch_bounds__(kT) void nmf_vtx_mfma_kernel(const float* __restric
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = v4d{0.0, 0.0, 0.0, 0.0};
-    for (int64_t is = i0; is < i1; is += kTI) {
-        // X tile: kTI rows x 256 columns, one column per thread
+    // the next step's tiles (kTI rows x 256 columns of X, one column per thread,
+    // and the r x kTI tile of V') are loaded into registers during this one
+    constexpr int VE = (R * kTI + kT - 1) / kT;
+    float xr[kTI];
+    double vr[VE];
+    auto fetch = [&](int64_t is) {
 #pragma unroll
         for (int ii = 0; ii < kTI; ++ii) {
             const int64_t i = is + ii, j = jb + threadIdx.x;
-            Xs[ii][threadIdx.x] = (i < i1 && j < n) ? X[i * ldx + j] : 0.0f;
+            xr[ii] = (i < i1 && j < n) ? X[i * ldx + j] : 0.0f;
         }
-        for (int li = threadIdx.x; li < R * kTI; li += kT) {
+#pragma unroll
+        for (int e = 0; e < VE; ++e) {
+            const int li = threadIdx.x + kT * e;
             const int a = li / kTI, ii = li % kTI;
             const int64_t i = is + ii;
-            Vs[a][ii] = (a < r && i < i1) ? Vt[(int64_t)a * m + i] : 0.0;
+            vr[e] = (li < R * kTI && a < r && i < i1) ? Vt[(int64_t)a * m + i] : 0.0;
+        }
+    };
+    if (i0 < i1) fetch(i0);
+    for (int64_t is = i0; is < i1; is += kTI) {
+#pragma unroll
+        for (int ii = 0; ii < kTI; ++ii) Xs[ii][threadIdx.x] = xr[ii];
+#pragma unroll
+        for (int e = 0; e < VE; ++e) {
+            const int li = threadIdx.x + kT * e;
+            if (li < R * kTI) Vs[li / kTI][li % kTI] = vr[e];
         }
         __syncthreads();
+        if (is + kTI < i1) fetch(is + kTI);
 #pragma unroll
         for (int kk = 0; kk < kTI; kk += 4) {
             const int k = kk + (lane >> 4);
@@ -430,11 +348,8 @@ __global__ void nmf_objective_kernel(const double* __restrict__ scal, const doub
     f[0] = scal[0] - 2.0 * scal[1] + c;
 }
 
-// Accumulator width of the dispatched kernels: ranks up to 32 run the VALU
-// passes, padded to a multiple of 8; larger ranks the matrix-core passes,
-// padded to a multiple of 16.
-int rpad(int r) { return r <= 32 ? (r + 7) / 8 * 8 : (r + 15) / 16 * 16; }
-constexpr bool use_mfma(int R) { return R > 32; }
+// The rank padded to whole 16-row matrix-core tiles.
+int rpad(int r) { return (r + 15) / 16 * 16; }
 
 inline unsigned grid_for(int64_t m) { return (unsigned)min((int64_t)8192, max((int64_t)1, (m + kT - 1) / kT)); }
 
@@ -514,16 +429,10 @@ template <int R>
 void nmf_vtx_gram(nmf_ctx* c, const double* Vt)
 {
     const int r = c->r;
+    const unsigned gn = (unsigned)((c->n + kT - 1) / kT);
     nmark(c, 1);
-    if constexpr (use_mfma(R)) {
-        const unsigned gn = (unsigned)((c->n + kT - 1) / kT);
-        hipLaunchKernelGGL((nmf_vtx_mfma_kernel<R / 16>), dim3(gn, c->ns_vtx), dim3(kT), 0, c->stream, c->X, c->m,
-                           c->n, c->ldx, r, Vt, c->rows, c->part);
-    } else {
-        const unsigned gn = (unsigned)((c->n + kT * per_thread<R>() - 1) / (kT * per_thread<R>()));
-        hipLaunchKernelGGL((nmf_vtx_valu_kernel<R>), dim3(gn, c->ns_vtx), dim3(kT), 0, c->stream, c->X, c->m, c->n,
-                           c->ldx, r, Vt, c->rows, c->part);
-    }
+    hipLaunchKernelGGL((nmf_vtx_kernel<R / 16>), dim3(gn, c->ns_vtx), dim3(kT), 0, c->stream, c->X, c->m, c->n,
+                       c->ldx, r, Vt, c->rows, c->part);
     nmark(c, 1);
     hipLaunchKernelGGL(nmf_reduce_kernel, dim3(grid_for((int64_t)r * c->n)), dim3(kT), 0, c->stream, c->part,
                        c->ns_vtx, (int64_t)r * c->n, c->num);
@@ -537,12 +446,8 @@ hipError_t nmf_iteration(nmf_ctx* c, int algo, double eps, double* Vt, double* W
     const int r = c->r;
     const unsigned gm = (unsigned)((c->m + kT - 1) / kT), gn = (unsigned)((c->n + kT - 1) / kT);
     nmark(c, 0);
-    if constexpr (use_mfma(R))
-        hipLaunchKernelGGL((nmf_wxt_mfma_kernel<R / 16>), dim3(gm, c->ns_wxt), dim3(kT), 0, c->stream, c->X, c->m,
-                           c->n, c->ldx, r, W, c->cols, c->part);
-    else
-        hipLaunchKernelGGL((nmf_wxt_valu_kernel<R>), dim3(gm, c->ns_wxt), dim3(kT), 0, c->stream, c->X, c->m, c->n,
-                           c->ldx, r, W, c->cols, c->part);
+    hipLaunchKernelGGL((nmf_wxt_kernel<R / 16>), dim3(gm, c->ns_wxt), dim3(kT), 0, c->stream, c->X, c->m, c->n,
+                       c->ldx, r, W, c->cols, c->part);
     nmark(c, 0);
     hipLaunchKernelGGL(nmf_reduce_kernel, dim3(grid_for((int64_t)r * c->m)), dim3(kT), 0, c->stream, c->part,
                        c->ns_wxt, (int64_t)r * c->m, c->num);
@@ -573,9 +478,7 @@ hipError_t nmf_dispatch(nmf_ctx* c, int algo, double eps, double* Vt, double* W,
 hipError_t nmf_dispatch_r(nmf_ctx* c, int algo, double eps, double* Vt, double* W, int iters, bool vtx_only)
 {
     switch (rpad(c->r)) {
-    case 8: return nmf_dispatch<8>(c, algo, eps, Vt, W, iters, vtx_only);
     case 16: return nmf_dispatch<16>(c, algo, eps, Vt, W, iters, vtx_only);
-    case 24: return nmf_dispatch<24>(c, algo, eps, Vt, W, iters, vtx_only);
     case 32: return nmf_dispatch<32>(c, algo, eps, Vt, W, iters, vtx_only);
     case 48: return nmf_dispatch<48>(c, algo, eps, Vt, W, iters, vtx_only);
     default: return nmf_dispatch<64>(c, algo, eps, Vt, W, iters, vtx_only);
@@ -606,8 +509,7 @@ cox_status nmf_setup(nmf_ctx** out, const float* X, int64_t m, int64_t n, int64_
     c->ldx = ldx;
     c->r = r;
     // split the inner dimension so each pass has several workgroups per CU
-    const int pt = r <= 32 && rpad(r) <= 32 ? 2 : 1;  // columns per thread of the dispatched V' X pass
-    const int64_t gm = (m + kT - 1) / kT, gn = (n + kT * pt - 1) / (kT * pt);
+    const int64_t gm = (m + kT - 1) / kT, gn = (n + kT - 1) / kT;
     c->ns_wxt = (int)std::max<int64_t>(1, std::min<int64_t>((n + kTJ - 1) / kTJ, (1024 + gm - 1) / gm));
     c->ns_vtx = (int)std::max<int64_t>(1, std::min<int64_t>((m + kTI - 1) / kTI, (1024 + gn - 1) / gn));
     c->cols = ((n + c->ns_wxt - 1) / c->ns_wxt + kTJ - 1) / kTJ * kTJ;
