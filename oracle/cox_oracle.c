@@ -470,7 +470,7 @@ static double loglik_grad_hess(const oracle_matrix *X, const int64_t *cols, int6
 /* Solve A x = b for a symmetric positive definite m x m matrix A (row-major) by
  * Cholesky factorisation; A is overwritten by its factor.  Returns 0, or -1 when
  * A is not numerically positive definite. */
-static int cholesky_solve(double *A, int64_t m, double *x)
+static int cholesky_factor(double *A, int64_t m)
 {
     for (int64_t j = 0; j < m; ++j) {
         double d = A[j * m + j];
@@ -484,6 +484,12 @@ static int cholesky_solve(double *A, int64_t m, double *x)
             A[i * m + j] = v / d;
         }
     }
+    return 0;
+}
+
+/* x <- (L L')^{-1} x with the factor from cholesky_factor */
+static void cholesky_subst(const double *A, int64_t m, double *x)
+{
     for (int64_t i = 0; i < m; ++i) { /* forward: L y = b */
         double v = x[i];
         for (int64_t k = 0; k < i; ++k) v -= A[i * m + k] * x[k];
@@ -494,6 +500,12 @@ static int cholesky_solve(double *A, int64_t m, double *x)
         for (int64_t k = i + 1; k < m; ++k) v -= A[k * m + i] * x[k];
         x[i] = v / A[i * m + i];
     }
+}
+
+static int cholesky_solve(double *A, int64_t m, double *x)
+{
+    if (cholesky_factor(A, m)) return -1;
+    cholesky_subst(A, m, x);
     return 0;
 }
 
@@ -575,12 +587,16 @@ int cox_oracle_newton(int kind, const void *data, int64_t n, int64_t p, int64_t 
         L = Lt;
     }
     if (cov && rc >= 0) {
-        /* inverse of -H, column by column */
-        for (int64_t b = 0; b < m; ++b) {
-            for (int64_t a = 0; a < m * m; ++a) fac[a] = -hess[a];
-            for (int64_t a = 0; a < m; ++a) d[a] = (a == b) ? 1.0 : 0.0;
-            if (cholesky_solve(fac, m, d)) { rc = -2; break; }
-            for (int64_t a = 0; a < m; ++a) cov[a * m + b] = d[a];
+        /* inverse of -H, column by column from one factorisation */
+        for (int64_t a = 0; a < m * m; ++a) fac[a] = -hess[a];
+        if (cholesky_factor(fac, m)) {
+            rc = -2;
+        } else {
+            for (int64_t b = 0; b < m; ++b) {
+                for (int64_t a = 0; a < m; ++a) d[a] = (a == b) ? 1.0 : 0.0;
+                cholesky_subst(fac, m, d);
+                for (int64_t a = 0; a < m; ++a) cov[a * m + b] = d[a];
+            }
         }
     }
 out:
