@@ -394,8 +394,10 @@ def bench_refit(args):
     elapsed = t1 - t0
     M = m + q
     log(f"{it} Newton steps in {elapsed:.3f} s (status {st}); {h_n} Hessians, {h_ms / max(h_n, 1):.2f} ms each")
-    # the two Gram matrices of the information: n (M + 1) M / 2 products each, 2 flops
-    flops = 2 * n * M * (M + 1)
+    # the two Gram matrices of the information, M (M + 1) / 2 products per row at
+    # 2 flops: over the n subjects, and over the G tie groups that hold events
+    G = int(np.unique(d.time[d.event == 1]).size)
+    flops = (n + G) * M * (M + 1)
     hess_s = h_ms / max(h_n, 1) / 1e3
     res = {
         "metric": "unpenalised Cox refit, Newton steps/s",
@@ -412,9 +414,9 @@ def bench_refit(args):
         "data": "synthetic",
         "config": {"workload": f"post-selection refit: n={n}, {m} SNPs (FP8 counts, standardised, gathered to "
                                f"FP32) + {q} covariates, Newton to max|g| <= {args.refit_gtol}",
-                   "n": n, "columns": M, "status": int(st), "loglik": L},
+                   "n": n, "columns": M, "event_groups": G, "status": int(st), "loglik": L},
         "phases_ms_per_step": {"hessian": h_ms / max(h_n, 1), "factor_solve": s_ms / max(it, 1)},
-        "roofline": {"bound": "alu", "kernel": "gram_kernel (the information matrix's two Gram terms)",
+        "roofline": {"bound": "alu", "kernel": "the information matrix: its two Gram terms (gram_kernel) over the whole Hessian phase's time",
                      "achieved": flops / hess_s / 1e12, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": flops / hess_s / 1e12 / FP64_VALU_PEAK_TFLOPS, "traffic": None,
                      "flops_per_hessian": flops},

@@ -60,6 +60,10 @@ struct cox_ctx {
 
     int32_t *perm = nullptr, *gstart = nullptr, *gend = nullptr;
     uint8_t* ev = nullptr;
+    // tie groups with events: egidx[k] = g at the last sorted position k of the
+    // g-th such group (-1 elsewhere), egcnt[g] = its events
+    int32_t *egidx = nullptr, *egcnt = nullptr;
+    int64_t n_egroups = 0;
     double *eta = nullptr, *w = nullptr, *S = nullptr, *T = nullptr, *r64 = nullptr;
     float* r32 = nullptr;
     double *part_upd = nullptr, *part_gemv = nullptr;
@@ -720,9 +724,21 @@ cox_status cox_setup(cox_ctx** out, const cox_matrix* X, const double* time, con
         k = e + 1;
     }
     for (int64_t k = 0; k < n; ++k) evs[k] = (uint8_t)event[perm[k]];
+    std::vector<int32_t> egi(n, -1), egc;
+    for (int64_t k = 0; k < n; ++k) {
+        if (ge[k] != k) continue;
+        int32_t cnt = 0;
+        for (int64_t q = gs[k]; q <= k; ++q) cnt += evs[q];
+        if (cnt > 0) {
+            egi[k] = (int32_t)egc.size();
+            egc.push_back(cnt);
+        }
+    }
+    c->n_egroups = (int64_t)egc.size();
 
     const int64_t Bn = (int64_t)max_batch * n, Bp = (int64_t)max_batch * p;
     bool ok = dalloc(c, &c->perm, n) && dalloc(c, &c->gstart, n) && dalloc(c, &c->gend, n) && dalloc(c, &c->ev, n) &&
+              dalloc(c, &c->egidx, n) && dalloc(c, &c->egcnt, std::max<size_t>(1, egc.size())) &&
               dalloc(c, &c->eta, Bn) && dalloc(c, &c->w, Bn) && dalloc(c, &c->S, Bn) && dalloc(c, &c->T, Bn) &&
               dalloc(c, &c->r64, Bn) && dalloc(c, &c->r32, (size_t)max_batch * c->rstride) &&
               dalloc(c, &c->part_upd, (size_t)c->ncg * Bn) && dalloc(c, &c->part_gemv, (size_t)c->ncb * kGroup * n) &&
@@ -774,6 +790,8 @@ cox_status cox_setup(cox_ctx** out, const cox_matrix* X, const double* time, con
     up(c->gstart, gs.data(), sizeof(int32_t) * n);
     up(c->gend, ge.data(), sizeof(int32_t) * n);
     up(c->ev, evs.data(), n);
+    up(c->egidx, egi.data(), sizeof(int32_t) * n);
+    if (!egc.empty()) up(c->egcnt, egc.data(), sizeof(int32_t) * egc.size());
     auto chk = [&](hipError_t e) {
         if (st == COX_OK && e != hipSuccess) st = COX_ERR_DEVICE;
     };
@@ -1258,34 +1276,33 @@ cox_status cox_refit(cox_ctx* c, const int64_t* cols, int32_t m, const cox_refit
     for (int a = 0; a < M; ++a)
         if (!std::isfinite(coef[a])) return fail(c, COX_ERR_INVALID_ARG, "coef must be finite");
 
-    const int nc = gram_chunks(n), nrb = refit_row_blocks(n);
+    const int64_t G = c->n_egroups, ldd = refit_ld(n), ldp = refit_ld(G);
+    const int nc1 = gram_chunks(n, M), nc2 = gram_chunks(G, M), nch = scan_chunks(n), nrb = refit_row_blocks(n);
     const size_t MM = (size_t)M * M;
     Scratch w;
     float* D;
-    double *S, *wt, *p1, *p2, *H, *scr, *g, *d, *b, *bt, *gpart, *sed, *pvd;
+    double *Pg, *wg, *wt, *rs, *csum, *p1, *p2, *H, *g, *d, *b, *bt, *gpart, *sed, *pvd;
     int32_t* colsd;
     int* okd;
-    if (!(w.get(&D, (size_t)M * n) && w.get(&S, (size_t)(M + 1) * n) && w.get(&wt, n) && w.get(&p1, nc * MM) &&
-          w.get(&p2, nc * MM) && w.get(&H, MM) && w.get(&scr, MM) && w.get(&g, M) && w.get(&d, M) && w.get(&b, M) &&
-          w.get(&bt, M) && w.get(&gpart, (size_t)nrb * M) && w.get(&sed, M) && w.get(&pvd, M) &&
-          w.get(&colsd, std::max(m, 1)) && w.get(&okd, 1)))
+    if (!(w.get(&D, (size_t)M * ldd) && w.get(&Pg, (size_t)(M + 1) * ldp) && w.get(&wg, ldp) && w.get(&wt, ldd) &&
+          w.get(&rs, n) &&
+          w.get(&csum, (size_t)(M + 1) * nch) && w.get(&p1, nc1 * MM) && w.get(&p2, nc2 * MM) && w.get(&H, MM) &&
+          w.get(&g, M) && w.get(&d, M) && w.get(&b, M) && w.get(&bt, M) && w.get(&gpart, (size_t)nrb * M) &&
+          w.get(&sed, M) && w.get(&pvd, M) && w.get(&colsd, std::max(m, 1)) && w.get(&okd, 1)))
         return fail(c, COX_ERR_OUT_OF_MEMORY, "refit workspace");
 
     if (m > 0) {
         STCHK(h2d(c, colsd, cols32.data(), sizeof(int32_t) * m));
-        HIPCHK(launch_gather_cols(c->x, colsd, m, D, n, c->stream), "gather columns");
+        HIPCHK(launch_gather_cols(c->x, colsd, m, c->perm, D, ldd, c->stream), "gather columns");
     }
-    if (q)
-        HIPCHK(hipMemcpy2DAsync(D + (size_t)m * n, sizeof(float) * n, c->Z, sizeof(float) * c->ldz,
-                                sizeof(float) * n, q, hipMemcpyDeviceToDevice, c->stream),
-               "copy covariates");
+    if (q) HIPCHK(launch_gather_z(c->Z, c->ldz, n, q, c->perm, D + (size_t)m * ldd, ldd, c->stream), "gather covariates");
     STCHK(h2d(c, b, coef, sizeof(double) * M));
 
     RiskArgs ra = risk_args(c, 1);
     ra.r32 = nullptr;
     ra.r64 = c->r64;
     auto eval = [&](const double* bb, double* Lout) -> cox_status {
-        HIPCHK(launch_refit_eta(D, n, n, M, bb, c->eta, c->stream), "D b");
+        HIPCHK(launch_refit_eta(D, ldd, n, M, c->perm, bb, c->eta, c->stream), "D b");
         HIPCHK(launch_risk(ra, c->stream), "risk-set sums");
         STCHK(d2h(c, Lout, c->L, sizeof(double)));
         if (!std::isfinite(*Lout)) return fail(c, COX_ERR_NUMERIC, "non-finite log likelihood");
@@ -1293,9 +1310,9 @@ cox_status cox_refit(cox_ctx* c, const int64_t* cols, int32_t m, const cox_refit
     };
     auto hessian = [&]() -> cox_status {
         tmark(c, COX_PHASE_REFIT_HESSIAN);
-        HIPCHK(launch_refit_hessian(D, n, n, M, c->perm, c->gstart, c->gend, c->ev, c->w, c->r64, wt, S, p1, p2, H,
-                                    c->stream),
-               "Hessian");
+        const RefitHess hs{D, ldd, n, M, c->perm, c->ev, c->w, c->r64, c->egidx, c->egcnt, G, ldp,
+                           wt, csum, Pg, wg, p1, p2, H};
+        HIPCHK(launch_refit_hessian(hs, c->stream), "Hessian");
         tmark(c, COX_PHASE_REFIT_HESSIAN);
         tmark(c, COX_PHASE_REFIT_SOLVE);
         HIPCHK(launch_chol(H, M, okd, c->stream), "Cholesky");
@@ -1312,7 +1329,7 @@ cox_status cox_refit(cox_ctx* c, const int64_t* cols, int32_t m, const cox_refit
     bool converged = false;
     int it = 0;
     for (;; ++it) {
-        HIPCHK(launch_refit_grad(D, n, n, M, c->r64, gpart, g, c->stream), "D' r");
+        HIPCHK(launch_refit_grad(D, ldd, n, M, c->perm, c->r64, rs, gpart, g, c->stream), "D' r");
         STCHK(d2h(c, gh.data(), g, sizeof(double) * M));
         double gmax = 0.0;
         for (double v : gh) gmax = std::max(gmax, std::fabs(v));
@@ -1347,7 +1364,7 @@ cox_status cox_refit(cox_ctx* c, const int64_t* cols, int32_t m, const cox_refit
         L = Lt;
     }
     STCHK(hessian());
-    HIPCHK(launch_wald(H, M, b, scr, sed, pvd, c->stream), "Wald statistics");
+    HIPCHK(launch_wald(H, M, b, sed, pvd, c->stream), "Wald statistics");
     STCHK(d2h(c, coef, b, sizeof(double) * M));
     if (se) STCHK(d2h(c, se, sed, sizeof(double) * M));
     if (pval) STCHK(d2h(c, pval, pvd, sizeof(double) * M));

@@ -22,7 +22,7 @@ constexpr int kCovRows = 8192;                      // rows per workgroup of Z' 
 constexpr int kMaxCov = 64;                         // covariates in the dense block beside X
 constexpr int kMaxRefit = 1024;                     // columns of an unpenalised refit
 constexpr int kRefitRows = 8192;                    // rows per workgroup of the refit's D' r
-constexpr int kGramChunks = 32;                     // row chunks of the refit's Gram partials
+constexpr int kGramChunks = 64;                     // most row chunks of a refit Gram term
 
 // Read-only description of X as the kernels see it.
 struct XDesc {
@@ -212,28 +212,54 @@ hipError_t launch_merge_coef(const double* x64, const double* z64, int64_t p, in
 hipError_t launch_sqnorm_add(const double* v, int q, double* acc, hipStream_t s);
 
 // ---- the unpenalised refit on chosen columns (refit.hip)
-// D[a][i] = x~(i, cols[a]) as FP32 for a < m (ldd >= n)
-hipError_t launch_gather_cols(const XDesc& x, const int32_t* cols, int m, float* D, int64_t ldd, hipStream_t s);
-// eta = D b over M columns
-hipError_t launch_refit_eta(const float* D, int64_t ldd, int64_t n, int M, const double* b, double* eta, hipStream_t s);
+// leading dimension of the refit's tall arrays: rows rounded up to 8 (at least 8)
+int64_t refit_ld(int64_t rows);
+// D[a][k] = x~(perm[k], cols[a]) as FP32 for a < m, k < x.n (sorted order), 0 up
+// to ldd >= refit_ld(x.n)
+hipError_t launch_gather_cols(const XDesc& x, const int32_t* cols, int m, const int32_t* perm, float* D, int64_t ldd,
+                              hipStream_t s);
+// D[a][k] = Z[a][perm[k]] for a < q (Z column-major, ldz), 0 past n
+hipError_t launch_gather_z(const float* Z, int64_t ldz, int64_t n, int q, const int32_t* perm, float* D, int64_t ldd,
+                           hipStream_t s);
+// eta[perm[k]] = sum_a D[a][k] b[a] over M columns
+hipError_t launch_refit_eta(const float* D, int64_t ldd, int64_t n, int M, const int32_t* perm, const double* b,
+                            double* eta, hipStream_t s);
 int refit_row_blocks(int64_t n);
-// g = D' r (part: [refit_row_blocks(n)][M] scratch)
-hipError_t launch_refit_grad(const float* D, int64_t ldd, int64_t n, int M, const double* r, double* part, double* g,
-                             hipStream_t s);
-int gram_chunks(int64_t n);
+// g = D' r with r in subject order (rs [n]: r in sorted order, written;
+// part: [refit_row_blocks(n)][M] scratch)
+hipError_t launch_refit_grad(const float* D, int64_t ldd, int64_t n, int M, const int32_t* perm, const double* r,
+                             double* rs, double* part, double* g, hipStream_t s);
+// row chunks of a Gram term over `rows` rows and M columns; risk-set scan chunks
+int gram_chunks(int64_t rows, int M);
+int scan_chunks(int64_t n);
 // H = -Hessian of L in the M coefficients (M x M, row-major) at the risk-set
-// state (w sorted, r in subject order).  wt [n], S [(M + 1) n], part1 and part2
-// [gram_chunks(n)][M][M] scratch.
-hipError_t launch_refit_hessian(const float* D, int64_t ldd, int64_t n, int M, const int32_t* perm,
-                                const int32_t* gstart, const int32_t* gend, const uint8_t* ev, const double* w,
-                                const double* r, double* wt, double* S, double* part1, double* part2, double* H,
-                                hipStream_t s);
+// state (w sorted, r in subject order).  egidx [n]: event group of each sorted
+// position that ends a tie group with events, else -1; egcnt [G]: its events.
+struct RefitHess {
+    const float* D;
+    int64_t ldd, n;
+    int M;
+    const int32_t* perm;
+    const uint8_t* ev;
+    const double* w;
+    const double* r;
+    const int32_t* egidx;
+    const int32_t* egcnt;
+    int64_t G, ldp;
+    double* wt;     // [ldd]
+    double* csum;   // [M + 1][scan_chunks(n)]
+    double* P;      // [M + 1][ldp], ldp >= refit_ld(G)
+    double* wg;     // [ldp]
+    double* part1;  // [gram_chunks(n, M)][M][M]
+    double* part2;  // [gram_chunks(G, M)][M][M]
+    double* H;      // [M][M]
+};
+hipError_t launch_refit_hessian(const RefitHess& h, hipStream_t s);
 // A = L L' in place (lower triangle), ok[0] = 1 if positive definite
 hipError_t launch_chol(double* A, int M, int* ok, hipStream_t s);
 hipError_t launch_chol_solve(const double* L, int M, const double* g, double* x, hipStream_t s);
-// se = sqrt(diag((L L')^{-1})), pval = erfc(|b / se| / sqrt 2); scratch [M][M]
-hipError_t launch_wald(const double* L, int M, const double* b, double* scratch, double* se, double* pval,
-                       hipStream_t s);
+// se = sqrt(diag((L L')^{-1})), pval = erfc(|b / se| / sqrt 2)
+hipError_t launch_wald(const double* L, int M, const double* b, double* se, double* pval, hipStream_t s);
 hipError_t launch_axpy(const double* b, const double* d, double t, int M, double* out, hipStream_t s);
 // entry[j] = first l with path[l][j] != 0 (-1: never), coef[j] = |path[entry[j]][j]|, j < p
 hipError_t launch_entry(const float* path, int L, int64_t ptot, int64_t p, int32_t* entry, float* coef, hipStream_t s);

@@ -97,6 +97,43 @@ def test_refit_covariates_only_and_without_covariates(prob):
     assert L0 == pytest.approx(Lo0, rel=1e-12)
 
 
+def test_refit_spans_several_factor_blocks(prob):
+    """211 coefficients: six full 32-column blocks of the blocked Cholesky and
+    the triangular solves, and a ragged tail of 19; Newton to convergence."""
+    d, Z = prob
+    cox, M = _setup(prob, "fp8")
+    cols = np.sort(np.random.default_rng(31).choice(d.p, 200, replace=False))
+    coef, se, pv, L, it, st = cox.refit(cols, gtol=1e-9)
+    assert st == P.OK and coef.shape == (211,)
+    X32 = M.to_dense64()[cols].astype(np.float32).astype(np.float64)
+    bo, seo, Lo = _oracle_refit(d, Z, X32)
+    assert np.abs(coef - bo).max() <= 1e-7 * np.abs(bo).max()
+    np.testing.assert_allclose(se, seo, rtol=1e-7)
+    assert L == pytest.approx(Lo, rel=1e-12)
+
+
+def test_refit_at_the_column_limit():
+    """COX_MAX_REFIT = 1024 coefficients (1013 SNPs + 11 covariates, 32 full
+    blocks): one Newton step from zero, then the standard errors at the new
+    point, against the oracle taking the same step."""
+    d, Z, _ = coxsim.genotype_problem_with_covariates(4000, 1100, 8, Q, 0.7, 777, days=True)
+    cox, M = device_problem(d, "int8", ldx=4000)
+    Zd = torch.from_numpy(Z).cuda()
+    cox.set_covariates(Zd)
+    cox._keep = Zd
+    cols = np.arange(P.MAX_REFIT - Q)
+    coef, se, pv, L, it, st = cox.refit(cols, max_iter=1, gtol=1e-11)
+    assert st == P.ERR_NOT_CONVERGED and it == 1
+    X32 = M.to_dense64()[cols].astype(np.float32).astype(np.float64)
+    Mo = oracle.Matrix.dense(np.vstack([X32, Z.astype(np.float64)]))
+    bo, cov, ito, conv = oracle.newton(Mo, d.time, d.event, np.arange(Mo.p), maxit=1, gtol=1e-11)
+    assert ito == 1 and not conv
+    assert np.abs(coef - bo).max() <= 1e-7 * np.abs(bo).max()
+    np.testing.assert_allclose(se, np.sqrt(np.diag(cov)), rtol=1e-7)
+    Lo, _ = oracle.loglik(oracle.xbeta(Mo, bo), d.time, d.event)
+    assert L == pytest.approx(Lo, rel=1e-12)
+
+
 def test_refit_from_a_start_and_iteration_cap(prob):
     d, Z = prob
     cox, M = _setup(prob, "int8")
