@@ -287,20 +287,20 @@ __device__ __forceinline__ void load_seg(const double* p, double* o)
 // nullable: 1) for the 64 x 64 output tile (ta, tb), ta <= tb, on the FP64
 // matrix cores (v_mfma_f64_16x16x4f64; per lane A holds (row lane % 16, k
 // lane / 16), B holds (k lane / 16, column lane % 16), D holds rows
-// lane / 16 + 4 v of column lane % 16).  Wavefront wv owns the 16 rows
-// 16 wv .. 16 wv + 15 of the tile and its 4 blocks of 16 columns; in a
-// diagonal tile the blocks left of its own are not stored (the reduction reads
-// the upper triangle).  The rows are taken in steps of 4 GL: lane l loads
+// lane / 16 + 4 v of column lane % 16).  Each of the 4 / SW wavefronts owns
+// SW bands of 16 rows of the tile and its 4 blocks of 16 columns, so a
+// loaded B row serves SW products; in a diagonal tile the blocks left of a
+// band are not stored (the reduction reads the upper triangle).  The rows are taken in steps of 4 GL: lane l loads
 // rows GL q .. GL q + GL - 1 (q = l / 16) of its column straight from
 // memory, and the s-th product of a step puts row GL q + s in k-slot q -- one
 // permutation of the rows, shared by both operands, so every product pairs up
 // as in the plain sum.  The next step's rows are loaded while the current
 // ones are multiplied.  A is column-major (lda a multiple of 8, 0 past the
 // rows, wt likewise); every chunk starts on a multiple of kGR (GL = 4 or 8).
-template <class T, int GL>
-__global__ __launch_bounds__(kT) void gram_kernel(const T* __restrict__ A, int64_t lda, int64_t n, int M,
-                                                  const double* __restrict__ wt, int64_t rows, int ntile,
-                                                  double* __restrict__ part)
+template <class T, int GL, int SW>
+__global__ __launch_bounds__(256 / SW) void gram_kernel(const T* __restrict__ A, int64_t lda, int64_t n, int M,
+                                                        const double* __restrict__ wt, int64_t rows, int ntile,
+                                                        double* __restrict__ part)
 {
     int idx = blockIdx.x, ta = 0;
     while (idx >= ntile - ta) {
@@ -311,17 +311,20 @@ __global__ __launch_bounds__(kT) void gram_kernel(const T* __restrict__ A, int64
     const bool diag = ta == tb;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, c = lane & 15, q = lane >> 4;
     const int64_t r0 = (int64_t)blockIdx.y * rows, r1 = min(n, r0 + rows);
-    const int ca = ta * kGT + wv * 16 + c;
     // columns past M are read from column M - 1: they only reach outputs that
     // are not stored
-    const T* pa = A + (int64_t)min(ca, M - 1) * lda;
+    const T* pa[SW];
+#pragma unroll
+    for (int u = 0; u < SW; ++u) pa[u] = A + (int64_t)min(ta * kGT + (wv * SW + u) * 16 + c, M - 1) * lda;
     const T* pb[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) pb[t] = A + (int64_t)min(tb * kGT + t * 16 + c, M - 1) * lda;
-    v4d acc[4];
+    v4d acc[SW][4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
-    T na[GL], nb[4][GL];
+    for (int u = 0; u < SW; ++u)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[u][t] = v4d{0.0, 0.0, 0.0, 0.0};
+    T na[SW][GL], nb[4][GL];
     double nw[GL];
     // a lane's segment at or past r1 is read at r0 with weight 0 (a segment
     // that starts before r1 ends before lda: r1 <= the rows, lda >= them
@@ -330,7 +333,8 @@ __global__ __launch_bounds__(kT) void gram_kernel(const T* __restrict__ A, int64
         const int64_t k = s0 + GL * q;
         const bool in = k < r1;
         const int64_t kl = in ? k : r0;
-        load_seg<GL>(pa + kl, na);
+#pragma unroll
+        for (int u = 0; u < SW; ++u) load_seg<GL>(pa[u] + kl, na[u]);
 #pragma unroll
         for (int t = 0; t < 4; ++t) load_seg<GL>(pb[t] + kl, nb[t]);
         if (wt)
@@ -343,30 +347,38 @@ __global__ __launch_bounds__(kT) void gram_kernel(const T* __restrict__ A, int64
     };
     if (r0 < r1) fetch(r0);
     for (int64_t s0 = r0; s0 < r1; s0 += 4 * GL) {
-        T cak[GL], cbk[4][GL];
+        T cak[SW][GL], cbk[4][GL];
         double cwk[GL];
 #pragma unroll
         for (int e = 0; e < GL; ++e) {
-            cak[e] = na[e];
             cwk[e] = nw[e];
+#pragma unroll
+            for (int u = 0; u < SW; ++u) cak[u][e] = na[u][e];
 #pragma unroll
             for (int t = 0; t < 4; ++t) cbk[t][e] = nb[t][e];
         }
         if (s0 + 4 * GL < r1) fetch(s0 + 4 * GL);
 #pragma unroll
         for (int e = 0; e < GL; ++e) {
-            const double av = (double)cak[e] * cwk[e];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) acc[t] = mfma_f64(av, (double)cbk[t][e], acc[t]);
+            for (int u = 0; u < SW; ++u) {
+                const double av = (double)cak[u][e] * cwk[e];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) acc[u][t] = mfma_f64(av, (double)cbk[t][e], acc[u][t]);
+            }
         }
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        if (diag && t < wv) continue;  // below the diagonal: the reduction reads the mirror
+    for (int u = 0; u < SW; ++u) {
+        const int band = wv * SW + u;  // 16-row band of the tile
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int a = ta * kGT + wv * 16 + q + 4 * v, b = tb * kGT + t * 16 + c;
-            if (a < M && b < M) part[((int64_t)blockIdx.y * M + a) * M + b] = acc[t][v];
+        for (int t = 0; t < 4; ++t) {
+            if (diag && t < band) continue;  // below the diagonal: the reduction reads the mirror
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int a = ta * kGT + band * 16 + q + 4 * v, b = tb * kGT + t * 16 + c;
+                if (a < M && b < M) part[((int64_t)blockIdx.y * M + a) * M + b] = acc[u][t][v];
+            }
         }
     }
 }
@@ -690,7 +702,9 @@ hipError_t launch_refit_grad(const float* D, int64_t ldd, int64_t n, int M, cons
 int gram_chunks(int64_t rows, int M)
 {
     const int ntile = (M + kGT - 1) / kGT, npair = ntile * (ntile + 1) / 2;
-    const int want = (1024 + npair - 1) / npair;  // about 4 workgroups per compute unit
+    // at most 1024 workgroups, resident in one round: the FP32 term's are one
+    // wavefront at one per SIMD, the FP64 term's two at two per SIMD
+    const int want = max(1, 1024 / npair);
     const int64_t cap = max((int64_t)1, rows / 1024);
     return (int)max((int64_t)1, min((int64_t)min(want, kGramChunks), cap));
 }
@@ -707,14 +721,14 @@ hipError_t launch_refit_hessian(const RefitHess& h, hipStream_t s)
     const int nc1 = gram_chunks(h.n, M), nc2 = gram_chunks(h.G, M), nch = scan_chunks(h.n);
     hipLaunchKernelGGL(hess_weight_kernel, dim3(grid_for(h.ldd)), dim3(kT), 0, s, h.perm, h.ev, h.r, h.n, h.ldd,
                        h.wt);
-    hipLaunchKernelGGL((gram_kernel<float, 8>), dim3(npair, nc1), dim3(kT), 0, s, h.D, h.ldd, h.n, M, h.wt,
+    hipLaunchKernelGGL((gram_kernel<float, 8, 4>), dim3(npair, nc1), dim3(kT / 4), 0, s, h.D, h.ldd, h.n, M, h.wt,
                        gram_rows(h.n, nc1), ntile, h.part1);
     hipLaunchKernelGGL(chunk_sum_kernel, dim3(nch, M + 1), dim3(kT), 0, s, h.D, h.ldd, h.n, M, h.w, nch, h.csum);
     hipLaunchKernelGGL(scan_p_kernel, dim3(nch, M + 1), dim3(kT), 0, s, h.D, h.ldd, h.n, M, h.w, h.csum, nch, h.egidx,
                        h.G, h.ldp, h.P);
     hipLaunchKernelGGL(event_weight_kernel, dim3(grid_for(h.ldp)), dim3(kT), 0, s, h.P + (int64_t)M * h.ldp, h.egcnt,
                        h.G, h.ldp, h.wg);
-    hipLaunchKernelGGL((gram_kernel<double, 4>), dim3(npair, nc2), dim3(kT), 0, s, h.P, h.ldp, h.G, M, h.wg,
+    hipLaunchKernelGGL((gram_kernel<double, 4, 2>), dim3(npair, nc2), dim3(kT / 2), 0, s, h.P, h.ldp, h.G, M, h.wg,
                        gram_rows(h.G, nc2), ntile, h.part2);
     hipLaunchKernelGGL(gram_reduce_kernel, dim3(grid_for((int64_t)M * M)), dim3(kT), 0, s, h.part1, nc1, h.part2,
                        nc2, M, h.H);
