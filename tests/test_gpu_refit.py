@@ -134,6 +134,49 @@ def test_refit_at_the_column_limit():
     assert L == pytest.approx(Lo, rel=1e-12)
 
 
+def _dense_cox(X, time, event):
+    Xd = torch.from_numpy(X).cuda()
+    cox = P.Cox(Xd, time, event, n=X.shape[1])
+    cox._keep = Xd
+    return cox
+
+
+def test_refit_one_tie_group():
+    """Every subject at the same time: one tie group, so the second Hessian
+    term has a single row (the whole cohort's risk-set sums)."""
+    rng = np.random.default_rng(8)
+    n, p = 2000, 6
+    X = rng.standard_normal((p, n)).astype(np.float32)
+    time = np.full(n, 5.0)
+    event = (rng.random(n) < 0.4).astype(np.int32)
+    cox = _dense_cox(X, time, event)
+    coef, se, pv, L, it, st = cox.refit(np.arange(p), gtol=1e-10)
+    assert st == P.OK
+    Mo = oracle.Matrix.dense(X.astype(np.float64))
+    bo, cov, _, conv = oracle.newton(Mo, time, event, np.arange(p), gtol=1e-11, maxit=100)
+    assert conv
+    np.testing.assert_allclose(coef, bo, rtol=1e-8, atol=1e-10)
+    np.testing.assert_allclose(se, np.sqrt(np.diag(cov)), rtol=1e-8)
+    # the closed form of the tied score at the solution: sum over events of x_i
+    # minus d times the exp-weighted mean of x over everyone
+    eta = X.astype(np.float64).T @ coef
+    wgt = np.exp(eta - eta.max())
+    score = X[:, event == 1].astype(np.float64).sum(axis=1) - event.sum() * (X.astype(np.float64) @ wgt) / wgt.sum()
+    assert np.abs(score).max() <= 1e-8
+
+
+def test_refit_without_events_is_not_positive_definite():
+    """No events: no event groups (an empty second term) and a zero first
+    term, so the information matrix is 0 and the factorisation reports it."""
+    rng = np.random.default_rng(9)
+    n, p = 700, 4
+    X = rng.standard_normal((p, n)).astype(np.float32)
+    cox = _dense_cox(X, rng.random(n), np.zeros(n, np.int32))
+    with pytest.raises(P.CoxError) as ei:
+        cox.refit(np.arange(p))
+    assert ei.value.status == P.ERR_NUMERIC
+
+
 def test_refit_from_a_start_and_iteration_cap(prob):
     d, Z = prob
     cox, M = _setup(prob, "int8")
