@@ -10,11 +10,12 @@
 //   W X'   (r x m)  nmf_wxt_kernel: workgroups over (256 rows of X, a split of
 //                   the columns); the 256 x 32 X tile and the r x 32 W tile of a
 //                   step pass through LDS into FP64 matrix-core tiles, the next
-//                   step's tiles loading into registers meanwhile.  The split
-//                   partials are added by nmf_reduce_kernel.
+//                   step's tiles loading into registers meanwhile (with aligned
+//                   rows, nmf_wxt_direct_kernel loads them straight into
+//                   registers).  The split partials are added by nmf_reduce_kernel.
 //   W W'   (r x r)  nmf_gram_kernel, one workgroup per entry of the upper
 //                   triangle, fixed-order reduction.
-//   V' <- update    nmf_update_kernel, one thread per column of V': the r x r
+//   V' <- update    nmf_update_kernel, 4 threads per column of V': the r x r
 //                   product with W W', then the multiplicative update
 //                   V .* (X W') ./ (V W W' + eps) or the projected step
 //                   max(0, V - sigma (V W W' - X W')), sigma = 1/(2||W W'||_F^2 + eps).
@@ -232,6 +233,111 @@ __global__ __launch_bounds__(kT) void nmf_vtx_kernel(const float* __restrict__ X
             }
 }
 
+// W X' with both operands loaded straight from memory into registers, no
+// LDS: used when the rows of X start 16-byte aligned (X aligned, ldx a
+// multiple of 4) and so do the rows of W (aligned, n even), as at the paper's
+// 10,000 x 10,000; otherwise the kernel above.  Each lane loads GL
+// consecutive columns, and the s-th product of a step puts column GL q + s of
+// the step in k-slot q (q = lane / 16) -- one permutation shared by both
+// operands, so the products pair up as in the plain sum.  The next step's
+// values load while the current ones are multiplied.  (The same form of V' X,
+// with 16-byte pieces of 4 columns per row, measured slower than the LDS
+// kernel: 0.19 against 0.15 ms at 10,000 x 10,000, r = 20.)
+
+// part[split][a][i] = sum over the split's columns j of W[a][j] X[i][j].  A
+// wavefront owns 64 rows of X (4 N tiles) and all MT rank tiles; a step covers
+// 4 GL columns; lane (c, q) reads columns js + GL q .. + GL - 1 of X row
+// ib + 16 nt + c and of W row 16 mt + c.  Rows of X past m are read from row
+// m - 1 (their outputs are not stored), W rows past r and columns past the
+// split give 0.
+template <int MT, int GL>
+__global__ __launch_bounds__(kT) void nmf_wxt_direct_kernel(const float* __restrict__ X, int64_t m, int64_t n,
+                                                            int64_t ldx, int r, const double* __restrict__ W,
+                                                            int64_t cols, double* __restrict__ part)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, c = lane & 15, q = lane >> 4;
+    const int64_t ib = (int64_t)blockIdx.x * kT + wid * 64;
+    const int64_t j0 = (int64_t)blockIdx.y * cols, j1 = min(n, j0 + cols);
+    const float* xr[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) xr[nt] = X + min(ib + nt * 16 + c, m - 1) * ldx;
+    const double* wr[MT];
+    bool wok[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const int a = mt * 16 + c;
+        wok[mt] = a < r;
+        wr[mt] = W + (int64_t)min(a, r - 1) * n;
+    }
+    v4d acc[MT][4];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = v4d{0.0, 0.0, 0.0, 0.0};
+    float nx[4][GL];
+    double nw[MT][GL];
+    auto fetch = [&](int64_t js) {
+        const int64_t j = js + GL * q;
+        if (js + 4 * GL <= j1) {
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                for (int e = 0; e < GL; e += 4) {
+                    const float4 v = *reinterpret_cast<const float4*>(xr[nt] + j + e);
+                    nx[nt][e] = v.x, nx[nt][e + 1] = v.y, nx[nt][e + 2] = v.z, nx[nt][e + 3] = v.w;
+                }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int e = 0; e < GL; e += 2) {
+                    const double2 v = wok[mt] ? *reinterpret_cast<const double2*>(wr[mt] + j + e) : double2{0.0, 0.0};
+                    nw[mt][e] = v.x, nw[mt][e + 1] = v.y;
+                }
+        } else {
+#pragma unroll
+            for (int e = 0; e < GL; ++e) {
+                const bool in = j + e < j1;
+                const int64_t jc = in ? j + e : j0;
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) nx[nt][e] = xr[nt][jc];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) nw[mt][e] = (in && wok[mt]) ? wr[mt][jc] : 0.0;
+            }
+        }
+    };
+    if (j0 < j1) fetch(j0);
+    for (int64_t js = j0; js < j1; js += 4 * GL) {
+        float cx[4][GL];
+        double cw[MT][GL];
+#pragma unroll
+        for (int e = 0; e < GL; ++e) {
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) cx[nt][e] = nx[nt][e];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) cw[mt][e] = nw[mt][e];
+        }
+        if (js + 4 * GL < j1) fetch(js + 4 * GL);
+#pragma unroll
+        for (int e = 0; e < GL; ++e)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const double b = (double)cx[nt][e];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) acc[mt][nt] = mfma_f64(cw[mt][e], b, acc[mt][nt]);
+            }
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int a = mt * 16 + q + 4 * v;
+                const int64_t i = ib + nt * 16 + c;
+                if (a < r && i < m) part[((int64_t)blockIdx.y * r + a) * m + i] = acc[mt][nt][v];
+            }
+}
+
 // num[t] = sum over splits of part[split][t], t < r * len, in split order
 __global__ __launch_bounds__(kT) void nmf_reduce_kernel(const double* __restrict__ part, int nsplit, int64_t count,
                                                         double* __restrict__ num)
@@ -263,40 +369,47 @@ __global__ __launch_bounds__(kT) void nmf_gram_kernel(const double* __restrict__
     }
 }
 
-// One factor's update, one thread per column k of F (r x len):
+// One factor's update, kUP threads per column k of F (r x len), thread p
+// taking the rows a = p, p + kUP, ...:
 //   num[a][k]                                (X W' or V' X, the split sums)
 //   den = (G F)[a][k]                        (W W' V' or V' V W)
 //   multiplicative: F <- F num / (den + eps); APG: F <- max(0, F - step (den - num)),
 //   step = 1 / (2 ||G||_F^2 + eps)
+// Every old value of the workgroup's columns is read before any is written.
+constexpr int kUC = 64;         // columns per workgroup of the update
+constexpr int kUP = kT / kUC;   // threads per column
 template <int R>
 __global__ __launch_bounds__(kT) void nmf_update_kernel(double* __restrict__ F, int r, int64_t len,
                                                         const double* __restrict__ num_, const double* __restrict__ G,
                                                         int algo, double eps)
 {
     __shared__ double Gs[R * R];
-    __shared__ double step;
+    __shared__ double sh[kT / kWave];
     for (int q = threadIdx.x; q < R * R; q += kT) {
         const int a = q / R, b = q % R;
         Gs[q] = (a < r && b < r) ? G[a * r + b] : 0.0;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int q = 0; q < r * r; ++q) s += G[q] * G[q];
-        step = 1.0 / (2.0 * s + eps);
+    double step = 0.0;
+    if (algo == 1) {
+        double s2 = 0.0;
+        for (int q = threadIdx.x; q < R * R; q += kT) s2 += Gs[q] * Gs[q];
+        step = 1.0 / (2.0 * block_sum256(s2, sh) + eps);
     }
-    __syncthreads();
-    const int64_t k = (int64_t)blockIdx.x * kT + threadIdx.x;
-    if (k >= len) return;
+    const int p = threadIdx.x / kUC;
+    const int64_t k = (int64_t)blockIdx.x * kUC + threadIdx.x % kUC;
+    const bool live = k < len;
     double old[R];
 #pragma unroll
-    for (int a = 0; a < R; ++a) old[a] = a < r ? F[(int64_t)a * len + k] : 0.0;
-    for (int a = 0; a < r; ++a) {
+    for (int a = 0; a < R; ++a) old[a] = (live && a < r) ? F[(int64_t)a * len + k] : 0.0;
+    __syncthreads();
+    if (!live) return;
+    for (int a = p; a < r; a += kUP) {
         const double num = num_[(int64_t)a * len + k];
         double den = 0.0;
 #pragma unroll
         for (int b = 0; b < R; ++b) den += Gs[a * R + b] * old[b];
-        // F[a][k] itself is still the old value: rows a' < a only have been written
+        // only this thread writes row a of column k, so F[a][k] is still the old value
         const double oa = F[(int64_t)a * len + k];
         F[(int64_t)a * len + k] = algo == 0 ? oa * num / (den + eps) : fmax(0.0, oa - step * (den - num));
     }
@@ -425,6 +538,16 @@ void nmark(nmf_ctx* c, int ph)
 }
 
 // V'X split partials and V'V of the current V'
+// the rows of X and of W start 16-byte aligned: W X' loads straight from memory
+bool nmf_direct(const nmf_ctx* c, const double* W)
+{
+    return reinterpret_cast<uintptr_t>(c->X) % 16 == 0 && c->ldx % 4 == 0 && c->n % 2 == 0 &&
+           reinterpret_cast<uintptr_t>(W) % 16 == 0;
+}
+
+// columns per lane in a step of the direct W X' pass
+constexpr int direct_gl(int R) { return R <= 16 ? 8 : 4; }
+
 template <int R>
 void nmf_vtx_gram(nmf_ctx* c, const double* Vt)
 {
@@ -446,18 +569,22 @@ hipError_t nmf_iteration(nmf_ctx* c, int algo, double eps, double* Vt, double* W
     const int r = c->r;
     const unsigned gm = (unsigned)((c->m + kT - 1) / kT), gn = (unsigned)((c->n + kT - 1) / kT);
     nmark(c, 0);
-    hipLaunchKernelGGL((nmf_wxt_kernel<R / 16>), dim3(gm, c->ns_wxt), dim3(kT), 0, c->stream, c->X, c->m, c->n,
-                       c->ldx, r, W, c->cols, c->part);
+    if (nmf_direct(c, W))
+        hipLaunchKernelGGL((nmf_wxt_direct_kernel<R / 16, direct_gl(R)>), dim3(gm, c->ns_wxt), dim3(kT), 0, c->stream,
+                           c->X, c->m, c->n, c->ldx, r, W, c->cols, c->part);
+    else
+        hipLaunchKernelGGL((nmf_wxt_kernel<R / 16>), dim3(gm, c->ns_wxt), dim3(kT), 0, c->stream, c->X, c->m, c->n,
+                           c->ldx, r, W, c->cols, c->part);
     nmark(c, 0);
     hipLaunchKernelGGL(nmf_reduce_kernel, dim3(grid_for((int64_t)r * c->m)), dim3(kT), 0, c->stream, c->part,
                        c->ns_wxt, (int64_t)r * c->m, c->num);
     hipLaunchKernelGGL(nmf_gram_kernel, dim3((unsigned)(r * (r + 1) / 2)), dim3(kT), 0, c->stream, W, r, c->n,
                        c->WWt);
-    hipLaunchKernelGGL((nmf_update_kernel<R>), dim3(gm), dim3(kT), 0, c->stream, Vt, r, c->m, c->num, c->WWt, algo,
-                       eps);
+    hipLaunchKernelGGL((nmf_update_kernel<R>), dim3((unsigned)((c->m + kUC - 1) / kUC)), dim3(kT), 0, c->stream, Vt, r,
+                       c->m, c->num, c->WWt, algo, eps);
     nmf_vtx_gram<R>(c, Vt);
-    hipLaunchKernelGGL((nmf_update_kernel<R>), dim3(gn), dim3(kT), 0, c->stream, W, r, c->n, c->num, c->VtV, algo,
-                       eps);
+    hipLaunchKernelGGL((nmf_update_kernel<R>), dim3((unsigned)((c->n + kUC - 1) / kUC)), dim3(kT), 0, c->stream, W, r,
+                       c->n, c->num, c->VtV, algo, eps);
     return hipGetLastError();
 }
 

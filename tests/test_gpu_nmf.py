@@ -38,11 +38,20 @@ def _rel(a, b):
     return np.abs(a - b).max() / np.abs(b).max()
 
 
+# (n, row padding): 777 + 5 leaves rows of X unaligned, so the passes stage
+# through LDS; 778 + 2 gives 16-byte-aligned rows and even factor lengths,
+# so they load straight from memory, with a ragged last step in both
+# directions (m = 1000 rows, 778 columns)
+LAYOUTS = {"lds": (777, 5), "direct": (778, 2)}
+
+
+@pytest.mark.parametrize("layout", sorted(LAYOUTS))
 @pytest.mark.parametrize("r", [5, 20, 40, 60])
 @pytest.mark.parametrize("algo", [P.NMF_MULTIPLICATIVE, P.NMF_APG])
-def test_nmf_matches_oracle(r, algo):
-    m, n, K = 1000, 777, 20
-    X, Vt0, W0, Xd = _data(m, n, r, 10 + r, pad=5)
+def test_nmf_matches_oracle(r, algo, layout):
+    m, K = 1000, 20
+    n, pad = LAYOUTS[layout]
+    X, Vt0, W0, Xd = _data(m, n, r, 10 + r, pad=pad)
     nmf = P.NMF(Xd, r, n=n)
     Vt = torch.from_numpy(Vt0).cuda()
     W = torch.from_numpy(W0).cuda()
