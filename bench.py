@@ -480,7 +480,9 @@ def bench_nmf(args):
     elapsed = t1 - t0
     # per pass over X: X once (4mn bytes), the factor tile reads and the split partials
     kms = max(w_ms / max(w_n, 1), v_ms / max(v_n, 1))
-    kname = "nmf_wxt_kernel (W X')" if w_ms / max(w_n, 1) >= v_ms / max(v_n, 1) else "nmf_vtx_kernel (V' X)"
+    wxt_name = ("the W X' pass (nmf_wxt_direct_kernel when the rows of X and W are 16-byte aligned, "
+                "else nmf_wxt_kernel)")
+    kname = wxt_name if w_ms / max(w_n, 1) >= v_ms / max(v_n, 1) else "nmf_vtx_kernel (V' X)"
     nbytes = 4.0 * m * n
     flops = 2.0 * m * n * r
     gbs = nbytes / (kms / 1e3) / 1e9
