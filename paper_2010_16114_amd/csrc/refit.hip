@@ -136,13 +136,13 @@ __global__ void hess_weight_kernel(const int32_t* __restrict__ perm, const uint8
 
 constexpr int kScanJ = kScanChunk / (4 * kT);  // sub-blocks of 4 kT positions in a scan chunk
 
-// v[j][e] = w[k] D[a][k] (or w[k] with Dcol null), u[j][e] = w[k] and
-// g[j][e] = egidx[k] (when egidx is given) at position k = k0 + 4 kT j + 4 t
-// + e of thread t: consecutive threads read consecutive 16-byte pieces.  0
-// (and g = -1) at or past n.  k0 is a multiple of 4 kT, ldd of 8.
+// v[j][e] = w[k] D[a][k] (or w[k] with Dcol null) and g[j][e] = egidx[k]
+// (when egidx is given) at position k = k0 + 4 kT j + 4 t + e of thread t:
+// consecutive threads read consecutive 16-byte pieces.  0 (and g = -1) at or
+// past n.  k0 is a multiple of 4 kT, ldd of 8.
 __device__ __forceinline__ void scan_load(const float* __restrict__ Dcol, const double* __restrict__ w,
                                           const int32_t* __restrict__ egidx, int64_t k0, int64_t n,
-                                          double (*v)[4], double (*u)[4], int32_t (*g)[4])
+                                          double (*v)[4], int32_t (*g)[4])
 {
 #pragma unroll
     for (int j = 0; j < kScanJ; ++j) {
@@ -150,14 +150,10 @@ __device__ __forceinline__ void scan_load(const float* __restrict__ Dcol, const 
         if (kb + 4 <= n) {
             const double2 x0 = *reinterpret_cast<const double2*>(w + kb);
             const double2 x1 = *reinterpret_cast<const double2*>(w + kb + 2);
-            u[j][0] = x0.x, u[j][1] = x0.y, u[j][2] = x1.x, u[j][3] = x1.y;
+            v[j][0] = x0.x, v[j][1] = x0.y, v[j][2] = x1.x, v[j][3] = x1.y;
             if (Dcol) {
                 const float4 d = *reinterpret_cast<const float4*>(Dcol + kb);
-                v[j][0] = u[j][0] * (double)d.x, v[j][1] = u[j][1] * (double)d.y;
-                v[j][2] = u[j][2] * (double)d.z, v[j][3] = u[j][3] * (double)d.w;
-            } else {
-#pragma unroll
-                for (int e = 0; e < 4; ++e) v[j][e] = u[j][e];
+                v[j][0] *= (double)d.x, v[j][1] *= (double)d.y, v[j][2] *= (double)d.z, v[j][3] *= (double)d.w;
             }
             if (egidx) {
                 const int4 q = *reinterpret_cast<const int4*>(egidx + kb);
@@ -167,8 +163,7 @@ __device__ __forceinline__ void scan_load(const float* __restrict__ Dcol, const 
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int64_t k = kb + e;
-                u[j][e] = k < n ? w[k] : 0.0;
-                v[j][e] = k < n ? (Dcol ? u[j][e] * (double)Dcol[k] : u[j][e]) : 0.0;
+                v[j][e] = k < n ? (Dcol ? w[k] * (double)Dcol[k] : w[k]) : 0.0;
                 if (egidx) g[j][e] = k < n ? egidx[k] : -1;
             }
         }
@@ -183,8 +178,8 @@ __global__ __launch_bounds__(kT) void chunk_sum_kernel(const float* __restrict__
 {
     __shared__ double sh[kT / kWave];
     const int ch = blockIdx.x, a = blockIdx.y;
-    double v[kScanJ][4], u[kScanJ][4];
-    scan_load(a < M ? D + (int64_t)a * ldd : nullptr, w, nullptr, (int64_t)ch * kScanChunk, n, v, u, nullptr);
+    double v[kScanJ][4];
+    scan_load(a < M ? D + (int64_t)a * ldd : nullptr, w, nullptr, (int64_t)ch * kScanChunk, n, v, nullptr);
     double s = 0.0;
 #pragma unroll
     for (int j = 0; j < kScanJ; ++j)
@@ -212,9 +207,9 @@ __global__ __launch_bounds__(kT) void scan_p_kernel(const float* __restrict__ D,
     const int ch = blockIdx.x, a = blockIdx.y;
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     const int64_t k0 = (int64_t)ch * kScanChunk;
-    double v[kScanJ][4], u[kScanJ][4];
+    double v[kScanJ][4];
     int32_t g[kScanJ][4];
-    scan_load(a < M ? D + (int64_t)a * ldd : nullptr, w, egidx, k0, n, v, u, g);
+    scan_load(a < M ? D + (int64_t)a * ldd : nullptr, w, egidx, k0, n, v, g);
     double cv = 0.0;
     for (int c = threadIdx.x; c < ch; c += kT) cv += csum[(int64_t)a * nch + c];
     cv = block_sum256(cv, sh);
