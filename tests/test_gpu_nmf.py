@@ -78,11 +78,12 @@ def test_objective_without_iterations_and_continuation():
     assert f == pytest.approx(tr[-1], rel=OBJ_TOL)
 
 
-def test_full_size_10000_square():
-    """The paper's GPU shape, 10,000 x 10,000 at r = 20: two iterations of each
-    algorithm against the oracle, every entry of both factors."""
+@pytest.mark.parametrize("r", [20, 60])
+def test_full_size_10000_square(r):
+    """The paper's GPU shape, 10,000 x 10,000 at r = 20 and 60 (the largest of
+    its ranks): two iterations of each algorithm against the oracle, every
+    entry of both factors."""
     m = n = 10000
-    r = 20
     X, Vt0, W0, Xd = _data(m, n, r, 77)
     nmf = P.NMF(Xd, r)
     for algo in (P.NMF_MULTIPLICATIVE, P.NMF_APG):
