@@ -197,12 +197,19 @@ __global__ __launch_bounds__(kT) void eta_update_kernel(XDesc x, const int32_t* 
     }
 }
 
+// Concatenates the per-block change lists in block order: sel = the idx[blk]
+// entries, cnt[blk] of them, for blk = 0, 1, ...; *nsel = their number.  One
+// workgroup; per round of 1024 blocks each thread scans one block's count,
+// then groups of kGemvtCols lanes copy whole blocks, one entry per lane.
 __global__ __launch_bounds__(1024) void compact_kernel(const int32_t* __restrict__ cnt,
                                                        const int32_t* __restrict__ idx, int nblk,
                                                        int32_t* __restrict__ sel, int32_t* __restrict__ nsel)
 {
+    static_assert(1024 % kGemvtCols == 0 && kGemvtCols <= 64, "lane groups tile the workgroup");
     __shared__ int sh[17];
+    __shared__ int sstart[1024], scnt[1024];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int grp = threadIdx.x / kGemvtCols, q = threadIdx.x % kGemvtCols;
     int carry = 0;
     for (int base = 0; base < nblk; base += 1024) {
         const int blk = base + threadIdx.x;
@@ -227,9 +234,12 @@ __global__ __launch_bounds__(1024) void compact_kernel(const int32_t* __restrict
             if (lane == 15) sh[16] = ti;
         }
         __syncthreads();
-        const int ex = sh[wid] + inc - c;
+        sstart[threadIdx.x] = carry + sh[wid] + inc - c;
+        scnt[threadIdx.x] = c;
         const int tot = sh[16];
-        for (int q = 0; q < c; ++q) sel[carry + ex + q] = idx[(int64_t)blk * kGemvtCols + q];
+        __syncthreads();
+        for (int bb = grp; bb < 1024; bb += 1024 / kGemvtCols)
+            if (q < scnt[bb]) sel[sstart[bb] + q] = idx[(int64_t)(base + bb) * kGemvtCols + q];
         carry += tot;
         __syncthreads();
     }
