@@ -37,7 +37,10 @@ def _setup(prob, storage, B):
     return device_problem(prob, storage, ldx=ldx, max_batch=B)
 
 
-@pytest.mark.parametrize("storage,B", [("int8", 64), ("fp8", 64), ("int8", 20), ("fp8", 33)])
+# B = 9: the smallest batch on the matrix cores (one 16-wide group, 7 padded);
+# 49: four groups with a partial last one
+@pytest.mark.parametrize("storage,B", [("int8", 64), ("fp8", 64), ("int8", 20), ("fp8", 33), ("int8", 9),
+                                       ("fp8", 49)])
 def test_batched_fit_matches_oracle(prob, storage, B):
     cox, M = _setup(prob, storage, B)
     lm = oracle.lambda_max(M, prob.time, prob.event)
