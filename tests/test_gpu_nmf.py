@@ -110,3 +110,22 @@ def test_nmf_argument_checks():
     with pytest.raises(P.CoxError) as ei:
         nmf.run(Vt, W, P.NMF_APG, 1, eps=-1.0)
     assert ei.value.status == P.ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("layout", sorted(LAYOUTS))
+def test_nmf_is_deterministic(layout):
+    """The split partials are added in a fixed order: two runs from the same
+    start agree bit for bit."""
+    m, r = 1000, 20
+    n, pad = LAYOUTS[layout]
+    X, Vt0, W0, Xd = _data(m, n, r, 404, pad=pad)
+    nmf = P.NMF(Xd, r, n=n)
+    out = []
+    for _ in range(2):
+        Vt = torch.from_numpy(Vt0).cuda()
+        W = torch.from_numpy(W0).cuda()
+        f = nmf.run(Vt, W, P.NMF_APG, 10)
+        out.append((Vt.cpu().numpy(), W.cpu().numpy(), f))
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+    assert out[0][2] == out[1][2]

@@ -257,3 +257,15 @@ def test_section6_protocol_end_to_end(prob):
     print(f"{order.size} SNPs entered; {keep.size} pass Bonferroni; strong causal {list(strong)} -> kept "
           f"{sorted(set(strong) & set(keep))}")
     assert set(strong) <= set(keep)
+
+
+def test_refit_is_deterministic(prob):
+    """Every sum of the refit runs in a fixed order: two calls agree bit for bit."""
+    d, Z = prob
+    cox, M = _setup(prob, "fp8")
+    cols = np.sort(np.random.default_rng(5).choice(d.p, 90, replace=False))
+    first = cox.refit(cols, gtol=1e-9)
+    second = cox.refit(cols, gtol=1e-9)
+    for a, b in zip(first[:3], second[:3]):
+        np.testing.assert_array_equal(a, b)
+    assert first[3] == second[3] and first[4] == second[4]
