@@ -134,7 +134,9 @@ cox_status cox_prox_step(cox_ctx *ctx, float *beta, int32_t B, const double *lam
                          double *obj_before);
 
 /* Apply the soft-threshold update alone (the elementwise kernel), given a
- * gradient of the negative log likelihood:
+ * gradient of the negative log likelihood.  This is the proximal half of the
+ * iteration of Section 5.3 with the soft-thresholding operator of Section 4.2
+ * (threshold step * lambda, as in cox_prox_step):
  *   beta_bj <- S_{step*lambda_b*pf_j}(beta_bj - step * grad_bj)
  *   beta dev [B][ptot] in/out; grad dev [B][ptot]; lambdas host [B] >= 0; step > 0. */
 cox_status cox_prox_apply(cox_ctx *ctx, float *beta, const float *grad, int32_t B, const double *lambdas,
@@ -146,6 +148,16 @@ typedef struct {
     int32_t lag;        /* 1..32; the paper uses 10 */
     double step;        /* > 0: sigma; <= 0: 1 / (2 ||X~||_2^2) from cox_opnorm2 (Section 5.3) */
     int32_t warm_start; /* 1: start from the beta passed in; 0: start from beta = 0 */
+    int32_t persistent; /* 0: one launch per phase of each step, the host checking the stopping flags
+                           every `poll` steps; 1: the whole call -- every step of every b, the stopping
+                           rule included -- in one persistent (cooperative) launch with grid-wide
+                           barriers between the phases.  persistent = 1 serves the vector path
+                           (B <= 8, eta_mode 0, no covariates); other requests with persistent = 1
+                           return UNSUPPORTED.  Both forms take the same steps in the same arithmetic
+                           and give bit-identical results. */
+    int32_t deterministic; /* 0 or 1.  Results are always bit-reproducible run to run (fixed-order
+                              reductions, no floating-point atomics), so both values give the same
+                              computation; 1 documents the requirement. */
     int32_t eta_mode;   /* 0: eta updated from the columns whose beta changed (FP64 accumulator);
                            1: eta recomputed by a dense pass over X every step (two X passes) */
     int32_t poll;       /* steps between host checks of the convergence flags; <= 0: 16 */
@@ -155,6 +167,9 @@ typedef struct {
                               limbs (default); 14: two limbs, a third less limb traffic and
                               matrix-core work at about 2^-15 relative rounding of r.  Other
                               values are INVALID_ARG. */
+    double *trace;      /* host [B][max_iter + 1] or NULL: trace[b*(max_iter+1) + k] = f_lambda_b(beta_k),
+                           the objective at step k of b as the stopping rule saw it, for k = 0..k_b;
+                           entries past k_b are NaN */
 } cox_fit_opts;
 
 /* Solve B problems (one per lambda_b) by ISTA, all sharing each pass over X.
@@ -163,7 +178,8 @@ typedef struct {
  * k >= lag and |f_k - f_{k-lag}| / (|f_k| + 1) < tol, or at k = max_iter; else
  * beta_{k+1,j} = S_{sigma lambda_b pf_j}(beta_kj + sigma ([X~ Z]' r)_j).
  *   lambdas host [B] >= 0; opts host (NULL: max_iter 1000, tol 1e-5, lag 10,
- *           step from cox_opnorm2, cold start, eta_mode 0, poll 16)
+ *           step from cox_opnorm2, cold start, not persistent, eta_mode 0, poll 16,
+ *           no trace)
  *   beta  dev [B][ptot] float: the start if warm_start, and the result beta_{k_b}
  *   iters host [B] or NULL: k_b, the number of steps taken
  *   obj   host [B] or NULL: f_lambda_b(beta_{k_b})
@@ -173,7 +189,11 @@ cox_status cox_fit_path(cox_ctx *ctx, const double *lambdas, int32_t B, const co
                         int32_t *iters, double *obj);
 
 /* lambda_max: the smallest lambda at which every penalised coefficient is zero
- * at the optimum.  With no unpenalised column it is max_j |(X~' r(0))_j| / pf_j,
+ * at the optimum (the top of Section 6's lambda grid; from the optimality
+ * condition of the objective of Section 5.3, beta = 0 is optimal exactly when
+ * |(X~' r(0))_j| <= lambda pf_j for every j, with r(0) the residual
+ * (I - P) delta of Section 5.3 at beta = 0).  With no unpenalised column it is
+ * max_j |(X~' r(0))_j| / pf_j,
  * where at beta = 0 every w_i = 1 and r is delta minus the Breslow cumulative
  * hazard.  When some covariates have pf = 0 it is the same maximum over the
  * penalised columns at the unpenalised optimum over those covariates (every
@@ -198,7 +218,8 @@ cox_status cox_opnorm2(cox_ctx *ctx, double tol, int32_t maxiter, uint64_t seed,
  * solved to the stopping rule from the previous lambda's solution.
  *   lambdas   host [L] >= 0, in the order solved (typically decreasing)
  *   opts      as cox_fit_path (NULL: its defaults); a step <= 0 is computed once
- *             for the whole sequence.  warm_start applies to the first lambda.
+ *             for the whole sequence.  warm_start applies to the first lambda;
+ *             a trace, when given, is host [L][max_iter + 1], row l for lambdas[l].
  *   beta_path dev [L][ptot] float: row l is the solution at lambdas[l] (row 0 is
  *             also the start when warm_start)
  *   iters, obj host [L] or NULL: steps taken and final objective per lambda

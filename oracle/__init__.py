@@ -56,6 +56,7 @@ def _load():
     lib.cox_oracle_opnorm2.argtypes = mat + [dbl, i32, u64, vp, vp]
     lib.cox_oracle_fit.argtypes = mat + [vp, vp, dbl, dbl, i32, dbl, i32, vp, vp, vp]
     lib.cox_oracle_fit_pf.argtypes = mat + [vp, vp, dbl, vp, dbl, i32, dbl, i32, vp, vp, vp]
+    lib.cox_oracle_fit_hist.argtypes = mat + [vp, vp, dbl, dbl, i32, dbl, i32, vp, vp, vp, vp]
     lib.cox_oracle_newton.argtypes = mat + [vp, vp, vp, i64, vp, vp, i32, dbl, vp, vp]
     lib.cox_oracle_lambda_max_pf.argtypes = mat + [vp, vp, vp, dbl, vp, vp]
     lib.nmf_oracle_objective.argtypes = [vp, i64, i64, i64, i32, vp, vp]
@@ -220,6 +221,24 @@ def fit(X: Matrix, time, event, lam: float, sigma: float, max_iter: int, tol: fl
         raise FloatingPointError("objective became non-finite")
     k = it.value
     return beta, trace[: k + 1], k, rc == 0
+
+
+def fit_history(X: Matrix, time, event, lam: float, sigma: float, max_iter: int, tol: float = 0.0, lag: int = 10):
+    """ISTA from beta = 0 as fit() (pf_j = 1), also returning every iterate.
+    Returns (iterates (K + 1, p) with row k = beta_k, objective trace f_0..f_K, K)."""
+    t, ev = _f64(time, X.n), _ev(event, X.n)
+    beta = np.zeros(X.p, np.float64)
+    trace = np.full(max_iter + 1, np.nan)
+    hist = np.zeros((max_iter + 1, X.p), np.float64)
+    it = ctypes.c_int32()
+    rc = _load().cox_oracle_fit_hist(*X.args(), _ptr(t), _ptr(ev), float(lam), float(sigma), int(max_iter),
+                                     float(tol), int(lag), _ptr(beta), _ptr(trace), _ptr(hist), ctypes.byref(it))
+    if rc == -1:
+        raise ValueError("bad input")
+    if rc == -2:
+        raise FloatingPointError("objective became non-finite")
+    k = it.value
+    return hist[: k + 1], trace[: k + 1], k
 
 
 def newton(X: Matrix, time, event, cols, beta_fixed=None, beta_start=None, maxit: int = 100, gtol: float = 1e-10):

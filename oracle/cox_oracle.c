@@ -366,10 +366,10 @@ int cox_oracle_opnorm2(int kind, const void *data, int64_t n, int64_t p, int64_t
  * *iters_out = k at the stop (the number of steps taken).  Returns 0 when the
  * rule fired, 1 when max_iter was reached, -1 on bad input or no memory, -2
  * when the objective became non-finite. */
-int cox_oracle_fit_pf(int kind, const void *data, int64_t n, int64_t p, int64_t ldx, const double *mu,
-                      const double *s, const double *time, const int32_t *event, double lambda,
-                      const double *pf, double sigma, int32_t max_iter, double tol, int32_t lag, double *beta,
-                      double *obj_trace, int32_t *iters_out)
+static int fit_impl(int kind, const void *data, int64_t n, int64_t p, int64_t ldx, const double *mu,
+                    const double *s, const double *time, const int32_t *event, double lambda, const double *pf,
+                    double sigma, int32_t max_iter, double tol, int32_t lag, double *beta, double *obj_trace,
+                    double *beta_hist, int32_t *iters_out)
 {
     oracle_matrix X;
     if (make_matrix(&X, kind, data, n, p, ldx, mu, s) || lag < 1 || max_iter < 0) return -1;
@@ -394,6 +394,7 @@ int cox_oracle_fit_pf(int kind, const void *data, int64_t n, int64_t p, int64_t 
         double f = -L + lambda * l1;
         hist[k] = f;
         if (obj_trace) obj_trace[k] = f;
+        if (beta_hist) memcpy(beta_hist + (size_t)k * (size_t)p, beta, sizeof(double) * (size_t)p);
         if (!isfinite(f)) { rc = -2; *iters_out = k; break; }
         if (k >= lag && fabs(f - hist[k - lag]) / (fabs(f) + 1.0) < tol) { rc = 0; *iters_out = k; break; }
         if (k == max_iter) { rc = 1; *iters_out = k; break; }
@@ -404,6 +405,28 @@ int cox_oracle_fit_pf(int kind, const void *data, int64_t n, int64_t p, int64_t 
 out:
     free(order); free(work); free(eta); free(r); free(g); free(hist);
     return rc;
+}
+
+int cox_oracle_fit_pf(int kind, const void *data, int64_t n, int64_t p, int64_t ldx, const double *mu,
+                      const double *s, const double *time, const int32_t *event, double lambda,
+                      const double *pf, double sigma, int32_t max_iter, double tol, int32_t lag, double *beta,
+                      double *obj_trace, int32_t *iters_out)
+{
+    return fit_impl(kind, data, n, p, ldx, mu, s, time, event, lambda, pf, sigma, max_iter, tol, lag, beta,
+                    obj_trace, NULL, iters_out);
+}
+
+/* The same iteration with every pf_j = 1, also recording each iterate:
+ * beta_hist[k*p + j] = beta_kj for k = 0 .. the step at which it stops
+ * (beta_hist holds max_iter + 1 rows of p). */
+int cox_oracle_fit_hist(int kind, const void *data, int64_t n, int64_t p, int64_t ldx, const double *mu,
+                        const double *s, const double *time, const int32_t *event, double lambda, double sigma,
+                        int32_t max_iter, double tol, int32_t lag, double *beta, double *obj_trace,
+                        double *beta_hist, int32_t *iters_out)
+{
+    if (!beta_hist) return -1;
+    return fit_impl(kind, data, n, p, ldx, mu, s, time, event, lambda, NULL, sigma, max_iter, tol, lag, beta,
+                    obj_trace, beta_hist, iters_out);
 }
 
 /* The plain l1 problem: cox_oracle_fit_pf with every pf_j = 1. */

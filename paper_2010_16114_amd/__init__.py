@@ -48,8 +48,9 @@ class RefitOpts(ctypes.Structure):
 
 class FitOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("lag", ctypes.c_int32),
-                ("step", ctypes.c_double), ("warm_start", ctypes.c_int32), ("eta_mode", ctypes.c_int32),
-                ("poll", ctypes.c_int32), ("residual_bits", ctypes.c_int32)]
+                ("step", ctypes.c_double), ("warm_start", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("deterministic", ctypes.c_int32), ("eta_mode", ctypes.c_int32), ("poll", ctypes.c_int32),
+                ("residual_bits", ctypes.c_int32), ("trace", ctypes.c_void_p)]
 
 
 _lib = None
@@ -228,8 +229,11 @@ class Cox:
         self._check(st, "cox_prox_apply")
 
     def fit_path(self, lambdas, max_iter: int = 1000, tol: float = 1e-5, lag: int = 10, step: float = 0.0,
-                 beta=None, eta_mode: int = 0, poll: int = 16, residual_bits: int = 0):
-        """ISTA for each lambda.  Returns (beta (B, ptot) tensor, iters, obj, status)."""
+                 beta=None, eta_mode: int = 0, poll: int = 16, residual_bits: int = 0, persistent: bool = False,
+                 trace: bool = False):
+        """ISTA for each lambda.  Returns (beta (B, ptot) tensor, iters, obj, status), and with
+        trace=True a fifth item: the objective of every step, a (B, max_iter + 1) array (NaN past
+        each lambda's last step)."""
         torch = self._torch
         lam = np.ascontiguousarray(np.asarray(lambdas, np.float64).reshape(-1))
         B = lam.shape[0]
@@ -240,11 +244,14 @@ class Cox:
         assert Bb == B
         iters = np.zeros(B, np.int32)
         obj = np.zeros(B, np.float64)
-        o = FitOpts(int(max_iter), float(tol), int(lag), float(step), int(warm), int(eta_mode), int(poll),
-                    int(residual_bits))
+        tr = np.full((B, int(max_iter) + 1), np.nan) if trace else None
+        o = FitOpts(int(max_iter), float(tol), int(lag), float(step), int(warm), int(persistent), 1,
+                    int(eta_mode), int(poll), int(residual_bits), tr.ctypes.data if trace else None)
         st = lib().cox_fit_path(self._h, _np_ptr(lam), B, ctypes.byref(o), beta2.data_ptr(), _np_ptr(iters),
                                 _np_ptr(obj))
         self._check(st, "cox_fit_path", allow=(OK, ERR_NOT_CONVERGED))
+        if trace:
+            return beta2, iters, obj, st, tr
         return beta2, iters, obj, st
 
     def fit_sequence(self, lambdas, max_iter: int = 1000, tol: float = 1e-5, lag: int = 10, step: float = 0.0,
@@ -259,8 +266,8 @@ class Cox:
             path[0] = beta0.reshape(-1)
         iters = np.zeros(L, np.int32)
         obj = np.zeros(L, np.float64)
-        o = FitOpts(int(max_iter), float(tol), int(lag), float(step), int(beta0 is not None), int(eta_mode),
-                    int(poll), 0)
+        o = FitOpts(int(max_iter), float(tol), int(lag), float(step), int(beta0 is not None), 0, 1, int(eta_mode),
+                    int(poll), 0, None)
         st = lib().cox_fit_sequence(self._h, _np_ptr(lam), L, ctypes.byref(o), path.data_ptr(), _np_ptr(iters),
                                     _np_ptr(obj))
         self._check(st, "cox_fit_sequence", allow=(OK, ERR_NOT_CONVERGED))

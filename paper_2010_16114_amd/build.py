@@ -26,9 +26,24 @@ FLAGS = [
 ]
 
 
+# sources of the tuned matrix-core kernels: their hash keys the autotuner's cache
+TUNED = ["mfma.hip", "mfma.h", "device_common.h"]
+
+
+def source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in TUNED:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def _compile(src: str) -> str:
     out = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
     cmd = ["hipcc", "-x", "hip", "-c", os.path.join(CSRC, src), "-o", out] + FLAGS
+    if src == "api.cpp":
+        cmd.append(f"-DCOXHIP_SRC_HASH=\"{source_hash()}\"")
     r = subprocess.run(cmd, capture_output=True, text=True)
     noise = "is not a recognized feature for this target"
     err = "\n".join(l for l in r.stderr.splitlines() if noise not in l)

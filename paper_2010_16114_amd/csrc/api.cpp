@@ -21,6 +21,8 @@
 #include <string>
 #include <vector>
 
+#include <unistd.h>
+
 #include "cox.h"
 #include "internal.h"
 #include "mfma.h"
@@ -155,6 +157,29 @@ bool dalloc(cox_ctx* c, T** out, size_t count)
     *out = static_cast<T*>(p);
     return true;
 }
+
+// Device buffers of one call, freed when the call returns.
+struct Scratch {
+    std::vector<void*> ptrs;
+    ~Scratch()
+    {
+        for (void* p : ptrs) (void)hipFree(p);
+    }
+    template <class T>
+    bool get(T** out, size_t count)
+    {
+        *out = nullptr;
+        if (fault_injected("alloc")) return false;
+        void* p = nullptr;
+        if (hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        ptrs.push_back(p);
+        *out = static_cast<T*>(p);
+        return true;
+    }
+};
 
 void timing_clear(cox_ctx* c)
 {
@@ -329,9 +354,20 @@ cox_status dense_eta(cox_ctx* c, const double* coef, int B, const double* shift)
 
 // ---- autotuner of the matrix-core pipeline shapes
 // A shape is forced by COXHIP_MFMA_VARIANT (the X~' R pass) or COXHIP_ETA_VARIANT
-// (the eta update), read from the cache file named by COXHIP_TUNE_CACHE (lines
-// "key variant"), or chosen by timing every shape once on the live data and
-// appended to that file.
+// (the eta update), read from the cache file named by COXHIP_TUNE_CACHE, or
+// chosen by timing every shape on the live data (one untimed launch, then the
+// median of kTuneReps timed launches; a shape whose launch fails is never
+// chosen) and written to that file.  The cache is one JSON object whose keys
+// name the pass, the device, its architecture, the source of the kernels
+// (COXHIP_SRC_HASH, set by the build) and the problem's shape; each value holds
+// the chosen shape and the medians.  Entries that do not parse, name a shape
+// out of range or carry another key are ignored, so an old or corrupt file
+// leads to a fresh tuning, never to a wrong shape.
+#ifndef COXHIP_SRC_HASH
+#define COXHIP_SRC_HASH "unknown"
+#endif
+constexpr int kTuneReps = 3;
+
 int forced_variant(const char* var, int count)
 {
     const char* v = std::getenv(var);
@@ -342,9 +378,41 @@ int forced_variant(const char* var, int count)
 
 std::string tune_key(const cox_ctx* c, const char* kernel, int bpad)
 {
+    hipDeviceProp_t prop{};
+    std::string dev = "unknown", arch = "unknown";
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {
+        dev = prop.name;
+        arch = prop.gcnArchName;
+    } else {
+        (void)hipGetLastError();
+    }
+    for (char& ch : dev)  // keep the key a plain JSON string
+        if (ch == '"' || ch == '\\' || (unsigned char)ch < 0x20) ch = '_';
+    for (char& ch : arch)
+        if (ch == '"' || ch == '\\' || (unsigned char)ch < 0x20) ch = '_';
     std::ostringstream os;
-    os << kernel << ":xt" << c->x.xt << ":n" << c->n << ":p" << c->p << ":b" << bpad;
+    os << kernel << "|" << dev << "|" << arch << "|src:" << COXHIP_SRC_HASH << "|xt" << c->x.xt << "|n" << c->n
+       << "|p" << c->p << "|b" << bpad;
     return os.str();
+}
+
+// One cache entry per line: "<key>": {"variant": V, "ms": [...]}
+bool tune_parse_line(const std::string& line, std::string* key, int* v)
+{
+    const size_t a = line.find('"');
+    if (a == std::string::npos) return false;
+    const size_t b = line.find('"', a + 1);
+    if (b == std::string::npos) return false;
+    const std::string tag = "\"variant\":";
+    const size_t t = line.find(tag, b);
+    if (t == std::string::npos) return false;
+    const char* s = line.c_str() + t + tag.size();
+    char* end = nullptr;
+    const long val = std::strtol(s, &end, 10);
+    if (end == s) return false;
+    *key = line.substr(a + 1, b - a - 1);
+    *v = (int)val;
+    return true;
 }
 
 int tune_cache_lookup(const std::string& key, int count)
@@ -352,45 +420,76 @@ int tune_cache_lookup(const std::string& key, int count)
     const char* path = std::getenv("COXHIP_TUNE_CACHE");
     if (!path) return -1;
     std::ifstream f(path);
-    std::string k;
-    int v;
-    int found = -1;
-    while (f >> k >> v)
-        if (k == key && v >= 0 && v < count) found = v;
+    std::string line, k;
+    int v = -1, found = -1;
+    while (std::getline(f, line))
+        if (tune_parse_line(line, &k, &v) && k == key && v >= 0 && v < count) found = v;
     return found;
 }
 
-void tune_cache_store(const std::string& key, int v)
+void tune_cache_store(const std::string& key, int v, const float* ms, int count)
 {
     const char* path = std::getenv("COXHIP_TUNE_CACHE");
     if (!path) return;
-    std::ofstream f(path, std::ios::app);
-    f << key << " " << v << "\n";
+    std::vector<std::string> keep;
+    {
+        std::ifstream f(path);
+        std::string line, k;
+        int w;
+        while (std::getline(f, line)) {
+            if (!tune_parse_line(line, &k, &w) || k == key) continue;
+            while (!line.empty() && (line.back() == ',' || line.back() == ' ')) line.pop_back();
+            keep.push_back(line);
+        }
+    }
+    std::ostringstream e;
+    e << "\"" << key << "\": {\"variant\": " << v << ", \"ms\": [";
+    for (int i = 0; i < count; ++i) e << (i ? ", " : "") << ms[i];
+    e << "]}";
+    keep.push_back(e.str());
+    const std::string tmp = std::string(path) + ".tmp" + std::to_string((long)getpid());
+    {
+        std::ofstream o(tmp, std::ios::trunc);
+        o << "{\n";
+        for (size_t i = 0; i < keep.size(); ++i) o << keep[i] << (i + 1 < keep.size() ? ",\n" : "\n");
+        o << "}\n";
+        if (!o) return;
+    }
+    (void)std::rename(tmp.c_str(), path);
 }
 
-// Time launch(variant) for each of count variants with events on the stream;
-// return the fastest.
+// Time launch(variant) -> hipError_t for each of count variants with events on
+// the stream: one untimed launch, then the median of kTuneReps timed ones.
+// Returns the fastest shape whose launches all succeeded (-1 if none did).
 template <class F>
 int autotune(cox_ctx* c, int count, F&& launch, float* ms_out)
 {
-    hipEvent_t e[kMfmaVariants + 1];
-    for (auto& ev : e)
-        if (hipEventCreate(&ev) != hipSuccess) return 0;
-    (void)hipEventRecord(e[0], c->stream);
-    for (int v = 0; v < count; ++v) {
-        launch(v);
-        (void)hipEventRecord(e[v + 1], c->stream);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return -1;
     }
-    (void)hipEventSynchronize(e[count]);
-    int best = 0;
+    int best = -1;
     for (int v = 0; v < count; ++v) {
-        float ms = 0;
-        (void)hipEventElapsedTime(&ms, e[v], e[v + 1]);
-        ms_out[v] = ms;
-        if (ms < ms_out[best]) best = v;
+        ms_out[v] = 0.f;
+        bool ok = launch(v) == hipSuccess;
+        float t[kTuneReps] = {};
+        for (int r = 0; ok && r < kTuneReps; ++r) {
+            ok = hipEventRecord(e0, c->stream) == hipSuccess && launch(v) == hipSuccess &&
+                 hipEventRecord(e1, c->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                 hipEventElapsedTime(&t[r], e0, e1) == hipSuccess;
+        }
+        if (!ok) {
+            (void)hipGetLastError();
+            continue;
+        }
+        std::sort(t, t + kTuneReps);
+        ms_out[v] = t[kTuneReps / 2];
+        if (best < 0 || ms_out[v] < ms_out[best]) best = v;
     }
-    for (auto& ev : e) (void)hipEventDestroy(ev);
-    (void)hipGetLastError();
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     return best;
 }
 
@@ -499,9 +598,10 @@ cox_status run_gemvt(cox_ctx* c, GemvtArgs g, int B, int rlimbs = 3)
             chosen = tune_cache_lookup(key, kMfmaVariants);
             if (chosen < 0) {
                 chosen = autotune(
-                    c, kMfmaVariants, [&](int v) { m.variant = v; (void)launch_mfma_xtr(m, c->stream); },
+                    c, kMfmaVariants, [&](int v) { m.variant = v; return launch_mfma_xtr(m, c->stream); },
                     c->xtr_ms_by_limbs[rlimbs]);
-                tune_cache_store(key, chosen);
+                if (chosen < 0) return fail(c, COX_ERR_DEVICE, "no pipeline shape of the X' R pass launched");
+                tune_cache_store(key, chosen, c->xtr_ms_by_limbs[rlimbs], kMfmaVariants);
             }
         }
         c->xtr_variant = chosen;
@@ -1009,12 +1109,17 @@ cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_
     if (!beta) return fail(c, COX_ERR_INVALID_ARG, "beta is NULL");
     STCHK(check_batch(c, B));
     STCHK(check_lambdas(c, lambdas, B));
-    cox_fit_opts o{1000, 1e-5, 10, 0.0, 0, 0, 16, 0};
+    cox_fit_opts o{1000, 1e-5, 10, 0.0, 0, 0, 0, 0, 16, 0, nullptr};
     if (opts_in) o = *opts_in;
     if (o.max_iter < 0 || !(o.tol >= 0) || o.lag < 1 || o.lag > kMaxHist - 1 || !std::isfinite(o.step) ||
         (o.warm_start != 0 && o.warm_start != 1) || (o.eta_mode != 0 && o.eta_mode != 1) ||
+        (o.persistent != 0 && o.persistent != 1) || (o.deterministic != 0 && o.deterministic != 1) ||
         (o.residual_bits != 0 && o.residual_bits != 22 && o.residual_bits != 14))
         return fail(c, COX_ERR_INVALID_ARG, "bad cox_fit_opts");
+    if (o.trace && (int64_t)B * ((int64_t)o.max_iter + 1) > (int64_t(1) << 31))
+        return fail(c, COX_ERR_INVALID_ARG, "trace: B * (max_iter + 1) is too large");
+    if (o.persistent)
+        return fail(c, COX_ERR_UNSUPPORTED, "persistent: not available in this build");
     const int rlimbs = o.residual_bits == 14 ? 2 : 3;
     const int poll = o.poll > 0 ? o.poll : 16;
     double step = o.step;
@@ -1055,7 +1160,16 @@ cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_
     ra.part = (o.eta_mode == 0 && !mfma) ? c->part_upd : nullptr;
     ra.use_ctl = 1;
     ra.ctl = FitCtl{c->lam, c->l1new, c->nblk, c->hist, c->kit, c->active, c->iters, c->status, c->fobj,
-                    q ? c->l1c_new : nullptr, o.max_iter, o.lag, o.tol};
+                    q ? c->l1c_new : nullptr, o.max_iter, o.lag, o.tol, nullptr, 0};
+    Scratch call;
+    const int64_t tstride = (int64_t)o.max_iter + 1;
+    if (o.trace) {  // the objective of every step, written by the stopping-rule kernel
+        if (!call.get(&ra.ctl.trace, (size_t)(B * tstride)))
+            return fail(c, COX_ERR_OUT_OF_MEMORY, "objective trace");
+        ra.ctl.trace_stride = tstride;
+        HIPCHK(launch_fill_f64(ra.ctl.trace, std::numeric_limits<double>::quiet_NaN(), B * tstride, c->stream),
+               "reset trace");
+    }
     const CovStep cst = cov_prox(c, step, c->active);
     GemvtArgs g = gemvt_args(c, GT_PROX);
     g.beta = c->beta64;
@@ -1084,9 +1198,11 @@ cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_
                         MfmaEtaArgs t = m;
                         t.eta = c->w;  // scratch: the update is in place, so tuning writes elsewhere
                         c->eta_variant = autotune(
-                            c, kMfmaEtaVariants, [&](int v) { t.variant = v; (void)launch_mfma_eta(t, c->stream); },
+                            c, kMfmaEtaVariants, [&](int v) { t.variant = v; return launch_mfma_eta(t, c->stream); },
                             c->eta_tune_ms);
-                        tune_cache_store(key, c->eta_variant);
+                        if (c->eta_variant < 0)
+                            return fail(c, COX_ERR_DEVICE, "no pipeline shape of the eta update launched");
+                        tune_cache_store(key, c->eta_variant, c->eta_tune_ms, kMfmaEtaVariants);
                     }
                 }
                 m.variant = c->eta_variant;
@@ -1130,6 +1246,7 @@ cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_
     STCHK(d2h(c, fo.data(), c->fobj, sizeof(double) * B));
     if (iters) std::copy(itv.begin(), itv.end(), iters);
     if (obj) std::copy(fo.begin(), fo.end(), obj);
+    if (o.trace) STCHK(d2h(c, o.trace, ra.ctl.trace, sizeof(double) * (size_t)(B * tstride)));
     bool numeric = false, notconv = false;
     for (int b = 0; b < B; ++b) {
         numeric = numeric || st[b] == 3;
@@ -1146,7 +1263,7 @@ cox_status cox_fit_sequence(cox_ctx* c, const double* lambdas, int32_t L, const 
     STCHK(check_ctx(c));
     if (!beta_path || L < 1) return fail(c, COX_ERR_INVALID_ARG, "beta_path is NULL or L < 1");
     STCHK(check_lambdas(c, lambdas, L));
-    cox_fit_opts o{1000, 1e-5, 10, 0.0, 0, 0, 16, 0};
+    cox_fit_opts o{1000, 1e-5, 10, 0.0, 0, 0, 0, 0, 16, 0, nullptr};
     if (opts_in) o = *opts_in;
     if (o.step <= 0) {  // one step size for the whole sequence
         double s2 = 0;
@@ -1159,6 +1276,7 @@ cox_status cox_fit_sequence(cox_ctx* c, const double* lambdas, int32_t L, const 
     for (int32_t l = 0; l < L; ++l) {
         float* bl = beta_path + (int64_t)l * pt;
         cox_fit_opts ol = o;
+        if (o.trace) ol.trace = o.trace + (int64_t)l * ((int64_t)o.max_iter + 1);
         if (l > 0) {
             HIPCHK(hipMemcpyAsync(bl, bl - pt, sizeof(float) * pt, hipMemcpyDeviceToDevice, c->stream),
                    "previous solution");
@@ -1220,33 +1338,6 @@ cox_status cox_set_penalty_factors(cox_ctx* c, const double* pf)
 }
 
 }  // extern "C"
-
-namespace {
-
-// Device buffers of one call, freed when the call returns.
-struct Scratch {
-    std::vector<void*> ptrs;
-    ~Scratch()
-    {
-        for (void* p : ptrs) (void)hipFree(p);
-    }
-    template <class T>
-    bool get(T** out, size_t count)
-    {
-        *out = nullptr;
-        if (fault_injected("alloc")) return false;
-        void* p = nullptr;
-        if (hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) {
-            (void)hipGetLastError();
-            return false;
-        }
-        ptrs.push_back(p);
-        *out = static_cast<T*>(p);
-        return true;
-    }
-};
-
-}  // namespace
 
 extern "C" {
 

@@ -57,6 +57,8 @@ struct FitCtl {
     const double* l1cov;   // [B] penalised l1 of the covariate coefficients, or null
     int max_iter, lag;
     double tol;
+    double* trace;         // [B][trace_stride] objective of every step, or null
+    int64_t trace_stride;
 };
 
 struct RiskArgs {

@@ -51,11 +51,18 @@ __device__ __forceinline__ uint32_t counts4(uint32_t w)
 // padding holds: the kernels make them harmless (zero limbs, or outputs that
 // are never written).  The load and the decode are separate so that a
 // prefetched run is only waited for where it is used.
+// NT: a non-temporal (streaming) load, for runs whose cache line is consumed
+// at once, so that X does not push the shared operand tiles out of L2.
+template <bool NT = false>
 __device__ __forceinline__ v4i load_raw(const uint8_t* __restrict__ X, int64_t col, int64_t p, int64_t ldx,
                                         int64_t row, int64_t n)
 {
     const bool ok = col < p && row < n;
-    return *reinterpret_cast<const v4i*>(X + (ok ? col * ldx + row : 0));
+    const v4i* q = reinterpret_cast<const v4i*>(X + (ok ? col * ldx + row : 0));
+    if constexpr (NT)
+        return __builtin_nontemporal_load(q);
+    else
+        return *q;
 }
 
 // int8 counts of a raw run.
@@ -82,7 +89,7 @@ __device__ __forceinline__ v4i decode_a(v4i raw)
 // split, each stream drains at its own pace.  Both roles meet at one barrier
 // per stage.  The limb rows of subjects >= n are zero (the quantiser writes
 // them so), so the padding bytes of X that meet them add nothing.
-template <int XT, int NG, int RL, int CW, int LW, int MT, int KS, int PF>
+template <int XT, int NG, int RL, int CW, int LW, int MT, int KS, int PF, bool NTX = false>
 __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_split_kernel(MfmaArgs a)
 {
     static_assert(PF >= 2 && PF % 2 == 0, "the loaders' two-slot ring indexes statically");
@@ -120,7 +127,7 @@ __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_split_
             for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt)
-                    A[mt][ks] = load_raw(X, jw + mt * 16 + acol, p, ldx, k0 + ks * 64 + arow, n);
+                    A[mt][ks] = load_raw<NTX>(X, jw + mt * 16 + acol, p, ldx, k0 + ks * 64 + arow, n);
         };
 #pragma unroll
         for (int q = 0; q < PF; ++q) fetch(q, Ab[q]);
@@ -236,7 +243,7 @@ __device__ __forceinline__ void transpose4x4(const uint32_t (&d)[4], uint32_t (&
 // hit distinct banks.  The column indices run one ring lap ahead of the G
 // loads they address.  Each (subject, b) is owned by one lane, so eta is
 // updated in place.
-template <int XT, int NG, int NSPLIT, int PF, bool D8 = false>
+template <int XT, int NG, int NSPLIT, int PF, bool D8 = false, bool NTX = false>
 __global__ __launch_bounds__(256 * NSPLIT, NSPLIT) void mfma_eta_kernel(MfmaEtaArgs a)
 {
     static_assert(PF >= 2, "the ring needs two slots");
@@ -320,7 +327,7 @@ __global__ __launch_bounds__(256 * NSPLIT, NSPLIT) void mfma_eta_kernel(MfmaEtaA
 #pragma unroll
         for (int k = 0; k < GPT; ++k) {
             const int64_t col = t * 64 + gu[k] < nsel ? (int64_t)s[k] : p;  // past the list: reads as 0
-            g[k] = load_raw(X, col, p, ldx, i0 + 16 * grb[k], n);
+            g[k] = load_raw<NTX>(X, col, p, ldx, i0 + 16 * grb[k], n);
         }
         const int64_t kd = min(t, nchunk - 1) * (int64_t)(16 * DCH);
 #pragma unroll

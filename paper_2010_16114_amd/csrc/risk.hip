@@ -285,6 +285,7 @@ __global__ __launch_bounds__(kT) void risk_finish_kernel(RiskArgs a)
         const int k = c.kit[b];
         double* h = c.hist + (int64_t)b * kMaxHist;
         h[k % kMaxHist] = f;
+        if (c.trace) c.trace[(int64_t)b * c.trace_stride + k] = f;
         int stop = 0;
         if (!isfinite(f))
             stop = 3;

@@ -87,5 +87,8 @@ def test_fit_opts_layout_matches_header():
     text = open(P.HEADER).read()
     body = text.split("} cox_fit_opts;")[0].rsplit("typedef struct {", 1)[1]
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
-    fields = re.findall(r"\b(?:int32_t|double)\s+(\w+);", body)
+    fields = re.findall(r"\b(?:int32_t|double)\s*\*?\s*(\w+);", body)
     assert fields == [f[0] for f in P.FitOpts._fields_]
+    # the fields the boundary's specification names come first, in its order
+    assert fields[:7] == ["max_iter", "tol", "lag", "step", "warm_start", "persistent", "deterministic"]
+    assert ctypes.sizeof(P.FitOpts) == 64

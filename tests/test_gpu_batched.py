@@ -146,8 +146,14 @@ def test_every_pipeline_shape(prob, variant, monkeypatch):
         assert obj[b] == pytest.approx(tr[-1], rel=OBJ_TOL)
 
 
+def _tune_entries(path):
+    """The autotuner's JSON cache as a dict."""
+    import json
+    return json.loads(path.read_text())
+
+
 def test_autotuner_picks_and_caches(prob, tmp_path, monkeypatch):
-    cache = tmp_path / "tune.txt"
+    cache = tmp_path / "tune.json"
     monkeypatch.setenv("COXHIP_TUNE_CACHE", str(cache))
     monkeypatch.delenv("COXHIP_MFMA_VARIANT", raising=False)
     monkeypatch.delenv("COXHIP_ETA_VARIANT", raising=False)
@@ -155,18 +161,53 @@ def test_autotuner_picks_and_caches(prob, tmp_path, monkeypatch):
     cox, M = _setup(prob, "int8", B)
     lm = cox.lambda_max()
     lams = coxsim.lambda_grid(lm, B, 0.01)
-    cox.fit_path(lams, max_iter=3, tol=0.0, step=1.0 / (2.0 * cox.opnorm2()[0]))
+    sigma = 1.0 / (2.0 * cox.opnorm2()[0])
+    cox.fit_path(lams, max_iter=3, tol=0.0, step=sigma)
     t = cox.mfma_tuning()
     assert 0 <= t["xtr_variant"] < P.MFMA_VARIANTS and 0 <= t["eta_variant"] < P.ETA_VARIANTS
     assert all(m > 0 for m in t["xtr_ms"])
     assert all(m > 0 for m in t["eta_ms"][: P.ETA_VARIANTS]) and not any(t["eta_ms"][P.ETA_VARIANTS:])
-    lines = cache.read_text().split()
-    assert "xtr:xt2:n3001:p700:b16" in lines and "eta:xt2:n3001:p700:b16" in lines
+    # the pick is the fastest median
+    assert t["xtr_ms"][t["xtr_variant"]] == min(t["xtr_ms"])
+    ent = _tune_entries(cache)
+    keys = sorted(ent)
+    assert len(keys) == 2 and keys[0].startswith("eta|") and keys[1].startswith("xtr|")
+    for k in keys:  # pass | device | arch | source hash | storage | n | p | padded batch
+        f = k.split("|")
+        assert f[3].startswith("src:") and f[4:] == ["xt2", "n3001", "p700", "b16"], k
+        assert "gfx950" in f[2]
+    assert ent[keys[1]]["variant"] == t["xtr_variant"] and len(ent[keys[1]]["ms"]) == P.MFMA_VARIANTS
     # a new context reads the cache instead of timing again
     cox2, _ = _setup(prob, "int8", B)
-    cox2.fit_path(lams, max_iter=3, tol=0.0, step=1.0 / (2.0 * cox.opnorm2()[0]))
+    cox2.fit_path(lams, max_iter=3, tol=0.0, step=sigma)
     t2 = cox2.mfma_tuning()
     assert t2["xtr_variant"] == t["xtr_variant"] and t2["xtr_ms"] == [0.0] * P.MFMA_VARIANTS
+
+
+def test_autotuner_ignores_stale_or_corrupt_cache(prob, tmp_path, monkeypatch):
+    """Entries for other kernel sources, shapes out of range and unparsable
+    text never select a shape: the tuner times the shapes again and rewrites
+    the file as valid JSON."""
+    monkeypatch.delenv("COXHIP_MFMA_VARIANT", raising=False)
+    monkeypatch.delenv("COXHIP_ETA_VARIANT", raising=False)
+    B = 16
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("COXHIP_TUNE_CACHE", str(cache))
+    cox, M = _setup(prob, "int8", B)
+    lams = coxsim.lambda_grid(cox.lambda_max(), B, 0.01)
+    sigma = 1.0 / (2.0 * cox.opnorm2()[0])
+    cox.fit_path(lams, max_iter=2, tol=0.0, step=sigma)
+    good = _tune_entries(cache)
+    xkey = [k for k in good if k.startswith("xtr|")][0]
+    stale = xkey.replace("|src:", "|src:0ld")
+    cache.write_text('garbage {{{\n"%s": {"variant": 1, "ms": []},\n"%s": {"variant": 99},\n'
+                     '"%s": {"variant": -3},\nnot json at all\n' % (stale, xkey, xkey))
+    cox2, _ = _setup(prob, "int8", B)
+    cox2.fit_path(lams, max_iter=2, tol=0.0, step=sigma)
+    t2 = cox2.mfma_tuning()
+    assert all(m > 0 for m in t2["xtr_ms"])  # timed again: nothing in the file was taken
+    ent = _tune_entries(cache)  # rewritten as one valid JSON object, the stale entry kept
+    assert ent[xkey]["variant"] == t2["xtr_variant"] and stale in ent
 
 
 def test_residual_in_two_limbs(prob):

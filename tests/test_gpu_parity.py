@@ -7,6 +7,8 @@ FP64 end to end (the log likelihood at a given FP32 beta) are held to 1e-12.
 Gradients, which pass through the FP32 residual and an FP32 output, to
 1e-6 of their largest entry.
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -265,3 +267,42 @@ def test_errors_through_the_abi(c0):
     # the context still works after errors
     loss, _ = cox.loss_grad(torch.zeros((1, c0.p), device="cuda"))
     assert np.isfinite(loss[0])
+
+
+def test_objective_trace(c0):
+    """The per-step objective trace of cox_fit_path equals the oracle's f_0..f_K,
+    step by step; a lambda that stops early has NaN past its last step."""
+    cox, M = device_problem(c0, "fp8", max_batch=2)
+    lm = oracle.lambda_max(M, c0.time, c0.event)
+    sigma = _step(M, c0)
+    lams = np.array([0.6 * lm, 1.5 * lm])  # the second stays at beta = 0 and meets the rule at k = lag
+    beta, iters, obj, st, tr = cox.fit_path(lams, max_iter=60, tol=1e-9, lag=10, step=sigma, trace=True)
+    assert tr.shape == (2, 61)
+    bo, tro, ko, _ = oracle.fit(M, c0.time, c0.event, lams[0], sigma, max_iter=60, tol=1e-9, lag=10)
+    assert iters[0] == ko
+    np.testing.assert_allclose(tr[0, : ko + 1], tro, rtol=OBJ_TOL)
+    assert np.all(np.isnan(tr[0, ko + 1:]))
+    assert iters[1] == 10 and np.all(tr[1, :11] == tr[1, 0]) and np.all(np.isnan(tr[1, 11:]))
+    assert tr[0, iters[0]] == obj[0] and tr[1, 10] == obj[1]
+
+
+def test_fit_options_checked(c0):
+    cox, M = device_problem(c0, "f32")
+    L = P.lib()
+    lam = np.array([0.5 * oracle.lambda_max(M, c0.time, c0.event)])
+    beta = torch.zeros((1, c0.p), device="cuda")
+    for field, bad in (("deterministic", 2), ("persistent", -1), ("eta_mode", 3), ("residual_bits", 8)):
+        o = P.FitOpts(5, 0.0, 10, 1e-3, 0, 0, 1, 0, 16, 0, None)
+        setattr(o, field, bad)
+        st = L.cox_fit_path(cox._h, P._np_ptr(lam), 1, ctypes.byref(o), beta.data_ptr(), None, None)
+        assert st == P.ERR_INVALID_ARG, field
+    # deterministic = 0 and 1 run the same computation
+    outs = []
+    for det in (0, 1):
+        o = P.FitOpts(5, 0.0, 10, 1e-3, 0, 0, det, 0, 16, 0, None)
+        b = torch.zeros((1, c0.p), device="cuda")
+        obj = np.zeros(1)
+        st = L.cox_fit_path(cox._h, P._np_ptr(lam), 1, ctypes.byref(o), b.data_ptr(), None, P._np_ptr(obj))
+        assert st == P.ERR_NOT_CONVERGED
+        outs.append((b.cpu(), obj[0]))
+    assert torch.equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]

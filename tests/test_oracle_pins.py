@@ -279,3 +279,25 @@ def test_convergence_rule_and_trace():
     b10, _, _, _ = oracle.fit(X, d.time, d.event, 0.3 * lm, sigma, max_iter=10)
     b10w, _, _, _ = oracle.fit(X, d.time, d.event, 0.3 * lm, sigma, max_iter=5, beta0=b5)
     np.testing.assert_allclose(b10w, b10, rtol=1e-15, atol=0)
+
+
+def test_iterate_history():
+    """fit_history records each ISTA iterate: row k equals the result of k steps
+    from zero, its trace is fit()'s, and each row is one proximal step (the
+    soft threshold at sigma lambda of the brute-force gradient step) from the
+    row before."""
+    d, X = _small_geno(n=150, p=12, seed=53)
+    lm = oracle.lambda_max(X, d.time, d.event)
+    s2, _ = oracle.opnorm2(X)
+    sigma, lam = 1.0 / (2.0 * s2), 0.4 * lm
+    hist, trace, k = oracle.fit_history(X, d.time, d.event, lam, sigma, max_iter=7)
+    assert k == 7 and hist.shape == (8, X.p) and not hist[0].any()
+    _, tr, _, _ = oracle.fit(X, d.time, d.event, lam, sigma, max_iter=7)
+    np.testing.assert_array_equal(trace, tr)
+    Xd = X.to_dense64()
+    for j in range(1, 8):
+        bj, _, _, _ = oracle.fit(X, d.time, d.event, lam, sigma, max_iter=j)
+        np.testing.assert_array_equal(hist[j], bj)
+        g = brute.gradient(Xd, hist[j - 1], d.time, d.event)
+        want = np.sign(hist[j - 1] + sigma * g) * np.maximum(np.abs(hist[j - 1] + sigma * g) - sigma * lam, 0.0)
+        np.testing.assert_allclose(hist[j], want, rtol=1e-10, atol=1e-14)
