@@ -261,6 +261,24 @@ cox_status cox_set_penalty_factors(cox_ctx *ctx, const double *pf);
 cox_status cox_rank_path(cox_ctx *ctx, const float *path, int32_t L, int32_t *entry, float *entry_coef,
                          int64_t *order, int64_t *n_entered);
 
+/* cox_rank_path_noalloc: cox_rank_path for callers that cannot allocate
+ * memory (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc).  The same computation and the same outputs as cox_rank_path,
+ * bit for bit, but it calls no hipMalloc, hipFree or other allocating routine:
+ * its device working memory is a static array inside the library (8 bytes per
+ * column, COX_NOALLOC_MAX_COLS columns: 16 MiB, held on each GPU the library
+ * runs on until the process ends; its device address is looked up once per
+ * GPU, by cox_setup).  Differences: entry_coef must not be NULL (the ranking's
+ * tie-break reads it; there is no buffer to hold it otherwise), and p above
+ * COX_NOALLOC_MAX_COLS returns UNSUPPORTED before any device work.  Every call
+ * on one GPU shares the array: calls that overlap on one GPU (from several
+ * threads or streams, before the earlier one returned) race and give wrong
+ * results; calls in sequence are safe (each writes every entry it reads).
+ * Synchronises. */
+#define COX_NOALLOC_MAX_COLS 2097152
+cox_status cox_rank_path_noalloc(cox_ctx *ctx, const float *path, int32_t L, int32_t *entry, float *entry_coef,
+                                 int64_t *order, int64_t *n_entered);
+
 /* cox_refit: maximum partial likelihood (no penalty) over the m chosen columns
  * of X (cols host [m], distinct, each < p; X~ standardised as everywhere) and
  * all q attached covariates, every other coefficient zero, by Newton's method

@@ -28,6 +28,7 @@ MFMA_VARIANTS = 5  # COX_MFMA_VARIANTS: pipeline shapes of the X~' R pass (and t
 ETA_VARIANTS = 5  # COX_MFMA_ETA_VARIANTS: pipeline shapes of the eta update
 MAX_COVARIATES = 64  # COX_MAX_COVARIATES
 MAX_REFIT = 1024  # COX_MAX_REFIT
+NOALLOC_MAX_COLS = 2097152  # COX_NOALLOC_MAX_COLS
 OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NUMERIC, ERR_NOT_CONVERGED, ERR_UNSUPPORTED = range(7)
 
 
@@ -83,6 +84,7 @@ def lib():
         "cox_set_covariates": [vp, vp, i64, i64],
         "cox_set_penalty_factors": [vp, vp],
         "cox_rank_path": [vp, vp, i32, vp, vp, vp, ctypes.POINTER(i64)],
+        "cox_rank_path_noalloc": [vp, vp, i32, vp, vp, vp, ctypes.POINTER(i64)],
         "cox_refit": [vp, vp, i32, ctypes.POINTER(RefitOpts), vp, vp, vp, ctypes.POINTER(dbl),
                       ctypes.POINTER(i32)],
         "cox_lambda_max": [vp, ctypes.POINTER(dbl)],
@@ -283,6 +285,20 @@ class Cox:
         ne = ctypes.c_int64()
         self._check(lib().cox_rank_path(self._h, path2.data_ptr(), path2.shape[0], _np_ptr(entry), _np_ptr(coef),
                                         _np_ptr(order), ctypes.byref(ne)), "cox_rank_path")
+        return entry, coef, order[: ne.value]
+
+    def rank_path_noalloc(self, path):
+        """rank_path through cox_rank_path_noalloc: the same outputs, with the
+        library's static device scratch instead of any allocation (at most
+        NOALLOC_MAX_COLS columns)."""
+        path2 = path.contiguous().view(-1, self.ptot)
+        entry = np.zeros(self.p, np.int32)
+        coef = np.zeros(self.p, np.float32)
+        order = np.zeros(self.p, np.int64)
+        ne = ctypes.c_int64()
+        self._check(lib().cox_rank_path_noalloc(self._h, path2.data_ptr(), path2.shape[0], _np_ptr(entry),
+                                                _np_ptr(coef), _np_ptr(order), ctypes.byref(ne)),
+                    "cox_rank_path_noalloc")
         return entry, coef, order[: ne.value]
 
     def refit(self, cols, coef0=None, max_iter: int = 50, gtol: float = 1e-8):

@@ -16,6 +16,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -46,6 +47,20 @@ constexpr double kFreeCovGtol = 1e-10;   // its stop: max |g_k| below this fract
 int64_t round_up(int64_t a, int64_t m) { return (a + m - 1) / m * m; }
 
 }  // namespace
+
+// Device memory of cox_rank_path_noalloc: a file-scope array that every call on
+// one GPU shares (each GPU holds its own copy, at its own address, until the
+// process ends), so that the call allocates nothing.  It holds the entry index
+// (int32) and the |coefficient| at entry (float) of up to kNoallocMaxCols
+// columns.  In host code `scratch` names a host-side stand-in, never the
+// device array: kernels and copies take the address hipGetSymbolAddress
+// returned for the device, kept in g_scratch_addr.
+constexpr int64_t kNoallocMaxCols = int64_t(1) << 21;
+static_assert(kNoallocMaxCols == COX_NOALLOC_MAX_COLS, "static scratch size differs from the header");
+constexpr int kNoallocMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[8 * kNoallocMaxCols];
+static std::mutex g_scratch_mu;
+static void* g_scratch_addr[kNoallocMaxDevices] = {};
 
 struct cox_ctx {
     int device = 0;
@@ -211,6 +226,53 @@ void release(cox_ctx* c)
     c->allocs.clear();
     if (c->pinned) (void)hipHostFree(c->pinned);
     c->pinned = nullptr;
+}
+
+// Look up the device address of `scratch` for the context's device (which is
+// current), once per device; every later call on that device uses it.
+cox_status scratch_init(cox_ctx* c)
+{
+    if (c->device < 0 || c->device >= kNoallocMaxDevices)
+        return fail(c, COX_ERR_UNSUPPORTED, "device index beyond the static scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_addr[c->device]) return COX_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return fail(c, COX_ERR_DEVICE, std::string("static scratch lookup: ") + hipGetErrorString(e));
+    }
+    g_scratch_addr[c->device] = ptr;
+    return COX_OK;
+}
+
+void* scratch_addr(int device)
+{
+    if (device < 0 || device >= kNoallocMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_addr[device];
+}
+
+// Section 6's ranking of the columns a path selects: by entry (the first row
+// of a decreasing-lambda path where the column is nonzero, i.e. the largest
+// lambda), ties by |coef| at entry (larger first), then by index.  Writes the
+// ranked columns to order[0..m) when order is not null (sorting in place, no
+// allocation) and returns m, the number of entered columns.
+int64_t rank_entries(const int32_t* entry, const float* coef, int64_t p, int64_t* order)
+{
+    int64_t m = 0;
+    for (int64_t j = 0; j < p; ++j)
+        if (entry[j] >= 0) {
+            if (order) order[m] = j;
+            ++m;
+        }
+    if (order)
+        std::sort(order, order + m, [&](int64_t a, int64_t b) {
+            if (entry[a] != entry[b]) return entry[a] < entry[b];
+            if (coef[a] != coef[b]) return coef[a] > coef[b];
+            return a < b;
+        });
+    return m;
 }
 
 cox_status check_ctx(cox_ctx* c)
@@ -777,6 +839,10 @@ cox_status cox_setup(cox_ctx** out, const cox_matrix* X, const double* time, con
     c->stream = static_cast<hipStream_t>(hip_stream);
     if (hipGetDevice(&c->device) != hipSuccess) {
         (void)hipGetLastError();
+        delete c;
+        return COX_ERR_DEVICE;
+    }
+    if (c->device < kNoallocMaxDevices && scratch_init(c) != COX_OK) {
         delete c;
         return COX_ERR_DEVICE;
     }
@@ -1480,18 +1546,33 @@ cox_status cox_rank_path(cox_ctx* c, const float* path, int32_t L, int32_t* entr
     STCHK(d2h(c, entry, ed, sizeof(int32_t) * p));
     STCHK(d2h(c, coefv.data(), cd, sizeof(float) * p));
     if (entry_coef) std::copy(coefv.begin(), coefv.end(), entry_coef);
-    std::vector<int64_t> idx;
-    for (int64_t j = 0; j < p; ++j)
-        if (entry[j] >= 0) idx.push_back(j);
-    // Section 6's ranking: the largest lambda at which the column is nonzero
-    // (the earliest position on a decreasing path), ties by |coef| on entry
-    std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
-        if (entry[a] != entry[b]) return entry[a] < entry[b];
-        if (coefv[a] != coefv[b]) return coefv[a] > coefv[b];
-        return a < b;
-    });
-    if (order) std::copy(idx.begin(), idx.end(), order);
-    if (n_entered) *n_entered = (int64_t)idx.size();
+    const int64_t m = rank_entries(entry, coefv.data(), p, order);
+    if (n_entered) *n_entered = m;
+    return COX_OK;
+}
+
+cox_status cox_rank_path_noalloc(cox_ctx* c, const float* path, int32_t L, int32_t* entry, float* entry_coef,
+                                 int64_t* order, int64_t* n_entered)
+{
+    STCHK(check_ctx(c));
+    if (!path || L < 1 || !entry || !entry_coef)
+        return fail(c, COX_ERR_INVALID_ARG, "rank_path_noalloc needs path, L >= 1, entry and entry_coef");
+    const int64_t p = c->p;
+    if (p > kNoallocMaxCols)
+        return fail(c, COX_ERR_UNSUPPORTED, "rank_path_noalloc serves at most " + std::to_string(kNoallocMaxCols) +
+                                                " columns (its static scratch); use cox_rank_path");
+    unsigned char* base = static_cast<unsigned char*>(scratch_addr(c->device));
+    if (!base) STCHK(scratch_init(c));
+    base = static_cast<unsigned char*>(scratch_addr(c->device));
+    // the entry kernel writes every one of the p entries it later reads, so the
+    // previous call's contents need no clearing
+    int32_t* ed = reinterpret_cast<int32_t*>(base);
+    float* cd = reinterpret_cast<float*>(base + 4 * kNoallocMaxCols);
+    HIPCHK(launch_entry(path, L, ptot(c), p, ed, cd, c->stream), "entry points");
+    STCHK(d2h(c, entry, ed, sizeof(int32_t) * p));
+    STCHK(d2h(c, entry_coef, cd, sizeof(float) * p));
+    const int64_t m = rank_entries(entry, entry_coef, p, order);
+    if (n_entered) *n_entered = m;
     return COX_OK;
 }
 

@@ -59,6 +59,7 @@ def test_null_context_calls():
     assert L.cox_set_covariates(None, None, 0, 0) == P.ERR_INVALID_ARG
     assert L.cox_set_penalty_factors(None, None) == P.ERR_INVALID_ARG
     assert L.cox_rank_path(None, None, 1, None, None, None, None) == P.ERR_INVALID_ARG
+    assert L.cox_rank_path_noalloc(None, None, 1, None, None, None, None) == P.ERR_INVALID_ARG
     assert L.cox_refit(None, None, 1, None, None, None, None, None, None) == P.ERR_INVALID_ARG
     assert L.nmf_run(None, 0, 1, 0.0, None, None, None) == P.ERR_INVALID_ARG
     assert L.nmf_destroy(None) == P.OK
@@ -74,6 +75,7 @@ def test_header_constants_match_binding():
     assert int(re.search(r"#define COX_MFMA_ETA_VARIANTS (\d+)", text).group(1)) == P.ETA_VARIANTS
     assert int(re.search(r"#define COX_MAX_COVARIATES (\d+)", text).group(1)) == P.MAX_COVARIATES
     assert int(re.search(r"#define COX_MAX_REFIT (\d+)", text).group(1)) == P.MAX_REFIT
+    assert int(re.search(r"#define COX_NOALLOC_MAX_COLS (\d+)", text).group(1)) == P.NOALLOC_MAX_COLS
     ntext = open(P.NMF_HEADER).read()
     assert int(re.search(r"#define NMF_MAX_RANK (\d+)", ntext).group(1)) == P.NMF_MAX_RANK
     assert re.search(r"NMF_APG\s*=\s*(\d+)", ntext).group(1) == str(P.NMF_APG)
