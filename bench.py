@@ -98,6 +98,59 @@ def cpu_threads() -> int:
         return os.cpu_count() or 1
 
 
+def hbm_probe(gib: float = 4.0, reps: int = 10) -> dict:
+    """Measured HBM bandwidth of this GPU, taken in the same run as the
+    workload: the median of `reps` device-to-device copies of a `gib` GiB
+    buffer (bytes read + bytes written, per second) and of `reps` full
+    reductions of it (bytes read per second), timed with events on torch's
+    stream, on which both run."""
+    import torch
+
+    m = int(gib * (1 << 30)) // 4
+    a = torch.ones(m, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    a.sum()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(2 * reps)]
+    for k in range(reps):
+        ev[k][0].record()
+        b.copy_(a)
+        ev[k][1].record()
+    for k in range(reps, 2 * reps):
+        ev[k][0].record()
+        a.sum()
+        ev[k][1].record()
+    torch.cuda.synchronize()
+    t_copy = float(np.median([s.elapsed_time(e) for s, e in ev[:reps]])) / 1e3
+    t_read = float(np.median([s.elapsed_time(e) for s, e in ev[reps:]])) / 1e3
+    del a, b
+    torch.cuda.empty_cache()
+    return {"copy_gbs": 2 * 4 * m / t_copy / 1e9, "read_gbs": 4 * m / t_read / 1e9, "buffer_bytes": 4 * m,
+            "method": f"median of {reps} torch copies (read + write) and of {reps} torch sums (read) of a "
+                      f"{gib:g} GiB buffer"}
+
+
+def gpu_clocks() -> dict:
+    """The GPU's clocks as the driver reports them at this moment (rocm-smi),
+    and its name; empty fields when the tool is not there."""
+    import subprocess
+
+    import torch
+
+    out = {"device": torch.cuda.get_device_name(0)}
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True, timeout=30)
+        for line in r.stdout.splitlines():
+            low = line.lower()
+            for key in ("sclk", "mclk", "fclk"):
+                if f"{key} clock level" in low and key not in out:
+                    out[key] = line.split(":", 2)[-1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return out
+
+
 def bench_gauss_fp32(args):
     import torch
 
@@ -116,19 +169,21 @@ def bench_gauss_fp32(args):
     sigma = 1.0 / (2.0 * s2)
     log(f"lambda_max={lmax:.6g} ||X||^2={s2:.6g} ({pit} power steps), sigma={sigma:.4g}")
 
-    log(f"warmup {args.warmup} steps")
-    cox.fit_path([lam], max_iter=args.warmup, tol=0.0, step=sigma)
+    per = bool(args.persistent)
+    log(f"warmup {args.warmup} steps ({'one persistent launch' if per else 'one launch per phase'})")
+    cox.fit_path([lam], max_iter=args.warmup, tol=0.0, step=sigma, persistent=per)
     torch.cuda.synchronize()
     log(f"timing {args.steps} steps")
     cox.timing(True)
     t0 = time.perf_counter()
-    beta, iters, obj, _ = cox.fit_path([lam], max_iter=args.steps, tol=0.0, step=sigma)
+    beta, iters, obj, _ = cox.fit_path([lam], max_iter=args.steps, tol=0.0, step=sigma, persistent=per)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     xtr_ms, xtr_n = cox.timing_read("xtr")
     risk_ms, risk_n = cox.timing_read("risk")
     eta_ms, eta_n = cox.timing_read("eta")
     xk_ms, xk_n = cox.timing_read("xtr_kernel")
+    pk_ms, pk_n = cox.timing_read("persistent")
     cox.timing(False)
     elapsed = t1 - t0
     nnz = int((beta != 0).sum().item())
@@ -137,7 +192,7 @@ def bench_gauss_fp32(args):
     # Algorithmic bytes of one launch of the column-sum kernel (B = 1): X once,
     # r once, one FP64 sum per column written.
     xtr_bytes = n * p * 4 + n * 4 + p * 8
-    xtr_avg_s = xk_ms / max(xk_n, 1) / 1e3
+    xtr_avg_s = xk_ms / max(xk_n, 1) / 1e3 if not per else pk_ms / 1e3 / args.steps
     achieved = xtr_bytes / xtr_avg_s / 1e9
     steps_per_s = args.steps / elapsed
     res = {
@@ -154,12 +209,15 @@ def bench_gauss_fp32(args):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"l1-Cox ISTA, Gaussian FP32 X n={n} p={p}, lambda=0.3*lambda_max, B=1, "
-                               f"{args.steps} steps from beta=0",
+                               f"{args.steps} steps from beta=0" + (", one persistent launch" if per else ""),
                    "n": n, "p": p, "B": 1, "x_storage": "f32", "accumulate": "f64",
                    "eta": "active-set FP64 accumulator"},
         "phases_ms_per_step": {"xtr_prox": xtr_ms / max(xtr_n, 1), "risk": risk_ms / max(risk_n, 1),
                                "eta_update": eta_ms / max(eta_n, 1)},
-        "roofline": {"bound": "hbm", "kernel": "gemvt_sums_kernel (X~' r column sums)", "achieved": achieved,
+        "persistent": per,
+        "roofline": {"bound": "hbm", "kernel": "gemvt_sums_kernel (X~' r column sums)" if not per else
+                     "fit_persistent_kernel (the whole step; X~' r bytes over the launch time per step)",
+                     "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": stored_traffic(f"gemvt_sums_kernel_gauss_fp32_{n}x{p}_traffic.md", GEMVT_SOURCES),
                      "algorithmic_bytes_per_launch": xtr_bytes, "kernel_ms": 1e3 * xtr_avg_s,
@@ -198,6 +256,9 @@ def bench_geno_batched(args):
 
     n, p, B = args.n or 400000, args.p or 500000, args.batch
     ldx = (n + 15) // 16 * 16
+    probe = hbm_probe()
+    clocks = gpu_clocks()
+    log(f"HBM probe: copy {probe['copy_gbs']:.0f} GB/s, read {probe['read_gbs']:.0f} GB/s; clocks {clocks}")
     log(f"drawing survival times from the causal columns (n={n}, p={p})")
     d = coxsim.config4(n=n, p=p, materialize=False)
     log("generating FP8 genotype matrix in HBM")
@@ -219,13 +280,18 @@ def bench_geno_batched(args):
     log(f"warmup {args.warmup} steps (B={B}, residual in {args.residual_bits}-bit integers)")
     cox.fit_path(lams, max_iter=args.warmup, tol=0.0, step=sigma, residual_bits=args.residual_bits)
     torch.cuda.synchronize()
-    log(f"timing {args.steps} steps")
+    log(f"timing {args.steps} steps from beta = 0, {args.repeats} times")
     cox.timing(True)
-    t0 = time.perf_counter()
-    beta, iters, obj, _ = cox.fit_path(lams, max_iter=args.steps, tol=0.0, step=sigma,
-                                       residual_bits=args.residual_bits)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    runs = []
+    for rep in range(args.repeats):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        beta, iters, obj, _ = cox.fit_path(lams, max_iter=args.steps, tol=0.0, step=sigma,
+                                           residual_bits=args.residual_bits)
+        torch.cuda.synchronize()
+        runs.append(time.perf_counter() - t0)
+        log(f"repeat {rep}: {1e3 * runs[-1] / args.steps:.2f} ms per step")
+    eta_cols = cox.timing_columns()
     xtr_ms, xtr_n = cox.timing_read("xtr")
     risk_ms, risk_n = cox.timing_read("risk")
     eta_ms, eta_n = cox.timing_read("eta")
@@ -233,9 +299,10 @@ def bench_geno_batched(args):
     ek_ms, ek_n = cox.timing_read("eta_kernel")
     cov_ms, cov_n = cox.timing_read("cov")
     cox.timing(False)
-    elapsed = t1 - t0
+    elapsed = float(np.median(runs))
     nnz = (beta != 0).sum(dim=1).cpu().numpy()
-    log(f"{args.steps} steps x {B} lambdas in {elapsed:.3f} s; nnz per lambda {nnz.min()}..{nnz.max()}")
+    log(f"{args.steps} steps x {B} lambdas in {elapsed:.3f} s (median of {len(runs)}); "
+        f"nnz per lambda {nnz.min()}..{nnz.max()}")
     bpad = (B + 15) // 16 * 16
     tuning = cox.mfma_tuning()
     # Algorithmic bytes of one launch of the matrix-core X~' R kernel: X once,
@@ -245,6 +312,15 @@ def bench_geno_batched(args):
     xtr_avg = xk_ms / max(xk_n, 1) / 1e3
     achieved = xtr_bytes / xtr_avg / 1e9
     tops = 2.0 * n * p * limbs * bpad / xtr_avg / 1e12
+    # A whole step's algorithmic bytes: the X~' R pass above, and the eta
+    # update -- the changed columns of X (counted on the device), the update's
+    # limbs, the FP64 eta read and written once.  The O((n + p) B) phases
+    # (risk-set scans, quantisation, the proximal epilogue) move about 3 GB
+    # more at 400,000 x 500,000 and are left out.
+    cols_per_step = eta_cols / max(args.repeats * args.steps, 1)
+    eta_bytes = n * cols_per_step + 3 * bpad * cols_per_step + 2 * 8 * B * n
+    step_bytes = xtr_bytes + eta_bytes
+    step_gbs = step_bytes / elapsed * args.steps / 1e9
     res = {
         "metric": METRIC,
         "value": args.steps * B / elapsed,
@@ -271,12 +347,29 @@ def bench_geno_batched(args):
                                "eta_update": eta_ms / max(eta_n, 1),
                                "covariates": cov_ms / args.steps if args.covariates else 0.0},
         "kernels_ms_per_launch": {"mfma_xtr_split_kernel": xk_ms / max(xk_n, 1), "mfma_eta_kernel": ek_ms / max(ek_n, 1)},
+        "repeats": args.repeats,
+        "ms_per_step_runs": [1e3 * r / args.steps for r in runs],
+        "hbm_probe": probe,
+        "clocks": clocks,
+        "roofline_step": {"bound": "hbm", "what": "one whole step: X~' R pass + eta update over the changed "
+                                                  "columns, algorithmic bytes over the median step time",
+                          "bytes_per_step": step_bytes, "xtr_bytes": xtr_bytes, "eta_bytes": eta_bytes,
+                          "changed_columns_per_step": cols_per_step, "achieved": step_gbs, "peak": HBM_PEAK_GBS,
+                          "unit": "GB/s", "frac": step_gbs / HBM_PEAK_GBS,
+                          "frac_of_copy_probe": step_gbs / probe["copy_gbs"]},
         "roofline": {"bound": "hbm", "kernel": "mfma_xtr_split_kernel (X~' R for B lambdas)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "frac_of_copy_probe": achieved / probe["copy_gbs"],
+                     "frac_of_read_probe": achieved / probe["read_gbs"],
                      "traffic": stored_traffic(f"mfma_xtr_kernel_geno_fp8_{n}x{p}_b{B}_traffic.md", MFMA_SOURCES,
                                                f"shape{tuning['xtr_variant']}" + ("" if limbs == 3 else "_limbs2")),
                      "algorithmic_bytes_per_launch": xtr_bytes, "kernel_ms": 1e3 * xtr_avg, "launches_timed": xk_n,
                      "mfma_tops": tops, "mfma_frac_int8": tops / INT8_MFMA_PEAK_TOPS},
+        "eta_kernel_roofline": {"bound": "hbm", "kernel": "mfma_eta_kernel (eta += X[:, U] D for B lambdas)",
+                                "achieved": eta_bytes / (ek_ms / max(ek_n, 1) / 1e3) / 1e9 if ek_n else None,
+                                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": eta_bytes / (ek_ms / max(ek_n, 1) / 1e3) / 1e9 / HBM_PEAK_GBS if ek_n else None,
+                                "algorithmic_bytes_per_launch": eta_bytes},
         "nnz_range": [int(nnz.min()), int(nnz.max())],
         "autotune": tuning,
     }
@@ -533,8 +626,8 @@ def bench_nmf(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=0, help="default: 10 (batched) or 500 (gauss-fp32)")
-    ap.add_argument("--warmup", type=int, default=-1, help="default: 2 (batched) or 20 (gauss-fp32)")
+    ap.add_argument("--steps", type=int, default=0, help="default: 50 (batched), 1000 (nmf) or 500")
+    ap.add_argument("--warmup", type=int, default=-1, help="default: 3 (batched) or 20")
     ap.add_argument("--workload", default="geno-fp8-batched",
                     choices=["geno-fp8-batched", "gauss-fp32", "refit", "nmf"])
     ap.add_argument("--nmf-rank", type=int, default=20, help="nmf workload: rank r")
@@ -542,6 +635,8 @@ def main():
     ap.add_argument("--refit-cols", type=int, default=333, help="refit workload: SNP columns refitted")
     ap.add_argument("--refit-gtol", type=float, default=1e-6, help="refit workload: Newton stop, max |gradient|")
     ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--repeats", type=int, default=3,
+                    help="batched workload: timed runs of K steps from beta = 0; the median is reported")
     ap.add_argument("--power-steps", type=int, default=20)
     ap.add_argument("--residual-bits", type=int, default=22, choices=[22, 14],
                     help="batched workload: residual rounding of the matrix-core gradient pass "
@@ -555,6 +650,8 @@ def main():
                     help="batched workload: attach this many unpenalised covariates (sex + principal components)")
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--p", type=int, default=0)
+    ap.add_argument("--persistent", action="store_true",
+                    help="gauss-fp32 workload: the whole fit in one persistent launch")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -575,9 +672,9 @@ def main():
         torch.cuda.empty_cache()
     batched = args.workload == "geno-fp8-batched"
     if args.steps <= 0:
-        args.steps = {"geno-fp8-batched": 10, "nmf": 1000}.get(args.workload, 500)
+        args.steps = {"geno-fp8-batched": 50, "nmf": 1000}.get(args.workload, 500)
     if args.warmup < 0:
-        args.warmup = 2 if batched else 20
+        args.warmup = 3 if batched else 20
     res = {"gauss-fp32": bench_gauss_fp32, "geno-fp8-batched": bench_geno_batched,
            "refit": bench_refit, "nmf": bench_nmf}[args.workload](args)
     print(json.dumps(res), flush=True)

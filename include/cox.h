@@ -150,11 +150,14 @@ typedef struct {
     int32_t warm_start; /* 1: start from the beta passed in; 0: start from beta = 0 */
     int32_t persistent; /* 0: one launch per phase of each step, the host checking the stopping flags
                            every `poll` steps; 1: the whole call -- every step of every b, the stopping
-                           rule included -- in one persistent (cooperative) launch with grid-wide
-                           barriers between the phases.  persistent = 1 serves the vector path
-                           (B <= 8, eta_mode 0, no covariates); other requests with persistent = 1
-                           return UNSUPPORTED.  Both forms take the same steps in the same arithmetic
-                           and give bit-identical results. */
+                           rule included -- in one persistent (cooperative) launch whose workgroups are
+                           all resident at once, with grid-wide barriers between the phases.
+                           persistent = 1 serves the vector path: B <= 8 (not the batched matrix-core
+                           pass), eta_mode 0, no covariate block, X 16-byte aligned with ldx times the
+                           element size a multiple of 16; other requests return UNSUPPORTED before any
+                           device work.  Both forms run the same per-workgroup code in the same order
+                           and give bit-identical results.  A barrier that waits longer than 60 s
+                           abandons the launch (DEVICE). */
     int32_t deterministic; /* 0 or 1.  Results are always bit-reproducible run to run (fixed-order
                               reductions, no floating-point atomics), so both values give the same
                               computation; 1 documents the requirement. */
@@ -329,8 +332,10 @@ cox_status cox_nll_backward(cox_ctx *ctx, const double *grad_loss, int32_t B, vo
  * 8 vectors), COX_PHASE_ETA_KERNEL (each launch of the matrix-core eta kernel
  * alone), COX_PHASE_COV (the covariate block's Z' r with its proximal step, and
  * its eta update; nothing without covariates), COX_PHASE_REFIT_HESSIAN (each
- * evaluation of the refit's information matrix) and COX_PHASE_REFIT_SOLVE (each
- * Cholesky factorisation and Newton solve of the refit).
+ * evaluation of the refit's information matrix), COX_PHASE_REFIT_SOLVE (each
+ * Cholesky factorisation and Newton solve of the refit) and
+ * COX_PHASE_PERSISTENT (each persistent launch of cox_fit_path, all its steps;
+ * the other phases record nothing inside it).
  * cox_timing_enable(ctx, 1) starts recording and clears the totals; 0 stops.
  * cox_timing_read returns the summed milliseconds and the number of timed
  * launches of a phase since the last enable.  Synchronises. */
@@ -342,7 +347,8 @@ typedef enum {
     COX_PHASE_ETA_KERNEL = 4,
     COX_PHASE_COV = 5,
     COX_PHASE_REFIT_HESSIAN = 6,
-    COX_PHASE_REFIT_SOLVE = 7
+    COX_PHASE_REFIT_SOLVE = 7,
+    COX_PHASE_PERSISTENT = 8
 } cox_phase;
 
 /* The batched matrix-core passes (X~' R and the eta update, used when X holds
@@ -354,11 +360,18 @@ typedef enum {
  * choices (-1: not yet tuned) and the tuning times in milliseconds (host
  * [COX_MFMA_VARIANTS] each, nullable; entries past a pass's shape count and
  * entries of a pass that was not timed are 0). */
-#define COX_MFMA_VARIANTS 5
+#define COX_MFMA_VARIANTS 8
 #define COX_MFMA_ETA_VARIANTS 5
 cox_status cox_mfma_tuning(cox_ctx *ctx, int32_t *xtr_variant, int32_t *eta_variant, float *xtr_ms, float *eta_ms);
 cox_status cox_timing_enable(cox_ctx *ctx, int32_t enable);
 cox_status cox_timing_read(cox_ctx *ctx, int32_t phase, double *total_ms, int64_t *count);
+
+/* Measurement: the columns of X the active-set eta updates of cox_fit_path
+ * read since cox_timing_enable(ctx, 1) (the change list's length summed over
+ * the steps; the multi-launch form with eta_mode 0 only -- dense passes and
+ * persistent launches add nothing).  It gives the bytes of X a step moves
+ * beside the full pass of X~' r.  eta_columns host [1].  Synchronises. */
+cox_status cox_timing_columns(cox_ctx *ctx, int64_t *eta_columns);
 
 #ifdef __cplusplus
 }

@@ -24,7 +24,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "cox.h")
 NMF_HEADER = os.path.join(os.path.dirname(_HERE), "include", "nmf.h")
 
 X_F32, X_FP8_E4M3, X_INT8 = 0, 1, 2
-MFMA_VARIANTS = 5  # COX_MFMA_VARIANTS: pipeline shapes of the X~' R pass (and the tuning arrays' length)
+MFMA_VARIANTS = 8  # COX_MFMA_VARIANTS: pipeline shapes of the X~' R pass (and the tuning arrays' length)
 ETA_VARIANTS = 5  # COX_MFMA_ETA_VARIANTS: pipeline shapes of the eta update
 MAX_COVARIATES = 64  # COX_MAX_COVARIATES
 MAX_REFIT = 1024  # COX_MAX_REFIT
@@ -94,6 +94,7 @@ def lib():
         "cox_timing_enable": [vp, i32],
         "cox_mfma_tuning": [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), vp, vp],
         "cox_timing_read": [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64)],
+        "cox_timing_columns": [vp, ctypes.POINTER(i64)],
         "nmf_setup": [ctypes.POINTER(vp), vp, i64, i64, i64, i32, vp],
         "nmf_destroy": [vp],
         "nmf_last_error": [vp, ctypes.c_char_p, ctypes.c_size_t],
@@ -343,7 +344,7 @@ class Cox:
         return loss
 
     PHASES = {"xtr": 0, "risk": 1, "eta": 2, "xtr_kernel": 3, "eta_kernel": 4, "cov": 5, "refit_hessian": 6,
-              "refit_solve": 7}
+              "refit_solve": 7, "persistent": 8}
 
     def mfma_tuning(self):
         """Pipeline shapes chosen by the autotuner and their tuning times (ms)."""
@@ -364,6 +365,12 @@ class Cox:
         self._check(lib().cox_timing_read(self._h, self.PHASES[phase], ctypes.byref(ms), ctypes.byref(cnt)),
                     "cox_timing_read")
         return ms.value, cnt.value
+
+    def timing_columns(self) -> int:
+        """Columns of X read by the active-set eta updates since timing(True)."""
+        v = ctypes.c_int64()
+        self._check(lib().cox_timing_columns(self._h, ctypes.byref(v)), "cox_timing_columns")
+        return v.value
 
     @staticmethod
     def forward_key(eta):

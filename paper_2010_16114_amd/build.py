@@ -15,7 +15,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcoxhip.so")
-SOURCES = ["api.cpp", "risk.hip", "gemv.hip", "gemvt.hip", "misc.hip", "mfma.hip", "covar.hip", "refit.hip", "nmf.hip"]
+SOURCES = ["api.cpp", "risk.hip", "gemv.hip", "gemvt.hip", "misc.hip", "mfma.hip", "covar.hip", "refit.hip", "nmf.hip",
+           "persist.hip"]
 ARCH = os.environ.get("COXHIP_ARCH", "gfx950")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -30,7 +30,7 @@
 
 using namespace cox;
 
-constexpr int kPhases = 8;  // cox_phase values
+constexpr int kPhases = 9;  // cox_phase values
 
 static_assert(kMfmaVariants == COX_MFMA_VARIANTS && kMfmaEtaVariants == COX_MFMA_ETA_VARIANTS,
               "pipeline shape counts differ from the header");
@@ -43,6 +43,7 @@ constexpr int kMaxBatch = 64;
 constexpr int kGroup = 8;  // coefficient vectors per VALU pass over X
 constexpr int kFreeCovMaxIter = 100000;  // steps of the unpenalised covariate fit inside cox_lambda_max
 constexpr double kFreeCovGtol = 1e-10;   // its stop: max |g_k| below this fraction of its value at zero
+constexpr double kPersistWaitLimit = 60.0;  // seconds one grid barrier of the persistent fit may wait
 
 int64_t round_up(int64_t a, int64_t m) { return (a + m - 1) / m * m; }
 
@@ -109,6 +110,10 @@ struct cox_ctx {
     double *l1old = nullptr, *l1new = nullptr;
     double *L = nullptr, *sumr = nullptr, *lam = nullptr, *fobj = nullptr, *hist = nullptr, *scal = nullptr;
     int32_t *kit = nullptr, *active = nullptr, *iters = nullptr, *status = nullptr;
+    // the persistent fit's grid barrier: arrival counter, abort flag, generation words
+    unsigned long long* bar_words = nullptr;
+    long long* col_count = nullptr;  // columns of X read by eta updates while timing is on
+    int persist_grid = 0;  // workgroups of the last persistent launch
     int fwd_B = 0, fwd_f64 = 0;
     int64_t n_events = 0;
     // the dense covariate block Z beside X, and the penalty factors
@@ -924,7 +929,8 @@ cox_status cox_setup(cox_ctx** out, const cox_matrix* X, const double* time, con
               dalloc(c, &c->cov_part, (size_t)max_batch * cov_row_blocks(n) * kMaxCov) &&
               dalloc(c, &c->betaZ, (size_t)max_batch * kMaxCov) && dalloc(c, &c->dZ, (size_t)max_batch * kMaxCov) &&
               dalloc(c, &c->gZ, (size_t)max_batch * kMaxCov) && dalloc(c, &c->l1c_old, max_batch) &&
-              dalloc(c, &c->l1c_new, max_batch) && dalloc(c, &c->pf, p + kMaxCov);
+              dalloc(c, &c->l1c_new, max_batch) && dalloc(c, &c->pf, p + kMaxCov) &&
+              dalloc(c, &c->bar_words, persist_barrier_words()) && dalloc(c, &c->col_count, 1);
     const bool mfma_able = X->xtype != COX_X_F32 && c->x.vec16 && max_batch > kGroup;
     if (ok && mfma_able) {
         c->bpad_max = (int)round_up(max_batch, 16);
@@ -1184,8 +1190,10 @@ cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_
         return fail(c, COX_ERR_INVALID_ARG, "bad cox_fit_opts");
     if (o.trace && (int64_t)B * ((int64_t)o.max_iter + 1) > (int64_t(1) << 31))
         return fail(c, COX_ERR_INVALID_ARG, "trace: B * (max_iter + 1) is too large");
-    if (o.persistent)
-        return fail(c, COX_ERR_UNSUPPORTED, "persistent: not available in this build");
+    if (o.persistent && (use_mfma(c, B) || B > kGroup || o.eta_mode != 0 || c->q != 0 || !c->x.vec16))
+        return fail(c, COX_ERR_UNSUPPORTED,
+                    "persistent = 1 serves the vector path: B <= 8 (not the batched matrix-core pass), eta_mode 0, "
+                    "no covariate block, X 16-byte aligned with ldx * element size a multiple of 16");
     const int rlimbs = o.residual_bits == 14 ? 2 : 3;
     const int poll = o.poll > 0 ? o.poll : 16;
     double step = o.step;
@@ -1244,7 +1252,23 @@ cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_
     g.active = c->active;
     const int64_t cstride = (int64_t)c->Bmax * c->n;
 
-    for (int it = 0; it <= o.max_iter; ++it) {
+    if (o.persistent) {
+        PersistArgs pa{ra, g, c->sel, c->sel, c->nsel, c->dcoef, c->part_upd, cstride, c->ncg, o.max_iter, B};
+        pa.g.b0 = 0;
+        pa.g.nb = B;
+        pa.g.first_group = 1;
+        HIPCHK(launch_fill_f64(reinterpret_cast<double*>(c->bar_words), 0.0, persist_barrier_words(), c->stream),
+               "reset");
+        tmark(c, COX_PHASE_PERSISTENT);
+        HIPCHK(launch_fit_persistent(pa, c->bar_words, kPersistWaitLimit, c->stream, &c->persist_grid),
+               "persistent fit");
+        tmark(c, COX_PHASE_PERSISTENT);
+        unsigned long long aborted = 0;
+        STCHK(d2h(c, &aborted, c->bar_words + persist_abort_word(), sizeof(aborted)));
+        if (aborted)
+            return fail(c, COX_ERR_DEVICE, "persistent fit: a grid barrier waited past its limit; launch abandoned");
+    }
+    for (int it = 0; it <= o.max_iter && !o.persistent; ++it) {
         if (it > 0) {
             if (o.eta_mode == 0 && mfma) {
                 tmark(c, COX_PHASE_ETA);
@@ -1296,7 +1320,10 @@ cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_
         if (it < o.max_iter) {
             STCHK(run_gemvt(c, g, B, rlimbs));
             STCHK(cov_grad(c, ra, B, c->active, cst));
-            if (o.eta_mode == 0) HIPCHK(launch_compact(c->chg_cnt, c->chg_idx, c->nblk, c->sel, c->nsel, c->stream), "compact");
+            if (o.eta_mode == 0) {
+                HIPCHK(launch_compact(c->chg_cnt, c->chg_idx, c->nblk, c->sel, c->nsel, c->stream), "compact");
+                if (c->timing) HIPCHK(launch_count_add(c->nsel, c->col_count, c->stream), "column count");
+            }
         }
         if ((it + 1) % poll == 0 && it < o.max_iter) {
             std::vector<int32_t> act(B);
@@ -1620,6 +1647,17 @@ cox_status cox_timing_enable(cox_ctx* c, int32_t enable)
     STCHK(sync(c));
     timing_clear(c);
     c->timing = enable != 0;
+    HIPCHK(launch_fill_f64(reinterpret_cast<double*>(c->col_count), 0.0, 1, c->stream), "reset column count");
+    return COX_OK;
+}
+
+cox_status cox_timing_columns(cox_ctx* c, int64_t* eta_columns)
+{
+    STCHK(check_ctx(c));
+    if (!eta_columns) return fail(c, COX_ERR_INVALID_ARG, "eta_columns is NULL");
+    long long v = 0;
+    STCHK(d2h(c, &v, c->col_count, sizeof(v)));
+    *eta_columns = (int64_t)v;
     return COX_OK;
 }
 

@@ -128,6 +128,36 @@ struct GemvtArgs {
     int first_group;       // 1 on the launch with b0 == 0: it resets the change lists
 };
 
+// cox_fit_path as one persistent launch (persist.hip): the vector path (B <=
+// 8, active-set eta update, no covariate block, 16-byte loads legal).  Each
+// step runs the phases of the multi-launch form -- eta update (from the second
+// step), the five risk-set phases with the stopping rule, X~' r with the
+// proximal epilogue, the change-list compaction -- over a grid of co-resident
+// workgroups separated by grid-wide barriers, with the same per-workgroup code
+// and therefore the same arithmetic; the loop ends when every b has stopped.
+struct PersistArgs {
+    RiskArgs ra;           // use_ctl = 1; part = the eta partials
+    GemvtArgs g;           // GT_PROX, b0 = 0, nb = B, first_group = 1
+    const int32_t* sel;    // change list (compacted), device count nsel
+    int32_t* sel_w;        // the same buffer, written by the compaction
+    int32_t* nsel;
+    const double* dcoef;   // [B][p] coefficient changes times the genotype scale
+    double* part_upd;      // [ncg][Bmax][n] eta partials
+    int64_t cstride;       // Bmax * n
+    int ncg;
+    int max_iter;
+    int B;
+};
+// words: persist_barrier_words() device words zeroed before the launch (the
+// barrier's arrival counter, abort flag -- word persist_abort_word() -- and
+// generation words); limit_s: the longest wait at one barrier before the
+// launch is abandoned (abort flag set to 1).  grid_out: workgroups launched
+// (co-resident, from the kernel's occupancy).
+int persist_barrier_words();
+constexpr int persist_abort_word() { return 32; }
+hipError_t launch_fit_persistent(const PersistArgs& a, unsigned long long* words, double limit_s, hipStream_t s,
+                                 int* grid_out);
+
 // Launchers (return hipError_t of the launch).
 hipError_t launch_risk(const RiskArgs& a, hipStream_t s);
 hipError_t launch_gemvt(const GemvtArgs& a, hipStream_t s);       // sums, then epilogue
@@ -170,6 +200,8 @@ hipError_t launch_to_r32(const double* u, const double* shift, float* r32, doubl
 // out[b] = a * sum_i in[b*m + i], one workgroup per b, fixed order
 hipError_t launch_rowsum(const double* in, int64_t m, int B, double a, double* out, hipStream_t s);
 hipError_t launch_fill_f64(double* p, double v, int64_t m, hipStream_t s);
+// acc[0] += v[0]
+hipError_t launch_count_add(const int32_t* v, long long* acc, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t m, hipStream_t s);
 
 // ---- the dense covariate block Z beside X (covar.hip)

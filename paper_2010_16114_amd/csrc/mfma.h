@@ -24,9 +24,11 @@ struct MfmaArgs {
     double* out;            // [B][p] raw sums q_b * sum_i g_ij R_bi
     int variant;            // pipeline shape (compute + loader wavefronts, M tiles per compute
                             // wavefront, subjects per stage, stages ahead): 0 = 7+1, 3, 64, 6;
-                            // 1 = 7+1, 3, 64, 4; 2 = 6+2, 3, 64, 6; 3 = 6+2, 3, 64, 4; 4 = 6+2, 3, 128, 2
+                            // 1 = 7+1, 3, 64, 4; 2 = 6+2, 3, 64, 6; 3 = 6+2, 3, 64, 4; 4 = 6+2, 3, 128, 2;
+                            // direct-to-LDS limb tiles, 8 compute wavefronts, bpad = 64 only:
+                            // 5 = 3, 128, 3; 6 = the same with streaming X loads; 7 = 3, 128, 2
 };
-constexpr int kMfmaVariants = 5;     // shapes of the X~' R pass
+constexpr int kMfmaVariants = 8;     // shapes of the X~' R pass
 constexpr int kMfmaEtaVariants = 5;  // shapes of the eta update
 
 // eta_b(i) += q_b * sum_{u < nsel} g(i, sel[u]) D_b(u), D in three int8 limbs.

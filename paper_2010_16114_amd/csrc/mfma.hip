@@ -212,6 +212,133 @@ __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_split_
     }
 }
 
+// X~' R with the limb tile moved by direct global-to-LDS loads
+// (global_load_lds_dwordx4): B = 49..64 (four N groups of 16), CW = 8 compute
+// wavefronts and no loader.  Each wavefront issues its share of every stage's
+// limb tile beside its own A runs, PF stages ahead, into an LDS ring of PF + 1
+// stage slots; the loads of one wavefront complete in issue order, so waiting
+// until at most (PF - 1) stages of its loads are outstanding leaves stage t's
+// A runs in registers and its share of stage t's limb tile in LDS, and one
+// barrier then makes the whole tile visible.  The slot written for stage
+// t + PF is the one stage t - 1 used, which every wavefront left at that
+// barrier.  A 64-lane load writes 64 consecutive 16-byte chunks of LDS, so each
+// fills one third (three limbs) or one half (two) of a chunk row; the rows
+// keep the padded stride of the split kernel's tile.  With the limb loads in
+// the same in-order queue as the A runs and no loader wavefront, a limb tile
+// is requested PF stages before it is used instead of two.
+template <int XT, int RL, int MT, int KS, int PF, bool NTX>
+__global__ __launch_bounds__(512, 2) void mfma_xtr_lds_kernel(MfmaArgs a)
+{
+    constexpr int CW = 8, NG = 4;
+    constexpr int WCOLS = 16 * MT * CW;  // SNP columns per workgroup
+    constexpr int KC = 64 * KS;          // subjects per stage
+    constexpr int NT = RL * NG;          // N tiles, limb-major
+    constexpr int NCOL = 16 * NT;        // limb columns = 16-byte chunks per 16-subject row
+    constexpr int QC = KC / 16;          // chunk rows per stage
+    constexpr int CHUNKS = NCOL * QC;
+    constexpr int NI = CHUNKS / 64;      // 64-chunk loads per stage
+    constexpr int NIW = NI / CW;         // per wavefront
+    constexpr int RS = NCOL + 8;         // LDS row stride (chunks)
+    constexpr int NS = PF + 1;           // LDS stage slots
+    constexpr int GPR = NCOL / 64;       // loads per chunk row
+    static_assert(NI % CW == 0 && NCOL % 64 == 0, "the limb tile splits evenly over the wavefronts");
+    static_assert(PF >= 2, "at least one stage in flight");
+    // outstanding loads of one wavefront allowed at the top of a stage
+    constexpr int VM_KEEP = (PF - 1) * (MT * KS + NIW);
+    static_assert(VM_KEEP < 64, "vmcnt holds 6 bits");
+    __shared__ v4i sR[NS][QC * RS];
+
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int64_t n = a.n, p = a.p, ldx = a.ldx;
+    const uint8_t* __restrict__ X = static_cast<const uint8_t*>(a.X);
+    const int64_t nstage = (n + KC - 1) / KC;
+    const int64_t nloop = (nstage + PF - 1) / PF * PF;
+    const int arow = 16 * (lane >> 4);
+    const int acol = lane & 15;
+    const int64_t jw = (int64_t)blockIdx.x * WCOLS + wid * (16 * MT);
+
+    // this wavefront's limb loads: load q = wid + CW u covers chunk row q / GPR,
+    // chunks 64 (q % GPR) .. + 63 of it
+    int lsrc[NIW], ldst[NIW];
+#pragma unroll
+    for (int u = 0; u < NIW; ++u) {
+        const int q = wid + CW * u;
+        lsrc[u] = ((q / GPR) * NCOL + 64 * (q % GPR) + lane) * 16;
+        ldst[u] = (q / GPR) * RS + 64 * (q % GPR);
+    }
+
+    v4i acc[MT][NT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = v4i{0, 0, 0, 0};
+    v4i Ab[PF][MT][KS];
+    // stage t: A runs into ring slot t mod PF, limb tile into LDS slot t mod NS
+    // (stages past the end load the last stage's tile again; they are never used)
+    auto issue = [&](int64_t t, v4i (&A)[MT][KS]) {
+        const int64_t k0 = t * KC;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                A[mt][ks] = load_raw<NTX>(X, jw + mt * 16 + acol, p, ldx, k0 + ks * 64 + arow, n);
+        const int8_t* src = a.limbs + min(t, nstage - 1) * (int64_t)(16 * CHUNKS);
+        v4i* slot = sR[(int)(t % NS)];
+#pragma unroll
+        for (int u = 0; u < NIW; ++u)
+            __builtin_amdgcn_global_load_lds(static_cast<const void*>(src + lsrc[u]),
+                                             (__attribute__((address_space(3))) void*)(slot + ldst[u]), 16, 0, 0);
+    };
+#pragma unroll
+    for (int q = 0; q < PF; ++q) issue(q, Ab[q]);
+    for (int64_t s0 = 0; s0 < nloop; s0 += PF) {
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int64_t t = s0 + q;
+            // this wavefront's loads of stage t are done (vmcnt: low 4 bits in
+            // [3:0], high 2 in [15:14]; expcnt and lgkmcnt left at their maxima)
+            __builtin_amdgcn_s_waitcnt((VM_KEEP & 15) | ((VM_KEEP >> 4) << 14) | (7 << 4) | (15 << 8));
+            __builtin_amdgcn_s_barrier();
+            if (t < nstage) {
+                const v4i* sb = &sR[(int)(t % NS)][(lane >> 4) * RS + acol];
+                v4i bcur = sb[0];
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) {
+                    v4i A[MT];
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) A[mt] = decode_a<XT>(Ab[q][mt][ks]);
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) {
+                        const int f = ks * NT + nt + 1;  // next fragment
+                        v4i bnext = bcur;
+                        if (f < KS * NT) bnext = sb[(f / NT) * 4 * RS + (f % NT) * 16];
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt)
+                            acc[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], bcur, acc[mt][nt], 0, 0, 0);
+                        bcur = bnext;
+                    }
+                }
+            }
+            issue(t + PF, Ab[q]);
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // no load into LDS outlives the workgroup
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int bq = 0; bq < NG; ++bq)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int b = bq * 16 + acol;
+                const int64_t j = jw + mt * 16 + mfma_c_row(lane, v);
+                if (j < p && b < a.B) {
+                    int64_t tot = (int64_t)acc[mt][bq][v] + 256 * (int64_t)acc[mt][NG + bq][v];
+                    if constexpr (RL == 3) tot += 65536 * (int64_t)acc[mt][2 * NG + bq][v];
+                    a.out[(int64_t)b * p + j] = a.qscale[b] * (double)tot;
+                }
+            }
+}
+
 // Byte transpose of a 4 x 4 block: d[r] holds bytes (x_r0, x_r1, x_r2, x_r3);
 // o[c] receives (x_0c, x_1c, x_2c, x_3c).  __builtin_amdgcn_perm(hi, lo, sel)
 // picks byte sel_k of the 8-byte value hi:lo for result byte k.
@@ -613,9 +740,29 @@ hipError_t launch_split(const MfmaArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int XT, int RL, int MT, int KS, int PF, bool NTX>
+hipError_t launch_lds(const MfmaArgs& a, hipStream_t s)
+{
+    constexpr int WCOLS = 16 * MT * 8;
+    hipLaunchKernelGGL((mfma_xtr_lds_kernel<XT, RL, MT, KS, PF, NTX>), dim3((unsigned)((a.p + WCOLS - 1) / WCOLS)),
+                       dim3(512), 0, s, a);
+    return hipGetLastError();
+}
+
 template <int XT, int NG, int RL>
 hipError_t launch_ng(const MfmaArgs& a, hipStream_t s)
 {
+    // shapes 5..7 (direct-to-LDS limb tiles) serve four N groups only (B = 49..64)
+    if constexpr (NG == 4) {
+        switch (a.variant) {
+        case 5: return launch_lds<XT, RL, 3, 2, 3, false>(a, s);
+        case 6: return launch_lds<XT, RL, 3, 2, 3, true>(a, s);
+        case 7: return launch_lds<XT, RL, 3, 2, 2, false>(a, s);
+        default: break;
+        }
+    } else {
+        if (a.variant >= 5) return hipErrorInvalidValue;
+    }
     switch (a.variant) {
     case 1: return launch_split<XT, NG, RL, 7, 1, 3, 1, 4>(a, s);
     case 2: return launch_split<XT, NG, RL, 6, 2, 3, 1, 6>(a, s);

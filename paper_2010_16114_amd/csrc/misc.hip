@@ -135,6 +135,9 @@ __global__ void to_r32_kernel(const double* __restrict__ u, const double* __rest
     if (threadIdx.x == 0) sumr[0] = s;
 }
 
+// acc[0] += v[0] (one thread): running count of the columns the eta updates read.
+__global__ void count_add_kernel(const int32_t* __restrict__ v, long long* __restrict__ acc) { acc[0] += v[0]; }
+
 __global__ void rowsum_kernel(const double* __restrict__ in, int64_t m, double a, double* __restrict__ out)
 {
     const int64_t b = blockIdx.x;
@@ -207,6 +210,12 @@ hipError_t launch_to_r32(const double* u, const double* shift, float* r32, doubl
 {
     COX_LAUNCH(to_r32_kernel, 1, u, shift, r32, sumr, n);
 }
+hipError_t launch_count_add(const int32_t* v, long long* acc, hipStream_t s)
+{
+    hipLaunchKernelGGL(count_add_kernel, dim3(1), dim3(1), 0, s, v, acc);
+    return hipGetLastError();
+}
+
 hipError_t launch_rowsum(const double* in, int64_t m, int B, double a, double* out, hipStream_t s)
 {
     COX_LAUNCH(rowsum_kernel, B, in, m, a, out);
