@@ -23,6 +23,21 @@ Workloads (synthetic, seeded; they stand in for the UK Biobank genotypes):
   nmf        : Section 5.1's NMF on its GPU shape, X 10,000 x 10,000 uniform
                FP32, rank 20 (--nmf-rank), multiplicative update (--nmf-algo 1:
                APG), 1000 iterations timed.
+  geno-fp8-c3: n = 200,000 x p = 200,000 FP8 genotypes, one lambda =
+               0.2 lambda_max, ISTA to a relative objective change below 1e-8
+               over 10 steps; beside it the plain FP32 method on the same X
+               standardised to FP32 (160 GB resident), unscaled, to the same
+               tolerance, both checked against the FP64 oracle's objective.
+  autograd-c2: n = 100,000 x p = 10,000 FP32 standardised genotypes with
+               times in days (ties): milliseconds per forward + backward of
+               the torch.autograd functions.
+
+The batched workload times K steps from beta = 0 `--repeats` times (default
+3) and reports the median run; it also measures the HBM bandwidth the same
+run sees (a torch copy and a torch reduction of a 4 GiB buffer), reads the
+GPU clocks, and reports a per-step roofline: the algorithmic bytes of the
+X~' R pass plus those of the eta update over the columns that changed
+(counted on the device) over the median step time.
 
 The oracle (plain FP64 C) is timed on the host cores on a bounded sample of
 the same workload as the CPU baseline.
@@ -395,14 +410,7 @@ def fp32_comparator(args, d, G, mu_d, sc_d, lams, sigma, n, p):
 
     ps = min(args.fp32_slice, p)
     log(f"FP32 comparator: standardising {ps} columns to FP32")
-    X32 = torch.empty((ps, G.shape[1]), dtype=torch.float32, device="cuda")
-    for j0 in range(0, ps, 4096):
-        j1 = min(ps, j0 + 4096)
-        code = G[j0:j1].to(torch.int32)
-        cnt = ((code >> 3) & 1) | ((code >> 5) & 2)  # FP8 E4M3 codes of 0, 1, 2 -> counts
-        X32[j0:j1] = (cnt.to(torch.float32) - mu_d[j0:j1, None]) * sc_d[j0:j1, None]
-        del code, cnt
-    X32[:, n:] = 0.0
+    X32 = standardise_fp8_to_fp32(G, mu_d, sc_d, ps, n)
     torch.cuda.synchronize()
     cox = P.Cox(X32, d.time, d.event, n=n, max_batch=1)
     rates = []
@@ -446,6 +454,175 @@ def cpu_baseline_geno(d, lam, sigma, p_full, p_sample: int = 8000, budget_s: flo
     return {"value": k / dt * p_sample / p_full, "unit": "lambda-iters/s", "cores": cpu_threads(), "kind": "oracle",
             "sample": f"first {k} ISTA steps from beta=0 at lambda=0.01*lambda_max on the first {p_sample} of "
                       f"{p_full} columns (n={d.n}), scaled by {p_sample}/{p_full}"}
+
+
+def standardise_fp8_to_fp32(G, mu_d, sc_d, ps, n, step=4096):
+    """FP32 X~ = (g - mu) s of the first ps columns of FP8-coded counts G (on the device)."""
+    import torch
+
+    X32 = torch.empty((ps, G.shape[1]), dtype=torch.float32, device="cuda")
+    for j0 in range(0, ps, step):
+        j1 = min(ps, j0 + step)
+        code = G[j0:j1].to(torch.int32)
+        cnt = ((code >> 3) & 1) | ((code >> 5) & 2)  # FP8 E4M3 codes of 0, 1, 2 -> counts
+        X32[j0:j1] = (cnt.to(torch.float32) - mu_d[j0:j1, None]) * sc_d[j0:j1, None]
+        del code, cnt
+    X32[:, n:] = 0.0
+    return X32
+
+
+def bench_geno_fp8_c3(args):
+    """The precision workload: 200,000 x 200,000 genotypes stored as FP8 E4M3 codes
+    (40 GB), one lambda = 0.2 lambda_max, ISTA from beta = 0 until the relative
+    objective change over 10 steps is below 1e-8; beside it the plain FP32 method
+    on the same X standardised to FP32 (160 GB, resident too), same step, same
+    stopping rule.  Both results are checked against the FP64 oracle's objective
+    at the returned beta (from the support columns regenerated on the host)."""
+    import torch
+
+    import coxsim
+    import oracle
+    import paper_2010_16114_amd as P
+
+    n, p = args.n or 200000, args.p or 200000
+    tol, lag = 1e-8, 10
+    ldx = (n + 15) // 16 * 16
+    probe = hbm_probe()
+    d = coxsim.config3(n=n, p=p)
+    log(f"generating FP8 genotype matrix {n}x{p} in HBM")
+    G, c1, c2 = coxsim.genotype_device(n, p, d.seed, d.thresholds, fmt=1, ldx=ldx)
+    mu, sc = coxsim.standardisation(c1, c2, n)
+    mu_d, sc_d = torch.from_numpy(mu).cuda(), torch.from_numpy(sc).cuda()
+    cox = P.Cox(G, d.time, d.event, xtype=P.X_FP8_E4M3, n=n, center=mu_d, scale=sc_d)
+    lam = 0.2 * cox.lambda_max()
+    s2, pit = cox.opnorm2(maxiter=args.power_steps)
+    sigma = 1.0 / (2.0 * s2)
+    runs = {}
+    for name, c in (("fp8", cox),):
+        c.fit_path([lam], max_iter=3, tol=0.0, step=sigma)
+        torch.cuda.synchronize()
+        c.timing(True)
+        t0 = time.perf_counter()
+        beta, it, obj, st = c.fit_path([lam], max_iter=5000, tol=tol, lag=lag, step=sigma)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        xk_ms, xk_n = c.timing_read("xtr_kernel")
+        c.timing(False)
+        runs[name] = (beta.cpu().numpy()[0].astype(np.float64), int(it[0]), float(obj[0]), dt, xk_ms / max(xk_n, 1))
+        log(f"{name}: {it[0]} steps to tolerance in {dt:.3f} s ({1e3 * dt / it[0]:.3f} ms per step), f = {obj[0]:.12g}")
+    log("standardising to FP32 (160 GB)")
+    X32 = standardise_fp8_to_fp32(G, mu_d, sc_d, p, n)
+    torch.cuda.synchronize()
+    c32 = P.Cox(X32, d.time, d.event, n=n)
+    c32.fit_path([lam], max_iter=3, tol=0.0, step=sigma)
+    torch.cuda.synchronize()
+    c32.timing(True)
+    t0 = time.perf_counter()
+    beta, it, obj, st = c32.fit_path([lam], max_iter=5000, tol=tol, lag=lag, step=sigma)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    xk_ms, xk_n = c32.timing_read("xtr_kernel")
+    c32.timing(False)
+    runs["fp32"] = (beta.cpu().numpy()[0].astype(np.float64), int(it[0]), float(obj[0]), dt, xk_ms / max(xk_n, 1))
+    log(f"fp32: {it[0]} steps to tolerance in {dt:.3f} s ({1e3 * dt / it[0]:.3f} ms per step), f = {obj[0]:.12g}")
+    c32.close()
+    del X32
+    torch.cuda.empty_cache()
+    # the oracle's FP64 objective at each returned beta, from its support columns
+    b8, b32 = runs["fp8"][0], runs["fp32"][0]
+    cols = np.union1d(np.flatnonzero(b8), np.flatnonzero(b32))
+    Gh = coxsim.genotype_columns(n, cols, d.seed, d.thresholds[cols])
+    M = oracle.Matrix.genotype(Gh, mu[cols], sc[cols])
+    checks = {}
+    for name in ("fp8", "fp32"):
+        bv = runs[name][0]
+        L, _ = oracle.loglik(oracle.xbeta(M, bv[cols]), d.time, d.event)
+        f_or = -L + lam * np.abs(bv).sum()
+        checks[name] = abs(runs[name][2] - f_or) / abs(f_or)
+    k8, t8, ms8 = runs["fp8"][1], runs["fp8"][3], runs["fp8"][4]
+    k32, t32, ms32 = runs["fp32"][1], runs["fp32"][3], runs["fp32"][4]
+    x8 = n * p + 4 * n + 24 * p
+    x32 = 4 * n * p + 4 * n + 24 * p
+    res = {
+        "metric": METRIC,
+        "value": k8 / t8,
+        "unit": "lambda-iters/s",
+        "n_gpus": 1, "steps": k8, "warmup": 3, "ms_per_step": 1e3 * t8 / k8, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "fp8", "data": "synthetic",
+        "config": {"workload": f"l1-Cox ISTA, FP8 E4M3 genotype X n={n} p={p}, lambda=0.2*lambda_max, B=1, "
+                               f"from beta=0 to |f_k - f_k-{lag}|/(|f_k|+1) < {tol:g}", "n": n, "p": p, "B": 1},
+        "time_to_tolerance_s": t8,
+        "fp32_comparator": {"value": k32 / t32, "unit": "lambda-iters/s", "steps": k32, "time_to_tolerance_s": t32,
+                            "ms_per_step": 1e3 * t32 / k32, "x_bytes": 4 * n * p,
+                            "method": "plain FP32 X (the same counts standardised, 160 GB resident), same step and "
+                                      "stopping rule, unscaled"},
+        "speedup_at_equal_tolerance": t32 / t8,
+        "precision": {"rel_objective_fp8_vs_fp32": abs(runs["fp8"][2] - runs["fp32"][2]) / abs(runs["fp32"][2]),
+                      "rel_beta_fp8_vs_fp32": float(np.abs(b8 - b32).max() / max(np.abs(b32).max(), 1e-300)),
+                      "nnz": [int(np.count_nonzero(b8)), int(np.count_nonzero(b32))],
+                      "oracle_objective_at_returned_beta_rel_diff": checks},
+        "roofline": {"bound": "hbm", "kernel": "gemvt_sums_kernel (X~' r column sums, FP8 X)",
+                     "achieved": x8 / (ms8 / 1e3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": x8 / (ms8 / 1e3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": x8, "kernel_ms": ms8,
+                     "fp32_kernel": {"achieved": x32 / (ms32 / 1e3) / 1e9, "kernel_ms": ms32,
+                                     "algorithmic_bytes_per_launch": x32}},
+        "hbm_probe": probe,
+    }
+    return res
+
+
+def bench_autograd_c2(args):
+    """The autograd workload: 100,000 x 10,000 standardised genotypes in FP32,
+    survival times discretised to days (ties), time per forward + backward of
+    CoxLinearNLL (beta -> -L(X~ beta), gradient -X~' r) and of BreslowNLL
+    (eta -> -L(eta), gradient -r)."""
+    import torch
+
+    import coxsim
+    import paper_2010_16114_amd as P
+
+    d = coxsim.config2(n=args.n or 100000, p=args.p or 10000)
+    X = torch.from_numpy(d.standardized32()).cuda()
+    cox = P.Cox(X, d.time, d.event, max_batch=1)
+    beta = torch.tensor(d.beta_true[None], dtype=torch.float32, device="cuda", requires_grad=True)
+    K = args.steps
+
+    def lin():
+        loss = P.CoxLinearNLL.apply(beta, cox)
+        loss.sum().backward()
+
+    eta0 = (beta.detach() @ X).detach()
+    eta = eta0.clone().requires_grad_(True)
+
+    def bres():
+        loss = P.BreslowNLL.apply(eta, cox)
+        loss.sum().backward()
+
+    out = {}
+    for name, fn in (("linear", lin), ("breslow", bres)):
+        for _ in range(max(args.warmup, 1)):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            fn()
+        torch.cuda.synchronize()
+        out[name] = 1e3 * (time.perf_counter() - t0) / K
+        log(f"{name}: {out[name]:.4f} ms per forward + backward")
+    xbytes = 4 * d.n * d.p
+    return {
+        "metric": "Cox negative log partial likelihood, forward + backward through torch.autograd",
+        "value": out["linear"], "unit": "ms", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": out["linear"], "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"autograd: CoxLinearNLL on standardised FP32 genotypes n={d.n} p={d.p}, "
+                               f"times in days (ties), beta at the true effects", "n": d.n, "p": d.p},
+        "breslow_on_eta_ms": out["breslow"],
+        "roofline": {"bound": "hbm", "kernel": "forward + backward of CoxLinearNLL (two passes over X)",
+                     "achieved": 2 * xbytes / (out["linear"] / 1e3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": 2 * xbytes / (out["linear"] / 1e3) / 1e9 / HBM_PEAK_GBS, "traffic": None},
+    }
 
 
 FP64_VALU_PEAK_TFLOPS = 78.6
@@ -629,7 +806,7 @@ def main():
     ap.add_argument("--steps", type=int, default=0, help="default: 50 (batched), 1000 (nmf) or 500")
     ap.add_argument("--warmup", type=int, default=-1, help="default: 3 (batched) or 20")
     ap.add_argument("--workload", default="geno-fp8-batched",
-                    choices=["geno-fp8-batched", "gauss-fp32", "refit", "nmf"])
+                    choices=["geno-fp8-batched", "gauss-fp32", "refit", "nmf", "geno-fp8-c3", "autograd-c2"])
     ap.add_argument("--nmf-rank", type=int, default=20, help="nmf workload: rank r")
     ap.add_argument("--nmf-algo", type=int, default=0, choices=[0, 1], help="nmf workload: 0 multiplicative, 1 APG")
     ap.add_argument("--refit-cols", type=int, default=333, help="refit workload: SNP columns refitted")
@@ -672,11 +849,12 @@ def main():
         torch.cuda.empty_cache()
     batched = args.workload == "geno-fp8-batched"
     if args.steps <= 0:
-        args.steps = {"geno-fp8-batched": 50, "nmf": 1000}.get(args.workload, 500)
+        args.steps = {"geno-fp8-batched": 50, "nmf": 1000, "autograd-c2": 50}.get(args.workload, 500)
     if args.warmup < 0:
         args.warmup = 3 if batched else 20
     res = {"gauss-fp32": bench_gauss_fp32, "geno-fp8-batched": bench_geno_batched,
-           "refit": bench_refit, "nmf": bench_nmf}[args.workload](args)
+           "refit": bench_refit, "nmf": bench_nmf, "geno-fp8-c3": bench_geno_fp8_c3,
+           "autograd-c2": bench_autograd_c2}[args.workload](args)
     print(json.dumps(res), flush=True)
 
 

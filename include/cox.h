@@ -147,7 +147,16 @@ typedef struct {
     double tol;         /* >= 0: stop b when |f_k - f_{k-lag}| / (|f_k| + 1) < tol (Section 6); 0: never */
     int32_t lag;        /* 1..32; the paper uses 10 */
     double step;        /* > 0: sigma; <= 0: 1 / (2 ||X~||_2^2) from cox_opnorm2 (Section 5.3) */
-    int32_t warm_start; /* 1: start from the beta passed in; 0: start from beta = 0 */
+    int32_t warm_start; /* 0: start from beta = 0; 1: start from the beta passed in (FP32; eta is formed
+                           afresh by a dense pass); 2: resume -- continue the last cox_fit_path on this
+                           context from its own FP64 iterate, accumulated eta and stopping-rule history,
+                           so that K1 steps and a resume to max_iter = K2 give bit for bit the results
+                           of one call with max_iter = K2.  Resuming needs the same B, lambdas, step
+                           (<= 0: the last call's), eta_mode, residual_bits and covariates, max_iter at
+                           least the last call's, and no other call on the context in between that
+                           uses its workspace (INVALID_ARG otherwise; UNSUPPORTED with persistent).
+                           Lambdas that had converged stay as they were; beta is output only; the
+                           trace holds NaN for the steps of the earlier call. */
     int32_t persistent; /* 0: one launch per phase of each step, the host checking the stopping flags
                            every `poll` steps; 1: the whole call -- every step of every b, the stopping
                            rule included -- in one persistent (cooperative) launch whose workgroups are
@@ -360,8 +369,8 @@ typedef enum {
  * choices (-1: not yet tuned) and the tuning times in milliseconds (host
  * [COX_MFMA_VARIANTS] each, nullable; entries past a pass's shape count and
  * entries of a pass that was not timed are 0). */
-#define COX_MFMA_VARIANTS 8
-#define COX_MFMA_ETA_VARIANTS 5
+#define COX_MFMA_VARIANTS 13
+#define COX_MFMA_ETA_VARIANTS 7
 cox_status cox_mfma_tuning(cox_ctx *ctx, int32_t *xtr_variant, int32_t *eta_variant, float *xtr_ms, float *eta_ms);
 cox_status cox_timing_enable(cox_ctx *ctx, int32_t enable);
 cox_status cox_timing_read(cox_ctx *ctx, int32_t phase, double *total_ms, int64_t *count);
@@ -372,6 +381,13 @@ cox_status cox_timing_read(cox_ctx *ctx, int32_t phase, double *total_ms, int64_
  * persistent launches add nothing).  It gives the bytes of X a step moves
  * beside the full pass of X~' r.  eta_columns host [1].  Synchronises. */
 cox_status cox_timing_columns(cox_ctx *ctx, int64_t *eta_columns);
+
+/* Device memory the library holds at this moment, in bytes, over every live
+ * context and the buffers of calls in progress (the static array of
+ * cox_rank_path_noalloc is not counted: it belongs to the loaded library).
+ * A failed call releases what it allocated, so the count returns to its
+ * value before the call.  bytes host [1]. */
+cox_status cox_device_bytes(int64_t *bytes);
 
 #ifdef __cplusplus
 }

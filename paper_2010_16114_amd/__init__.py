@@ -24,8 +24,8 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "cox.h")
 NMF_HEADER = os.path.join(os.path.dirname(_HERE), "include", "nmf.h")
 
 X_F32, X_FP8_E4M3, X_INT8 = 0, 1, 2
-MFMA_VARIANTS = 8  # COX_MFMA_VARIANTS: pipeline shapes of the X~' R pass (and the tuning arrays' length)
-ETA_VARIANTS = 5  # COX_MFMA_ETA_VARIANTS: pipeline shapes of the eta update
+MFMA_VARIANTS = 13  # COX_MFMA_VARIANTS: pipeline shapes of the X~' R pass (and the tuning arrays' length)
+ETA_VARIANTS = 7  # COX_MFMA_ETA_VARIANTS: pipeline shapes of the eta update
 MAX_COVARIATES = 64  # COX_MAX_COVARIATES
 MAX_REFIT = 1024  # COX_MAX_REFIT
 NOALLOC_MAX_COLS = 2097152  # COX_NOALLOC_MAX_COLS
@@ -95,6 +95,7 @@ def lib():
         "cox_mfma_tuning": [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), vp, vp],
         "cox_timing_read": [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64)],
         "cox_timing_columns": [vp, ctypes.POINTER(i64)],
+        "cox_device_bytes": [ctypes.POINTER(i64)],
         "nmf_setup": [ctypes.POINTER(vp), vp, i64, i64, i64, i32, vp],
         "nmf_destroy": [vp],
         "nmf_last_error": [vp, ctypes.c_char_p, ctypes.c_size_t],
@@ -114,6 +115,16 @@ def lib():
 
 def _np_ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
+
+
+
+def device_bytes() -> int:
+    """Device memory the library holds now (every context and call), in bytes."""
+    v = ctypes.c_int64()
+    st = lib().cox_device_bytes(ctypes.byref(v))
+    if st != OK:
+        raise CoxError(st, "cox_device_bytes")
+    return v.value
 
 
 class Cox:
@@ -233,14 +244,15 @@ class Cox:
 
     def fit_path(self, lambdas, max_iter: int = 1000, tol: float = 1e-5, lag: int = 10, step: float = 0.0,
                  beta=None, eta_mode: int = 0, poll: int = 16, residual_bits: int = 0, persistent: bool = False,
-                 trace: bool = False):
+                 trace: bool = False, resume: bool = False):
         """ISTA for each lambda.  Returns (beta (B, ptot) tensor, iters, obj, status), and with
         trace=True a fifth item: the objective of every step, a (B, max_iter + 1) array (NaN past
-        each lambda's last step)."""
+        each lambda's last step).  resume=True continues the context's last fit_path (same B,
+        lambdas, step, options) to max_iter in total, bit for bit as one call would."""
         torch = self._torch
         lam = np.ascontiguousarray(np.asarray(lambdas, np.float64).reshape(-1))
         B = lam.shape[0]
-        warm = beta is not None
+        warm = 2 if resume else int(beta is not None)
         if beta is None:
             beta = torch.zeros((B, self.ptot), dtype=torch.float32, device=self.device)
         beta2, Bb = self._beta(beta)

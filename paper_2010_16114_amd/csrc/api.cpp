@@ -15,6 +15,7 @@
 #include <sstream>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <limits>
 #include <mutex>
 #include <new>
@@ -61,6 +62,8 @@ static_assert(kNoallocMaxCols == COX_NOALLOC_MAX_COLS, "static scratch size diff
 constexpr int kNoallocMaxDevices = 64;
 static __device__ __align__(256) unsigned char scratch[8 * kNoallocMaxCols];
 static std::mutex g_scratch_mu;
+// device bytes the library holds (contexts and calls' own buffers), for cox_device_bytes
+static std::atomic<int64_t> g_dev_bytes{0};
 static void* g_scratch_addr[kNoallocMaxDevices] = {};
 
 struct cox_ctx {
@@ -73,6 +76,7 @@ struct cox_ctx {
     int nblk = 0, ncg = 0, ncb = 0;
     std::string err;
     std::vector<void*> allocs;
+    std::vector<size_t> alloc_bytes;
     void* pinned = nullptr;  // small host staging buffer (page-locked)
     size_t pinned_bytes = 0;
 
@@ -114,6 +118,14 @@ struct cox_ctx {
     unsigned long long* bar_words = nullptr;
     long long* col_count = nullptr;  // columns of X read by eta updates while timing is on
     int persist_grid = 0;  // workgroups of the last persistent launch
+    // the state cox_fit_path left (beta64, eta, residual, stopping-rule history) and what
+    // produced it, for a resumed call (warm_start = 2); any other call that uses the
+    // workspace clears fit_valid
+    bool fit_valid = false;
+    int fit_B = 0, fit_max_iter = 0, fit_eta_mode = 0, fit_rlimbs = 3;
+    int64_t fit_q = 0;
+    double fit_step = 0.0;
+    std::vector<double> fit_lams;
     int fwd_B = 0, fwd_f64 = 0;
     int64_t n_events = 0;
     // the dense covariate block Z beside X, and the penalty factors
@@ -157,10 +169,28 @@ cox_status dev_fail(cox_ctx* c, hipError_t e, const char* what)
         if (_s != COX_OK) return _s;       \
     } while (0)
 
+// Allocation-failure injection for tests, from the environment variable
+// COXHIP_FAULT: "alloc" fails every device allocation of the library; "alloc@N"
+// fails only the N-th one counted from when the variable took that value, so
+// that the clean-up after a failure part way through cox_setup (or through a
+// call's own buffers) can be exercised.
 bool fault_injected(const char* what)
 {
+    static std::mutex mu;
+    static std::string last;
+    static long count = 0;
     const char* f = std::getenv("COXHIP_FAULT");
-    return f && std::strcmp(f, what) == 0;
+    if (!f) return false;
+    const size_t w = std::strlen(what);
+    if (std::strncmp(f, what, w) != 0) return false;
+    if (f[w] == '\0') return true;
+    if (f[w] != '@') return false;
+    std::lock_guard<std::mutex> lock(mu);
+    if (last != f) {
+        last = f;
+        count = 0;
+    }
+    return ++count == std::atol(f + w + 1);
 }
 
 template <class T>
@@ -169,11 +199,14 @@ bool dalloc(cox_ctx* c, T** out, size_t count)
     *out = nullptr;
     if (fault_injected("alloc")) return false;
     void* p = nullptr;
-    if (hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) {
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    if (hipMalloc(&p, bytes) != hipSuccess) {
         (void)hipGetLastError();
         return false;
     }
     c->allocs.push_back(p);
+    c->alloc_bytes.push_back(bytes);
+    g_dev_bytes += (int64_t)bytes;
     *out = static_cast<T*>(p);
     return true;
 }
@@ -181,9 +214,11 @@ bool dalloc(cox_ctx* c, T** out, size_t count)
 // Device buffers of one call, freed when the call returns.
 struct Scratch {
     std::vector<void*> ptrs;
+    int64_t bytes = 0;
     ~Scratch()
     {
         for (void* p : ptrs) (void)hipFree(p);
+        g_dev_bytes -= bytes;
     }
     template <class T>
     bool get(T** out, size_t count)
@@ -191,11 +226,14 @@ struct Scratch {
         *out = nullptr;
         if (fault_injected("alloc")) return false;
         void* p = nullptr;
-        if (hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) {
+        const size_t b = std::max<size_t>(count, 1) * sizeof(T);
+        if (hipMalloc(&p, b) != hipSuccess) {
             (void)hipGetLastError();
             return false;
         }
         ptrs.push_back(p);
+        bytes += (int64_t)b;
+        g_dev_bytes += (int64_t)b;
         *out = static_cast<T*>(p);
         return true;
     }
@@ -228,7 +266,9 @@ void release(cox_ctx* c)
 {
     timing_clear(c);
     for (void* p : c->allocs) (void)hipFree(p);
+    for (size_t b : c->alloc_bytes) g_dev_bytes -= (int64_t)b;
     c->allocs.clear();
+    c->alloc_bytes.clear();
     if (c->pinned) (void)hipHostFree(c->pinned);
     c->pinned = nullptr;
 }
@@ -912,7 +952,7 @@ cox_status cox_setup(cox_ctx** out, const cox_matrix* X, const double* time, con
               dalloc(c, &c->egidx, n) && dalloc(c, &c->egcnt, std::max<size_t>(1, egc.size())) &&
               dalloc(c, &c->eta, Bn) && dalloc(c, &c->w, Bn) && dalloc(c, &c->S, Bn) && dalloc(c, &c->T, Bn) &&
               dalloc(c, &c->r64, Bn) && dalloc(c, &c->r32, (size_t)max_batch * c->rstride) &&
-              dalloc(c, &c->part_upd, (size_t)c->ncg * Bn) && dalloc(c, &c->part_gemv, (size_t)c->ncb * kGroup * n) &&
+              dalloc(c, &c->part_upd, (size_t)c->ncg * Bn) && dalloc(c, &c->part_gemv, (size_t)std::max<int64_t>((int64_t)c->ncb * kGroup, (int64_t)gemv16_blocks(n, p) * 4) * n) &&
               dalloc(c, &c->beta64, Bp) && dalloc(c, &c->coef, Bp) && dalloc(c, &c->dcoef, Bp) &&
               dalloc(c, &c->g64, Bp) && dalloc(c, &c->chg_flag, p) && dalloc(c, &c->chg_cnt, c->nblk) &&
               dalloc(c, &c->chg_idx, (size_t)c->nblk * kGemvtCols) && dalloc(c, &c->sel, p) &&
@@ -1000,6 +1040,7 @@ cox_status cox_destroy(cox_ctx* c)
 cox_status cox_loss_grad(cox_ctx* c, const float* beta, int32_t B, double* loss, float* grad)
 {
     STCHK(check_ctx(c));
+    c->fit_valid = false;
     if (!beta || !loss) return fail(c, COX_ERR_INVALID_ARG, "beta and loss must not be NULL");
     STCHK(check_batch(c, B));
     STCHK(load_beta(c, beta, B));
@@ -1034,6 +1075,7 @@ cox_status cox_loss_grad(cox_ctx* c, const float* beta, int32_t B, double* loss,
 cox_status cox_prox_step(cox_ctx* c, float* beta, int32_t B, const double* lambdas, double step, double* obj_before)
 {
     STCHK(check_ctx(c));
+    c->fit_valid = false;
     if (!beta) return fail(c, COX_ERR_INVALID_ARG, "beta is NULL");
     STCHK(check_batch(c, B));
     STCHK(check_lambdas(c, lambdas, B));
@@ -1086,6 +1128,7 @@ cox_status cox_prox_apply(cox_ctx* c, float* beta, const float* grad, int32_t B,
 cox_status cox_lambda_max(cox_ctx* c, double* lambda_max)
 {
     STCHK(check_ctx(c));
+    c->fit_valid = false;
     if (!lambda_max) return fail(c, COX_ERR_INVALID_ARG, "lambda_max is NULL");
     const int64_t p = c->p, q = c->q;
     for (int64_t j = 0; j < p; ++j)
@@ -1127,6 +1170,7 @@ cox_status cox_lambda_max(cox_ctx* c, double* lambda_max)
 cox_status cox_opnorm2(cox_ctx* c, double tol, int32_t maxiter, uint64_t seed, double* s2, int32_t* iters)
 {
     STCHK(check_ctx(c));
+    c->fit_valid = false;
     if (!s2 || !(tol >= 0) || maxiter < 1) return fail(c, COX_ERR_INVALID_ARG, "bad opnorm2 arguments");
     const int q = (int)c->q;
     std::vector<double> v(ptot(c));
@@ -1184,7 +1228,7 @@ cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_
     cox_fit_opts o{1000, 1e-5, 10, 0.0, 0, 0, 0, 0, 16, 0, nullptr};
     if (opts_in) o = *opts_in;
     if (o.max_iter < 0 || !(o.tol >= 0) || o.lag < 1 || o.lag > kMaxHist - 1 || !std::isfinite(o.step) ||
-        (o.warm_start != 0 && o.warm_start != 1) || (o.eta_mode != 0 && o.eta_mode != 1) ||
+        (o.warm_start < 0 || o.warm_start > 2) || (o.eta_mode != 0 && o.eta_mode != 1) ||
         (o.persistent != 0 && o.persistent != 1) || (o.deterministic != 0 && o.deterministic != 1) ||
         (o.residual_bits != 0 && o.residual_bits != 22 && o.residual_bits != 14))
         return fail(c, COX_ERR_INVALID_ARG, "bad cox_fit_opts");
@@ -1196,7 +1240,20 @@ cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_
                     "no covariate block, X 16-byte aligned with ldx * element size a multiple of 16");
     const int rlimbs = o.residual_bits == 14 ? 2 : 3;
     const int poll = o.poll > 0 ? o.poll : 16;
-    double step = o.step;
+    const bool resume = o.warm_start == 2;
+    if (resume) {
+        if (o.persistent) return fail(c, COX_ERR_UNSUPPORTED, "resume: not served by the persistent form");
+        if (!c->fit_valid)
+            return fail(c, COX_ERR_INVALID_ARG, "resume: the last call on this context was not a completed fit");
+        if (B != c->fit_B || !std::equal(lambdas, lambdas + B, c->fit_lams.begin()) || o.eta_mode != c->fit_eta_mode ||
+            rlimbs != c->fit_rlimbs || c->q != c->fit_q || (o.step > 0 && o.step != c->fit_step) ||
+            o.max_iter < c->fit_max_iter)
+            return fail(c, COX_ERR_INVALID_ARG,
+                        "resume: B, lambdas, step, eta_mode, residual_bits and covariates must be those of the "
+                        "fit it continues, and max_iter at least its max_iter");
+    }
+    c->fit_valid = false;
+    double step = resume ? c->fit_step : o.step;
     if (step <= 0) {
         double s2 = 0;
         STCHK(cox_opnorm2(c, 1e-6, 1000, 95376, &s2, nullptr));
@@ -1206,7 +1263,11 @@ cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_
     STCHK(h2d(c, c->lam, lambdas, sizeof(double) * B));
     const int64_t Bp = (int64_t)B * c->p, Bn = (int64_t)B * c->n;
     const int q = (int)c->q;
-    if (o.warm_start) {
+    if (resume) {
+        // the iterate, eta and the stopping-rule state stay as the last fit left them; the
+        // lambdas that stopped at its max_iter go on from there
+        HIPCHK(launch_resume(c->status, c->active, c->kit, c->iters, B, c->stream), "resume");
+    } else if (o.warm_start) {
         STCHK(load_beta(c, beta, B));
         HIPCHK(launch_scale_coef(c->beta64, geno_scale(c), c->coef, c->p, B, c->stream), "coefficients");
         STCHK(dense_eta(c, c->coef, B, nullptr));
@@ -1222,12 +1283,14 @@ cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_
             HIPCHK(launch_fill_f64(c->l1c_new, 0.0, B, c->stream), "zero l1");
         }
     }
-    HIPCHK(launch_fill_i32(c->nsel, 0, 1, c->stream), "reset");
-    HIPCHK(launch_fill_i32(c->kit, 0, B, c->stream), "reset");
-    HIPCHK(launch_fill_i32(c->active, 1, B, c->stream), "reset");
-    HIPCHK(launch_fill_i32(c->status, 0, B, c->stream), "reset");
-    HIPCHK(launch_fill_i32(c->iters, 0, B, c->stream), "reset");
-    HIPCHK(launch_fill_f64(c->hist, 0.0, (int64_t)B * kMaxHist, c->stream), "reset");
+    if (!resume) {
+        HIPCHK(launch_fill_i32(c->nsel, 0, 1, c->stream), "reset");
+        HIPCHK(launch_fill_i32(c->kit, 0, B, c->stream), "reset");
+        HIPCHK(launch_fill_i32(c->active, 1, B, c->stream), "reset");
+        HIPCHK(launch_fill_i32(c->status, 0, B, c->stream), "reset");
+        HIPCHK(launch_fill_i32(c->iters, 0, B, c->stream), "reset");
+        HIPCHK(launch_fill_f64(c->hist, 0.0, (int64_t)B * kMaxHist, c->stream), "reset");
+    }
 
     const bool mfma = use_mfma(c, B);
     RiskArgs ra = risk_args(c, B);
@@ -1268,8 +1331,12 @@ cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_
         if (aborted)
             return fail(c, COX_ERR_DEVICE, "persistent fit: a grid barrier waited past its limit; launch abandoned");
     }
-    for (int it = 0; it <= o.max_iter && !o.persistent; ++it) {
-        if (it > 0) {
+    // a resumed fit starts where the last one ended: after the risk-set pass of
+    // its last step, with that step's proximal update still to take
+    const int it0 = resume ? c->fit_max_iter : 0;
+    for (int it = it0; it <= o.max_iter && !o.persistent; ++it) {
+        const bool first_resumed = resume && it == it0;
+        if (it > 0 && !first_resumed) {
             if (o.eta_mode == 0 && mfma) {
                 tmark(c, COX_PHASE_ETA);
                 const int bpad = (int)round_up(B, 16);
@@ -1314,9 +1381,11 @@ cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_
             // the covariates' share: a fresh eta needs all of Z beta_Z, an updated one the change
             STCHK(cov_eta(c, o.eta_mode == 1 ? c->betaZ : c->dZ, B, o.eta_mode == 1 ? nullptr : c->active));
         }
-        tmark(c, COX_PHASE_RISK);
-        HIPCHK(launch_risk(ra, c->stream), "risk-set sums");
-        tmark(c, COX_PHASE_RISK);
+        if (!first_resumed) {
+            tmark(c, COX_PHASE_RISK);
+            HIPCHK(launch_risk(ra, c->stream), "risk-set sums");
+            tmark(c, COX_PHASE_RISK);
+        }
         if (it < o.max_iter) {
             STCHK(run_gemvt(c, g, B, rlimbs));
             STCHK(cov_grad(c, ra, B, c->active, cst));
@@ -1346,6 +1415,16 @@ cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_
         notconv = notconv || st[b] == 2 || st[b] == 0;
     }
     if (numeric) return fail(c, COX_ERR_NUMERIC, "non-finite objective");
+    if (!o.persistent) {
+        c->fit_valid = true;
+        c->fit_B = B;
+        c->fit_lams.assign(lambdas, lambdas + B);
+        c->fit_step = step;
+        c->fit_eta_mode = o.eta_mode;
+        c->fit_rlimbs = rlimbs;
+        c->fit_q = c->q;
+        c->fit_max_iter = o.max_iter;
+    }
     if (notconv) return fail(c, COX_ERR_NOT_CONVERGED, "max_iter reached");
     return COX_OK;
 }
@@ -1354,6 +1433,7 @@ cox_status cox_fit_sequence(cox_ctx* c, const double* lambdas, int32_t L, const 
                             float* beta_path, int32_t* iters, double* obj)
 {
     STCHK(check_ctx(c));
+    c->fit_valid = false;
     if (!beta_path || L < 1) return fail(c, COX_ERR_INVALID_ARG, "beta_path is NULL or L < 1");
     STCHK(check_lambdas(c, lambdas, L));
     cox_fit_opts o{1000, 1e-5, 10, 0.0, 0, 0, 0, 0, 16, 0, nullptr};
@@ -1392,6 +1472,7 @@ cox_status cox_fit_sequence(cox_ctx* c, const double* lambdas, int32_t L, const 
 cox_status cox_set_covariates(cox_ctx* c, const float* Z, int64_t q, int64_t ldz)
 {
     STCHK(check_ctx(c));
+    c->fit_valid = false;
     if (q < 0 || q > kMaxCov) return fail(c, COX_ERR_INVALID_ARG, "q must be in 0..COX_MAX_COVARIATES");
     if (q > 0 && (!Z || ldz < c->n || ldz > (int64_t(1) << 40)))
         return fail(c, COX_ERR_INVALID_ARG, "Z is NULL or ldz < n");
@@ -1409,6 +1490,7 @@ cox_status cox_set_covariates(cox_ctx* c, const float* Z, int64_t q, int64_t ldz
 cox_status cox_set_penalty_factors(cox_ctx* c, const double* pf)
 {
     STCHK(check_ctx(c));
+    c->fit_valid = false;
     const int64_t pt = ptot(c);
     std::vector<double> v(pt);
     if (pf) {
@@ -1438,6 +1520,7 @@ cox_status cox_refit(cox_ctx* c, const int64_t* cols, int32_t m, const cox_refit
                      double* se, double* pval, double* loglik, int32_t* iters)
 {
     STCHK(check_ctx(c));
+    c->fit_valid = false;
     const int q = (int)c->q, M = m + q;
     const int64_t n = c->n;
     if (m < 0 || M < 1 || M > kMaxRefit || (m > 0 && !cols) || !coef)
@@ -1606,6 +1689,7 @@ cox_status cox_rank_path_noalloc(cox_ctx* c, const float* path, int32_t L, int32
 cox_status cox_nll_forward(cox_ctx* c, const void* eta, int32_t eta_f64, int32_t B, double* loss)
 {
     STCHK(check_ctx(c));
+    c->fit_valid = false;
     if (!eta || !loss || (eta_f64 != 0 && eta_f64 != 1)) return fail(c, COX_ERR_INVALID_ARG, "bad nll_forward arguments");
     STCHK(check_batch(c, B));
     RiskArgs ra = risk_args(c, B);
@@ -1623,6 +1707,7 @@ cox_status cox_nll_forward(cox_ctx* c, const void* eta, int32_t eta_f64, int32_t
 cox_status cox_nll_backward(cox_ctx* c, const double* grad_loss, int32_t B, void* grad_eta)
 {
     STCHK(check_ctx(c));
+    c->fit_valid = false;
     if (!grad_loss || !grad_eta) return fail(c, COX_ERR_INVALID_ARG, "bad nll_backward arguments");
     if (B != c->fwd_B) return fail(c, COX_ERR_INVALID_ARG, "backward needs a forward with the same B");
     HIPCHK(launch_nll_backward(c->r64, grad_loss, c->n, B, grad_eta, c->fwd_f64, c->stream), "adjoint");
@@ -1648,6 +1733,13 @@ cox_status cox_timing_enable(cox_ctx* c, int32_t enable)
     timing_clear(c);
     c->timing = enable != 0;
     HIPCHK(launch_fill_f64(reinterpret_cast<double*>(c->col_count), 0.0, 1, c->stream), "reset column count");
+    return COX_OK;
+}
+
+cox_status cox_device_bytes(int64_t* bytes)
+{
+    if (!bytes) return COX_ERR_INVALID_ARG;
+    *bytes = g_dev_bytes.load();
     return COX_OK;
 }
 

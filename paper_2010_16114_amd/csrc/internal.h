@@ -168,6 +168,9 @@ hipError_t launch_gemvt_epilogue(const GemvtArgs& a, hipStream_t s);
 hipError_t launch_eta_update(const XDesc& x, const int32_t* sel, const int32_t* nsel, const double* dcoef,
                              int b0, int nb, double* part, int64_t part_cstride, int ncg,
                              const int32_t* active, hipStream_t s);
+// column blocks of the dense pass over one-byte X with 16-byte runs (the
+// partial buffer must hold gemv16_blocks(n, p) * 4 * n doubles)
+int gemv16_blocks(int64_t n, int64_t p);
 // dense eta = X~ coef for b in [b0, b0+nb): partials over column blocks, then reduced
 hipError_t launch_gemv(const XDesc& x, const double* coef, int b0, int nb, double* part, int ncb,
                        double* eta, const double* shift, hipStream_t s);
@@ -200,6 +203,9 @@ hipError_t launch_to_r32(const double* u, const double* shift, float* r32, doubl
 // out[b] = a * sum_i in[b*m + i], one workgroup per b, fixed order
 hipError_t launch_rowsum(const double* in, int64_t m, int B, double a, double* out, hipStream_t s);
 hipError_t launch_fill_f64(double* p, double v, int64_t m, hipStream_t s);
+// status 2 -> 0, active -> 1, kit = iters + 1 for b < B (B <= 64): a resumed fit
+hipError_t launch_resume(int32_t* status, int32_t* active, int32_t* kit, const int32_t* iters, int B,
+                         hipStream_t s);
 // acc[0] += v[0]
 hipError_t launch_count_add(const int32_t* v, long long* acc, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t m, hipStream_t s);

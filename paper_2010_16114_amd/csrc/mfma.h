@@ -24,12 +24,17 @@ struct MfmaArgs {
     double* out;            // [B][p] raw sums q_b * sum_i g_ij R_bi
     int variant;            // pipeline shape (compute + loader wavefronts, M tiles per compute
                             // wavefront, subjects per stage, stages ahead): 0 = 7+1, 3, 64, 6;
-                            // 1 = 7+1, 3, 64, 4; 2 = 6+2, 3, 64, 6; 3 = 6+2, 3, 64, 4; 4 = 6+2, 3, 128, 2;
-                            // direct-to-LDS limb tiles, 8 compute wavefronts, bpad = 64 only:
-                            // 5 = 3, 128, 3; 6 = the same with streaming X loads; 7 = 3, 128, 2
+                            // 1 = 7+1, 3, 64, 4; 2 = 6+2, 3, 64, 6; 3 = 6+2, 3, 64, 4; 4 = 6+2, 3, 128, 2
+                            // (limb loads two stages ahead); with limb loads three or four stages
+                            // ahead: 5 = 7+1, 3, 64, 6, 3; 6 = 7+1, 3, 64, 4, 4; 7 = 6+2, 3, 64, 6, 3;
+                            // streaming (non-temporal) X loads of whole 128-byte lines:
+                            // 8 = 6+2, 3, 128, 3, 3; 9 = 6+2, 3, 128, 2, 2;
+                            // A runs loaded along a column and moved to the matrix-core layout
+                            // through LDS, 64-byte runs: 10 = 7+1, 3, 64, 6; 11 = 7+1, 3, 64, 4;
+                            // 128-byte runs: 12 = 6+2, 3, 128, 2
 };
-constexpr int kMfmaVariants = 8;     // shapes of the X~' R pass
-constexpr int kMfmaEtaVariants = 5;  // shapes of the eta update
+constexpr int kMfmaVariants = 13;    // shapes of the X~' R pass
+constexpr int kMfmaEtaVariants = 7;  // shapes of the eta update
 
 // eta_b(i) += q_b * sum_{u < nsel} g(i, sel[u]) D_b(u), D in three int8 limbs.
 struct MfmaEtaArgs {
@@ -47,7 +52,8 @@ struct MfmaEtaArgs {
     const int32_t* active;  // [B] or null
     int variant;            // stages of 64 columns ahead (8 wavefronts load both operands): 0, 1 = 2, 3
                             // with the D tile moved in 8-byte pieces when bpad = 64 (16-byte chunks
-                            // otherwise); 2, 3, 4 = 4, 3, 2 with 16-byte chunks
+                            // otherwise); 2, 3, 4 = 4, 3, 2 with 16-byte chunks; 5, 6 = 3, 2 as 1, 0
+                            // with streaming (non-temporal) loads of G
 };
 
 int mfma_ntile(int64_t n);

@@ -89,10 +89,24 @@ __device__ __forceinline__ v4i decode_a(v4i raw)
 // split, each stream drains at its own pace.  Both roles meet at one barrier
 // per stage.  The limb rows of subjects >= n are zero (the quantiser writes
 // them so), so the padding bytes of X that meet them add nothing.
-template <int XT, int NG, int RL, int CW, int LW, int MT, int KS, int PF, bool NTX = false>
+//
+// XP (lanes per column run, 0 = off): the A runs are loaded so that XP
+// consecutive lanes read XP * 16 contiguous bytes of one column, and are moved
+// to the matrix-core layout (lane l: column l % 16, 16-subject chunk l / 16)
+// through a wavefront-private LDS slot.  In the direct layout the four lanes
+// of a quad address four columns 400 KB apart, so every lane of a load needs
+// its own address translation (rocprofv3 counts one UTCL1 request per 16
+// bytes of X, four times the rate of a contiguous read, with the address path
+// stalled by the L1 most of the time) and the L1 sends 64-byte requests.
+// XP = 4: a quad reads one 64-byte run (lane l: column l / 4, chunk l % 4);
+// XP = 8 (two 64-subject steps per stage): eight lanes read one 128-byte line
+// (load h of an M tile, lane l: column 8 h + l / 8, chunk l % 8).
+template <int XT, int NG, int RL, int CW, int LW, int MT, int KS, int PF, int LD = 2, bool NTX = false,
+          int XP = 0>
 __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_split_kernel(MfmaArgs a)
 {
-    static_assert(PF >= 2 && PF % 2 == 0, "the loaders' two-slot ring indexes statically");
+    static_assert(PF >= 2 && LD >= 2 && PF % LD == 0, "the loaders' ring of LD slots indexes statically");
+    static_assert(XP == 0 || XP == 4 || (XP == 8 && KS % 2 == 0), "runs of 4 lanes, or of 8 over two steps");
     static_assert(RL == 2 || RL == 3, "the residual comes in 2 or 3 limbs");
     constexpr int WCOLS = 16 * MT * CW;  // SNP columns per workgroup
     constexpr int KC = 64 * KS;
@@ -103,7 +117,9 @@ __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_split_
     constexpr int LTH = 64 * LW;
     constexpr int CPL = (CHUNKS + LTH - 1) / LTH;
     constexpr int RS = NCOL + 8;
+    constexpr int XS = 68;  // 16-byte entries of one A run's permutation slot (64, + 1 pad per 16 lanes)
     __shared__ v4i sR[2][QC * RS];
+    __shared__ v4i sX[XP ? CW * MT * KS * XS : 1];
 
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int64_t n = a.n, p = a.p, ldx = a.ldx;
@@ -114,6 +130,18 @@ __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_split_
     if (wid < CW) {
         const int arow = 16 * (lane >> 4);
         const int acol = lane & 15;
+        // where this lane's loads come from: the matrix-core layout, or (XP) runs along a column
+        const int lrow = XP == 4 ? 16 * (lane & 3) : (XP == 8 ? 16 * (lane & 7) : arow);
+        const int lcol = XP == 4 ? lane >> 2 : (XP == 8 ? lane >> 3 : acol);
+        // XP: the chunk a lane loaded belongs to lane 16 (chunk % 4) + column of the matrix-core
+        // layout (XP = 8: of step chunk / 4 of the load's pair); entries are padded by one after
+        // every 16 so that the writes of a run and the reads of 16 consecutive lanes meet
+        // distinct banks
+        const int xl = 16 * (lrow / 16 & 3) + lcol;
+        const int xw = xl + (xl >> 4);
+        const int xk = XP == 8 ? (lane & 7) >> 2 : 0;
+        const int xr = lane + (lane >> 4);
+        v4i* const xslot = sX + (XP ? wid * MT * KS * XS : 0);
         const int64_t jw = (int64_t)blockIdx.x * WCOLS + wid * (16 * MT);
         v4i acc[MT][NT];
 #pragma unroll
@@ -126,8 +154,13 @@ __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_split_
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt)
-                    A[mt][ks] = load_raw<NTX>(X, jw + mt * 16 + acol, p, ldx, k0 + ks * 64 + arow, n);
+                for (int mt = 0; mt < MT; ++mt) {
+                    if constexpr (XP == 8)  // ks even and odd: the two column halves of M tile mt
+                        A[mt][ks] = load_raw<NTX>(X, jw + mt * 16 + 8 * (ks & 1) + lcol, p, ldx,
+                                                  k0 + (ks >> 1) * 128 + lrow, n);
+                    else
+                        A[mt][ks] = load_raw<NTX>(X, jw + mt * 16 + lcol, p, ldx, k0 + ks * 64 + lrow, n);
+                }
         };
 #pragma unroll
         for (int q = 0; q < PF; ++q) fetch(q, Ab[q]);
@@ -140,6 +173,25 @@ __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_split_
                 if (t < nstage) {
                     const v4i* sb = &sR[buf][(lane >> 4) * RS + acol];
                     v4i bcur = sb[0];
+                    if constexpr (XP != 0) {
+                        // to the matrix-core layout through this wavefront's own LDS slot (LDS
+                        // operations of one wavefront complete in order: no barrier needed).
+                        // XP = 8: the load for (mt, ks) holds column half ks & 1 of steps
+                        // 2 (ks / 2) and 2 (ks / 2) + 1
+#pragma unroll
+                        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                            for (int mt = 0; mt < MT; ++mt) {
+                                if constexpr (XP == 8)
+                                    xslot[((2 * (ks >> 1) + xk) * MT + mt) * XS + xw + 8 * (ks & 1)] = Ab[q][mt][ks];
+                                else
+                                    xslot[(ks * MT + mt) * XS + xw] = Ab[q][mt][ks];
+                            }
+#pragma unroll
+                        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                            for (int mt = 0; mt < MT; ++mt) Ab[q][mt][ks] = xslot[(ks * MT + mt) * XS + xr];
+                    }
 #pragma unroll
                     for (int ks = 0; ks < KS; ++ks) {
                         v4i A[MT];
@@ -186,7 +238,10 @@ __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_split_
             rsrc[u] = a.limbs + 16 * c;
             rdst[u] = (c / NCOL) * RS + c % NCOL;
         }
-        v4i Rb[2][CPL];
+        // a ring of LD stages of limb loads: at step t the loads of stage t + LD
+        // go out before stage t + 1 (loaded LD - 1 steps earlier) is written to
+        // LDS, so each load has LD - 1 stage times to arrive
+        v4i Rb[LD][CPL];
         auto fetch_r = [&](int64_t t, v4i (&R)[CPL]) {
             const int64_t kr = min(t, nstage - 1) * (int64_t)(16 * CHUNKS);
 #pragma unroll
@@ -196,147 +251,21 @@ __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_split_
 #pragma unroll
             for (int u = 0; u < CPL; ++u) sR[buf][rdst[u]] = R[u];
         };
-        fetch_r(0, Rb[0]);
-        fetch_r(1, Rb[1]);
+#pragma unroll
+        for (int u = 0; u < LD; ++u) fetch_r(u, Rb[u]);
         store_r(0, Rb[0]);
         __syncthreads();
         for (int64_t s0 = 0; s0 < nloop; s0 += PF) {
 #pragma unroll
             for (int q = 0; q < PF; ++q) {
                 const int64_t t = s0 + q;
-                fetch_r(t + 2, Rb[q % 2]);
-                store_r((int)(t & 1) ^ 1, Rb[(q + 1) % 2]);
+                fetch_r(t + LD, Rb[q % LD]);
+                __builtin_amdgcn_sched_barrier(0);  // keep the new loads ahead of the stores below
+                store_r((int)(t & 1) ^ 1, Rb[(q + 1) % LD]);
                 __syncthreads();
             }
         }
     }
-}
-
-// X~' R with the limb tile moved by direct global-to-LDS loads
-// (global_load_lds_dwordx4): B = 49..64 (four N groups of 16), CW = 8 compute
-// wavefronts and no loader.  Each wavefront issues its share of every stage's
-// limb tile beside its own A runs, PF stages ahead, into an LDS ring of PF + 1
-// stage slots; the loads of one wavefront complete in issue order, so waiting
-// until at most (PF - 1) stages of its loads are outstanding leaves stage t's
-// A runs in registers and its share of stage t's limb tile in LDS, and one
-// barrier then makes the whole tile visible.  The slot written for stage
-// t + PF is the one stage t - 1 used, which every wavefront left at that
-// barrier.  A 64-lane load writes 64 consecutive 16-byte chunks of LDS, so each
-// fills one third (three limbs) or one half (two) of a chunk row; the rows
-// keep the padded stride of the split kernel's tile.  With the limb loads in
-// the same in-order queue as the A runs and no loader wavefront, a limb tile
-// is requested PF stages before it is used instead of two.
-template <int XT, int RL, int MT, int KS, int PF, bool NTX>
-__global__ __launch_bounds__(512, 2) void mfma_xtr_lds_kernel(MfmaArgs a)
-{
-    constexpr int CW = 8, NG = 4;
-    constexpr int WCOLS = 16 * MT * CW;  // SNP columns per workgroup
-    constexpr int KC = 64 * KS;          // subjects per stage
-    constexpr int NT = RL * NG;          // N tiles, limb-major
-    constexpr int NCOL = 16 * NT;        // limb columns = 16-byte chunks per 16-subject row
-    constexpr int QC = KC / 16;          // chunk rows per stage
-    constexpr int CHUNKS = NCOL * QC;
-    constexpr int NI = CHUNKS / 64;      // 64-chunk loads per stage
-    constexpr int NIW = NI / CW;         // per wavefront
-    constexpr int RS = NCOL + 8;         // LDS row stride (chunks)
-    constexpr int NS = PF + 1;           // LDS stage slots
-    constexpr int GPR = NCOL / 64;       // loads per chunk row
-    static_assert(NI % CW == 0 && NCOL % 64 == 0, "the limb tile splits evenly over the wavefronts");
-    static_assert(PF >= 2, "at least one stage in flight");
-    // outstanding loads of one wavefront allowed at the top of a stage
-    constexpr int VM_KEEP = (PF - 1) * (MT * KS + NIW);
-    static_assert(VM_KEEP < 64, "vmcnt holds 6 bits");
-    __shared__ v4i sR[NS][QC * RS];
-
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int64_t n = a.n, p = a.p, ldx = a.ldx;
-    const uint8_t* __restrict__ X = static_cast<const uint8_t*>(a.X);
-    const int64_t nstage = (n + KC - 1) / KC;
-    const int64_t nloop = (nstage + PF - 1) / PF * PF;
-    const int arow = 16 * (lane >> 4);
-    const int acol = lane & 15;
-    const int64_t jw = (int64_t)blockIdx.x * WCOLS + wid * (16 * MT);
-
-    // this wavefront's limb loads: load q = wid + CW u covers chunk row q / GPR,
-    // chunks 64 (q % GPR) .. + 63 of it
-    int lsrc[NIW], ldst[NIW];
-#pragma unroll
-    for (int u = 0; u < NIW; ++u) {
-        const int q = wid + CW * u;
-        lsrc[u] = ((q / GPR) * NCOL + 64 * (q % GPR) + lane) * 16;
-        ldst[u] = (q / GPR) * RS + 64 * (q % GPR);
-    }
-
-    v4i acc[MT][NT];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = v4i{0, 0, 0, 0};
-    v4i Ab[PF][MT][KS];
-    // stage t: A runs into ring slot t mod PF, limb tile into LDS slot t mod NS
-    // (stages past the end load the last stage's tile again; they are never used)
-    auto issue = [&](int64_t t, v4i (&A)[MT][KS]) {
-        const int64_t k0 = t * KC;
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-                A[mt][ks] = load_raw<NTX>(X, jw + mt * 16 + acol, p, ldx, k0 + ks * 64 + arow, n);
-        const int8_t* src = a.limbs + min(t, nstage - 1) * (int64_t)(16 * CHUNKS);
-        v4i* slot = sR[(int)(t % NS)];
-#pragma unroll
-        for (int u = 0; u < NIW; ++u)
-            __builtin_amdgcn_global_load_lds(static_cast<const void*>(src + lsrc[u]),
-                                             (__attribute__((address_space(3))) void*)(slot + ldst[u]), 16, 0, 0);
-    };
-#pragma unroll
-    for (int q = 0; q < PF; ++q) issue(q, Ab[q]);
-    for (int64_t s0 = 0; s0 < nloop; s0 += PF) {
-#pragma unroll
-        for (int q = 0; q < PF; ++q) {
-            const int64_t t = s0 + q;
-            // this wavefront's loads of stage t are done (vmcnt: low 4 bits in
-            // [3:0], high 2 in [15:14]; expcnt and lgkmcnt left at their maxima)
-            __builtin_amdgcn_s_waitcnt((VM_KEEP & 15) | ((VM_KEEP >> 4) << 14) | (7 << 4) | (15 << 8));
-            __builtin_amdgcn_s_barrier();
-            if (t < nstage) {
-                const v4i* sb = &sR[(int)(t % NS)][(lane >> 4) * RS + acol];
-                v4i bcur = sb[0];
-#pragma unroll
-                for (int ks = 0; ks < KS; ++ks) {
-                    v4i A[MT];
-#pragma unroll
-                    for (int mt = 0; mt < MT; ++mt) A[mt] = decode_a<XT>(Ab[q][mt][ks]);
-#pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) {
-                        const int f = ks * NT + nt + 1;  // next fragment
-                        v4i bnext = bcur;
-                        if (f < KS * NT) bnext = sb[(f / NT) * 4 * RS + (f % NT) * 16];
-#pragma unroll
-                        for (int mt = 0; mt < MT; ++mt)
-                            acc[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], bcur, acc[mt][nt], 0, 0, 0);
-                        bcur = bnext;
-                    }
-                }
-            }
-            issue(t + PF, Ab[q]);
-        }
-    }
-    __builtin_amdgcn_s_waitcnt(0);  // no load into LDS outlives the workgroup
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int bq = 0; bq < NG; ++bq)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int b = bq * 16 + acol;
-                const int64_t j = jw + mt * 16 + mfma_c_row(lane, v);
-                if (j < p && b < a.B) {
-                    int64_t tot = (int64_t)acc[mt][bq][v] + 256 * (int64_t)acc[mt][NG + bq][v];
-                    if constexpr (RL == 3) tot += 65536 * (int64_t)acc[mt][2 * NG + bq][v];
-                    a.out[(int64_t)b * p + j] = a.qscale[b] * (double)tot;
-                }
-            }
 }
 
 // Byte transpose of a 4 x 4 block: d[r] holds bytes (x_r0, x_r1, x_r2, x_r3);
@@ -699,10 +628,10 @@ __global__ __launch_bounds__(kT) void geno_check_kernel(const uint8_t* __restric
     if (__any(b) && (threadIdx.x & 63) == 0) atomicOr(bad, 1);
 }
 
-template <int XT, int NG, int NSPLIT, int PF, bool D8 = false>
+template <int XT, int NG, int NSPLIT, int PF, bool D8 = false, bool NTX = false>
 hipError_t launch_eta_shape(const MfmaEtaArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL((mfma_eta_kernel<XT, NG, NSPLIT, PF, D8>), dim3((unsigned)((a.n + 255) / 256)),
+    hipLaunchKernelGGL((mfma_eta_kernel<XT, NG, NSPLIT, PF, D8, NTX>), dim3((unsigned)((a.n + 255) / 256)),
                        dim3(256 * NSPLIT), 0, s, a);
     return hipGetLastError();
 }
@@ -716,6 +645,8 @@ hipError_t launch_eta_ng(const MfmaEtaArgs& a, hipStream_t s)
     case 2: return launch_eta_shape<XT, NG, 2, 4>(a, s);
     case 3: return launch_eta_shape<XT, NG, 2, 3>(a, s);
     case 4: return launch_eta_shape<XT, NG, 2, 2>(a, s);
+    case 5: return launch_eta_shape<XT, NG, 2, 3, NG == 4, true>(a, s);
+    case 6: return launch_eta_shape<XT, NG, 2, 2, NG == 4, true>(a, s);
     default: return launch_eta_shape<XT, NG, 2, 2, NG == 4>(a, s);
     }
 }
@@ -731,39 +662,28 @@ hipError_t launch_eta_xt(const MfmaEtaArgs& a, hipStream_t s)
     }
 }
 
-template <int XT, int NG, int RL, int CW, int LW, int MT, int KS, int PF>
+template <int XT, int NG, int RL, int CW, int LW, int MT, int KS, int PF, int LD = 2, bool NTX = false,
+          int XP = 0>
 hipError_t launch_split(const MfmaArgs& a, hipStream_t s)
 {
     constexpr int WCOLS = 16 * MT * CW;
-    hipLaunchKernelGGL((mfma_xtr_split_kernel<XT, NG, RL, CW, LW, MT, KS, PF>),
+    hipLaunchKernelGGL((mfma_xtr_split_kernel<XT, NG, RL, CW, LW, MT, KS, PF, LD, NTX, XP>),
                        dim3((unsigned)((a.p + WCOLS - 1) / WCOLS)), dim3(64 * (CW + LW)), 0, s, a);
-    return hipGetLastError();
-}
-
-template <int XT, int RL, int MT, int KS, int PF, bool NTX>
-hipError_t launch_lds(const MfmaArgs& a, hipStream_t s)
-{
-    constexpr int WCOLS = 16 * MT * 8;
-    hipLaunchKernelGGL((mfma_xtr_lds_kernel<XT, RL, MT, KS, PF, NTX>), dim3((unsigned)((a.p + WCOLS - 1) / WCOLS)),
-                       dim3(512), 0, s, a);
     return hipGetLastError();
 }
 
 template <int XT, int NG, int RL>
 hipError_t launch_ng(const MfmaArgs& a, hipStream_t s)
 {
-    // shapes 5..7 (direct-to-LDS limb tiles) serve four N groups only (B = 49..64)
-    if constexpr (NG == 4) {
-        switch (a.variant) {
-        case 5: return launch_lds<XT, RL, 3, 2, 3, false>(a, s);
-        case 6: return launch_lds<XT, RL, 3, 2, 3, true>(a, s);
-        case 7: return launch_lds<XT, RL, 3, 2, 2, false>(a, s);
-        default: break;
-        }
-    } else {
-        if (a.variant >= 5) return hipErrorInvalidValue;
-    }
     switch (a.variant) {
+    case 5: return launch_split<XT, NG, RL, 7, 1, 3, 1, 6, 3>(a, s);
+    case 6: return launch_split<XT, NG, RL, 7, 1, 3, 1, 4, 4>(a, s);
+    case 7: return launch_split<XT, NG, RL, 6, 2, 3, 1, 6, 3>(a, s);
+    case 8: return launch_split<XT, NG, RL, 6, 2, 3, 2, 3, 3, true>(a, s);
+    case 9: return launch_split<XT, NG, RL, 6, 2, 3, 2, 2, 2, true>(a, s);
+    case 10: return launch_split<XT, NG, RL, 7, 1, 3, 1, 6, 2, false, 4>(a, s);
+    case 11: return launch_split<XT, NG, RL, 7, 1, 3, 1, 4, 2, false, 4>(a, s);
+    case 12: return launch_split<XT, NG, RL, 6, 2, 3, 2, 2, 2, false, 8>(a, s);
     case 1: return launch_split<XT, NG, RL, 7, 1, 3, 1, 4>(a, s);
     case 2: return launch_split<XT, NG, RL, 6, 2, 3, 1, 6>(a, s);
     case 3: return launch_split<XT, NG, RL, 6, 2, 3, 1, 4>(a, s);

@@ -135,6 +135,19 @@ __global__ void to_r32_kernel(const double* __restrict__ u, const double* __rest
     if (threadIdx.x == 0) sumr[0] = s;
 }
 
+// The lambdas that stopped at max_iter (status 2) go on: active again, and the
+// step counter past the step whose objective was recorded last.
+__global__ void resume_kernel(int32_t* __restrict__ status, int32_t* __restrict__ active, int32_t* __restrict__ kit,
+                              const int32_t* __restrict__ iters, int B)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < B && status[b] == 2) {
+        status[b] = 0;
+        active[b] = 1;
+        kit[b] = iters[b] + 1;
+    }
+}
+
 // acc[0] += v[0] (one thread): running count of the columns the eta updates read.
 __global__ void count_add_kernel(const int32_t* __restrict__ v, long long* __restrict__ acc) { acc[0] += v[0]; }
 
@@ -210,6 +223,13 @@ hipError_t launch_to_r32(const double* u, const double* shift, float* r32, doubl
 {
     COX_LAUNCH(to_r32_kernel, 1, u, shift, r32, sumr, n);
 }
+hipError_t launch_resume(int32_t* status, int32_t* active, int32_t* kit, const int32_t* iters, int B,
+                         hipStream_t s)
+{
+    hipLaunchKernelGGL(resume_kernel, dim3(1), dim3(64), 0, s, status, active, kit, iters, B);
+    return hipGetLastError();
+}
+
 hipError_t launch_count_add(const int32_t* v, long long* acc, hipStream_t s)
 {
     hipLaunchKernelGGL(count_add_kernel, dim3(1), dim3(1), 0, s, v, acc);

@@ -1,0 +1,91 @@
+"""Device-allocation failures, injected through COXHIP_FAULT: cox_setup, a fit
+that allocates its objective trace, and the refit (which allocates its
+gathered columns per call) each return OUT_OF_MEMORY, free whatever they had
+already allocated -- the device's free memory is the same before and after --
+and leave the library usable: the next setup, and the same context's next
+calls, succeed.  "alloc" fails every allocation; "alloc@N" only the N-th, so
+that setup fails part way through its buffers (it makes about sixty).  What is
+checked is the library's own count of the device bytes it holds
+(cox_device_bytes): the device's free memory as the runtime reports it also
+moves with code-object loading and with frees the runtime defers."""
+import gc
+
+import numpy as np
+import pytest
+
+import coxsim
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+import paper_2010_16114_amd as P  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def prob():
+    d = coxsim.genotype_problem(3001, 400, 6, 0.3, 3131)
+    ldx = (d.n + 15) // 16 * 16
+    X = torch.zeros((d.p, ldx), dtype=torch.int8)
+    X[:, : d.n] = torch.from_numpy(d.G)
+    X = X.cuda()
+    # a first context and fit load the library's code objects (and the static
+    # scratch array) onto the device once per process; the byte counts below
+    # are taken after that
+    cox = _setup(d, X)
+    cox.fit_path([1.0], max_iter=2, step=1e-3, trace=True)
+    cox.refit(np.arange(3))
+    cox.rank_path(torch.zeros((1, d.p), device="cuda"))
+    cox.close()
+    return d, X
+
+
+def _held():
+    # contexts of earlier tests that are only waiting for the garbage collector
+    # would otherwise be destroyed in the middle of a measurement
+    gc.collect()
+    torch.cuda.synchronize()
+    return P.device_bytes()
+
+
+def _setup(d, X):
+    return P.Cox(X, d.time, d.event, xtype=P.X_INT8, n=d.n, max_batch=64)
+
+
+@pytest.mark.parametrize("spec", ["alloc", "alloc@1", "alloc@9", "alloc@33", "alloc@52"])
+def test_setup_failure_frees_everything(prob, spec, monkeypatch):
+    d, X = prob
+    held0 = _held()
+    monkeypatch.setenv("COXHIP_FAULT", spec)
+    with pytest.raises(P.CoxError) as ei:
+        _setup(d, X)
+    assert ei.value.status == P.ERR_OUT_OF_MEMORY
+    monkeypatch.delenv("COXHIP_FAULT")
+    assert _held() == held0
+    cox = _setup(d, X)
+    assert cox.lambda_max() > 0
+    cox.close()
+    assert _held() == held0
+
+
+def test_per_call_buffers_fail_cleanly(prob, monkeypatch):
+    d, X = prob
+    cox = _setup(d, X)
+    lam = [0.5 * cox.lambda_max()]
+    path = torch.zeros((2, d.p), device="cuda")
+    ref = cox.fit_path(lam, max_iter=5, tol=0.0, step=1e-3, trace=True)
+    held0 = _held()
+    monkeypatch.setenv("COXHIP_FAULT", "alloc")
+    for call in (lambda: cox.fit_path(lam, max_iter=5, tol=0.0, step=1e-3, trace=True),
+                 lambda: cox.refit(np.arange(5)),
+                 lambda: cox.rank_path(path)):
+        with pytest.raises(P.CoxError) as ei:
+            call()
+        assert ei.value.status == P.ERR_OUT_OF_MEMORY
+    monkeypatch.delenv("COXHIP_FAULT")
+    assert _held() == held0
+    again = cox.fit_path(lam, max_iter=5, tol=0.0, step=1e-3, trace=True)
+    np.testing.assert_array_equal(again[0].cpu().numpy(), ref[0].cpu().numpy())
+    np.testing.assert_array_equal(again[4], ref[4])
+    cox.close()
