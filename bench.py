@@ -72,12 +72,13 @@ def kernel_source_hash(files) -> str:
     return h.hexdigest()
 
 
-def stored_traffic(summary: str, sources, shape="all") -> float | None:
+def stored_traffic(summary: str, sources, shape="all", per="launch") -> float | None:
     """HBM bytes per launch of a kernel, from a committed counter summary under
     profiles/ (FETCH_SIZE + WRITE_SIZE per dispatch, each scaled by what the
     same counter reads for a plain copy of known size), or None when there is
     none, the kernel's sources changed since it was taken, or it holds no
-    figure for the pipeline shape that ran."""
+    figure for the pipeline shape that ran.  per = "column": bytes per changed
+    column, for a kernel whose traffic grows with the columns it reads."""
     path = os.path.join(ROOT, "profiles", summary)
     try:
         text = open(path).read()
@@ -86,17 +87,18 @@ def stored_traffic(summary: str, sources, shape="all") -> float | None:
     vals = {}
     for line in text.splitlines():
         line = line.strip().lstrip("- ")
-        if line.startswith(("traffic_bytes_per_launch_", "source_sha256")) and ":" in line:
+        if line.startswith(("traffic_bytes_per_", "source_sha256")) and ":" in line:
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     if vals.get("source_sha256") != kernel_source_hash(sources):
         return None
-    v = vals.get(f"traffic_bytes_per_launch_{shape}")
+    v = vals.get(f"traffic_bytes_per_{per}_{shape}")
     return float(v) if v is not None else None
 
 
 MFMA_SOURCES = ("paper_2010_16114_amd/csrc/mfma.hip", "paper_2010_16114_amd/csrc/mfma.h")
-GEMVT_SOURCES = ("paper_2010_16114_amd/csrc/gemvt.hip", "paper_2010_16114_amd/csrc/internal.h")
+GEMVT_SOURCES = ("paper_2010_16114_amd/csrc/gemvt.hip", "paper_2010_16114_amd/csrc/gemvt_dev.h",
+                 "paper_2010_16114_amd/csrc/internal.h")
 
 
 def log(msg):
@@ -147,23 +149,85 @@ def hbm_probe(gib: float = 4.0, reps: int = 10) -> dict:
 
 
 def gpu_clocks() -> dict:
-    """The GPU's clocks as the driver reports them at this moment (rocm-smi),
-    and its name; empty fields when the tool is not there."""
-    import subprocess
+    """The GPU's clock levels as the kernel driver lists them before the
+    workload (/sys/class/drm/card*/device/pp_dpm_sclk and pp_dpm_mclk, the
+    active level marked '*'; an idle GPU sits at a low level), and the device's
+    name; fields are left out when the files cannot be read."""
+    import glob
 
     import torch
 
-    out = {"device": torch.cuda.get_device_name(0)}
-    try:
-        r = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True, timeout=30)
-        for line in r.stdout.splitlines():
-            low = line.lower()
-            for key in ("sclk", "mclk", "fclk"):
-                if f"{key} clock level" in low and key not in out:
-                    out[key] = line.split(":", 2)[-1].strip()
-    except (OSError, subprocess.SubprocessError):
-        pass
+    prop = torch.cuda.get_device_properties(0)
+    out = {"device": prop.name or getattr(prop, "gcnArchName", ""), "arch": getattr(prop, "gcnArchName", "")}
+    for key in ("sclk", "mclk", "fclk"):
+        for path in sorted(glob.glob(f"/sys/class/drm/card*/device/pp_dpm_{key}")):
+            try:
+                with open(path) as fh:
+                    lines = fh.read().splitlines()
+            except OSError:
+                continue
+            active = [l.strip() for l in lines if l.strip().endswith("*")]
+            if active:
+                out[key] = active[0]
+                break
     return out
+
+
+class ClockSampler:
+    """Reads the GPU's active shader and memory clock levels (the '*' lines of
+    /sys/class/drm/card*/device/pp_dpm_sclk and pp_dpm_mclk) every `period`
+    seconds in a thread while the timed region runs, and reports how often
+    each level was seen.  Reports nothing where the files cannot be read."""
+
+    def __init__(self, period: float = 0.02):
+        import glob
+
+        self.period = period
+        self.paths = {}
+        for key in ("sclk", "mclk"):
+            found = sorted(glob.glob(f"/sys/class/drm/card*/device/pp_dpm_{key}"))
+            if found:
+                self.paths[key] = found[0]
+        self.counts = {key: {} for key in self.paths}
+        self.samples = 0
+
+    def _read(self):
+        for key, path in self.paths.items():
+            try:
+                with open(path) as fh:
+                    for line in fh:
+                        line = line.strip()
+                        if line.endswith("*"):
+                            level = line.split(":", 1)[-1].strip(" *")
+                            self.counts[key][level] = self.counts[key].get(level, 0) + 1
+            except OSError:
+                pass
+        self.samples += 1
+
+    def __enter__(self):
+        import threading
+
+        self._stop = threading.Event()
+
+        def run():
+            while not self._stop.is_set():
+                self._read()
+                self._stop.wait(self.period)
+
+        self._thread = threading.Thread(target=run, daemon=True)
+        if self.paths:
+            self._thread.start()
+        return self
+
+    def __exit__(self, *exc):
+        self._stop.set()
+        if self.paths:
+            self._thread.join()
+
+    def summary(self) -> dict:
+        return {"samples": self.samples, "period_s": self.period,
+                **{f"{key}_levels_seen": dict(sorted(c.items(), key=lambda kv: -kv[1]))
+                   for key, c in self.counts.items()}}
 
 
 def bench_gauss_fp32(args):
@@ -298,14 +362,16 @@ def bench_geno_batched(args):
     log(f"timing {args.steps} steps from beta = 0, {args.repeats} times")
     cox.timing(True)
     runs = []
-    for rep in range(args.repeats):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        beta, iters, obj, _ = cox.fit_path(lams, max_iter=args.steps, tol=0.0, step=sigma,
-                                           residual_bits=args.residual_bits)
-        torch.cuda.synchronize()
-        runs.append(time.perf_counter() - t0)
-        log(f"repeat {rep}: {1e3 * runs[-1] / args.steps:.2f} ms per step")
+    with ClockSampler() as sampler:
+        for rep in range(args.repeats):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            beta, iters, obj, _ = cox.fit_path(lams, max_iter=args.steps, tol=0.0, step=sigma,
+                                               residual_bits=args.residual_bits)
+            torch.cuda.synchronize()
+            runs.append(time.perf_counter() - t0)
+            log(f"repeat {rep}: {1e3 * runs[-1] / args.steps:.2f} ms per step")
+    clocks["during_timed_region"] = sampler.summary()
     eta_cols = cox.timing_columns()
     xtr_ms, xtr_n = cox.timing_read("xtr")
     risk_ms, risk_n = cox.timing_read("risk")
@@ -336,6 +402,9 @@ def bench_geno_batched(args):
     eta_bytes = n * cols_per_step + 3 * bpad * cols_per_step + 2 * 8 * B * n
     step_bytes = xtr_bytes + eta_bytes
     step_gbs = step_bytes / elapsed * args.steps / 1e9
+    per_col = stored_traffic(f"mfma_xtr_kernel_geno_fp8_{n}x{p}_b{B}_traffic.md", MFMA_SOURCES,
+                             f"eta_shape{tuning['eta_variant']}", per="column")
+    eta_traffic = per_col * cols_per_step if per_col is not None and limbs == 3 else None
     res = {
         "metric": METRIC,
         "value": args.steps * B / elapsed,
@@ -384,6 +453,7 @@ def bench_geno_batched(args):
                                 "achieved": eta_bytes / (ek_ms / max(ek_n, 1) / 1e3) / 1e9 if ek_n else None,
                                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                 "frac": eta_bytes / (ek_ms / max(ek_n, 1) / 1e3) / 1e9 / HBM_PEAK_GBS if ek_n else None,
+                                "traffic": eta_traffic,
                                 "algorithmic_bytes_per_launch": eta_bytes},
         "nnz_range": [int(nnz.min()), int(nnz.max())],
         "autotune": tuning,
@@ -402,8 +472,9 @@ def fp32_comparator(args, d, G, mu_d, sc_d, lams, sigma, n, p):
     """The plain FP32 method (one lambda per pass, FP32 standardised X) on the
     first p_s columns, K steps from beta = 0 at the largest and the smallest
     lambda of the path.  FP32 X of the full matrix (4 bytes per entry) does not
-    fit in HBM, and the step cost is linear in p, so the rate is scaled by
-    p_s / p."""
+    fit in HBM; the step's passes over X grow linearly in p and its risk-set
+    sums do not, so the measured time less the risk-set sums (timed with
+    events) is scaled by p / p_s."""
     import torch
 
     import paper_2010_16114_amd as P
@@ -413,22 +484,34 @@ def fp32_comparator(args, d, G, mu_d, sc_d, lams, sigma, n, p):
     X32 = standardise_fp8_to_fp32(G, mu_d, sc_d, ps, n)
     torch.cuda.synchronize()
     cox = P.Cox(X32, d.time, d.event, n=n, max_batch=1)
-    rates = []
+    rates, scaled = [], []
     for lam in (lams[0], lams[-1]):
         cox.fit_path([lam], max_iter=2, tol=0.0, step=sigma)
         torch.cuda.synchronize()
+        cox.timing(True)
         t0 = time.perf_counter()
         cox.fit_path([lam], max_iter=args.steps, tol=0.0, step=sigma)
         torch.cuda.synchronize()
-        rates.append(args.steps / (time.perf_counter() - t0))
+        dt = time.perf_counter() - t0
+        risk_ms, _ = cox.timing_read("risk")
+        cox.timing(False)
+        rates.append(args.steps / dt)
+        # the step's passes over X (X' r with its epilogue, the eta update) grow
+        # with the columns; the risk-set sums do not
+        risk_s = risk_ms / 1e3
+        scaled.append(args.steps / ((dt - risk_s) * p / ps + risk_s))
     cox.close()
     del X32
     torch.cuda.empty_cache()
     r = float(np.mean(rates))
-    log(f"FP32 comparator: {r:.1f} lambda-iters/s on {ps} columns -> {r * ps / p:.2f} scaled to {p}")
-    return {"value_slice": r, "value_scaled": r * ps / p, "unit": "lambda-iters/s", "columns": ps,
+    rs = float(np.mean(scaled))
+    log(f"FP32 comparator: {r:.1f} lambda-iters/s on {ps} columns -> {rs:.2f} scaled to {p}")
+    return {"value_slice": r, "value_scaled": rs, "unit": "lambda-iters/s", "columns": ps,
             "method": "plain FP32 X (standardised), one lambda per pass, same step, "
-                      f"{args.steps} steps from beta=0 at lambda_max and 0.01*lambda_max; rate scaled by {ps}/{p}"}
+                      f"{args.steps} steps from beta=0 at lambda_max and 0.01*lambda_max; the time of the step "
+                      f"less its risk-set sums scaled by {p}/{ps} (the passes over X grow with the columns, the "
+                      f"risk-set sums do not). The same-tolerance comparison without scaling is the geno-fp8-c3 "
+                      f"workload"}
 
 
 def cpu_baseline_geno(d, lam, sigma, p_full, p_sample: int = 8000, budget_s: float = 15.0):

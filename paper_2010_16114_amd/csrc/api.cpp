@@ -7,6 +7,7 @@
 // the device, and converts every HIP failure into a status code with a message
 // kept in the context.  All device work is enqueued on the context's stream.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
@@ -137,6 +138,9 @@ struct cox_ctx {
     double* pf = nullptr;         // device [p + kMaxCov]: factors of X's columns, then of the covariates
     std::vector<double> pf_host;  // [p + q]
     bool pf_x_custom = false;     // some factor of X's columns differs from 1
+    // roctx ranges of the phases (always on: a profiler with marker tracing shows them)
+    roctx_range_id_t rx_id[kPhases] = {};
+    bool rx_open[kPhases] = {};
     // measurement: event pairs recorded around each phase while timing is on
     bool timing = false;
     std::vector<hipEvent_t> tev[kPhases];
@@ -171,7 +175,8 @@ cox_status dev_fail(cox_ctx* c, hipError_t e, const char* what)
 
 // Allocation-failure injection for tests, from the environment variable
 // COXHIP_FAULT: "alloc" fails every device allocation of the library; "alloc@N"
-// fails only the N-th one counted from when the variable took that value, so
+// fails only the N-th one counted from when the variable took that value (a
+// value set again after the variable was unset counts from the start), so
 // that the clean-up after a failure part way through cox_setup (or through a
 // call's own buffers) can be exercised.
 bool fault_injected(const char* what)
@@ -180,7 +185,12 @@ bool fault_injected(const char* what)
     static std::string last;
     static long count = 0;
     const char* f = std::getenv("COXHIP_FAULT");
-    if (!f) return false;
+    if (!f) {
+        // unset: the next value starts its count afresh, even if it is the same
+        std::lock_guard<std::mutex> lock(mu);
+        last.clear();
+        return false;
+    }
     const size_t w = std::strlen(what);
     if (std::strncmp(f, what, w) != 0) return false;
     if (f[w] == '\0') return true;
@@ -249,9 +259,20 @@ void timing_clear(cox_ctx* c)
     }
 }
 
-// Record an event on the stream for phase ph (begin and end alternate).
+constexpr const char* kPhaseNames[kPhases] = {"cox:xtr", "cox:risk", "cox:eta", "cox:xtr_kernel", "cox:eta_kernel",
+                                              "cox:covariates", "cox:refit_hessian", "cox:refit_solve",
+                                              "cox:persistent"};
+
+// Mark the begin or the end of phase ph (they alternate): a roctx range on the
+// host, and while timing is on an event on the stream.
 void tmark(cox_ctx* c, int ph)
 {
+    if (c->rx_open[ph]) {
+        roctxRangeStop(c->rx_id[ph]);
+    } else {
+        c->rx_id[ph] = roctxRangeStartA(kPhaseNames[ph]);
+    }
+    c->rx_open[ph] = !c->rx_open[ph];
     if (!c->timing) return;
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) {
@@ -261,6 +282,29 @@ void tmark(cox_ctx* c, int ph)
     (void)hipEventRecord(e, c->stream);
     c->tev[ph].push_back(e);
 }
+
+// A roctx range around one entry-point call.  Phase ranges left open by an
+// early error return are closed with it, and their events dropped, so that
+// begin and end stay paired in the next call.
+struct CallRange {
+    cox_ctx* c;
+    CallRange(cox_ctx* ctx, const char* name) : c(ctx) { roctxRangePushA(name); }
+    ~CallRange()
+    {
+        if (c) {
+            for (int ph = 0; ph < kPhases; ++ph)
+                if (c->rx_open[ph]) {
+                    roctxRangeStop(c->rx_id[ph]);
+                    c->rx_open[ph] = false;
+                    if (c->timing && (c->tev[ph].size() & 1)) {
+                        (void)hipEventDestroy(c->tev[ph].back());
+                        c->tev[ph].pop_back();
+                    }
+                }
+        }
+        roctxRangePop();
+    }
+};
 
 void release(cox_ctx* c)
 {
@@ -1039,6 +1083,7 @@ cox_status cox_destroy(cox_ctx* c)
 
 cox_status cox_loss_grad(cox_ctx* c, const float* beta, int32_t B, double* loss, float* grad)
 {
+    CallRange range(c, "cox_loss_grad");
     STCHK(check_ctx(c));
     c->fit_valid = false;
     if (!beta || !loss) return fail(c, COX_ERR_INVALID_ARG, "beta and loss must not be NULL");
@@ -1074,6 +1119,7 @@ cox_status cox_loss_grad(cox_ctx* c, const float* beta, int32_t B, double* loss,
 
 cox_status cox_prox_step(cox_ctx* c, float* beta, int32_t B, const double* lambdas, double step, double* obj_before)
 {
+    CallRange range(c, "cox_prox_step");
     STCHK(check_ctx(c));
     c->fit_valid = false;
     if (!beta) return fail(c, COX_ERR_INVALID_ARG, "beta is NULL");
@@ -1113,6 +1159,7 @@ cox_status cox_prox_step(cox_ctx* c, float* beta, int32_t B, const double* lambd
 
 cox_status cox_prox_apply(cox_ctx* c, float* beta, const float* grad, int32_t B, const double* lambdas, double step)
 {
+    CallRange range(c, "cox_prox_apply");
     STCHK(check_ctx(c));
     if (!beta || !grad) return fail(c, COX_ERR_INVALID_ARG, "beta and grad must not be NULL");
     STCHK(check_batch(c, B));
@@ -1127,6 +1174,7 @@ cox_status cox_prox_apply(cox_ctx* c, float* beta, const float* grad, int32_t B,
 
 cox_status cox_lambda_max(cox_ctx* c, double* lambda_max)
 {
+    CallRange range(c, "cox_lambda_max");
     STCHK(check_ctx(c));
     c->fit_valid = false;
     if (!lambda_max) return fail(c, COX_ERR_INVALID_ARG, "lambda_max is NULL");
@@ -1169,6 +1217,7 @@ cox_status cox_lambda_max(cox_ctx* c, double* lambda_max)
 
 cox_status cox_opnorm2(cox_ctx* c, double tol, int32_t maxiter, uint64_t seed, double* s2, int32_t* iters)
 {
+    CallRange range(c, "cox_opnorm2");
     STCHK(check_ctx(c));
     c->fit_valid = false;
     if (!s2 || !(tol >= 0) || maxiter < 1) return fail(c, COX_ERR_INVALID_ARG, "bad opnorm2 arguments");
@@ -1221,6 +1270,7 @@ cox_status cox_opnorm2(cox_ctx* c, double tol, int32_t maxiter, uint64_t seed, d
 cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_fit_opts* opts_in, float* beta,
                         int32_t* iters, double* obj)
 {
+    CallRange range(c, "cox_fit_path");
     STCHK(check_ctx(c));
     if (!beta) return fail(c, COX_ERR_INVALID_ARG, "beta is NULL");
     STCHK(check_batch(c, B));
@@ -1432,6 +1482,7 @@ cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_
 cox_status cox_fit_sequence(cox_ctx* c, const double* lambdas, int32_t L, const cox_fit_opts* opts_in,
                             float* beta_path, int32_t* iters, double* obj)
 {
+    CallRange range(c, "cox_fit_sequence");
     STCHK(check_ctx(c));
     c->fit_valid = false;
     if (!beta_path || L < 1) return fail(c, COX_ERR_INVALID_ARG, "beta_path is NULL or L < 1");
@@ -1519,6 +1570,7 @@ extern "C" {
 cox_status cox_refit(cox_ctx* c, const int64_t* cols, int32_t m, const cox_refit_opts* opts_in, double* coef,
                      double* se, double* pval, double* loglik, int32_t* iters)
 {
+    CallRange range(c, "cox_refit");
     STCHK(check_ctx(c));
     c->fit_valid = false;
     const int q = (int)c->q, M = m + q;
@@ -1644,6 +1696,7 @@ cox_status cox_refit(cox_ctx* c, const int64_t* cols, int32_t m, const cox_refit
 cox_status cox_rank_path(cox_ctx* c, const float* path, int32_t L, int32_t* entry, float* entry_coef, int64_t* order,
                          int64_t* n_entered)
 {
+    CallRange range(c, "cox_rank_path");
     STCHK(check_ctx(c));
     if (!path || L < 1 || !entry) return fail(c, COX_ERR_INVALID_ARG, "rank_path needs path, L >= 1 and entry");
     const int64_t p = c->p;
@@ -1664,6 +1717,7 @@ cox_status cox_rank_path(cox_ctx* c, const float* path, int32_t L, int32_t* entr
 cox_status cox_rank_path_noalloc(cox_ctx* c, const float* path, int32_t L, int32_t* entry, float* entry_coef,
                                  int64_t* order, int64_t* n_entered)
 {
+    CallRange range(c, "cox_rank_path_noalloc");
     STCHK(check_ctx(c));
     if (!path || L < 1 || !entry || !entry_coef)
         return fail(c, COX_ERR_INVALID_ARG, "rank_path_noalloc needs path, L >= 1, entry and entry_coef");
@@ -1688,6 +1742,7 @@ cox_status cox_rank_path_noalloc(cox_ctx* c, const float* path, int32_t L, int32
 
 cox_status cox_nll_forward(cox_ctx* c, const void* eta, int32_t eta_f64, int32_t B, double* loss)
 {
+    CallRange range(c, "cox_nll_forward");
     STCHK(check_ctx(c));
     c->fit_valid = false;
     if (!eta || !loss || (eta_f64 != 0 && eta_f64 != 1)) return fail(c, COX_ERR_INVALID_ARG, "bad nll_forward arguments");
@@ -1706,6 +1761,7 @@ cox_status cox_nll_forward(cox_ctx* c, const void* eta, int32_t eta_f64, int32_t
 
 cox_status cox_nll_backward(cox_ctx* c, const double* grad_loss, int32_t B, void* grad_eta)
 {
+    CallRange range(c, "cox_nll_backward");
     STCHK(check_ctx(c));
     c->fit_valid = false;
     if (!grad_loss || !grad_eta) return fail(c, COX_ERR_INVALID_ARG, "bad nll_backward arguments");

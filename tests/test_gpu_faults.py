@@ -57,16 +57,26 @@ def _setup(d, X):
 def test_setup_failure_frees_everything(prob, spec, monkeypatch):
     d, X = prob
     held0 = _held()
-    monkeypatch.setenv("COXHIP_FAULT", spec)
-    with pytest.raises(P.CoxError) as ei:
-        _setup(d, X)
-    assert ei.value.status == P.ERR_OUT_OF_MEMORY
-    monkeypatch.delenv("COXHIP_FAULT")
-    assert _held() == held0
-    cox = _setup(d, X)
-    assert cox.lambda_max() > 0
-    cox.close()
-    assert _held() == held0
+    # a context left by an earlier test module can be freed part way through
+    # (the count then falls, never rises): the first attempt may absorb that,
+    # the second must leave the count exactly where it found it.  The setup
+    # that succeeds in between runs with the variable unset, so the second
+    # attempt counts its allocations from the start again.
+    for attempt in range(2):
+        monkeypatch.setenv("COXHIP_FAULT", spec)
+        with pytest.raises(P.CoxError) as ei:
+            _setup(d, X)
+        assert ei.value.status == P.ERR_OUT_OF_MEMORY
+        monkeypatch.delenv("COXHIP_FAULT")
+        held = _held()
+        cox = _setup(d, X)
+        assert cox.lambda_max() > 0
+        cox.close()
+        held1 = _held()
+        if held == held0 and held1 == held0:
+            break
+        assert attempt == 0 and held1 <= held <= held0, (held0, held, held1)
+        held0 = held1
 
 
 def test_per_call_buffers_fail_cleanly(prob, monkeypatch):
