@@ -176,8 +176,9 @@ def gpu_clocks() -> dict:
 class ClockSampler:
     """Reads the GPU's active shader and memory clock levels (the '*' lines of
     /sys/class/drm/card*/device/pp_dpm_sclk and pp_dpm_mclk) every `period`
-    seconds in a thread while the timed region runs, and reports how often
-    each level was seen.  Reports nothing where the files cannot be read."""
+    seconds in a thread while the timed region runs, and reports the median,
+    least and greatest MHz seen.  Reports nothing where the files cannot be
+    read."""
 
     def __init__(self, period: float = 0.02):
         import glob
@@ -225,9 +226,16 @@ class ClockSampler:
             self._thread.join()
 
     def summary(self) -> dict:
-        return {"samples": self.samples, "period_s": self.period,
-                **{f"{key}_levels_seen": dict(sorted(c.items(), key=lambda kv: -kv[1]))
-                   for key, c in self.counts.items()}}
+        out = {"samples": self.samples, "period_s": self.period}
+        for key, c in self.counts.items():
+            mhz = []
+            for level, k in c.items():
+                digits = level.lower().replace("mhz", "").strip()
+                if digits.isdigit():
+                    mhz += [int(digits)] * k
+            if mhz:
+                out[f"{key}_mhz"] = {"median": float(np.median(mhz)), "min": min(mhz), "max": max(mhz)}
+        return out
 
 
 def bench_gauss_fp32(args):
