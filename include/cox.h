@@ -363,14 +363,17 @@ typedef enum {
 /* The batched matrix-core passes (X~' R and the eta update, used when X holds
  * allele counts and B > 8) come in several pipeline shapes: COX_MFMA_VARIANTS
  * for X~' R, COX_MFMA_ETA_VARIANTS for the eta update.  The first batched call
- * times every shape once on the live data and keeps the fastest (the
+ * times every shape on the live data (one untimed and three timed launches,
+ * the median kept) and keeps the fastest (the
  * environment variable COXHIP_TUNE_CACHE names a file that caches the choice;
- * COXHIP_MFMA_VARIANT and COXHIP_ETA_VARIANT force one).  This reports the
+ * COXHIP_MFMA_VARIANT and COXHIP_ETA_VARIANT force one; COXHIP_ETA_SHARES sets
+ * how many workgroups the eta shapes that share blocks between workgroups use,
+ * at most the compute units, so that tests can make small problems share them).  This reports the
  * choices (-1: not yet tuned) and the tuning times in milliseconds (host
  * [COX_MFMA_VARIANTS] each, nullable; entries past a pass's shape count and
  * entries of a pass that was not timed are 0). */
 #define COX_MFMA_VARIANTS 13
-#define COX_MFMA_ETA_VARIANTS 7
+#define COX_MFMA_ETA_VARIANTS 13
 cox_status cox_mfma_tuning(cox_ctx *ctx, int32_t *xtr_variant, int32_t *eta_variant, float *xtr_ms, float *eta_ms);
 cox_status cox_timing_enable(cox_ctx *ctx, int32_t enable);
 cox_status cox_timing_read(cox_ctx *ctx, int32_t phase, double *total_ms, int64_t *count);

@@ -36,6 +36,7 @@ constexpr int kPhases = 9;  // cox_phase values
 
 static_assert(kMfmaVariants == COX_MFMA_VARIANTS && kMfmaEtaVariants == COX_MFMA_ETA_VARIANTS,
               "pipeline shape counts differ from the header");
+static_assert(kMfmaEtaVariants <= kMfmaVariants, "tuning times of both passes share one array size");
 static_assert(kMaxCov == COX_MAX_COVARIATES, "covariate limit differs from the header");
 static_assert(kMaxRefit == COX_MAX_REFIT, "refit column limit differs from the header");
 
@@ -100,6 +101,8 @@ struct cox_ctx {
     long long* rsump = nullptr;
     int* geno_bad = nullptr;
     int8_t* dlimbs = nullptr;    // [3][Bmax16][dstride] eta-update limbs
+    long long* eta_part = nullptr;  // [ncu][2][Bmax16][256] partial sums of blocks two eta workgroups share
+    int ncu = 0;                 // compute units of the device
     int64_t dstride = 0;
     double *dscale = nullptr, *dmaxp = nullptr;
     int xtr_variant = -1, eta_variant = -1;  // pipeline shapes last used (-1: not tuned yet)
@@ -1024,6 +1027,11 @@ cox_status cox_setup(cox_ctx** out, const cox_matrix* X, const double* time, con
              dalloc(c, &c->rmaxp, (size_t)max_batch * nt) && dalloc(c, &c->rsump, (size_t)max_batch * nt) &&
              dalloc(c, &c->geno_bad, 1) && dalloc(c, &c->dlimbs, (size_t)3 * c->bpad_max * c->dstride) &&
              dalloc(c, &c->dscale, max_batch) && dalloc(c, &c->dmaxp, (size_t)max_batch * ((c->dstride + 4095) / 4096));
+        if (ok && hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) {
+            (void)hipGetLastError();
+            c->ncu = 0;
+        }
+        if (ok && c->ncu > 0) ok = dalloc(c, &c->eta_part, (size_t)c->ncu * 2 * c->bpad_max * 256);
     }
     if (ok) {
         c->pinned_bytes = 64 * 1024;
@@ -1394,7 +1402,11 @@ cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_
                                          c->dscale, c->stream),
                        "quantise eta update");
                 MfmaEtaArgs m{c->x.X, c->x.xt, c->n, c->p, c->x.ldx, c->sel, c->nsel, c->dlimbs, c->dstride,
-                              bpad, B, c->dscale, c->eta, c->active, 0};
+                              bpad, B, c->dscale, c->eta, c->active, 0, c->eta_part, c->ncu};
+                if (const char* e = std::getenv("COXHIP_ETA_SHARES")) {
+                    const int v = std::atoi(e);
+                    if (v > 0 && v <= c->ncu) m.sk_grid = v;
+                }
                 const int forced = forced_variant("COXHIP_ETA_VARIANT", kMfmaEtaVariants);
                 if (forced >= 0) {
                     c->eta_variant = forced;

@@ -27,14 +27,11 @@ struct MfmaArgs {
                             // 1 = 7+1, 3, 64, 4; 2 = 6+2, 3, 64, 6; 3 = 6+2, 3, 64, 4; 4 = 6+2, 3, 128, 2
                             // (limb loads two stages ahead); with limb loads three or four stages
                             // ahead: 5 = 7+1, 3, 64, 6, 3; 6 = 7+1, 3, 64, 4, 4; 7 = 6+2, 3, 64, 6, 3;
-                            // streaming (non-temporal) X loads of whole 128-byte lines:
-                            // 8 = 6+2, 3, 128, 3, 3; 9 = 6+2, 3, 128, 2, 2;
-                            // A runs loaded along a column and moved to the matrix-core layout
-                            // through LDS, 64-byte runs: 10 = 7+1, 3, 64, 6; 11 = 7+1, 3, 64, 4;
-                            // 128-byte runs: 12 = 6+2, 3, 128, 2
+                            // limb-tile fragments read three ahead of their use (one otherwise):
+                            // 8 = 1, 10 = 3, 11 = 6, 12 = 4; five ahead: 9 = 1
 };
 constexpr int kMfmaVariants = 13;    // shapes of the X~' R pass
-constexpr int kMfmaEtaVariants = 7;  // shapes of the eta update
+constexpr int kMfmaEtaVariants = 13;  // shapes of the eta update
 
 // eta_b(i) += q_b * sum_{u < nsel} g(i, sel[u]) D_b(u), D in three int8 limbs.
 struct MfmaEtaArgs {
@@ -50,10 +47,19 @@ struct MfmaEtaArgs {
     const double* dscale;   // [B]
     double* eta;            // [B][n] FP64, updated in place
     const int32_t* active;  // [B] or null
-    int variant;            // stages of 64 columns ahead (8 wavefronts load both operands): 0, 1 = 2, 3
-                            // with the D tile moved in 8-byte pieces when bpad = 64 (16-byte chunks
-                            // otherwise); 2, 3, 4 = 4, 3, 2 with 16-byte chunks; 5, 6 = 3, 2 as 1, 0
-                            // with streaming (non-temporal) loads of G
+    int variant;            // pipeline shape.  One kernel, 8 wavefronts that load both operands,
+                            // 2 stages of 64 columns ahead: 0 = D tile in 8-byte pieces when
+                            // bpad = 64, 1 = in 16-byte chunks.  Loader and compute roles in separate
+                            // wavefronts (compute + loader wavefronts, stages of loads in the
+                            // loaders' ring, LDS buffers), one workgroup per 256 subjects:
+                            // 2 = 4+4, 3, 2; 3 = 4+4, 4, 2; 4 = 8+4, 3, 2; 5 = 4+4, 5, 2;
+                            // 6 = 2 with streaming loads of G; 7 = 8+4, 3, 3 (three buffers: the
+                            // compute wavefronts read the next stage's fragments ahead).  The same
+                            // with one workgroup per compute unit sharing the blocks evenly
+                            // (sk_grid, part): 8 = 6; 9 = 2; 10 = 3 with streaming loads; 11 = 4
+                            // with streaming loads; 12 = 5 with streaming loads
+    long long* part;        // [sk_grid][2][bpad][256] partial sums of shared blocks (variants 8..12), or null
+    int sk_grid;            // workgroups of variants 8..12: the compute units (0: one per block)
 };
 
 int mfma_ntile(int64_t n);

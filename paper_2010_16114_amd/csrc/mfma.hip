@@ -35,12 +35,13 @@ constexpr int kQBits = 22;       // |R| <= 2^22 keeps the top limb within int8
 constexpr int kQBits2 = 14;      // the same for two limbs (the residual's faster, coarser form)
 
 // Allele-count bytes -> int8 counts.  FP8 E4M3 codes of 0, 1, 2 are 0x00, 0x38,
-// 0x40: bit 3 marks 1 and bit 6 marks 2 (other codes are rejected beforehand).
+// 0x40, whose top three bits are the count itself (000, 001, 010); other codes
+// are rejected before any matrix-core pass runs.
 template <int XT>
 __device__ __forceinline__ uint32_t counts4(uint32_t w)
 {
     if constexpr (XT == XT_FP8)
-        return ((w >> 3) & 0x01010101u) | ((w >> 5) & 0x02020202u);
+        return (w >> 5) & 0x07070707u;
     else
         return w;
 }
@@ -90,24 +91,18 @@ __device__ __forceinline__ v4i decode_a(v4i raw)
 // per stage.  The limb rows of subjects >= n are zero (the quantiser writes
 // them so), so the padding bytes of X that meet them add nothing.
 //
-// XP (lanes per column run, 0 = off): the A runs are loaded so that XP
-// consecutive lanes read XP * 16 contiguous bytes of one column, and are moved
-// to the matrix-core layout (lane l: column l % 16, 16-subject chunk l / 16)
-// through a wavefront-private LDS slot.  In the direct layout the four lanes
-// of a quad address four columns 400 KB apart, so every lane of a load needs
-// its own address translation (rocprofv3 counts one UTCL1 request per 16
-// bytes of X, four times the rate of a contiguous read, with the address path
-// stalled by the L1 most of the time) and the L1 sends 64-byte requests.
-// XP = 4: a quad reads one 64-byte run (lane l: column l / 4, chunk l % 4);
-// XP = 8 (two 64-subject steps per stage): eight lanes read one 128-byte line
-// (load h of an M tile, lane l: column 8 h + l / 8, chunk l % 8).
+// BR (B fragments in flight): each compute wavefront reads the limb tile's
+// fragments from LDS BR - 1 fragments ahead of the matrix-core operations that
+// use them (a fragment serves MT of them), so that the LDS latency of a read
+// hides behind the work on the fragments before it.  Scheduling barriers keep
+// the compiler from sinking the reads next to their first use.
 template <int XT, int NG, int RL, int CW, int LW, int MT, int KS, int PF, int LD = 2, bool NTX = false,
-          int XP = 0>
+          int BR = 2>
 __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_split_kernel(MfmaArgs a)
 {
     static_assert(PF >= 2 && LD >= 2 && PF % LD == 0, "the loaders' ring of LD slots indexes statically");
-    static_assert(XP == 0 || XP == 4 || (XP == 8 && KS % 2 == 0), "runs of 4 lanes, or of 8 over two steps");
     static_assert(RL == 2 || RL == 3, "the residual comes in 2 or 3 limbs");
+    static_assert(BR >= 2, "one fragment read ahead at least");
     constexpr int WCOLS = 16 * MT * CW;  // SNP columns per workgroup
     constexpr int KC = 64 * KS;
     constexpr int NT = RL * NG;         // N tiles, limb-major: tile = limb * NG + b / 16
@@ -117,9 +112,8 @@ __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_split_
     constexpr int LTH = 64 * LW;
     constexpr int CPL = (CHUNKS + LTH - 1) / LTH;
     constexpr int RS = NCOL + 8;
-    constexpr int XS = 68;  // 16-byte entries of one A run's permutation slot (64, + 1 pad per 16 lanes)
+    constexpr int NF = KS * NT;  // B fragments per stage
     __shared__ v4i sR[2][QC * RS];
-    __shared__ v4i sX[XP ? CW * MT * KS * XS : 1];
 
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int64_t n = a.n, p = a.p, ldx = a.ldx;
@@ -130,18 +124,6 @@ __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_split_
     if (wid < CW) {
         const int arow = 16 * (lane >> 4);
         const int acol = lane & 15;
-        // where this lane's loads come from: the matrix-core layout, or (XP) runs along a column
-        const int lrow = XP == 4 ? 16 * (lane & 3) : (XP == 8 ? 16 * (lane & 7) : arow);
-        const int lcol = XP == 4 ? lane >> 2 : (XP == 8 ? lane >> 3 : acol);
-        // XP: the chunk a lane loaded belongs to lane 16 (chunk % 4) + column of the matrix-core
-        // layout (XP = 8: of step chunk / 4 of the load's pair); entries are padded by one after
-        // every 16 so that the writes of a run and the reads of 16 consecutive lanes meet
-        // distinct banks
-        const int xl = 16 * (lrow / 16 & 3) + lcol;
-        const int xw = xl + (xl >> 4);
-        const int xk = XP == 8 ? (lane & 7) >> 2 : 0;
-        const int xr = lane + (lane >> 4);
-        v4i* const xslot = sX + (XP ? wid * MT * KS * XS : 0);
         const int64_t jw = (int64_t)blockIdx.x * WCOLS + wid * (16 * MT);
         v4i acc[MT][NT];
 #pragma unroll
@@ -154,13 +136,8 @@ __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_split_
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt) {
-                    if constexpr (XP == 8)  // ks even and odd: the two column halves of M tile mt
-                        A[mt][ks] = load_raw<NTX>(X, jw + mt * 16 + 8 * (ks & 1) + lcol, p, ldx,
-                                                  k0 + (ks >> 1) * 128 + lrow, n);
-                    else
-                        A[mt][ks] = load_raw<NTX>(X, jw + mt * 16 + lcol, p, ldx, k0 + ks * 64 + lrow, n);
-                }
+                for (int mt = 0; mt < MT; ++mt)
+                    A[mt][ks] = load_raw<NTX>(X, jw + mt * 16 + acol, p, ldx, k0 + ks * 64 + arow, n);
         };
 #pragma unroll
         for (int q = 0; q < PF; ++q) fetch(q, Ab[q]);
@@ -172,41 +149,24 @@ __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_split_
                 const int buf = (int)(t & 1);
                 if (t < nstage) {
                     const v4i* sb = &sR[buf][(lane >> 4) * RS + acol];
-                    v4i bcur = sb[0];
-                    if constexpr (XP != 0) {
-                        // to the matrix-core layout through this wavefront's own LDS slot (LDS
-                        // operations of one wavefront complete in order: no barrier needed).
-                        // XP = 8: the load for (mt, ks) holds column half ks & 1 of steps
-                        // 2 (ks / 2) and 2 (ks / 2) + 1
+                    auto boff = [](int f) { return (f / NT) * 4 * RS + (f % NT) * 16; };
+                    v4i br[BR];
 #pragma unroll
-                        for (int ks = 0; ks < KS; ++ks)
+                    for (int f = 0; f < BR - 1 && f < NF; ++f) br[f] = sb[boff(f)];
+                    v4i A[MT];
 #pragma unroll
-                            for (int mt = 0; mt < MT; ++mt) {
-                                if constexpr (XP == 8)
-                                    xslot[((2 * (ks >> 1) + xk) * MT + mt) * XS + xw + 8 * (ks & 1)] = Ab[q][mt][ks];
-                                else
-                                    xslot[(ks * MT + mt) * XS + xw] = Ab[q][mt][ks];
-                            }
+                    for (int f = 0; f < NF; ++f) {
+                        if (f + BR - 1 < NF) br[(f + BR - 1) % BR] = sb[boff(f + BR - 1)];
+                        if (f % NT == 0) {
 #pragma unroll
-                        for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-                            for (int mt = 0; mt < MT; ++mt) Ab[q][mt][ks] = xslot[(ks * MT + mt) * XS + xr];
-                    }
-#pragma unroll
-                    for (int ks = 0; ks < KS; ++ks) {
-                        v4i A[MT];
-#pragma unroll
-                        for (int mt = 0; mt < MT; ++mt) A[mt] = decode_a<XT>(Ab[q][mt][ks]);
-#pragma unroll
-                        for (int nt = 0; nt < NT; ++nt) {
-                            const int f = ks * NT + nt + 1;  // next fragment
-                            v4i bnext = bcur;
-                            if (f < KS * NT) bnext = sb[(f / NT) * 4 * RS + (f % NT) * 16];
-#pragma unroll
-                            for (int mt = 0; mt < MT; ++mt)
-                                acc[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], bcur, acc[mt][nt], 0, 0, 0);
-                            bcur = bnext;
+                            for (int mt = 0; mt < MT; ++mt) A[mt] = decode_a<XT>(Ab[q][mt][f / NT]);
                         }
+                        if constexpr (BR > 2) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt)
+                            acc[mt][f % NT] =
+                                __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], br[f % BR], acc[mt][f % NT], 0, 0, 0);
+                        if constexpr (BR > 2) __builtin_amdgcn_sched_barrier(0);
                     }
                 }
                 fetch(t + PF, Ab[q]);
@@ -477,6 +437,348 @@ __global__ __launch_bounds__(256 * NSPLIT, NSPLIT) void mfma_eta_kernel(MfmaEtaA
     }
 }
 
+// eta update with the two operand streams in their own wavefronts, as in the
+// X~' R pass: LW loader wavefronts move each stage's G tile (decoded to int8
+// counts) and D tile into LDS and keep LDF stages of loads in flight in
+// registers; CW compute wavefronts only read LDS and run the matrix cores.
+// One barrier per stage joins the roles.  In mfma_eta_kernel every wavefront
+// waits for its own loads of the next stage before the barrier, so about one
+// stage of G is in flight per workgroup; here LDF - NB + 1 are.
+//   NB = 2 LDS buffers: while the compute wavefronts work on buffer t % 2, the
+//   loaders fill buffer (t + 1) % 2 with stage t + 1.
+//   NB = 3: the loaders fill buffer (t + 2) % 3 with stage t + 2, so stage
+//   t + 1 is complete while stage t is computed, and the compute wavefronts
+//   read its G fragments before their matrix-core work on stage t.
+// The work is a list of units (a block of 256 subjects, a stage of 64 columns
+// of the change list), block by block; workgroup w takes an equal share of
+// consecutive units.  With one workgroup per block (gridDim.x = the number of
+// blocks) a share is one whole block.  With fewer workgroups, one per compute
+// unit, every compute unit stays busy to the end instead of the last round of
+// blocks running on a few of them; a block whose units two workgroups share is
+// written by neither: each stores its exact int64 partial sums (a.part, slots
+// [workgroup][head, tail]) and eta_fixup_kernel adds their sum, so eta gets
+// the same single update, bit for bit, as from one workgroup.
+// Tile layout (XOR-swizzled dword positions) and fragment transposes are
+// mfma_eta_kernel's.  CW = 4: one compute wavefront per 64 subjects with every
+// b group; CW = 8: two, with half the b groups each.
+template <int XT, int NG, int CW, int LW, int LDF, int NB = 2, bool NTX = false>
+__global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_eta_split_kernel(MfmaEtaArgs a)
+{
+    static_assert(CW == 4 || CW == 8, "one or two compute wavefronts per 64 subjects");
+    static_assert(NB == 2 || NB == 3, "two or three LDS buffers");
+    static_assert(LDF >= NB, "the loaders' ring must reach the buffer they fill");
+    constexpr int AH = NB - 1;            // stages between the one computed and the one stored
+    constexpr int SUB = 256;              // subjects per block
+    constexpr int SW = SUB / 4;           // dwords per column of the G tile
+    constexpr int RB = SUB / 16;          // 16-byte chunks per column of the G tile
+    constexpr int NT = kLimbs * NG;
+    constexpr int NCOL = 16 * NT;
+    constexpr int NSPLIT = CW / 4;
+    constexpr int NGH = (NG + NSPLIT - 1) / NSPLIT;  // b groups of 16 per compute wavefront
+    constexpr int LT = 64 * LW;           // loader threads
+    constexpr int GCH = 64 * RB;          // 16-byte chunks of G per stage
+    constexpr int GPT = GCH / LT;
+    constexpr int DCH = 4 * NCOL;         // 16-byte chunks of D per stage
+    constexpr int DPT = (DCH + LT - 1) / LT;
+    constexpr int DS = NCOL + 8;          // LDS row stride of the D tile (16-byte units)
+    static_assert(GPT * LT == GCH, "G tile splits evenly over the loaders");
+    constexpr bool DALL = DCH % LT == 0;  // every loader thread moves DPT chunks of D
+    __shared__ uint32_t sG[NB][64 * SW];
+    __shared__ v4i sD[NB][4 * DS];
+    const int nsel = *a.nsel;
+    if (nsel == 0) return;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int64_t n = a.n, ldx = a.ldx;
+    const int nchunk = (nsel + 63) / 64;
+    // this workgroup's units: R whole blocks w, w + G, ... (the rounds in which every
+    // workgroup has a block), then its share of the T blocks left over
+    const int64_t nblk = (n + SUB - 1) / SUB;
+    const int64_t G = gridDim.x, w = blockIdx.x;
+    const int R = (int)(nblk / G);
+    const int64_t T = nblk - (int64_t)R * G;
+    const int64_t tu = T * nchunk, tbase = tu / G, trem = tu % G;
+    const int64_t tu0 = w * tbase + min(w, trem);  // first unit of the share within the left-over blocks
+    const int tlen = (int)(tbase + (w < trem ? 1 : 0));
+    const int64_t tblk0 = (int64_t)R * G + tu0 / nchunk;  // the block it starts in
+    const int tst0 = (int)(tu0 % nchunk);
+    const int nst = R * nchunk + tlen;
+    const int nloop = (nst + LDF - 1) / LDF * LDF;
+    // a position in this workgroup's unit list, advanced one stage at a time:
+    // r < R: stage st of block w + r G; r == R: stage st of left-over block blk
+    struct Pos {
+        int64_t blk;
+        int st, r;
+    };
+    const Pos first = R > 0 ? Pos{w, 0, 0} : Pos{tblk0, tst0, R};
+    auto advance = [&](Pos& q) {
+        if (++q.st < nchunk) return;
+        q.st = 0;
+        if (q.r == R) {  // within the share of the left-over blocks
+            ++q.blk;
+            return;
+        }
+        if (++q.r < R) {  // the next round's block
+            q.blk += G;
+            return;
+        }
+        q.blk = tblk0;  // the rounds are done: the share of the left-over blocks
+        q.st = tst0;
+    };
+
+    if (wid >= CW) {
+        // loaders; 32-bit index arithmetic (the host launches this kernel only for ldx < 2^32)
+        const int lt = threadIdx.x - 64 * CW;
+        const uint8_t* __restrict__ X = static_cast<const uint8_t*>(a.X);
+        const int32_t* __restrict__ sel = a.sel;
+        const uint32_t ldx32 = (uint32_t)ldx;
+        int gu[GPT], grow[GPT], gdst[GPT];  // column in the stage, subject in the block, LDS dword
+#pragma unroll
+        for (int k = 0; k < GPT; ++k) {
+            const int ch = lt + LT * k;
+            const int grb = ch % RB;
+            gu[k] = ch / RB;
+            grow[k] = 16 * grb;
+            gdst[k] = gu[k] * SW + ((4 * grb) ^ (((gu[k] >> 4) & 3) << 4));
+        }
+        // a stage's D tile is one contiguous block of DCH chunks ([16-position quarter][limb column])
+        const int8_t* dsrc[DPT];
+        int ddst[DPT];  // byte offset in a D buffer
+        bool dok[DPT];
+#pragma unroll
+        for (int k = 0; k < DPT; ++k) {
+            const int c = lt + LT * k;
+            dok[k] = DALL || c < DCH;
+            const int cc = dok[k] ? c : 0;
+            dsrc[k] = a.dlimbs + 16 * cc;
+            ddst[k] = ((cc / NCOL) * DS + cc % NCOL) * 16;
+        }
+        auto load_sel = [&](const Pos& q, int32_t (&s)[GPT]) {
+#pragma unroll
+            for (int k = 0; k < GPT; ++k) s[k] = sel[min(q.st * 64 + gu[k], nsel - 1)];
+        };
+        v4i gr[LDF][GPT];
+        v4i dr[LDF][DPT];
+        int32_t sr[LDF][GPT];  // column indices of stage t + LDF, in slot t mod LDF
+        // stage at position q.  Nothing needs zeroing: positions past the change list load
+        // the clamped last column and meet D limbs that are zero there, and subjects past
+        // the last one (a chunk that starts at or after n loads the start of X) reach only
+        // outputs that are never written; stages past the share are never flushed
+        auto fetch = [&](const Pos& q, const int32_t (&s)[GPT], v4i (&g)[GPT], v4i (&dd)[DPT]) {
+            const int64_t r0 = q.blk * SUB;
+#pragma unroll
+            for (int k = 0; k < GPT; ++k) {
+                const uint64_t off = r0 + grow[k] < n ? (uint64_t)(uint32_t)s[k] * ldx32 + (uint32_t)(r0 + grow[k]) : 0;
+                const v4i* src = reinterpret_cast<const v4i*>(X + off);
+                if constexpr (NTX)
+                    g[k] = __builtin_nontemporal_load(src);
+                else
+                    g[k] = *src;
+            }
+            const int64_t kd = (int64_t)q.st * (16 * DCH);
+#pragma unroll
+            for (int k = 0; k < DPT; ++k)
+                if (dok[k]) dd[k] = *reinterpret_cast<const v4i*>(dsrc[k] + kd);
+        };
+        auto store = [&](int buf, const v4i (&g)[GPT], const v4i (&dd)[DPT]) {
+#pragma unroll
+            for (int k = 0; k < GPT; ++k) *reinterpret_cast<v4i*>(&sG[buf][gdst[k]]) = decode_a<XT>(g[k]);
+            char* sd = reinterpret_cast<char*>(sD[buf]);
+#pragma unroll
+            for (int k = 0; k < DPT; ++k)
+                if (dok[k]) *reinterpret_cast<v4i*>(sd + ddst[k]) = dd[k];
+        };
+        Pos pf = first, ps = first;  // the stage the next fetch and the next column-index load are for
+        {
+            int32_t s0[LDF][GPT];
+#pragma unroll
+            for (int q = 0; q < LDF; ++q) {
+                load_sel(ps, s0[q]);
+                advance(ps);
+            }
+#pragma unroll
+            for (int q = 0; q < LDF; ++q) {
+                load_sel(ps, sr[q]);
+                advance(ps);
+            }
+#pragma unroll
+            for (int q = 0; q < LDF; ++q) {
+                fetch(pf, s0[q], gr[q], dr[q]);
+                advance(pf);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < AH; ++q) store(q, gr[q], dr[q]);
+        __syncthreads();
+        int wb = AH % NB;  // the buffer stage t + AH goes to
+        for (int c0 = 0; c0 < nloop; c0 += LDF) {
+#pragma unroll
+            for (int q = 0; q < LDF; ++q) {
+                // at step t = c0 + q: the loads of stage t + LDF go to slot q, which held stage t,
+                // stored before the last barrier
+                fetch(pf, sr[q], gr[q], dr[q]);
+                advance(pf);
+                load_sel(ps, sr[q]);
+                advance(ps);
+                __builtin_amdgcn_sched_barrier(0);  // keep the new loads ahead of the stores below
+                store(wb, gr[(q + AH) % LDF], dr[(q + AH) % LDF]);
+                wb = wb + 1 == NB ? 0 : wb + 1;
+                __syncthreads();
+            }
+        }
+        return;
+    }
+
+    // compute wavefronts
+    const int wsub = wid & 3, half = wid >> 2;
+    int bqs[NGH];
+#pragma unroll
+    for (int j = 0; j < NGH; ++j) bqs[j] = min(half * NGH + j, NG - 1);
+    v4i acc[4][kLimbs][NGH];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int l = 0; l < kLimbs; ++l)
+#pragma unroll
+            for (int j = 0; j < NGH; ++j) acc[mt][l][j] = v4i{0, 0, 0, 0};
+
+    const int xr = wsub * 16 + (lane & 15);  // this lane's dword (4 subjects) within a column
+    const int xs = xr ^ ((lane >> 4) << 4);  // its swizzled position (the 16-group of its columns is lane / 16)
+    // the A fragments of 4 M tiles from a G buffer
+    auto read_a = [&](int buf, v4i (&A)[4]) {
+        uint32_t f[4][4];  // f[mt][dword of the fragment]
+#pragma unroll
+        for (int blk = 0; blk < 4; ++blk) {
+            uint32_t d[4], o[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) d[e] = sG[buf][(16 * (lane >> 4) + 4 * blk + e) * SW + xs];
+            transpose4x4(d, o);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) f[mt][blk] = o[mt];
+        }
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) A[mt] = v4i{(int)f[mt][0], (int)f[mt][1], (int)f[mt][2], (int)f[mt][3]};
+    };
+    // the sums of a block's units: eta += q_b * sum, or (a left-over block, shared
+    // among workgroups) the exact partial sums into this workgroup's slot
+    auto flush = [&](int64_t blk, int slot) {
+#pragma unroll
+        for (int j = 0; j < NGH; ++j) {
+            if (half * NGH + j >= NG) continue;  // the repeated group of an odd NG
+            const int b = bqs[j] * 16 + (lane & 15);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = 64 * wsub + 4 * mfma_c_row(lane, v) + mt;
+                    const int64_t i = blk * SUB + r;
+                    if (i < n && b < a.B && (a.active == nullptr || a.active[b])) {
+                        const int64_t tot = (int64_t)acc[mt][0][j][v] + 256 * (int64_t)acc[mt][1][j][v] +
+                                            65536 * (int64_t)acc[mt][2][j][v];
+                        if (slot < 0)
+                            a.eta[(int64_t)b * n + i] += a.dscale[b] * (double)tot;
+                        else
+                            a.part[((w * 2 + slot) * a.bpad + b) * SUB + r] = tot;
+                    }
+                    acc[mt][0][j][v] = acc[mt][1][j][v] = acc[mt][2][j][v] = 0;
+                }
+        }
+    };
+    // a stage's matrix-core work: every limb and b group of the D tile in buffer cb
+    // against the 4 A fragments
+    auto mfma_stage = [&](int cb, const v4i (&A)[4]) {
+        const v4i* sb = &sD[cb][(lane >> 4) * DS + (lane & 15)];
+        v4i bcur = sb[bqs[0] * 16];
+#pragma unroll
+        for (int l = 0; l < kLimbs; ++l)
+#pragma unroll
+            for (int j = 0; j < NGH; ++j) {
+                const int f = l * NGH + j + 1;  // next fragment
+                v4i bnext = bcur;
+                if (f < kLimbs * NGH) bnext = sb[((f / NGH) * NG + bqs[f % NGH]) * 16];
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt)
+                    acc[mt][l][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], bcur, acc[mt][l][j], 0, 0, 0);
+                bcur = bnext;
+            }
+    };
+    __syncthreads();  // the loaders' first stages are in LDS
+    v4i A[4];
+    if constexpr (NB == 3) read_a(0, A);
+    int cb = 0;  // the buffer of stage t
+    Pos pc = first;
+    for (int t = 0; t < nloop; ++t) {
+        if constexpr (NB == 3) {
+            // stage t + 1 is complete: issue its fragment reads first, transpose them after
+            // this stage's matrix-core work
+            uint32_t d[4][4];
+            const int nb = cb + 1 == NB ? 0 : cb + 1;
+#pragma unroll
+            for (int blk = 0; blk < 4; ++blk)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) d[blk][e] = sG[nb][(16 * (lane >> 4) + 4 * blk + e) * SW + xs];
+            mfma_stage(cb, A);
+            uint32_t f[4][4];  // f[mt][dword of the fragment]
+#pragma unroll
+            for (int blk = 0; blk < 4; ++blk) {
+                uint32_t o[4];
+                transpose4x4(d[blk], o);
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) f[mt][blk] = o[mt];
+            }
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) A[mt] = v4i{(int)f[mt][0], (int)f[mt][1], (int)f[mt][2], (int)f[mt][3]};
+        } else {
+            read_a(cb, A);
+            mfma_stage(cb, A);
+        }
+        // the last unit of a block, or of this workgroup's share of a left-over block
+        if (t < nst && (pc.st == nchunk - 1 || t == nst - 1))
+            flush(pc.blk, pc.r < R ? -1 : (pc.blk == tblk0 ? 0 : 1));
+        advance(pc);
+        cb = cb + 1 == NB ? 0 : cb + 1;
+        __syncthreads();
+    }
+}
+
+// The left-over blocks of mfma_eta_split_kernel (those after the last round in
+// which every one of its `shares` workgroups had a whole block), one workgroup
+// per block: eta += q_b * (the sum of the partial sums of the shares that
+// cover it, in share order; a share covers at most two of them, its first in
+// slot 0, its second in slot 1).
+__global__ __launch_bounds__(kT) void eta_fixup_kernel(MfmaEtaArgs a, int shares)
+{
+    const int nsel = *a.nsel;
+    if (nsel == 0) return;
+    constexpr int SUB = 256;
+    const int64_t n = a.n, G = shares;
+    const int64_t nchunk = (nsel + 63) / 64;
+    const int64_t nblk = (n + SUB - 1) / SUB;
+    const int64_t R = nblk / G, T = nblk - R * G;
+    const int64_t tu = T * nchunk, tbase = tu / G, trem = tu % G;
+    const int64_t tb = blockIdx.x;  // left-over block
+    if (tb >= T) return;
+    // the share holding unit u of the left-over list
+    auto share_of = [&](int64_t u) {
+        const int64_t big = trem * (tbase + 1);
+        return u < big ? u / (tbase + 1) : trem + (u - big) / tbase;
+    };
+    const int64_t wa = share_of(tb * nchunk), wb = share_of((tb + 1) * nchunk - 1);
+    const int64_t blk = R * G + tb;
+    for (int e = threadIdx.x; e < a.B * SUB; e += kT) {
+        const int b = e / SUB, r = e % SUB;
+        const int64_t i = blk * SUB + r;
+        if (i < n && (a.active == nullptr || a.active[b])) {
+            int64_t tot = 0;
+            for (int64_t w = wa; w <= wb; ++w) {
+                const int64_t first = (w * tbase + min(w, trem)) / nchunk;  // the first left-over block of w
+                const int slot = first == tb ? 0 : 1;
+                tot += a.part[((w * 2 + slot) * a.bpad + b) * SUB + r];
+            }
+            a.eta[(int64_t)b * n + i] += a.dscale[b] * (double)tot;
+        }
+    }
+}
+
 // Largest |D_b(u)| over a tile of 4096 positions of the change list.
 __global__ __launch_bounds__(kT) void dmax_kernel(const double* __restrict__ dcoef, int64_t p,
                                                   const int32_t* __restrict__ sel, const int32_t* __restrict__ nsel,
@@ -636,18 +938,39 @@ hipError_t launch_eta_shape(const MfmaEtaArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+// SK: one workgroup per compute unit (a.sk_grid of them) sharing the blocks evenly,
+// then the shared blocks' partial sums; otherwise one workgroup per block.
+template <int XT, int NG, int CW, int LW, int LDF, int NB = 2, bool NTX = false, bool SK = false>
+hipError_t launch_eta_split(const MfmaEtaArgs& a, hipStream_t s)
+{
+    if (a.ldx >= (int64_t(1) << 32)) return hipErrorInvalidValue;  // its loaders index X in 32 bits
+    const int64_t nblk = (a.n + 255) / 256;
+    int64_t grid = nblk;
+    if (SK && a.part && a.sk_grid > 0 && a.sk_grid < nblk) grid = a.sk_grid;
+    hipLaunchKernelGGL((mfma_eta_split_kernel<XT, NG, CW, LW, LDF, NB, NTX>), dim3((unsigned)grid),
+                       dim3(64 * (CW + LW)), 0, s, a);
+    const int64_t left = nblk % grid;  // blocks after the last whole round
+    if (left > 0) hipLaunchKernelGGL(eta_fixup_kernel, dim3((unsigned)left), dim3(kT), 0, s, a, (int)grid);
+    return hipGetLastError();
+}
+
 template <int XT, int NG>
 hipError_t launch_eta_ng(const MfmaEtaArgs& a, hipStream_t s)
 {
-    // the 8-byte D pieces divide evenly over 512 threads at NG = 4 only
     switch (a.variant) {
-    case 1: return launch_eta_shape<XT, NG, 2, 3, NG == 4>(a, s);
-    case 2: return launch_eta_shape<XT, NG, 2, 4>(a, s);
-    case 3: return launch_eta_shape<XT, NG, 2, 3>(a, s);
-    case 4: return launch_eta_shape<XT, NG, 2, 2>(a, s);
-    case 5: return launch_eta_shape<XT, NG, 2, 3, NG == 4, true>(a, s);
-    case 6: return launch_eta_shape<XT, NG, 2, 2, NG == 4, true>(a, s);
-    default: return launch_eta_shape<XT, NG, 2, 2, NG == 4>(a, s);
+    case 1: return launch_eta_shape<XT, NG, 2, 2>(a, s);
+    case 2: return launch_eta_split<XT, NG, 4, 4, 3>(a, s);
+    case 3: return launch_eta_split<XT, NG, 4, 4, 4>(a, s);
+    case 4: return launch_eta_split<XT, NG, 8, 4, 3>(a, s);
+    case 5: return launch_eta_split<XT, NG, 4, 4, 5>(a, s);
+    case 6: return launch_eta_split<XT, NG, 4, 4, 3, 2, true>(a, s);
+    case 7: return launch_eta_split<XT, NG, 8, 4, 3, 3>(a, s);
+    case 8: return launch_eta_split<XT, NG, 4, 4, 3, 2, true, true>(a, s);
+    case 9: return launch_eta_split<XT, NG, 4, 4, 3, 2, false, true>(a, s);
+    case 10: return launch_eta_split<XT, NG, 4, 4, 4, 2, true, true>(a, s);
+    case 11: return launch_eta_split<XT, NG, 8, 4, 3, 2, true, true>(a, s);
+    case 12: return launch_eta_split<XT, NG, 4, 4, 5, 2, true, true>(a, s);
+    default: return launch_eta_shape<XT, NG, 2, 2, NG == 4>(a, s);  // the 8-byte D pieces divide over 512 threads at NG = 4
     }
 }
 
@@ -663,11 +986,11 @@ hipError_t launch_eta_xt(const MfmaEtaArgs& a, hipStream_t s)
 }
 
 template <int XT, int NG, int RL, int CW, int LW, int MT, int KS, int PF, int LD = 2, bool NTX = false,
-          int XP = 0>
+          int BR = 2>
 hipError_t launch_split(const MfmaArgs& a, hipStream_t s)
 {
     constexpr int WCOLS = 16 * MT * CW;
-    hipLaunchKernelGGL((mfma_xtr_split_kernel<XT, NG, RL, CW, LW, MT, KS, PF, LD, NTX, XP>),
+    hipLaunchKernelGGL((mfma_xtr_split_kernel<XT, NG, RL, CW, LW, MT, KS, PF, LD, NTX, BR>),
                        dim3((unsigned)((a.p + WCOLS - 1) / WCOLS)), dim3(64 * (CW + LW)), 0, s, a);
     return hipGetLastError();
 }
@@ -679,11 +1002,11 @@ hipError_t launch_ng(const MfmaArgs& a, hipStream_t s)
     case 5: return launch_split<XT, NG, RL, 7, 1, 3, 1, 6, 3>(a, s);
     case 6: return launch_split<XT, NG, RL, 7, 1, 3, 1, 4, 4>(a, s);
     case 7: return launch_split<XT, NG, RL, 6, 2, 3, 1, 6, 3>(a, s);
-    case 8: return launch_split<XT, NG, RL, 6, 2, 3, 2, 3, 3, true>(a, s);
-    case 9: return launch_split<XT, NG, RL, 6, 2, 3, 2, 2, 2, true>(a, s);
-    case 10: return launch_split<XT, NG, RL, 7, 1, 3, 1, 6, 2, false, 4>(a, s);
-    case 11: return launch_split<XT, NG, RL, 7, 1, 3, 1, 4, 2, false, 4>(a, s);
-    case 12: return launch_split<XT, NG, RL, 6, 2, 3, 2, 2, 2, false, 8>(a, s);
+    case 8: return launch_split<XT, NG, RL, 7, 1, 3, 1, 4, 2, false, 4>(a, s);
+    case 9: return launch_split<XT, NG, RL, 7, 1, 3, 1, 4, 2, false, 6>(a, s);
+    case 10: return launch_split<XT, NG, RL, 6, 2, 3, 1, 4, 2, false, 4>(a, s);
+    case 11: return launch_split<XT, NG, RL, 7, 1, 3, 1, 4, 4, false, 4>(a, s);
+    case 12: return launch_split<XT, NG, RL, 6, 2, 3, 2, 2, 2, false, 4>(a, s);
     case 1: return launch_split<XT, NG, RL, 7, 1, 3, 1, 4>(a, s);
     case 2: return launch_split<XT, NG, RL, 6, 2, 3, 1, 6>(a, s);
     case 3: return launch_split<XT, NG, RL, 6, 2, 3, 1, 4>(a, s);

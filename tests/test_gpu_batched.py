@@ -146,6 +146,31 @@ def test_every_pipeline_shape(prob, variant, monkeypatch):
         assert obj[b] == pytest.approx(tr[-1], rel=OBJ_TOL)
 
 
+# shares: one workgroup for all 12 blocks of 256 subjects, five (each share 2.4
+# blocks, so four blocks are split between two of them), eleven
+@pytest.mark.parametrize("ev,B", [(8, 64), (9, 64), (10, 64), (11, 64), (12, 64), (11, 40), (8, 20)])
+@pytest.mark.parametrize("shares", [1, 5, 11])
+def test_eta_shared_blocks_bit_identical(prob, ev, B, shares, monkeypatch):
+    """The eta shapes whose workgroups share blocks of subjects (each adds the
+    exact partial sums of a shared block to a buffer, a second kernel adds the
+    two) give bit for bit the iterates of the shape that gives every block its
+    own workgroup."""
+    cox, M = _setup(prob, "fp8", B)
+    lm = oracle.lambda_max(M, prob.time, prob.event)
+    lams = coxsim.lambda_grid(lm, B, 0.01)
+    sigma = 1.0 / (2.0 * oracle.opnorm2(M)[0])
+    monkeypatch.setenv("COXHIP_MFMA_VARIANT", "0")
+    monkeypatch.setenv("COXHIP_ETA_VARIANT", "2")
+    ref, _, oref, _ = cox.fit_path(lams, max_iter=12, tol=0.0, step=sigma)
+    monkeypatch.setenv("COXHIP_ETA_VARIANT", str(ev))
+    monkeypatch.setenv("COXHIP_ETA_SHARES", str(shares))
+    got, _, ogot, _ = cox.fit_path(lams, max_iter=12, tol=0.0, step=sigma)
+    assert cox.mfma_tuning()["eta_variant"] == ev
+    assert (ref != 0).sum() > B  # the updates touched many columns
+    np.testing.assert_array_equal(got.cpu().numpy().view(np.uint32), ref.cpu().numpy().view(np.uint32))
+    np.testing.assert_array_equal(ogot, oref)
+
+
 def _tune_entries(path):
     """The autotuner's JSON cache as a dict."""
     import json
