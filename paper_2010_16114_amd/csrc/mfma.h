@@ -27,8 +27,9 @@ struct MfmaArgs {
                             // 1 = 7+1, 3, 64, 4; 2 = 6+2, 3, 64, 6; 3 = 6+2, 3, 64, 4; 4 = 6+2, 3, 128, 2
                             // (limb loads two stages ahead); with limb loads three or four stages
                             // ahead: 5 = 7+1, 3, 64, 6, 3; 6 = 7+1, 3, 64, 4, 4; 7 = 6+2, 3, 64, 6, 3;
-                            // limb-tile fragments read three ahead of their use (one otherwise):
-                            // 8 = 1, 10 = 3, 11 = 6, 12 = 4; five ahead: 9 = 1
+                            // two compute wavefronts on every SIMD (2 M tiles each, 4 loader
+                            // wavefronts): 8 = 8+4, 2, 64, 6; 9 = 8+4, 2, 64, 4; 11 = 8+4, 2, 128, 2;
+                            // 12 = 8+4, 2, 64, 6, 3; one with 4 M tiles: 10 = 4+4, 4, 64, 2
 };
 constexpr int kMfmaVariants = 13;    // shapes of the X~' R pass
 constexpr int kMfmaEtaVariants = 13;  // shapes of the eta update

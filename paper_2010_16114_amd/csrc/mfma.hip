@@ -91,18 +91,15 @@ __device__ __forceinline__ v4i decode_a(v4i raw)
 // per stage.  The limb rows of subjects >= n are zero (the quantiser writes
 // them so), so the padding bytes of X that meet them add nothing.
 //
-// BR (B fragments in flight): each compute wavefront reads the limb tile's
-// fragments from LDS BR - 1 fragments ahead of the matrix-core operations that
-// use them (a fragment serves MT of them), so that the LDS latency of a read
-// hides behind the work on the fragments before it.  Scheduling barriers keep
-// the compiler from sinking the reads next to their first use.
-template <int XT, int NG, int RL, int CW, int LW, int MT, int KS, int PF, int LD = 2, bool NTX = false,
-          int BR = 2>
+// Each compute wavefront reads the limb tile's fragments from LDS one ahead of
+// the MT matrix-core operations that use each.  (Reading three or five ahead,
+// with scheduling barriers to keep the reads early, measured no faster.)
+template <int XT, int NG, int RL, int CW, int LW, int MT, int KS, int PF, int LD = 2, bool NTX = false>
 __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_split_kernel(MfmaArgs a)
 {
     static_assert(PF >= 2 && LD >= 2 && PF % LD == 0, "the loaders' ring of LD slots indexes statically");
     static_assert(RL == 2 || RL == 3, "the residual comes in 2 or 3 limbs");
-    static_assert(BR >= 2, "one fragment read ahead at least");
+    constexpr int BR = 2;  // B fragments in flight
     constexpr int WCOLS = 16 * MT * CW;  // SNP columns per workgroup
     constexpr int KC = 64 * KS;
     constexpr int NT = RL * NG;         // N tiles, limb-major: tile = limb * NG + b / 16
@@ -161,12 +158,10 @@ __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_split_
 #pragma unroll
                             for (int mt = 0; mt < MT; ++mt) A[mt] = decode_a<XT>(Ab[q][mt][f / NT]);
                         }
-                        if constexpr (BR > 2) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                         for (int mt = 0; mt < MT; ++mt)
                             acc[mt][f % NT] =
                                 __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], br[f % BR], acc[mt][f % NT], 0, 0, 0);
-                        if constexpr (BR > 2) __builtin_amdgcn_sched_barrier(0);
                     }
                 }
                 fetch(t + PF, Ab[q]);
@@ -742,11 +737,13 @@ __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_eta_split_
 
 // The left-over blocks of mfma_eta_split_kernel (those after the last round in
 // which every one of its `shares` workgroups had a whole block), one workgroup
-// per block: eta += q_b * (the sum of the partial sums of the shares that
-// cover it, in share order; a share covers at most two of them, its first in
-// slot 0, its second in slot 1).
+// per block and vector b (blockIdx.y), one thread per subject: eta += q_b *
+// (the sum of the partial sums of the shares that cover the block, in share
+// order; a share covers at most two of them, its first in slot 0, its second
+// in slot 1).
 __global__ __launch_bounds__(kT) void eta_fixup_kernel(MfmaEtaArgs a, int shares)
 {
+    static_assert(kT == 256, "one thread per subject of a block");
     const int nsel = *a.nsel;
     if (nsel == 0) return;
     constexpr int SUB = 256;
@@ -764,18 +761,16 @@ __global__ __launch_bounds__(kT) void eta_fixup_kernel(MfmaEtaArgs a, int shares
     };
     const int64_t wa = share_of(tb * nchunk), wb = share_of((tb + 1) * nchunk - 1);
     const int64_t blk = R * G + tb;
-    for (int e = threadIdx.x; e < a.B * SUB; e += kT) {
-        const int b = e / SUB, r = e % SUB;
-        const int64_t i = blk * SUB + r;
-        if (i < n && (a.active == nullptr || a.active[b])) {
-            int64_t tot = 0;
-            for (int64_t w = wa; w <= wb; ++w) {
-                const int64_t first = (w * tbase + min(w, trem)) / nchunk;  // the first left-over block of w
-                const int slot = first == tb ? 0 : 1;
-                tot += a.part[((w * 2 + slot) * a.bpad + b) * SUB + r];
-            }
-            a.eta[(int64_t)b * n + i] += a.dscale[b] * (double)tot;
+    const int b = blockIdx.y, r = threadIdx.x;
+    const int64_t i = blk * SUB + r;
+    if (i < n && (a.active == nullptr || a.active[b])) {
+        int64_t tot = 0;
+        for (int64_t w = wa; w <= wb; ++w) {
+            const int64_t first = (w * tbase + min(w, trem)) / nchunk;  // the first left-over block of w
+            const int slot = first == tb ? 0 : 1;
+            tot += a.part[((w * 2 + slot) * a.bpad + b) * SUB + r];
         }
+        a.eta[(int64_t)b * n + i] += a.dscale[b] * (double)tot;
     }
 }
 
@@ -950,7 +945,7 @@ hipError_t launch_eta_split(const MfmaEtaArgs& a, hipStream_t s)
     hipLaunchKernelGGL((mfma_eta_split_kernel<XT, NG, CW, LW, LDF, NB, NTX>), dim3((unsigned)grid),
                        dim3(64 * (CW + LW)), 0, s, a);
     const int64_t left = nblk % grid;  // blocks after the last whole round
-    if (left > 0) hipLaunchKernelGGL(eta_fixup_kernel, dim3((unsigned)left), dim3(kT), 0, s, a, (int)grid);
+    if (left > 0) hipLaunchKernelGGL(eta_fixup_kernel, dim3((unsigned)left, (unsigned)a.B), dim3(kT), 0, s, a, (int)grid);
     return hipGetLastError();
 }
 
@@ -985,12 +980,11 @@ hipError_t launch_eta_xt(const MfmaEtaArgs& a, hipStream_t s)
     }
 }
 
-template <int XT, int NG, int RL, int CW, int LW, int MT, int KS, int PF, int LD = 2, bool NTX = false,
-          int BR = 2>
+template <int XT, int NG, int RL, int CW, int LW, int MT, int KS, int PF, int LD = 2, bool NTX = false>
 hipError_t launch_split(const MfmaArgs& a, hipStream_t s)
 {
     constexpr int WCOLS = 16 * MT * CW;
-    hipLaunchKernelGGL((mfma_xtr_split_kernel<XT, NG, RL, CW, LW, MT, KS, PF, LD, NTX, BR>),
+    hipLaunchKernelGGL((mfma_xtr_split_kernel<XT, NG, RL, CW, LW, MT, KS, PF, LD, NTX>),
                        dim3((unsigned)((a.p + WCOLS - 1) / WCOLS)), dim3(64 * (CW + LW)), 0, s, a);
     return hipGetLastError();
 }
@@ -1002,11 +996,11 @@ hipError_t launch_ng(const MfmaArgs& a, hipStream_t s)
     case 5: return launch_split<XT, NG, RL, 7, 1, 3, 1, 6, 3>(a, s);
     case 6: return launch_split<XT, NG, RL, 7, 1, 3, 1, 4, 4>(a, s);
     case 7: return launch_split<XT, NG, RL, 6, 2, 3, 1, 6, 3>(a, s);
-    case 8: return launch_split<XT, NG, RL, 7, 1, 3, 1, 4, 2, false, 4>(a, s);
-    case 9: return launch_split<XT, NG, RL, 7, 1, 3, 1, 4, 2, false, 6>(a, s);
-    case 10: return launch_split<XT, NG, RL, 6, 2, 3, 1, 4, 2, false, 4>(a, s);
-    case 11: return launch_split<XT, NG, RL, 7, 1, 3, 1, 4, 4, false, 4>(a, s);
-    case 12: return launch_split<XT, NG, RL, 6, 2, 3, 2, 2, 2, false, 4>(a, s);
+    case 8: return launch_split<XT, NG, RL, 8, 4, 2, 1, 6, 2>(a, s);
+    case 9: return launch_split<XT, NG, RL, 8, 4, 2, 1, 4, 2>(a, s);
+    case 10: return launch_split<XT, NG, RL, 4, 4, 4, 1, 2, 2>(a, s);
+    case 11: return launch_split<XT, NG, RL, 8, 4, 2, 2, 2, 2>(a, s);
+    case 12: return launch_split<XT, NG, RL, 8, 4, 2, 1, 6, 3>(a, s);
     case 1: return launch_split<XT, NG, RL, 7, 1, 3, 1, 4>(a, s);
     case 2: return launch_split<XT, NG, RL, 6, 2, 3, 1, 6>(a, s);
     case 3: return launch_split<XT, NG, RL, 6, 2, 3, 1, 4>(a, s);

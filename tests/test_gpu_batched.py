@@ -132,7 +132,7 @@ def test_every_pipeline_shape(prob, variant, monkeypatch):
     xv, ev = variant % P.MFMA_VARIANTS, variant % P.ETA_VARIANTS
     monkeypatch.setenv("COXHIP_MFMA_VARIANT", str(xv))
     monkeypatch.setenv("COXHIP_ETA_VARIANT", str(ev))
-    B = 64 if xv >= 5 else 32  # the direct-to-LDS shapes serve B = 49..64 only
+    B = 64 if xv >= 5 else 32  # both paddings of the limb tile: two b groups and four
     cox, M = _setup(prob, "fp8", B)
     lm = oracle.lambda_max(M, prob.time, prob.event)
     lams = coxsim.lambda_grid(lm, B, 0.01)
