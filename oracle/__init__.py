@@ -59,6 +59,7 @@ def _load():
     lib.cox_oracle_fit_hist.argtypes = mat + [vp, vp, dbl, dbl, i32, dbl, i32, vp, vp, vp, vp]
     lib.cox_oracle_newton.argtypes = mat + [vp, vp, vp, i64, vp, vp, i32, dbl, vp, vp]
     lib.cox_oracle_lambda_max_pf.argtypes = mat + [vp, vp, vp, dbl, vp, vp]
+    lib.cox_oracle_rank_path.argtypes = [vp, i32, i64, i64, vp, vp, vp, vp]
     lib.nmf_oracle_objective.argtypes = [vp, i64, i64, i64, i32, vp, vp]
     lib.nmf_oracle_objective.restype = dbl
     lib.nmf_oracle_run.argtypes = [vp, i64, i64, i64, i32, i32, dbl, i32, vp, vp, vp]
@@ -281,6 +282,21 @@ def lambda_max_pf(X: Matrix, time, event, pf, gtol: float = 1e-10):
 # ---- nonnegative matrix factorisation (Section 5.1), nmf_oracle.c
 
 NMF_MU, NMF_APG = 0, 1
+
+
+def rank_path(path):
+    """Section 6's ranking of a path of coefficient vectors (rows: the lambdas,
+    decreasing; float32): (entry row per column, -1 if never nonzero;
+    |coefficient| at entry; the entered columns in rank order)."""
+    P = np.ascontiguousarray(path, dtype=np.float32)
+    L, p = P.shape
+    entry = np.empty(p, np.int32)
+    coef = np.empty(p, np.float32)
+    order = np.empty(p, np.int64)
+    m = ctypes.c_int64()
+    if _load().cox_oracle_rank_path(_ptr(P), L, p, p, _ptr(entry), _ptr(coef), _ptr(order), ctypes.byref(m)):
+        raise ValueError("bad input")
+    return entry, coef, order[: m.value]
 
 
 def _nmf_args(X, Vt, W):

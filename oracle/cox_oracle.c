@@ -28,9 +28,15 @@
  *     sigma lambda pf_j (pf_j = 0: the column is unpenalised);
  *   - the unpenalised Cox fit on a chosen set of columns that the same section
  *     uses for its significance tests, here by Newton's method on L with its
- *     exact Hessian (the textbook maximiser; the paper names no method).
+ *     exact Hessian (the textbook maximiser; the paper names no method);
+ *   - Section 6's ranking of the selected columns: by the largest lambda of
+ *     the path at which a column's coefficient is nonzero, ties by the
+ *     magnitude of the coefficient when it joins the model.
  *
  * Readings taken where the paper is silent or inconsistent:
+ *   - the ranking reads a path given in decreasing lambda, so a column's
+ *     largest lambda is the first row where it is nonzero; columns tied on
+ *     both the row and |coefficient| go in increasing column order;
  *   - the threshold of the prox is sigma*lambda (standard ISTA for the stated
  *     objective), not lambda;
  *   - risk sets use the observed times y, ties included (Breslow): tied
@@ -671,4 +677,46 @@ int cox_oracle_lambda_max_pf(int kind, const void *data, int64_t n, int64_t p, i
 out:
     free(cols); free(beta); free(bu); free(g);
     return rc;
+}
+
+/* Section 6's ranking of a lambda path.  path is L x p (row l: the
+ * coefficients at the l-th lambda, the lambdas decreasing; row stride ldp).
+ * entry[j] = the first row where column j is nonzero (-1: never), coef[j] =
+ * |path[entry[j]][j]| (0 if never), order[0..m) = the columns with entry >= 0
+ * by entry ascending, then coef descending, then column ascending; m is
+ * returned through m_out.  Returns 0, or -1 on bad input. */
+static const int32_t *rank_entry;
+static const float *rank_coef;
+
+static int rank_cmp(const void *a, const void *b)
+{
+    const int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    if (rank_entry[x] != rank_entry[y]) return rank_entry[x] < rank_entry[y] ? -1 : 1;
+    if (rank_coef[x] != rank_coef[y]) return rank_coef[x] > rank_coef[y] ? -1 : 1;
+    return x < y ? -1 : (x > y);
+}
+
+int cox_oracle_rank_path(const float *path, int32_t L, int64_t p, int64_t ldp, int32_t *entry, float *coef,
+                         int64_t *order, int64_t *m_out)
+{
+    if (!path || L < 1 || p < 1 || ldp < p || !entry || !coef || !order || !m_out) return -1;
+    int64_t m = 0;
+    for (int64_t j = 0; j < p; ++j) {
+        entry[j] = -1;
+        coef[j] = 0.0f;
+        for (int32_t l = 0; l < L; ++l) {
+            const float v = path[(int64_t)l * ldp + j];
+            if (v != 0.0f) {
+                entry[j] = l;
+                coef[j] = fabsf(v);
+                break;
+            }
+        }
+        if (entry[j] >= 0) order[m++] = j;
+    }
+    rank_entry = entry;
+    rank_coef = coef;
+    qsort(order, (size_t)m, sizeof(int64_t), rank_cmp);
+    *m_out = m;
+    return 0;
 }

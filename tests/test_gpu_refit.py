@@ -1,8 +1,8 @@
 """GPU parity of the post-selection step of Section 6: ranking the columns a
 lasso path selects, the unpenalised Newton refit on them with the covariates,
 and the Wald statistics, through the C ABI, against the FP64 oracle's Newton
-fit and inverse information (pinned in tests/test_oracle_penalty.py) and a
-plain restatement of the ranking rule.
+fit and inverse information (pinned in tests/test_oracle_penalty.py) and the
+oracle's ranking (pinned in tests/test_oracle_rank.py).
 
 The refit gathers the chosen genotype columns as FP32 values of (g - mu) s.
 Against the oracle on those same FP32 values the coefficients, standard
@@ -203,17 +203,6 @@ def test_refit_argument_checks(prob):
     assert ei.value.status == P.ERR_INVALID_ARG
 
 
-def _rank_reference(path, p):
-    """Section 6's rule restated: entry = first row with a nonzero (the largest
-    lambda of a decreasing path), ties broken by |coef| at entry, then index."""
-    nz = path[:, :p] != 0
-    entry = np.where(nz.any(axis=0), nz.argmax(axis=0), -1)
-    coef = np.array([abs(path[e, j]) if e >= 0 else 0.0 for j, e in enumerate(entry)], np.float32)
-    idx = [j for j in range(p) if entry[j] >= 0]
-    idx.sort(key=lambda j: (entry[j], -coef[j], j))
-    return entry, coef, np.array(idx, np.int64)
-
-
 def test_rank_path_by_hand(prob):
     d, Z = prob
     cox, M = _setup(prob, "f32", with_cov=False)
@@ -227,6 +216,10 @@ def test_rank_path_by_hand(prob):
     path[2, 5] = 0.3     # tie with column 4 on |coef|: index order
     entry, coef, order = cox.rank_path(torch.from_numpy(path).cuda())
     np.testing.assert_array_equal(order, [7, 9, 2, 4, 5])
+    e_o, c_o, o_o = oracle.rank_path(path)
+    np.testing.assert_array_equal(order, o_o)
+    np.testing.assert_array_equal(entry, e_o)
+    np.testing.assert_array_equal(coef, c_o)
     assert entry[7] == 0 and entry[2] == 1 and entry[4] == 2 and entry[0] == -1
     assert coef[9] == np.float32(0.3) and coef[7] == np.float32(0.5)
 
@@ -241,7 +234,7 @@ def test_section6_protocol_end_to_end(prob):
     path, iters, obj, st = cox.fit_sequence(lams, max_iter=3000, tol=1e-5, lag=10)
     assert st == P.OK
     entry, coef, order = cox.rank_path(path)
-    ref_entry, ref_coef, ref_order = _rank_reference(path.cpu().numpy(), d.p)
+    ref_entry, ref_coef, ref_order = oracle.rank_path(path.cpu().numpy()[:, : d.p])
     np.testing.assert_array_equal(entry, ref_entry)
     np.testing.assert_array_equal(coef, ref_coef)
     np.testing.assert_array_equal(order, ref_order)

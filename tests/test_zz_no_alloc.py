@@ -8,6 +8,8 @@ work."""
 import numpy as np
 import pytest
 
+import oracle
+
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
@@ -55,6 +57,9 @@ def test_noalloc_rank_matches_rank_path_on_two_calls(sizes):
         np.testing.assert_array_equal(e, e_ref)
         np.testing.assert_array_equal(c.view(np.uint32), c_ref.view(np.uint32))
         np.testing.assert_array_equal(o, o_ref)
+        e_o, c_o, o_o = oracle.rank_path(path.cpu().numpy())  # and both are Section 6's ranking
+        np.testing.assert_array_equal(e, e_o)
+        np.testing.assert_array_equal(o, o_o)
         cox.close()
 
 
