@@ -27,9 +27,10 @@ struct MfmaArgs {
                             // 1 = 7+1, 3, 64, 4; 2 = 6+2, 3, 64, 6; 3 = 6+2, 3, 64, 4; 4 = 6+2, 3, 128, 2
                             // (limb loads two stages ahead); with limb loads three or four stages
                             // ahead: 5 = 7+1, 3, 64, 6, 3; 6 = 7+1, 3, 64, 4, 4; 7 = 6+2, 3, 64, 6, 3;
-                            // two compute wavefronts on every SIMD (2 M tiles each, 4 loader
-                            // wavefronts): 8 = 8+4, 2, 64, 6; 9 = 8+4, 2, 64, 4; 11 = 8+4, 2, 128, 2;
-                            // 12 = 8+4, 2, 64, 6, 3; one with 4 M tiles: 10 = 4+4, 4, 64, 2
+                            // X through LDS as well, loaded by the loader wavefronts (compute +
+                            // loader wavefronts, M tiles, stages of loads in flight): 8 = 4+4, 4, 3;
+                            // 9 = 4+4, 4, 4; 10 = 4+4, 3, 3; 11 = 8 with streaming X loads;
+                            // 12 = 8+4, 2, 3
 };
 constexpr int kMfmaVariants = 13;    // shapes of the X~' R pass
 constexpr int kMfmaEtaVariants = 13;  // shapes of the eta update

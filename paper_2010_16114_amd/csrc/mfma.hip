@@ -223,6 +223,161 @@ __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_split_
     }
 }
 
+// X~' R with both operands through LDS.  LW loader wavefronts move each
+// stage's X tile (the workgroup's WCOLS columns x 64 subjects, decoded to
+// counts) and limb tile into LDS, with LDF stages of loads in flight in
+// registers; CW compute wavefronts read both from LDS and run the matrix cores.
+// The loaders read a column's 64 bytes of a stage with 4 adjacent lanes, so
+// that they go out as one 64-byte request with one address translation; in
+// the matrix-core layout that mfma_xtr_split_kernel loads directly those bytes
+// sit in lanes 16 apart and go out as four 16-byte requests.  In LDS a column
+// takes 80 bytes (64 + 16 of padding), so that the 16 lanes of a fragment read
+// (16 consecutive columns, one 16-byte chunk each) hit distinct banks.
+template <int XT, int NG, int RL, int CW, int LW, int MT, int LDF, bool NTX = false>
+__global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_lds_kernel(MfmaArgs a)
+{
+    static_assert(LDF >= 2, "the loaders' ring needs two slots");
+    static_assert(RL == 2 || RL == 3, "the residual comes in 2 or 3 limbs");
+    constexpr int WCOLS = 16 * MT * CW;  // SNP columns per workgroup
+    constexpr int NT = RL * NG;          // N tiles, limb-major: tile = limb * NG + b / 16
+    constexpr int NCOL = 16 * NT;
+    constexpr int QC = 4;                // 16-subject chunks per stage of 64 subjects
+    constexpr int CHUNKS = NCOL * QC;    // limb chunks per stage
+    constexpr int XCH = WCOLS * QC;      // X chunks per stage
+    constexpr int LT = 64 * LW;
+    constexpr int XPT = (XCH + LT - 1) / LT;
+    constexpr int RPT = (CHUNKS + LT - 1) / LT;
+    constexpr int RS = NCOL + 8;         // LDS row stride of the limb tile (16-byte units)
+    constexpr int XS = 5;                // LDS stride of a column of the X tile (16-byte units)
+    constexpr bool XALL = XCH % LT == 0, RALL = CHUNKS % LT == 0;
+    __shared__ v4i sR[2][QC * RS];
+    __shared__ v4i sX[2][WCOLS * XS];
+
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int64_t n = a.n, p = a.p, ldx = a.ldx;
+    const int64_t nstage = (n + 63) / 64;
+    const int64_t nloop = (nstage + LDF - 1) / LDF * LDF;
+    const int64_t j0 = (int64_t)blockIdx.x * WCOLS;
+
+    if (wid >= CW) {
+        // loaders.  X chunk c: column c / 4 of the workgroup, subjects 16 (c % 4) .. + 15 of the
+        // stage; a column past p, or a chunk that starts at or after n, loads the start of X (the
+        // limb rows of subjects n .. round_up(n, 256) are zero, and columns >= p are never stored)
+        const int lt = threadIdx.x - 64 * CW;
+        const uint8_t* __restrict__ X = static_cast<const uint8_t*>(a.X);
+        uint64_t xbase[XPT];
+        int xrow[XPT], xdst[XPT];
+        bool xok[XPT];
+#pragma unroll
+        for (int k = 0; k < XPT; ++k) {
+            const int c = lt + LT * k;
+            xok[k] = XALL || c < XCH;
+            const int cc = xok[k] ? c : 0;
+            const int64_t col = j0 + cc / QC;
+            xbase[k] = col < p ? (uint64_t)col * (uint64_t)ldx : 0;
+            xrow[k] = 16 * (cc % QC);
+            xdst[k] = (cc / QC) * XS + cc % QC;
+        }
+        const int8_t* rsrc[RPT];
+        int rdst[RPT];
+        bool rok[RPT];
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int c = lt + LT * k;
+            rok[k] = RALL || c < CHUNKS;
+            const int cc = rok[k] ? c : 0;
+            rsrc[k] = a.limbs + 16 * cc;
+            rdst[k] = (cc / NCOL) * RS + cc % NCOL;
+        }
+        v4i xr[LDF][XPT];
+        v4i rr[LDF][RPT];
+        auto fetch = [&](int64_t t, v4i (&xg)[XPT], v4i (&rg)[RPT]) {
+#pragma unroll
+            for (int k = 0; k < XPT; ++k) {
+                const int64_t row = t * 64 + xrow[k];
+                const v4i* src = reinterpret_cast<const v4i*>(X + (row < n ? xbase[k] + (uint64_t)row : 0));
+                if (xok[k]) {
+                    if constexpr (NTX)
+                        xg[k] = __builtin_nontemporal_load(src);
+                    else
+                        xg[k] = *src;
+                }
+            }
+            const int64_t kr = min(t, nstage - 1) * (int64_t)(16 * CHUNKS);
+#pragma unroll
+            for (int k = 0; k < RPT; ++k)
+                if (rok[k]) rg[k] = *reinterpret_cast<const v4i*>(rsrc[k] + kr);
+        };
+        auto store = [&](int buf, const v4i (&xg)[XPT], const v4i (&rg)[RPT]) {
+#pragma unroll
+            for (int k = 0; k < XPT; ++k)
+                if (xok[k]) sX[buf][xdst[k]] = decode_a<XT>(xg[k]);
+#pragma unroll
+            for (int k = 0; k < RPT; ++k)
+                if (rok[k]) sR[buf][rdst[k]] = rg[k];
+        };
+#pragma unroll
+        for (int q = 0; q < LDF; ++q) fetch(q, xr[q], rr[q]);
+        store(0, xr[0], rr[0]);
+        __syncthreads();
+        for (int64_t s0 = 0; s0 < nloop; s0 += LDF) {
+#pragma unroll
+            for (int q = 0; q < LDF; ++q) {
+                const int64_t t = s0 + q;
+                fetch(t + LDF, xr[q], rr[q]);  // slot q held stage t, stored before the last barrier
+                __builtin_amdgcn_sched_barrier(0);  // keep the new loads ahead of the stores below
+                store((int)(t & 1) ^ 1, xr[(q + 1) % LDF], rr[(q + 1) % LDF]);
+                __syncthreads();
+            }
+        }
+        return;
+    }
+
+    // compute wavefronts
+    const int acol = lane & 15;
+    const int64_t jw = j0 + wid * (16 * MT);
+    v4i acc[MT][NT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = v4i{0, 0, 0, 0};
+    __syncthreads();  // the loaders' first stage is in LDS
+    for (int64_t t = 0; t < nloop; ++t) {
+        const int buf = (int)(t & 1);
+        if (t < nstage) {
+            v4i A[MT];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) A[mt] = sX[buf][(wid * MT * 16 + mt * 16 + acol) * XS + (lane >> 4)];
+            const v4i* sb = &sR[buf][(lane >> 4) * RS + acol];
+            v4i bcur = sb[0];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                v4i bnext = bcur;
+                if (nt + 1 < NT) bnext = sb[(nt + 1) * 16];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], bcur, acc[mt][nt], 0, 0, 0);
+                bcur = bnext;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int bq = 0; bq < NG; ++bq)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int b = bq * 16 + acol;
+                const int64_t j = jw + mt * 16 + mfma_c_row(lane, v);
+                if (j < p && b < a.B) {
+                    int64_t tot = (int64_t)acc[mt][bq][v] + 256 * (int64_t)acc[mt][NG + bq][v];
+                    if constexpr (RL == 3) tot += 65536 * (int64_t)acc[mt][2 * NG + bq][v];
+                    a.out[(int64_t)b * p + j] = a.qscale[b] * (double)tot;
+                }
+            }
+}
+
 // Byte transpose of a 4 x 4 block: d[r] holds bytes (x_r0, x_r1, x_r2, x_r3);
 // o[c] receives (x_0c, x_1c, x_2c, x_3c).  __builtin_amdgcn_perm(hi, lo, sel)
 // picks byte sel_k of the 8-byte value hi:lo for result byte k.
@@ -638,7 +793,7 @@ __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_eta_split_
 
     const int xr = wsub * 16 + (lane & 15);  // this lane's dword (4 subjects) within a column
     const int xs = xr ^ ((lane >> 4) << 4);  // its swizzled position (the 16-group of its columns is lane / 16)
-    // the A fragments of 4 M tiles from a G buffer
+    // the A fragments of 4 M tiles from a G buffer (M tile mt is subjects 4 r + mt)
     auto read_a = [&](int buf, v4i (&A)[4]) {
         uint32_t f[4][4];  // f[mt][dword of the fragment]
 #pragma unroll
@@ -989,6 +1144,15 @@ hipError_t launch_split(const MfmaArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int XT, int NG, int RL, int CW, int LW, int MT, int LDF, bool NTX = false>
+hipError_t launch_lds(const MfmaArgs& a, hipStream_t s)
+{
+    constexpr int WCOLS = 16 * MT * CW;
+    hipLaunchKernelGGL((mfma_xtr_lds_kernel<XT, NG, RL, CW, LW, MT, LDF, NTX>),
+                       dim3((unsigned)((a.p + WCOLS - 1) / WCOLS)), dim3(64 * (CW + LW)), 0, s, a);
+    return hipGetLastError();
+}
+
 template <int XT, int NG, int RL>
 hipError_t launch_ng(const MfmaArgs& a, hipStream_t s)
 {
@@ -996,11 +1160,11 @@ hipError_t launch_ng(const MfmaArgs& a, hipStream_t s)
     case 5: return launch_split<XT, NG, RL, 7, 1, 3, 1, 6, 3>(a, s);
     case 6: return launch_split<XT, NG, RL, 7, 1, 3, 1, 4, 4>(a, s);
     case 7: return launch_split<XT, NG, RL, 6, 2, 3, 1, 6, 3>(a, s);
-    case 8: return launch_split<XT, NG, RL, 8, 4, 2, 1, 6, 2>(a, s);
-    case 9: return launch_split<XT, NG, RL, 8, 4, 2, 1, 4, 2>(a, s);
-    case 10: return launch_split<XT, NG, RL, 4, 4, 4, 1, 2, 2>(a, s);
-    case 11: return launch_split<XT, NG, RL, 8, 4, 2, 2, 2, 2>(a, s);
-    case 12: return launch_split<XT, NG, RL, 8, 4, 2, 1, 6, 3>(a, s);
+    case 8: return launch_lds<XT, NG, RL, 4, 4, 4, 3>(a, s);
+    case 9: return launch_lds<XT, NG, RL, 4, 4, 4, 4>(a, s);
+    case 10: return launch_lds<XT, NG, RL, 4, 4, 3, 3>(a, s);
+    case 11: return launch_lds<XT, NG, RL, 4, 4, 4, 3, true>(a, s);
+    case 12: return launch_lds<XT, NG, RL, 8, 4, 2, 3>(a, s);
     case 1: return launch_split<XT, NG, RL, 7, 1, 3, 1, 4>(a, s);
     case 2: return launch_split<XT, NG, RL, 6, 2, 3, 1, 6>(a, s);
     case 3: return launch_split<XT, NG, RL, 6, 2, 3, 1, 4>(a, s);
