@@ -437,7 +437,7 @@ def bench_geno_batched(args):
         "iters_per_s": args.steps / elapsed,
         "phases_ms_per_step": {"xtr_prox": xtr_ms / max(xtr_n, 1), "risk": risk_ms / max(risk_n, 1),
                                "eta_update": eta_ms / max(eta_n, 1),
-                               "covariates": cov_ms / args.steps if args.covariates else 0.0},
+                               "covariates": cov_ms / (args.steps * args.repeats) if args.covariates else 0.0},
         "kernels_ms_per_launch": {"mfma_xtr_split_kernel": xk_ms / max(xk_n, 1), "mfma_eta_kernel": ek_ms / max(ek_n, 1)},
         "repeats": args.repeats,
         "ms_per_step_runs": [1e3 * r / args.steps for r in runs],
