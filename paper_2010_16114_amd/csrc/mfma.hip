@@ -15,10 +15,16 @@
 // Tiling: a workgroup of CW compute wavefronts owns 16 * MT * CW SNP columns
 // (MT M tiles of 16 per wavefront) and all 3 * B limb columns (N tiles of
 // 16), and walks K = n in stages of 64 * KS subjects; LW more wavefronts stage
-// the limb tiles.  X is read once per pass for all B vectors.  A fragments (16
-// subjects of one column per lane, one 16-byte load) stay in registers; the
-// stage's limb tile is staged in LDS.  Several (MT, KS, PF) shapes are
+// the limb tiles.  X is read once per pass for all B vectors.  In
+// mfma_xtr_split_kernel the A fragments (16 subjects of one column per lane,
+// one 16-byte load) go straight to registers; in mfma_xtr_lds_kernel the
+// loader wavefronts stage X through LDS too.  Several shapes of both are
 // compiled; the host times them on the live data and keeps the fastest.
+//
+// The eta update (eta += G[:, U] D over the changed columns U, the same limb
+// arithmetic with D = s * dbeta) contracts over columns, which X does not keep
+// contiguous: mfma_eta_kernel and mfma_eta_split_kernel move 64-column x
+// 256-subject tiles through LDS and transpose them into A fragments.
 #include <type_traits>
 
 #include "device_common.h"
