@@ -29,8 +29,7 @@ struct MfmaArgs {
                             // ahead: 5 = 7+1, 3, 64, 6, 3; 6 = 7+1, 3, 64, 4, 4; 7 = 6+2, 3, 64, 6, 3;
                             // X through LDS as well, loaded by the loader wavefronts (compute +
                             // loader wavefronts, M tiles, stages of loads in flight): 8 = 4+4, 4, 3;
-                            // 9 = 4+4, 4, 4; 10 = 4+4, 3, 3; 11 = 8 with streaming X loads;
-                            // 12 = 8+4, 2, 3
+                            // 9 = 4+4, 4, 4; 10 = 4+4, 4, 5; 11 = 8+4, 2, 4; 12 = 8+4, 2, 3
 };
 constexpr int kMfmaVariants = 13;    // shapes of the X~' R pass
 constexpr int kMfmaEtaVariants = 13;  // shapes of the eta update

@@ -1168,8 +1168,8 @@ hipError_t launch_ng(const MfmaArgs& a, hipStream_t s)
     case 7: return launch_split<XT, NG, RL, 6, 2, 3, 1, 6, 3>(a, s);
     case 8: return launch_lds<XT, NG, RL, 4, 4, 4, 3>(a, s);
     case 9: return launch_lds<XT, NG, RL, 4, 4, 4, 4>(a, s);
-    case 10: return launch_lds<XT, NG, RL, 4, 4, 3, 3>(a, s);
-    case 11: return launch_lds<XT, NG, RL, 4, 4, 4, 3, true>(a, s);
+    case 10: return launch_lds<XT, NG, RL, 4, 4, 4, 5>(a, s);
+    case 11: return launch_lds<XT, NG, RL, 8, 4, 2, 4>(a, s);
     case 12: return launch_lds<XT, NG, RL, 8, 4, 2, 3>(a, s);
     case 1: return launch_split<XT, NG, RL, 7, 1, 3, 1, 4>(a, s);
     case 2: return launch_split<XT, NG, RL, 6, 2, 3, 1, 6>(a, s);
