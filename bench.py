@@ -60,6 +60,21 @@ HBM_PEAK_GBS = 8000.0
 INT8_MFMA_PEAK_TOPS = 5000.0  # dense int8 matrix-core peak of the MI355X
 
 
+def mfma_kernel_names(xtr_variant: int, eta_variant: int) -> tuple[str, str]:
+    """Kernel names behind the matrix-core pipeline shapes the tuner kept:
+    X~' R shapes 0-7 are `mfma_xtr_split_kernel`, 8-12 `mfma_xtr_lds_kernel`;
+    eta shapes 0-1 are `mfma_eta_kernel`, 2-7 `mfma_eta_split_kernel`, and
+    8-12 that kernel on one workgroup per compute unit plus `eta_fixup_kernel`."""
+    xk = "mfma_xtr_split_kernel" if xtr_variant < 8 else "mfma_xtr_lds_kernel"
+    if eta_variant < 2:
+        ek = "mfma_eta_kernel"
+    elif eta_variant < 8:
+        ek = "mfma_eta_split_kernel"
+    else:
+        ek = "mfma_eta_split_kernel+eta_fixup_kernel"
+    return xk, ek
+
+
 def kernel_source_hash(files) -> str:
     """SHA-256 over the sources of a kernel, to tell whether a stored counter
     reading still describes the code that runs."""
@@ -394,6 +409,7 @@ def bench_geno_batched(args):
         f"nnz per lambda {nnz.min()}..{nnz.max()}")
     bpad = (B + 15) // 16 * 16
     tuning = cox.mfma_tuning()
+    xtr_kernel, eta_kernel = mfma_kernel_names(tuning["xtr_variant"], tuning["eta_variant"])
     # Algorithmic bytes of one launch of the matrix-core X~' R kernel: X once,
     # the residual limbs once, the raw column sums written once.
     limbs = 3 if args.residual_bits == 22 else 2
@@ -438,7 +454,7 @@ def bench_geno_batched(args):
         "phases_ms_per_step": {"xtr_prox": xtr_ms / max(xtr_n, 1), "risk": risk_ms / max(risk_n, 1),
                                "eta_update": eta_ms / max(eta_n, 1),
                                "covariates": cov_ms / (args.steps * args.repeats) if args.covariates else 0.0},
-        "kernels_ms_per_launch": {"mfma_xtr_split_kernel": xk_ms / max(xk_n, 1), "mfma_eta_kernel": ek_ms / max(ek_n, 1)},
+        "kernels_ms_per_launch": {xtr_kernel: xk_ms / max(xk_n, 1), eta_kernel: ek_ms / max(ek_n, 1)},
         "repeats": args.repeats,
         "ms_per_step_runs": [1e3 * r / args.steps for r in runs],
         "hbm_probe": probe,
@@ -449,7 +465,7 @@ def bench_geno_batched(args):
                           "changed_columns_per_step": cols_per_step, "achieved": step_gbs, "peak": HBM_PEAK_GBS,
                           "unit": "GB/s", "frac": step_gbs / HBM_PEAK_GBS,
                           "frac_of_copy_probe": step_gbs / probe["copy_gbs"]},
-        "roofline": {"bound": "hbm", "kernel": "mfma_xtr_split_kernel (X~' R for B lambdas)",
+        "roofline": {"bound": "hbm", "kernel": f"{xtr_kernel} (X~' R for B lambdas, shape {tuning['xtr_variant']})",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "frac_of_copy_probe": achieved / probe["copy_gbs"],
                      "frac_of_read_probe": achieved / probe["read_gbs"],
@@ -457,7 +473,7 @@ def bench_geno_batched(args):
                                                f"shape{tuning['xtr_variant']}" + ("" if limbs == 3 else "_limbs2")),
                      "algorithmic_bytes_per_launch": xtr_bytes, "kernel_ms": 1e3 * xtr_avg, "launches_timed": xk_n,
                      "mfma_tops": tops, "mfma_frac_int8": tops / INT8_MFMA_PEAK_TOPS},
-        "eta_kernel_roofline": {"bound": "hbm", "kernel": "mfma_eta_kernel (eta += X[:, U] D for B lambdas)",
+        "eta_kernel_roofline": {"bound": "hbm", "kernel": f"{eta_kernel} (eta += X[:, U] D for B lambdas, shape {tuning['eta_variant']})",
                                 "achieved": eta_bytes / (ek_ms / max(ek_n, 1) / 1e3) / 1e9 if ek_n else None,
                                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                 "frac": eta_bytes / (ek_ms / max(ek_n, 1) / 1e3) / 1e9 / HBM_PEAK_GBS if ek_n else None,
