@@ -31,6 +31,10 @@ Workloads (synthetic, seeded; they stand in for the UK Biobank genotypes):
   autograd-c2: n = 100,000 x p = 10,000 FP32 standardised genotypes with
                times in days (ties): milliseconds per forward + backward of
                the torch.autograd functions.
+  dense-eta-c4: the dense X~ beta behind cox_loss_grad and warm starts, for
+               B = 64 vectors over the default workload's 400,000 x 500,000 FP8
+               genotypes: milliseconds per product on the matrix cores (three
+               exact limb passes) and on the FP64 vector path.
 
 The batched workload times K steps from beta = 0 `--repeats` times (default
 3) and reports the median run; it also measures the HBM bandwidth the same
@@ -732,6 +736,89 @@ def bench_autograd_c2(args):
     }
 
 
+def bench_dense_eta_c4(args):
+    """Dense X~ beta for B = 64 vectors over 400,000 x 500,000 FP8 genotypes, the
+    pass behind cox_loss_grad, warm starts and the dense-eta ablation: three exact
+    limb passes of the matrix-core eta update (one FP64-accurate product), against
+    the FP64 vector passes of 8 vectors each (COXHIP_NO_MFMA=1).  Timed through
+    cox_loss_grad without the gradient: the dense phase, its eta-update launches,
+    and the losses of both forms."""
+    import numpy as np
+    import torch
+
+    import coxsim
+    import paper_2010_16114_amd as P
+
+    n, p, B = args.n or 400000, args.p or 500000, args.batch
+    ldx = (n + 15) // 16 * 16
+    probe = hbm_probe()
+    d = coxsim.config4(n=n, p=p, materialize=False)
+    log("generating FP8 genotype matrix in HBM")
+    G, c1, c2 = coxsim.genotype_device(n, p, d.seed, d.thresholds, fmt=1, ldx=ldx)
+    mu, sc = coxsim.standardisation(c1, c2, n)
+    cox = P.Cox(G, d.time, d.event, xtype=P.X_FP8_E4M3, n=n, center=torch.from_numpy(mu).cuda(),
+                scale=torch.from_numpy(sc).cuda(), max_batch=B)
+    rng = np.random.default_rng(7)
+    beta = np.zeros((B, p), np.float32)
+    for b in range(B):  # 5% nonzero coefficients per vector (the cost does not depend on it)
+        cols = rng.choice(p, p // 20, replace=False)
+        beta[b, cols] = 0.01 * rng.standard_normal(cols.size)
+    beta = torch.from_numpy(beta).cuda()
+    out = {}
+    for mode in ("mfma", "vector"):
+        if mode == "vector":
+            os.environ["COXHIP_NO_MFMA"] = "1"
+        K = args.steps if mode == "mfma" else max(1, args.steps // 5)
+        for _ in range(max(args.warmup, 1) if mode == "mfma" else 1):
+            cox.loss_grad(beta, want_grad=False)
+        cox.timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            loss, _ = cox.loss_grad(beta, want_grad=False)
+        torch.cuda.synchronize()
+        wall = 1e3 * (time.perf_counter() - t0) / K
+        eta_ms, eta_n = cox.timing_read("eta")
+        ek_ms, ek_n = cox.timing_read("eta_kernel")
+        cox.timing(False)
+        os.environ.pop("COXHIP_NO_MFMA", None)
+        out[mode] = {"loss_grad_ms": wall, "dense_ms": eta_ms / max(eta_n, 1), "calls": K,
+                     "eta_kernel_ms": ek_ms / ek_n if ek_n else None, "eta_kernel_launches": ek_n, "loss": loss}
+        log(f"{mode}: {out[mode]['dense_ms']:.2f} ms per dense pass of {B} vectors ({wall:.2f} ms per call)")
+    rel = float(np.max(np.abs(out["mfma"]["loss"] - out["vector"]["loss"]) / np.abs(out["vector"]["loss"])))
+    tuning = cox.mfma_tuning()
+    _, eta_kernel = mfma_kernel_names(0, tuning["eta_variant"])
+    # algorithmic bytes of one dense product: X once, the FP64 coefficients read, eta written
+    alg = n * p + 8 * B * p + 8 * B * n
+    # one of its three eta-update launches: X once, the D limbs, eta read and written
+    launch_bytes = n * p + 3 * ((B + 15) // 16 * 16) * ((p + 63) // 64 * 64) + 16 * B * n
+    kms = out["mfma"]["eta_kernel_ms"]
+    dense = out["mfma"]["dense_ms"]
+    for m in out.values():
+        m.pop("loss")
+    return {
+        "metric": "dense X~ beta for B vectors (cox_loss_grad, warm starts), ms per pass",
+        "value": dense, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dense, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int8", "data": "synthetic",
+        "config": {"workload": f"dense X~ beta, FP8 E4M3 genotype X n={n} p={p}, B={B} vectors 5% nonzero, "
+                               f"three exact 22-bit limb passes on the matrix cores", "n": n, "p": p, "B": B},
+        "modes": out,
+        "speedup_vs_vector": out["vector"]["dense_ms"] / dense,
+        "loss_max_rel_diff_vs_vector": rel,
+        "hbm_probe": probe,
+        "roofline": {"bound": "hbm", "kernel": f"{eta_kernel} (one limb pass, every column selected)",
+                     "achieved": launch_bytes / (kms / 1e3) / 1e9 if kms else None, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": launch_bytes / (kms / 1e3) / 1e9 / HBM_PEAK_GBS if kms else None,
+                     "traffic": stored_traffic(f"mfma_eta_kernel_dense_geno_fp8_{n}x{p}_b{B}_traffic.md",
+                                               MFMA_SOURCES, f"shape{tuning['eta_variant']}"),
+                     "algorithmic_bytes_per_launch": launch_bytes, "kernel_ms": kms},
+        "roofline_pass": {"what": "one dense product (three launches) against a single read of X",
+                          "bytes": alg, "achieved": alg / (dense / 1e3) / 1e9,
+                          "frac": alg / (dense / 1e3) / 1e9 / HBM_PEAK_GBS},
+    }
+
+
 FP64_VALU_PEAK_TFLOPS = 78.6
 
 
@@ -911,9 +998,10 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=0, help="default: 50 (batched), 1000 (nmf) or 500")
-    ap.add_argument("--warmup", type=int, default=-1, help="default: 3 (batched) or 20")
+    ap.add_argument("--warmup", type=int, default=-1, help="default: 3 (batched), 1 (dense-eta-c4) or 20")
     ap.add_argument("--workload", default="geno-fp8-batched",
-                    choices=["geno-fp8-batched", "gauss-fp32", "refit", "nmf", "geno-fp8-c3", "autograd-c2"])
+                    choices=["geno-fp8-batched", "gauss-fp32", "refit", "nmf", "geno-fp8-c3", "autograd-c2",
+                             "dense-eta-c4"])
     ap.add_argument("--nmf-rank", type=int, default=20, help="nmf workload: rank r")
     ap.add_argument("--nmf-algo", type=int, default=0, choices=[0, 1], help="nmf workload: 0 multiplicative, 1 APG")
     ap.add_argument("--refit-cols", type=int, default=333, help="refit workload: SNP columns refitted")
@@ -956,12 +1044,12 @@ def main():
         torch.cuda.empty_cache()
     batched = args.workload == "geno-fp8-batched"
     if args.steps <= 0:
-        args.steps = {"geno-fp8-batched": 50, "nmf": 1000, "autograd-c2": 50}.get(args.workload, 500)
+        args.steps = {"geno-fp8-batched": 50, "nmf": 1000, "autograd-c2": 50, "dense-eta-c4": 10}.get(args.workload, 500)
     if args.warmup < 0:
-        args.warmup = 3 if batched else 20
+        args.warmup = 3 if batched else (1 if args.workload == "dense-eta-c4" else 20)
     res = {"gauss-fp32": bench_gauss_fp32, "geno-fp8-batched": bench_geno_batched,
            "refit": bench_refit, "nmf": bench_nmf, "geno-fp8-c3": bench_geno_fp8_c3,
-           "autograd-c2": bench_autograd_c2}[args.workload](args)
+           "autograd-c2": bench_autograd_c2, "dense-eta-c4": bench_dense_eta_c4}[args.workload](args)
     print(json.dumps(res), flush=True)
 
 

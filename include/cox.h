@@ -120,6 +120,10 @@ cox_status cox_last_error(const cox_ctx *ctx, char *buf, size_t len);
  *   beta  dev [B][ptot] float
  *   loss  host [B] double: -L(beta_b)
  *   grad  dev [B][ptot] float, or NULL for the loss only: -[X~ Z]' r_b
+ * eta = X~ beta_b is formed to FP64 accuracy: by FP64 passes of up to 8 vectors,
+ * or, for B > 8 over one-byte allele counts, by three exact 22-bit integer
+ * passes on the matrix cores (whatever the first pass leaves of each vector is
+ * taken by the next; at most 2^-69 max|beta_b| per coefficient is left over).
  * NUMERIC if a loss is non-finite (e.g. NaN in beta). Synchronises. */
 cox_status cox_loss_grad(cox_ctx *ctx, const float *beta, int32_t B, double *loss, float *grad);
 

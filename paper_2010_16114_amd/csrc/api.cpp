@@ -101,6 +101,7 @@ struct cox_ctx {
     long long* rsump = nullptr;
     int* geno_bad = nullptr;
     int8_t* dlimbs = nullptr;    // [3][Bmax16][dstride] eta-update limbs
+    int32_t *sel_all = nullptr, *nsel_all = nullptr;  // 0 .. p - 1 and p: every column, for dense passes
     long long* eta_part = nullptr;  // [ncu][2][Bmax16][256] partial sums of blocks two eta workgroups share
     int ncu = 0;                 // compute units of the device
     int64_t dstride = 0;
@@ -494,10 +495,20 @@ CovStep cov_prox(cox_ctx* c, double step, const int32_t* active)
     return st;
 }
 
-// eta[b] = X~ coef[b] (no centring) for b < B; coef is b-major [B][p].
+cox_status dense_eta_mfma(cox_ctx* c, const double* coef, int B);
+bool use_mfma(cox_ctx* c, int B);
+
+// eta[b] = X~ coef[b] (no centring) for b < B; coef is b-major [B][p].  More
+// than 8 vectors over one-byte allele counts go through the matrix cores (three
+// passes over X for any B, against one FP64 pass per 8 vectors).
 cox_status dense_eta(cox_ctx* c, const double* coef, int B, const double* shift)
 {
     tmark(c, COX_PHASE_ETA);
+    if (!shift && c->sel_all && use_mfma(c, B)) {
+        const cox_status st = dense_eta_mfma(c, coef, B);
+        tmark(c, COX_PHASE_ETA);
+        return st;
+    }
     for (int b0 = 0; b0 < B; b0 += kGroup) {
         const int nb = std::min(kGroup, B - b0);
         HIPCHK(launch_gemv(c->x, coef, b0, nb, c->part_gemv, c->ncb, c->eta, shift, c->stream), "dense X beta");
@@ -645,6 +656,68 @@ int autotune(cox_ctx* c, int count, F&& launch, float* ms_out)
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return best;
+}
+
+// Arguments of the matrix-core eta update over the columns sel[0 .. *nsel) for
+// vectors 0 .. B - 1, D limbs and scales from launch_quantize_d.
+MfmaEtaArgs mfma_eta_args(cox_ctx* c, const int32_t* sel, const int32_t* nsel, int B, const int32_t* active)
+{
+    MfmaEtaArgs m{c->x.X, c->x.xt, c->n, c->p, c->x.ldx, sel, nsel, c->dlimbs, c->dstride,
+                  (int)round_up(B, 16), B, c->dscale, c->eta, active, 0, c->eta_part, c->ncu};
+    if (const char* e = std::getenv("COXHIP_ETA_SHARES")) {
+        const int v = std::atoi(e);
+        if (v > 0 && v <= c->ncu) m.sk_grid = v;
+    }
+    return m;
+}
+
+// The eta update's pipeline shape: forced, cached, or timed once per context on
+// these arguments (writing into scratch, since the update is in place).
+cox_status pick_eta_variant(cox_ctx* c, MfmaEtaArgs* m)
+{
+    const int forced = forced_variant("COXHIP_ETA_VARIANT", kMfmaEtaVariants);
+    if (forced >= 0) {
+        c->eta_variant = forced;
+    } else if (c->eta_variant < 0) {
+        const std::string key = tune_key(c, "eta", m->bpad);
+        c->eta_variant = tune_cache_lookup(key, kMfmaEtaVariants);
+        if (c->eta_variant < 0) {
+            MfmaEtaArgs t = *m;
+            t.eta = c->w;
+            c->eta_variant = autotune(
+                c, kMfmaEtaVariants, [&](int v) { t.variant = v; return launch_mfma_eta(t, c->stream); },
+                c->eta_tune_ms);
+            if (c->eta_variant < 0) return fail(c, COX_ERR_DEVICE, "no pipeline shape of the eta update launched");
+            tune_cache_store(key, c->eta_variant, c->eta_tune_ms, kMfmaEtaVariants);
+        }
+    }
+    m->variant = c->eta_variant;
+    return COX_OK;
+}
+
+// eta[b] = X coef[b] for b < B on the matrix cores (one-byte allele counts,
+// B > 8), to FP64 accuracy in three passes over X.  Each pass quantises what is
+// left of coef_b to integers of at most 22 bits on a per-vector scale q_b (the
+// eta update's D limbs, every column selected), adds q_b X R_b to eta with
+// exact integer sums, and leaves coef_b - q_b R_b, computed exactly, for the
+// next pass.  What remains after three passes is at most 2^-69 max|coef_b|.
+cox_status dense_eta_mfma(cox_ctx* c, const double* coef, int B)
+{
+    const int bpad = (int)round_up(B, 16);
+    HIPCHK(launch_fill_f64(c->eta, 0.0, (int64_t)B * c->n, c->stream), "clear eta");
+    MfmaEtaArgs m = mfma_eta_args(c, c->sel_all, c->nsel_all, B, nullptr);
+    for (int k = 0; k < 3; ++k) {
+        const double* src = k == 0 ? coef : c->dcoef;
+        HIPCHK(launch_quantize_d(src, c->p, c->sel_all, c->nsel_all, B, c->dmaxp, c->dlimbs, c->dstride, bpad,
+                                 c->dscale, c->stream),
+               "quantise coefficients");
+        if (k == 0) STCHK(pick_eta_variant(c, &m));
+        tmark(c, COX_PHASE_ETA_KERNEL);
+        HIPCHK(launch_mfma_eta(m, c->stream), "dense X beta on matrix cores");
+        tmark(c, COX_PHASE_ETA_KERNEL);
+        if (k < 2) HIPCHK(launch_coef_remainder(src, c->dcoef, c->p, B, c->dscale, c->stream), "coefficient remainder");
+    }
+    return COX_OK;
 }
 
 // The matrix-core pass serves batches of more than kGroup vectors when X holds
@@ -1026,7 +1099,8 @@ cox_status cox_setup(cox_ctx** out, const cox_matrix* X, const double* time, con
         ok = dalloc(c, &c->limbs, (size_t)3 * c->bpad_max * c->rstride) && dalloc(c, &c->qscale, max_batch) &&
              dalloc(c, &c->rmaxp, (size_t)max_batch * nt) && dalloc(c, &c->rsump, (size_t)max_batch * nt) &&
              dalloc(c, &c->geno_bad, 1) && dalloc(c, &c->dlimbs, (size_t)3 * c->bpad_max * c->dstride) &&
-             dalloc(c, &c->dscale, max_batch) && dalloc(c, &c->dmaxp, (size_t)max_batch * ((c->dstride + 4095) / 4096));
+             dalloc(c, &c->dscale, max_batch) && dalloc(c, &c->dmaxp, (size_t)max_batch * ((c->dstride + 4095) / 4096)) &&
+             dalloc(c, &c->sel_all, p) && dalloc(c, &c->nsel_all, 1);
         if (ok && hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) {
             (void)hipGetLastError();
             c->ncu = 0;
@@ -1068,6 +1142,10 @@ cox_status cox_setup(cox_ctx** out, const cox_matrix* X, const double* time, con
     if (c->limbs)
         chk(launch_fill_f64(reinterpret_cast<double*>(c->limbs), 0.0, (int64_t)3 * c->bpad_max * c->rstride / 8,
                             c->stream));
+    if (c->sel_all) {
+        chk(launch_iota_i32(c->sel_all, p, c->stream));
+        chk(launch_fill_i32(c->nsel_all, (int32_t)p, 1, c->stream));
+    }
     if (st == COX_OK && hipStreamSynchronize(c->stream) != hipSuccess) st = COX_ERR_DEVICE;
     if (st != COX_OK) {
         (void)hipGetLastError();
@@ -1401,30 +1479,8 @@ cox_status cox_fit_path(cox_ctx* c, const double* lambdas, int32_t B, const cox_
                 HIPCHK(launch_quantize_d(c->dcoef, c->p, c->sel, c->nsel, B, c->dmaxp, c->dlimbs, c->dstride, bpad,
                                          c->dscale, c->stream),
                        "quantise eta update");
-                MfmaEtaArgs m{c->x.X, c->x.xt, c->n, c->p, c->x.ldx, c->sel, c->nsel, c->dlimbs, c->dstride,
-                              bpad, B, c->dscale, c->eta, c->active, 0, c->eta_part, c->ncu};
-                if (const char* e = std::getenv("COXHIP_ETA_SHARES")) {
-                    const int v = std::atoi(e);
-                    if (v > 0 && v <= c->ncu) m.sk_grid = v;
-                }
-                const int forced = forced_variant("COXHIP_ETA_VARIANT", kMfmaEtaVariants);
-                if (forced >= 0) {
-                    c->eta_variant = forced;
-                } else if (c->eta_variant < 0) {
-                    const std::string key = tune_key(c, "eta", bpad);
-                    c->eta_variant = tune_cache_lookup(key, kMfmaEtaVariants);
-                    if (c->eta_variant < 0) {
-                        MfmaEtaArgs t = m;
-                        t.eta = c->w;  // scratch: the update is in place, so tuning writes elsewhere
-                        c->eta_variant = autotune(
-                            c, kMfmaEtaVariants, [&](int v) { t.variant = v; return launch_mfma_eta(t, c->stream); },
-                            c->eta_tune_ms);
-                        if (c->eta_variant < 0)
-                            return fail(c, COX_ERR_DEVICE, "no pipeline shape of the eta update launched");
-                        tune_cache_store(key, c->eta_variant, c->eta_tune_ms, kMfmaEtaVariants);
-                    }
-                }
-                m.variant = c->eta_variant;
+                MfmaEtaArgs m = mfma_eta_args(c, c->sel, c->nsel, B, c->active);
+                STCHK(pick_eta_variant(c, &m));
                 tmark(c, COX_PHASE_ETA_KERNEL);
                 HIPCHK(launch_mfma_eta(m, c->stream), "eta update on matrix cores");
                 tmark(c, COX_PHASE_ETA_KERNEL);

@@ -209,6 +209,12 @@ hipError_t launch_resume(int32_t* status, int32_t* active, int32_t* kit, const i
 // acc[0] += v[0]
 hipError_t launch_count_add(const int32_t* v, long long* acc, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t m, hipStream_t s);
+// p[i] = i for i < m
+hipError_t launch_iota_i32(int32_t* p, int64_t m, hipStream_t s);
+// dst[b*p + j] = src[b*p + j] - dscale[b] * llrint(src[b*p + j] / dscale[b]) for b < B, j < p
+// (src == dst allowed): what the eta update's D quantisation leaves of each entry
+hipError_t launch_coef_remainder(const double* src, double* dst, int64_t p, int B, const double* dscale,
+                                 hipStream_t s);
 
 // ---- the dense covariate block Z beside X (covar.hip)
 struct CovArgs {

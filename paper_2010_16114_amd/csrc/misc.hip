@@ -170,6 +170,23 @@ __global__ void fill_i32_kernel(int32_t* __restrict__ p, int32_t v, int64_t m)
     for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < m; i += (int64_t)gridDim.x * kT) p[i] = v;
 }
 
+__global__ void iota_i32_kernel(int32_t* __restrict__ p, int64_t m)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < m; i += (int64_t)gridDim.x * kT) p[i] = (int32_t)i;
+}
+
+// dst[b][j] = src[b][j] - q_b R, R = llrint(src[b][j] / q_b): the integer the
+// eta update's quantiser takes for that entry at the same scale q_b.  One fma,
+// so the remainder carries at most one rounding of 2^-53 q_b.
+__global__ void coef_remainder_kernel(const double* __restrict__ src, double* __restrict__ dst, int64_t p,
+                                      int64_t m, const double* __restrict__ dscale)
+{
+    for (int64_t k = (int64_t)blockIdx.x * kT + threadIdx.x; k < m; k += (int64_t)gridDim.x * kT) {
+        const double q = dscale[k / p], v = src[k];
+        dst[k] = fma(-q, (double)llrint(v / q), v);
+    }
+}
+
 }  // namespace
 
 #define COX_LAUNCH(kernel, grid, ...)                                        \
@@ -247,6 +264,16 @@ hipError_t launch_fill_f64(double* p, double v, int64_t m, hipStream_t s)
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t m, hipStream_t s)
 {
     COX_LAUNCH(fill_i32_kernel, grid_for(m), p, v, m);
+}
+hipError_t launch_iota_i32(int32_t* p, int64_t m, hipStream_t s)
+{
+    COX_LAUNCH(iota_i32_kernel, grid_for(m), p, m);
+}
+hipError_t launch_coef_remainder(const double* src, double* dst, int64_t p, int B, const double* dscale,
+                                 hipStream_t s)
+{
+    if (p < 1 || B < 1) return hipErrorInvalidValue;
+    COX_LAUNCH(coef_remainder_kernel, grid_for((int64_t)B * p), src, dst, p, (int64_t)B * p, dscale);
 }
 
 }  // namespace cox

@@ -77,6 +77,33 @@ def test_batched_loss_grad(prob):
         assert np.abs(grad[b] + g).max() <= 1e-6 * np.abs(g).max(), b
 
 
+@pytest.mark.parametrize("storage", ["int8", "fp8"])
+@pytest.mark.parametrize("B", [9, 49, 64])
+def test_dense_eta_on_matrix_cores(prob, storage, B, monkeypatch):
+    """Dense X~ beta for more than 8 vectors over allele counts runs as three
+    exact limb passes of the matrix-core eta update.  Its losses match the FP64
+    vector passes (COXHIP_NO_MFMA=1) and the oracle to FP64 rounding, for an
+    all-zero vector, one whose coefficients span 12 decades, and one with a
+    single nonzero."""
+    cox, M = _setup(prob, storage, B)
+    rng = np.random.default_rng(500 + B)
+    beta = (0.05 * rng.standard_normal((B, prob.p)) * (rng.random((B, prob.p)) < 0.3)).astype(np.float32)
+    beta[0] = 0.0
+    beta[1] = (rng.choice([-1.0, 1.0], prob.p) * 10.0 ** rng.uniform(-13, -1, prob.p)).astype(np.float32)
+    beta[2] = 0.0
+    beta[2, prob.p - 1] = 0.3
+    bt = torch.from_numpy(beta).cuda()
+    loss_m, _ = cox.loss_grad(bt, want_grad=False)
+    monkeypatch.setenv("COXHIP_NO_MFMA", "1")
+    loss_v, _ = cox.loss_grad(bt, want_grad=False)
+    monkeypatch.delenv("COXHIP_NO_MFMA")
+    rel = np.abs(loss_m - loss_v) / np.abs(loss_v)
+    assert rel.max() <= 1e-13, (rel.argmax(), rel.max())
+    for b in sorted({0, 1, 2, B // 2, B - 1}):
+        negL, _ = oracle.loss_grad(M, prob.time, prob.event, beta[b].astype(np.float64))
+        assert loss_m[b] == pytest.approx(negL, rel=1e-12), b
+
+
 def test_batched_equals_single(prob):
     """The 64-wide matrix-core pass and 64 separate vector passes agree."""
     B = 64
