@@ -102,6 +102,7 @@ struct cox_ctx {
     int* geno_bad = nullptr;
     int8_t* dlimbs = nullptr;    // [3][Bmax16][dstride] eta-update limbs
     int32_t *sel_all = nullptr, *nsel_all = nullptr;  // 0 .. p - 1 and p: every column, for dense passes
+    int32_t* nonfin = nullptr;   // [max_batch] a dense pass's coefficient vector holds a NaN or infinity
     long long* eta_part = nullptr;  // [ncu][2][Bmax16][256] partial sums of blocks two eta workgroups share
     int ncu = 0;                 // compute units of the device
     int64_t dstride = 0;
@@ -699,11 +700,15 @@ cox_status pick_eta_variant(cox_ctx* c, MfmaEtaArgs* m)
 // B > 8), to FP64 accuracy in three passes over X.  Each pass quantises what is
 // left of coef_b to integers of at most 22 bits on a per-vector scale q_b (the
 // eta update's D limbs, every column selected), adds q_b X R_b to eta with
-// exact integer sums, and leaves coef_b - q_b R_b, computed exactly, for the
-// next pass.  What remains after three passes is at most 2^-69 max|coef_b|.
+// exact integer sums, and leaves coef_b - q_b R_b (one fma) for the next pass.
+// What remains after three passes is at most 2^-69 max|coef_b|.  Integer limbs
+// cannot carry a NaN or an infinity, so a vector holding one gets eta = NaN,
+// as the FP64 passes would give it.
 cox_status dense_eta_mfma(cox_ctx* c, const double* coef, int B)
 {
     const int bpad = (int)round_up(B, 16);
+    HIPCHK(launch_fill_i32(c->nonfin, 0, B, c->stream), "clear flags");
+    HIPCHK(launch_nonfinite(coef, c->p, B, c->nonfin, c->stream), "coefficient check");
     HIPCHK(launch_fill_f64(c->eta, 0.0, (int64_t)B * c->n, c->stream), "clear eta");
     MfmaEtaArgs m = mfma_eta_args(c, c->sel_all, c->nsel_all, B, nullptr);
     for (int k = 0; k < 3; ++k) {
@@ -717,6 +722,7 @@ cox_status dense_eta_mfma(cox_ctx* c, const double* coef, int B)
         tmark(c, COX_PHASE_ETA_KERNEL);
         if (k < 2) HIPCHK(launch_coef_remainder(src, c->dcoef, c->p, B, c->dscale, c->stream), "coefficient remainder");
     }
+    HIPCHK(launch_poison_eta(c->eta, c->n, B, c->nonfin, c->stream), "non-finite coefficients");
     return COX_OK;
 }
 
@@ -1100,7 +1106,7 @@ cox_status cox_setup(cox_ctx** out, const cox_matrix* X, const double* time, con
              dalloc(c, &c->rmaxp, (size_t)max_batch * nt) && dalloc(c, &c->rsump, (size_t)max_batch * nt) &&
              dalloc(c, &c->geno_bad, 1) && dalloc(c, &c->dlimbs, (size_t)3 * c->bpad_max * c->dstride) &&
              dalloc(c, &c->dscale, max_batch) && dalloc(c, &c->dmaxp, (size_t)max_batch * ((c->dstride + 4095) / 4096)) &&
-             dalloc(c, &c->sel_all, p) && dalloc(c, &c->nsel_all, 1);
+             dalloc(c, &c->sel_all, p) && dalloc(c, &c->nsel_all, 1) && dalloc(c, &c->nonfin, max_batch);
         if (ok && hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) {
             (void)hipGetLastError();
             c->ncu = 0;

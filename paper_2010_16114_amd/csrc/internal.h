@@ -211,6 +211,10 @@ hipError_t launch_count_add(const int32_t* v, long long* acc, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t m, hipStream_t s);
 // p[i] = i for i < m
 hipError_t launch_iota_i32(int32_t* p, int64_t m, hipStream_t s);
+// flag[b] = 1 if coef[b*p + j] is not finite for some j < p (b < B; flags cleared beforehand)
+hipError_t launch_nonfinite(const double* coef, int64_t p, int B, int32_t* flag, hipStream_t s);
+// eta[b*n + i] = NaN for i < n, for each b < B with flag[b] set
+hipError_t launch_poison_eta(double* eta, int64_t n, int B, const int32_t* flag, hipStream_t s);
 // dst[b*p + j] = src[b*p + j] - dscale[b] * llrint(src[b*p + j] / dscale[b]) for b < B, j < p
 // (src == dst allowed): what the eta update's D quantisation leaves of each entry
 hipError_t launch_coef_remainder(const double* src, double* dst, int64_t p, int B, const double* dscale,

@@ -175,6 +175,26 @@ __global__ void iota_i32_kernel(int32_t* __restrict__ p, int64_t m)
     for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < m; i += (int64_t)gridDim.x * kT) p[i] = (int32_t)i;
 }
 
+// flag[b] = 1 when some coef[b][j], j < p, is not finite (the flags cleared by
+// the caller); one workgroup row per b (blockIdx.y), every writer stores 1
+__global__ void nonfinite_kernel(const double* __restrict__ coef, int64_t p, int32_t* __restrict__ flag)
+{
+    const int b = blockIdx.y;
+    bool bad = false;
+    for (int64_t j = (int64_t)blockIdx.x * kT + threadIdx.x; j < p; j += (int64_t)gridDim.x * kT)
+        bad |= !isfinite(coef[(int64_t)b * p + j]);
+    if (bad) flag[b] = 1;
+}
+
+// eta[b][i] = NaN for every i < n of each b whose flag is set
+__global__ void poison_eta_kernel(double* __restrict__ eta, int64_t n, const int32_t* __restrict__ flag)
+{
+    const int b = blockIdx.y;
+    if (!flag[b]) return;
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
+        eta[(int64_t)b * n + i] = __builtin_nan("");
+}
+
 // dst[b][j] = src[b][j] - q_b R, R = llrint(src[b][j] / q_b): the integer the
 // eta update's quantiser takes for that entry at the same scale q_b.  One fma,
 // so the remainder carries at most one rounding of 2^-53 q_b.
@@ -268,6 +288,20 @@ hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t m, hipStream_t s)
 hipError_t launch_iota_i32(int32_t* p, int64_t m, hipStream_t s)
 {
     COX_LAUNCH(iota_i32_kernel, grid_for(m), p, m);
+}
+hipError_t launch_nonfinite(const double* coef, int64_t p, int B, int32_t* flag, hipStream_t s)
+{
+    if (p < 1 || B < 1) return hipErrorInvalidValue;
+    const unsigned gx = (unsigned)min((int64_t)256, (p + kT - 1) / kT);
+    hipLaunchKernelGGL(nonfinite_kernel, dim3(gx, (unsigned)B), dim3(kT), 0, s, coef, p, flag);
+    return hipGetLastError();
+}
+hipError_t launch_poison_eta(double* eta, int64_t n, int B, const int32_t* flag, hipStream_t s)
+{
+    if (n < 1 || B < 1) return hipErrorInvalidValue;
+    const unsigned gx = (unsigned)min((int64_t)256, (n + kT - 1) / kT);
+    hipLaunchKernelGGL(poison_eta_kernel, dim3(gx, (unsigned)B), dim3(kT), 0, s, eta, n, flag);
+    return hipGetLastError();
 }
 hipError_t launch_coef_remainder(const double* src, double* dst, int64_t p, int B, const double* dscale,
                                  hipStream_t s)

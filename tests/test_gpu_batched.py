@@ -104,6 +104,26 @@ def test_dense_eta_on_matrix_cores(prob, storage, B, monkeypatch):
         assert loss_m[b] == pytest.approx(negL, rel=1e-12), b
 
 
+@pytest.mark.parametrize("bad", [float("nan"), float("inf"), -float("inf")])
+def test_dense_eta_on_matrix_cores_non_finite(prob, bad):
+    """A NaN or infinity in one coefficient vector is a NUMERIC error on the
+    matrix-core dense pass too (integer limbs cannot carry it), and the context
+    gives the right losses on the next call."""
+    B = 16
+    cox, M = _setup(prob, "fp8", B)
+    rng = np.random.default_rng(77)
+    beta = (0.05 * rng.standard_normal((B, prob.p)) * (rng.random((B, prob.p)) < 0.3)).astype(np.float32)
+    worse = beta.copy()
+    worse[5, 123] = bad
+    with pytest.raises(P.CoxError) as e:
+        cox.loss_grad(torch.from_numpy(worse).cuda(), want_grad=False)
+    assert e.value.status == P.ERR_NUMERIC
+    loss, _ = cox.loss_grad(torch.from_numpy(beta).cuda(), want_grad=False)
+    for b in (0, 5, B - 1):
+        negL, _ = oracle.loss_grad(M, prob.time, prob.event, beta[b].astype(np.float64))
+        assert loss[b] == pytest.approx(negL, rel=1e-12), b
+
+
 def test_batched_equals_single(prob):
     """The 64-wide matrix-core pass and 64 separate vector passes agree."""
     B = 64
