@@ -124,6 +124,24 @@ def test_dense_eta_on_matrix_cores_non_finite(prob, bad):
         assert loss[b] == pytest.approx(negL, rel=1e-12), b
 
 
+@pytest.mark.parametrize("mfma", [True, False])
+def test_warm_start_non_finite_is_numeric(prob, mfma, monkeypatch):
+    """A warm start holding a NaN in one vector ends the fit with NUMERIC on the
+    matrix-core path as on the FP64 vector path (the start's eta is formed by the
+    dense pass of each)."""
+    B = 16
+    cox, M = _setup(prob, "int8", B)
+    if not mfma:
+        monkeypatch.setenv("COXHIP_NO_MFMA", "1")
+    lams = coxsim.lambda_grid(oracle.lambda_max(M, prob.time, prob.event), B, 0.1)
+    sigma = 1.0 / (2.0 * oracle.opnorm2(M)[0])
+    beta0 = torch.zeros((B, prob.p), device="cuda")
+    beta0[3, 17] = float("nan")
+    with pytest.raises(P.CoxError) as e:
+        cox.fit_path(lams, max_iter=5, tol=0.0, step=sigma, beta=beta0)
+    assert e.value.status == P.ERR_NUMERIC
+
+
 def test_batched_equals_single(prob):
     """The 64-wide matrix-core pass and 64 separate vector passes agree."""
     B = 64
