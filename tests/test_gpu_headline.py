@@ -14,7 +14,9 @@ every oracle iterate (gpu_helpers.restricted_iterates).  What is checked:
   from the eta the matrix-core update accumulated over 25 steps -- against
   the oracle's f at the same step (1e-6); the oracle's f and gradient at the
   GPU's own iterate; and, for all 64 lambdas, the accumulated objective
-  against a fresh dense eta at the returned iterate.
+  against a fresh dense eta at the returned iterate, whose losses (three
+  exact limb passes on the matrix cores) match the FP64 vector passes'
+  (1e-13).
 * 400,000 x 2,000, B = 64, 200 steps: iterates and objectives of three
   lambdas against the oracle's; the active-set eta update against a dense
   eta every step over the whole path.
@@ -56,7 +58,7 @@ def _device(d, max_batch):
     return G, cox, mu, s
 
 
-def test_batched_400k_x_500k_iterates_against_oracle(release):
+def test_batched_400k_x_500k_iterates_against_oracle(release, monkeypatch):
     d = coxsim.config4()
     _say("generating 400,000 x 500,000 FP8 genotypes")
     G, cox, mu, s = _device(d, 64)
@@ -78,6 +80,13 @@ def test_batched_400k_x_500k_iterates_against_oracle(release):
     drift = np.abs(obj - f_dense) / np.abs(f_dense)
     _say(f"accumulated vs dense-eta objective over 64 lambdas: max rel. diff {drift.max():.2e}")
     assert drift.max() <= 1e-6
+    # that dense eta ran as three exact limb passes on the matrix cores; the FP64 vector passes agree
+    monkeypatch.setenv("COXHIP_NO_MFMA", "1")
+    loss_v, _ = cox.loss_grad(beta, want_grad=False)
+    monkeypatch.delenv("COXHIP_NO_MFMA")
+    dense_rel = np.abs(loss - loss_v) / np.abs(loss_v)
+    _say(f"dense eta, matrix-core limb passes vs FP64 vector passes: max rel. loss diff {dense_rel.max():.2e}")
+    assert dense_rel.max() <= 1e-13
 
     # lambda_0 = lambda_max puts the leading column exactly at its threshold (a tie decided by rounding);
     # the lambdas below it have well-separated supports
