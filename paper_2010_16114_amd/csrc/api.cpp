@@ -116,6 +116,7 @@ struct cox_ctx {
     int64_t split_rows = 0;
     double *bmax = nullptr, *mshift = nullptr, *stot = nullptr, *qtot = nullptr, *Lpart = nullptr, *rpart = nullptr;
     double *beta64 = nullptr, *coef = nullptr, *dcoef = nullptr, *g64 = nullptr;
+    double* red_part = nullptr;  // [kRedParts] scratch of the two-level reductions (power iteration)
     int32_t *chg_flag = nullptr, *chg_cnt = nullptr, *chg_idx = nullptr, *sel = nullptr, *nsel = nullptr;
     double *l1old = nullptr, *l1new = nullptr;
     double *L = nullptr, *sumr = nullptr, *lam = nullptr, *fobj = nullptr, *hist = nullptr, *scal = nullptr;
@@ -900,7 +901,7 @@ cox_status opnorm2_cov(cox_ctx* c, double* s2)
     for (int it = 0; it < 1000; ++it) {
         HIPCHK(launch_fill_f64(c->eta, 0.0, c->n, c->stream), "zero");
         HIPCHK(launch_cov_eta(ca, c->betaZ, 1, c->eta, nullptr, c->stream), "Z v");
-        HIPCHK(launch_dot(c->eta, c->eta, c->n, c->scal + 1, c->stream), "norm of Z v");
+        HIPCHK(launch_dot(c->eta, c->eta, c->n, c->red_part, c->scal + 1, c->stream), "norm of Z v");
         HIPCHK(launch_cov_xtr(ca, nullptr, 0, c->eta, 1, nullptr, c->stream), "Z' u");
         HIPCHK(launch_cov_epilogue(ca, raw, 1, c->stream), "Z' u");
         HIPCHK(launch_fill_f64(c->scal + 2, 0.0, 1, c->stream), "zero");
@@ -1096,7 +1097,8 @@ cox_status cox_setup(cox_ctx** out, const cox_matrix* X, const double* time, con
               dalloc(c, &c->betaZ, (size_t)max_batch * kMaxCov) && dalloc(c, &c->dZ, (size_t)max_batch * kMaxCov) &&
               dalloc(c, &c->gZ, (size_t)max_batch * kMaxCov) && dalloc(c, &c->l1c_old, max_batch) &&
               dalloc(c, &c->l1c_new, max_batch) && dalloc(c, &c->pf, p + kMaxCov) &&
-              dalloc(c, &c->bar_words, persist_barrier_words()) && dalloc(c, &c->col_count, 1);
+              dalloc(c, &c->bar_words, persist_barrier_words()) && dalloc(c, &c->col_count, 1) &&
+              dalloc(c, &c->red_part, kRedParts);
     const bool mfma_able = X->xtype != COX_X_F32 && c->x.vec16 && max_batch > kGroup;
     if (ok && mfma_able) {
         c->bpad_max = (int)round_up(max_batch, 16);
@@ -1328,15 +1330,17 @@ cox_status cox_opnorm2(cox_ctx* c, double tol, int32_t maxiter, uint64_t seed, d
     double est = 0.0, prev = 0.0;
     int it = 0;
     while (it < maxiter) {
-        if (centred) HIPCHK(launch_center_shift(c->x.center, scale, c->beta64, c->p, c->scal + 0, c->stream), "shift");
+        if (centred)
+            HIPCHK(launch_center_shift(c->x.center, scale, c->beta64, c->p, c->red_part, c->scal + 0, c->stream),
+                   "shift");
         STCHK(dense_eta(c, c->coef, 1, centred ? c->scal + 0 : nullptr));
         STCHK(cov_eta(c, c->betaZ, 1, nullptr));
-        HIPCHK(launch_dot(c->eta, c->eta, c->n, c->scal + 1, c->stream), "norm of X v");
-        HIPCHK(launch_to_r32(c->eta, nullptr, c->r32, c->sumr, c->n, c->stream), "u to FP32");
+        HIPCHK(launch_dot(c->eta, c->eta, c->n, c->red_part, c->scal + 1, c->stream), "norm of X v");
+        HIPCHK(launch_to_r32(c->eta, nullptr, c->r32, c->sumr, c->n, c->red_part, c->stream), "u to FP32");
         GemvtArgs g = gemvt_args(c, GT_RAW);
         g.out64 = c->g64;
         STCHK(run_gemvt(c, g, 1));
-        HIPCHK(launch_dot(c->g64, c->g64, c->p, c->scal + 2, c->stream), "norm of X' u");
+        HIPCHK(launch_dot(c->g64, c->g64, c->p, c->red_part, c->scal + 2, c->stream), "norm of X' u");
         if (q) {
             RiskArgs ru{};
             ru.r32 = c->r32;

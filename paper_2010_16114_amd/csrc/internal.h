@@ -189,16 +189,20 @@ hipError_t launch_prox_apply(float* beta, const float* grad, const double* lam, 
                              int64_t p, int B, hipStream_t s);
 hipError_t launch_nll_backward(const double* r64, const double* gl, int64_t n, int B, void* out, int out_f64,
                                hipStream_t s);
-// out[0] = sum_i a_i * (b ? b_i : 1) over m entries, one workgroup, fixed order
-hipError_t launch_dot(const double* a, const double* b, int64_t m, double* out, hipStream_t s);
+// Two-level reductions: part holds kRedParts doubles of scratch (contiguous
+// chunks summed by separate workgroups, then added in order by one), so the
+// result depends only on the length.
+constexpr int kRedParts = 256;
+// out[0] = sum_i a_i * (b ? b_i : 1) over m entries
+hipError_t launch_dot(const double* a, const double* b, int64_t m, double* part, double* out, hipStream_t s);
 // out[0] = -sum_j center_j * scale_j * v_j  (centring shift of X~ v)
-hipError_t launch_center_shift(const float* center, const float* scale, const double* v, int64_t p, double* out,
-                               hipStream_t s);
+hipError_t launch_center_shift(const float* center, const float* scale, const double* v, int64_t p, double* part,
+                               double* out, hipStream_t s);
 // out[j] = in[j] / sqrt(nrm2[0]) * (scale ? scale_j : 1) and vout[j] = in[j] / sqrt(nrm2[0])
 hipError_t launch_normalize(const double* in, const double* nrm2, const float* scale, double* vout, double* coef,
                             int64_t p, hipStream_t s);
-// r32[i] = (float) u[i] + shift[0]; sumr[0] = sum (double) r32[i]
-hipError_t launch_to_r32(const double* u, const double* shift, float* r32, double* sumr, int64_t n,
+// r32[i] = (float) u[i] + shift[0]; sumr[0] = sum (double) r32[i] (part: as for launch_dot)
+hipError_t launch_to_r32(const double* u, const double* shift, float* r32, double* sumr, int64_t n, double* part,
                          hipStream_t s);
 // out[b] = a * sum_i in[b*m + i], one workgroup per b, fixed order
 hipError_t launch_rowsum(const double* in, int64_t m, int B, double a, double* out, hipStream_t s);

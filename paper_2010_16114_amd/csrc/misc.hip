@@ -91,22 +91,45 @@ __device__ double wg_sum(double v)
     return sh[kT / kWave];
 }
 
-__global__ void dot_kernel(const double* __restrict__ a, const double* __restrict__ b, int64_t m,
-                           double* __restrict__ out)
+// Reductions over a long vector in two fixed-order levels: the gridDim.x
+// workgroups each sum one contiguous chunk into part[blockIdx.x], then one
+// workgroup adds the parts in order (part_sum_kernel).  The chunks depend only
+// on the length, so the result is the same on every run.
+__device__ __forceinline__ void chunk_of(int64_t m, int64_t& i0, int64_t& i1)
 {
+    const int64_t chunk = (m + gridDim.x - 1) / gridDim.x;
+    i0 = (int64_t)blockIdx.x * chunk;
+    i1 = min(m, i0 + chunk);
+}
+
+__global__ void dot_kernel(const double* __restrict__ a, const double* __restrict__ b, int64_t m,
+                           double* __restrict__ part)
+{
+    int64_t i0, i1;
+    chunk_of(m, i0, i1);
     double s = 0.0;
-    for (int64_t i = threadIdx.x; i < m; i += kT) s += a[i] * (b ? b[i] : 1.0);
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kT) s += a[i] * (b ? b[i] : 1.0);
     s = wg_sum(s);
-    if (threadIdx.x == 0) out[0] = s;
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// out[0] = scale * (part[0] + ... + part[nparts - 1]), nparts <= kT
+__global__ void part_sum_kernel(const double* __restrict__ part, int nparts, double scale, double* __restrict__ out)
+{
+    double s = threadIdx.x < nparts ? part[threadIdx.x] : 0.0;
+    s = wg_sum(s);
+    if (threadIdx.x == 0) out[0] = scale * s;
 }
 
 __global__ void center_shift_kernel(const float* __restrict__ center, const float* __restrict__ scale,
-                                    const double* __restrict__ v, int64_t p, double* __restrict__ out)
+                                    const double* __restrict__ v, int64_t p, double* __restrict__ part)
 {
+    int64_t j0, j1;
+    chunk_of(p, j0, j1);
     double s = 0.0;
-    for (int64_t j = threadIdx.x; j < p; j += kT) s += (double)center[j] * (scale ? (double)scale[j] : 1.0) * v[j];
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += kT) s += (double)center[j] * (scale ? (double)scale[j] : 1.0) * v[j];
     s = wg_sum(s);
-    if (threadIdx.x == 0) out[0] = -s;
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
 __global__ void normalize_kernel(const double* __restrict__ in, const double* __restrict__ nrm2,
@@ -122,17 +145,19 @@ __global__ void normalize_kernel(const double* __restrict__ in, const double* __
 }
 
 __global__ void to_r32_kernel(const double* __restrict__ u, const double* __restrict__ shift,
-                              float* __restrict__ r32, double* __restrict__ sumr, int64_t n)
+                              float* __restrict__ r32, int64_t n, double* __restrict__ part)
 {
+    int64_t i0, i1;
+    chunk_of(n, i0, i1);
     const double sh = shift ? shift[0] : 0.0;
     double s = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += kT) {
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kT) {
         const float f = (float)(u[i] + sh);
         r32[i] = f;
         s += (double)f;
     }
     s = wg_sum(s);
-    if (threadIdx.x == 0) sumr[0] = s;
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
 // The lambdas that stopped at max_iter (status 2) go on: active again, and the
@@ -242,23 +267,33 @@ hipError_t launch_nll_backward(const double* r64, const double* gl, int64_t n, i
 {
     COX_LAUNCH(nll_backward_kernel, grid_for(n * B), r64, gl, n, B, out, out_f64);
 }
-hipError_t launch_dot(const double* a, const double* b, int64_t m, double* out, hipStream_t s)
+// workgroups of a two-level reduction over m values: about 4,096 values each, at most kRedParts
+static unsigned red_parts(int64_t m) { return (unsigned)min((int64_t)kRedParts, max((int64_t)1, (m + 4095) / 4096)); }
+
+hipError_t launch_dot(const double* a, const double* b, int64_t m, double* part, double* out, hipStream_t s)
 {
-    COX_LAUNCH(dot_kernel, 1, a, b, m, out);
+    const unsigned g = red_parts(m);
+    hipLaunchKernelGGL(dot_kernel, dim3(g), dim3(kT), 0, s, a, b, m, part);
+    COX_LAUNCH(part_sum_kernel, 1, part, (int)g, 1.0, out);
 }
-hipError_t launch_center_shift(const float* center, const float* scale, const double* v, int64_t p, double* out,
-                               hipStream_t s)
+hipError_t launch_center_shift(const float* center, const float* scale, const double* v, int64_t p, double* part,
+                               double* out, hipStream_t s)
 {
-    COX_LAUNCH(center_shift_kernel, 1, center, scale, v, p, out);
+    const unsigned g = red_parts(p);
+    hipLaunchKernelGGL(center_shift_kernel, dim3(g), dim3(kT), 0, s, center, scale, v, p, part);
+    COX_LAUNCH(part_sum_kernel, 1, part, (int)g, -1.0, out);
 }
 hipError_t launch_normalize(const double* in, const double* nrm2, const float* scale, double* vout, double* coef,
                             int64_t p, hipStream_t s)
 {
     COX_LAUNCH(normalize_kernel, grid_for(p), in, nrm2, scale, vout, coef, p);
 }
-hipError_t launch_to_r32(const double* u, const double* shift, float* r32, double* sumr, int64_t n, hipStream_t s)
+hipError_t launch_to_r32(const double* u, const double* shift, float* r32, double* sumr, int64_t n, double* part,
+                         hipStream_t s)
 {
-    COX_LAUNCH(to_r32_kernel, 1, u, shift, r32, sumr, n);
+    const unsigned g = red_parts(n);
+    hipLaunchKernelGGL(to_r32_kernel, dim3(g), dim3(kT), 0, s, u, shift, r32, n, part);
+    COX_LAUNCH(part_sum_kernel, 1, part, (int)g, 1.0, sumr);
 }
 hipError_t launch_resume(int32_t* status, int32_t* active, int32_t* kit, const int32_t* iters, int B,
                          hipStream_t s)
