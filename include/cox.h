@@ -175,7 +175,9 @@ typedef struct {
                               reductions, no floating-point atomics), so both values give the same
                               computation; 1 documents the requirement. */
     int32_t eta_mode;   /* 0: eta updated from the columns whose beta changed (FP64 accumulator);
-                           1: eta recomputed by a dense pass over X every step (two X passes) */
+                           1: eta recomputed every step by a dense product (as in cox_loss_grad: FP64
+                           passes of up to 8 vectors, or three exact limb passes on the matrix cores
+                           for B > 8 over allele counts) */
     int32_t poll;       /* steps between host checks of the convergence flags; <= 0: 16 */
     int32_t residual_bits; /* batched matrix-core gradient pass only (allele counts, B > 8): the
                               residual r_b is rounded to integers |R| <= 2^bits relative to
