@@ -142,6 +142,26 @@ def test_warm_start_non_finite_is_numeric(prob, mfma, monkeypatch):
     assert e.value.status == P.ERR_NUMERIC
 
 
+def test_batched_prox_step(prob):
+    """One ISTA step for 16 vectors from a nonzero start (the dense eta and the
+    X~' R pass on the matrix cores, then the proximal step), against the
+    oracle's first step from the same start."""
+    B = 16
+    cox, M = _setup(prob, "fp8", B)
+    lams = coxsim.lambda_grid(oracle.lambda_max(M, prob.time, prob.event), B, 0.05)
+    sigma = 1.0 / (2.0 * oracle.opnorm2(M)[0])
+    rng = np.random.default_rng(21)
+    beta0 = (0.03 * rng.standard_normal((B, prob.p)) * (rng.random((B, prob.p)) < 0.2)).astype(np.float32)
+    bt = torch.from_numpy(beta0.copy()).cuda()
+    obj = cox.prox_step(bt, lams, sigma)
+    got = bt.cpu().numpy()
+    for b in (0, 7, B - 1):
+        bo, tr, _, _ = oracle.fit(M, prob.time, prob.event, lams[b], sigma, max_iter=1,
+                                  beta0=beta0[b].astype(np.float64))
+        assert obj[b] == pytest.approx(tr[0], rel=1e-12), b
+        assert rel_beta_err(got[b], bo) <= BETA_TOL, b
+
+
 def test_batched_equals_single(prob):
     """The 64-wide matrix-core pass and 64 separate vector passes agree."""
     B = 64
