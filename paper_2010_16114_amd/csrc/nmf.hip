@@ -568,7 +568,7 @@ template <int R>
 hipError_t nmf_iteration(nmf_ctx* c, int algo, double eps, double* Vt, double* W)
 {
     const int r = c->r;
-    const unsigned gm = (unsigned)((c->m + kT - 1) / kT), gn = (unsigned)((c->n + kT - 1) / kT);
+    const unsigned gm = (unsigned)((c->m + kT - 1) / kT);
     nmark(c, 0);
     if (nmf_direct(c, W))
         hipLaunchKernelGGL((nmf_wxt_direct_kernel<R / 16, direct_gl(R)>), dim3(gm, c->ns_wxt), dim3(kT), 0, c->stream,
