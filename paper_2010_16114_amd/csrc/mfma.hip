@@ -230,43 +230,46 @@ __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_split_
 }
 
 // X~' R with both operands through LDS.  LW loader wavefronts move each
-// stage's X tile (the workgroup's WCOLS columns x 64 subjects, decoded to
+// stage's X tile (the workgroup's WCOLS columns x 16 QC subjects, decoded to
 // counts) and limb tile into LDS, with LDF stages of loads in flight in
-// registers; CW compute wavefronts read both from LDS and run the matrix cores.
-// The loaders read a column's 64 bytes of a stage with 4 adjacent lanes, so
-// that they go out as one 64-byte request with one address translation; in
-// the matrix-core layout that mfma_xtr_split_kernel loads directly those bytes
-// sit in lanes 16 apart and go out as four 16-byte requests.  In LDS a column
-// takes 80 bytes (64 + 16 of padding), so that the 16 lanes of a fragment read
-// (16 consecutive columns, one 16-byte chunk each) hit distinct banks.
-template <int XT, int NG, int RL, int CW, int LW, int MT, int LDF, bool NTX = false>
+// registers; CW compute wavefronts read both from LDS and run the matrix cores,
+// QC / 4 steps of 64 subjects per stage.  The loaders read a column's 16 QC
+// bytes of a stage with QC adjacent lanes, so that they go out as one request
+// with one address translation (QC = 8: one whole 128-byte line per column and
+// stage, where QC = 4 reads each line in two halves, a stage apart); in the
+// matrix-core layout that mfma_xtr_split_kernel loads directly those bytes sit
+// in lanes 16 apart and go out as separate 16-byte requests.  In LDS a column
+// takes 16 (QC + 1) bytes (16 of padding), so that the 16 lanes of a fragment
+// read (16 consecutive columns, one 16-byte chunk each) hit distinct banks.
+template <int XT, int NG, int RL, int CW, int LW, int MT, int LDF, bool NTX = false, int QC = 4>
 __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_lds_kernel(MfmaArgs a)
 {
     static_assert(LDF >= 2, "the loaders' ring needs two slots");
     static_assert(RL == 2 || RL == 3, "the residual comes in 2 or 3 limbs");
+    static_assert(QC == 4 || QC == 8, "stages of 64 or 128 subjects");
     constexpr int WCOLS = 16 * MT * CW;  // SNP columns per workgroup
     constexpr int NT = RL * NG;          // N tiles, limb-major: tile = limb * NG + b / 16
     constexpr int NCOL = 16 * NT;
-    constexpr int QC = 4;                // 16-subject chunks per stage of 64 subjects
+    constexpr int SUBJ = 16 * QC;        // subjects per stage
     constexpr int CHUNKS = NCOL * QC;    // limb chunks per stage
     constexpr int XCH = WCOLS * QC;      // X chunks per stage
     constexpr int LT = 64 * LW;
     constexpr int XPT = (XCH + LT - 1) / LT;
     constexpr int RPT = (CHUNKS + LT - 1) / LT;
     constexpr int RS = NCOL + 8;         // LDS row stride of the limb tile (16-byte units)
-    constexpr int XS = 5;                // LDS stride of a column of the X tile (16-byte units)
+    constexpr int XS = QC + 1;           // LDS stride of a column of the X tile (16-byte units)
     constexpr bool XALL = XCH % LT == 0, RALL = CHUNKS % LT == 0;
     __shared__ v4i sR[2][QC * RS];
     __shared__ v4i sX[2][WCOLS * XS];
 
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int64_t n = a.n, p = a.p, ldx = a.ldx;
-    const int64_t nstage = (n + 63) / 64;
+    const int64_t nstage = (n + SUBJ - 1) / SUBJ;
     const int64_t nloop = (nstage + LDF - 1) / LDF * LDF;
     const int64_t j0 = (int64_t)blockIdx.x * WCOLS;
 
     if (wid >= CW) {
-        // loaders.  X chunk c: column c / 4 of the workgroup, subjects 16 (c % 4) .. + 15 of the
+        // loaders.  X chunk c: column c / QC of the workgroup, subjects 16 (c % QC) .. + 15 of the
         // stage; a column past p, or a chunk that starts at or after n, loads the start of X (the
         // limb rows of subjects n .. round_up(n, 256) are zero, and columns >= p are never stored)
         const int lt = threadIdx.x - 64 * CW;
@@ -300,7 +303,7 @@ __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_lds_ke
         auto fetch = [&](int64_t t, v4i (&xg)[XPT], v4i (&rg)[RPT]) {
 #pragma unroll
             for (int k = 0; k < XPT; ++k) {
-                const int64_t row = t * 64 + xrow[k];
+                const int64_t row = t * SUBJ + xrow[k];
                 const v4i* src = reinterpret_cast<const v4i*>(X + (row < n ? xbase[k] + (uint64_t)row : 0));
                 if (xok[k]) {
                     if constexpr (NTX)
@@ -351,19 +354,23 @@ __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_lds_ke
     for (int64_t t = 0; t < nloop; ++t) {
         const int buf = (int)(t & 1);
         if (t < nstage) {
-            v4i A[MT];
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) A[mt] = sX[buf][(wid * MT * 16 + mt * 16 + acol) * XS + (lane >> 4)];
-            const v4i* sb = &sR[buf][(lane >> 4) * RS + acol];
-            v4i bcur = sb[0];
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                v4i bnext = bcur;
-                if (nt + 1 < NT) bnext = sb[(nt + 1) * 16];
+            for (int h = 0; h < QC / 4; ++h) {  // 64 subjects per matrix-core step
+                v4i A[MT];
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt)
-                    acc[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], bcur, acc[mt][nt], 0, 0, 0);
-                bcur = bnext;
+                    A[mt] = sX[buf][(wid * MT * 16 + mt * 16 + acol) * XS + 4 * h + (lane >> 4)];
+                const v4i* sb = &sR[buf][(4 * h + (lane >> 4)) * RS + acol];
+                v4i bcur = sb[0];
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    v4i bnext = bcur;
+                    if (nt + 1 < NT) bnext = sb[(nt + 1) * 16];
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+                        acc[mt][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], bcur, acc[mt][nt], 0, 0, 0);
+                    bcur = bnext;
+                }
             }
         }
         __syncthreads();
@@ -1150,11 +1157,11 @@ hipError_t launch_split(const MfmaArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int XT, int NG, int RL, int CW, int LW, int MT, int LDF, bool NTX = false>
+template <int XT, int NG, int RL, int CW, int LW, int MT, int LDF, bool NTX = false, int QC = 4>
 hipError_t launch_lds(const MfmaArgs& a, hipStream_t s)
 {
     constexpr int WCOLS = 16 * MT * CW;
-    hipLaunchKernelGGL((mfma_xtr_lds_kernel<XT, NG, RL, CW, LW, MT, LDF, NTX>),
+    hipLaunchKernelGGL((mfma_xtr_lds_kernel<XT, NG, RL, CW, LW, MT, LDF, NTX, QC>),
                        dim3((unsigned)((a.p + WCOLS - 1) / WCOLS)), dim3(64 * (CW + LW)), 0, s, a);
     return hipGetLastError();
 }
@@ -1171,6 +1178,7 @@ hipError_t launch_ng(const MfmaArgs& a, hipStream_t s)
     case 10: return launch_lds<XT, NG, RL, 4, 4, 4, 5>(a, s);
     case 11: return launch_lds<XT, NG, RL, 8, 4, 2, 4>(a, s);
     case 12: return launch_lds<XT, NG, RL, 8, 4, 2, 3>(a, s);
+    case 13: return launch_lds<XT, NG, RL, 4, 4, 4, 2, false, 8>(a, s);
     case 1: return launch_split<XT, NG, RL, 7, 1, 3, 1, 4>(a, s);
     case 2: return launch_split<XT, NG, RL, 6, 2, 3, 1, 6>(a, s);
     case 3: return launch_split<XT, NG, RL, 6, 2, 3, 1, 4>(a, s);

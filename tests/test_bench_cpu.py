@@ -23,8 +23,10 @@ def test_kernel_names_cover_every_shape():
 
 @pytest.mark.parametrize("summary,keys", [
     ("mfma_xtr_kernel_geno_fp8_400000x500000_b64_traffic.md",
-     [("launch", f"shape{v}") for v in range(13)] + [("column", f"eta_shape{v}") for v in range(13)]),
-    ("mfma_eta_kernel_dense_geno_fp8_400000x500000_b64_traffic.md", [("launch", f"shape{v}") for v in range(13)]),
+     [("launch", f"shape{v}") for v in range(P.MFMA_VARIANTS)]
+     + [("column", f"eta_shape{v}") for v in range(P.ETA_VARIANTS)]),
+    ("mfma_eta_kernel_dense_geno_fp8_400000x500000_b64_traffic.md",
+     [("launch", f"shape{v}") for v in range(P.ETA_VARIANTS)]),
 ])
 def test_traffic_summaries(summary, keys):
     path = os.path.join(ROOT, "profiles", summary)
