@@ -14,8 +14,8 @@
 //
 // Tiling: a workgroup of CW compute wavefronts owns 16 * MT * CW SNP columns
 // (MT M tiles of 16 per wavefront) and all 3 * B limb columns (N tiles of
-// 16), and walks K = n in stages of 64 * KS subjects; LW more wavefronts stage
-// the limb tiles.  X is read once per pass for all B vectors.  In
+// 16), and walks K = n in stages of 64 or 128 subjects; LW more wavefronts
+// stage the limb tiles.  X is read once per pass for all B vectors.  In
 // mfma_xtr_split_kernel the A fragments (16 subjects of one column per lane,
 // one 16-byte load) go straight to registers; in mfma_xtr_lds_kernel the
 // loader wavefronts stage X through LDS too.  Several shapes of both are
