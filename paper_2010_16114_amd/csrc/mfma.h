@@ -30,9 +30,10 @@ struct MfmaArgs {
                             // X through LDS as well, loaded by the loader wavefronts (compute +
                             // loader wavefronts, M tiles, stages of loads in flight): 8 = 4+4, 4, 3;
                             // 9 = 4+4, 4, 4; 10 = 4+4, 4, 5; 11 = 8+4, 2, 4; 12 = 8+4, 2, 3; with
-                            // stages of 128 subjects (a whole 128-byte line per column): 13 = 4+4, 4, 2
+                            // stages of 128 subjects (a whole 128-byte line per column): 13 = 4+4, 4, 2;
+                            // 14 = 13 with streaming (non-temporal) loads of X
 };
-constexpr int kMfmaVariants = 14;    // shapes of the X~' R pass
+constexpr int kMfmaVariants = 15;    // shapes of the X~' R pass
 constexpr int kMfmaEtaVariants = 13;  // shapes of the eta update
 
 // eta_b(i) += q_b * sum_{u < nsel} g(i, sel[u]) D_b(u), D in three int8 limbs.

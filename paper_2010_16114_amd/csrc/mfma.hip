@@ -1179,6 +1179,7 @@ hipError_t launch_ng(const MfmaArgs& a, hipStream_t s)
     case 11: return launch_lds<XT, NG, RL, 8, 4, 2, 4>(a, s);
     case 12: return launch_lds<XT, NG, RL, 8, 4, 2, 3>(a, s);
     case 13: return launch_lds<XT, NG, RL, 4, 4, 4, 2, false, 8>(a, s);
+    case 14: return launch_lds<XT, NG, RL, 4, 4, 4, 2, true, 8>(a, s);
     case 1: return launch_split<XT, NG, RL, 7, 1, 3, 1, 4>(a, s);
     case 2: return launch_split<XT, NG, RL, 6, 2, 3, 1, 6>(a, s);
     case 3: return launch_split<XT, NG, RL, 6, 2, 3, 1, 4>(a, s);
