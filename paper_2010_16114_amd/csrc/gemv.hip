@@ -135,8 +135,12 @@ __global__ __launch_bounds__(kT) void gemv16_kernel(XDesc x, const double* __res
 #pragma unroll
         for (int e = 0; e < RPL; ++e) acc[b][e] = 0.0;
     run ring[kPre];
-    auto fetch = [&](int64_t j) -> run {
-        return live && j < jend ? *reinterpret_cast<const run*>(X + j * ldx + r0) : run{};
+    auto fetch = [&](int64_t j) -> run {  // X is read once per pass: streaming loads
+        if (!(live && j < jend)) return run{};
+        if constexpr (RPL == 16)
+            return load_u4_stream(X + j * ldx + r0);
+        else
+            return load_u2_stream(X + j * ldx + r0);
     };
 #pragma unroll
     for (int u = 0; u < kPre; ++u) ring[u] = fetch(jbeg + u);

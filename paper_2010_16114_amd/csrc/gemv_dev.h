@@ -27,13 +27,14 @@ __device__ __forceinline__ void load_rows4(const XDesc& x, int64_t col, int64_t 
     const int64_t off = col * x.ldx + r0;
     if (VEC && r0 + 3 < n) {
         if constexpr (XT == XT_F32) {
-            const float4 v = load_f4(static_cast<const float*>(x.X) + off);
+            const float4 v = load_f4_stream(static_cast<const float*>(x.X) + off);
             o[0] = v.x;
             o[1] = v.y;
             o[2] = v.z;
             o[3] = v.w;
         } else {
-            const uint32_t w = *reinterpret_cast<const uint32_t*>(static_cast<const uint8_t*>(x.X) + off);
+            const uint32_t w =
+                __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(static_cast<const uint8_t*>(x.X) + off));
             decode4<XT>(w, o);
         }
     } else {

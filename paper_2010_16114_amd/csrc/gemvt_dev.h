@@ -114,8 +114,8 @@ __device__ __forceinline__ void gemvt_sums_blk(const GemvtArgs& a, int bx, int b
                         for (int c = 0; c < 4; ++c) {
                             if (cg + c < ncols && row < v1) {
                                 const int64_t off = (j0 + cg + c) * ldx + row;
-                                xv[c][u] = XT == XT_F32 ? load_u4(static_cast<const float*>(a.x.X) + off)
-                                                        : load_u4(static_cast<const uint8_t*>(a.x.X) + off);
+                                xv[c][u] = XT == XT_F32 ? load_u4_stream(static_cast<const float*>(a.x.X) + off)
+                                                        : load_u4_stream(static_cast<const uint8_t*>(a.x.X) + off);
                             } else {
                                 xv[c][u] = make_uint4(0, 0, 0, 0);
                             }
