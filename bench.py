@@ -117,6 +117,7 @@ def stored_traffic(summary: str, sources, shape="all", per="launch") -> float | 
 
 MFMA_SOURCES = ("paper_2010_16114_amd/csrc/mfma.hip", "paper_2010_16114_amd/csrc/mfma.h")
 GEMVT_SOURCES = ("paper_2010_16114_amd/csrc/gemvt.hip", "paper_2010_16114_amd/csrc/gemvt_dev.h",
+                 "paper_2010_16114_amd/csrc/device_common.h",
                  "paper_2010_16114_amd/csrc/internal.h")
 
 

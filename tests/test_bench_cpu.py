@@ -43,3 +43,19 @@ def test_traffic_summaries(summary, keys):
             assert v is None
     assert bench.stored_traffic(summary, bench.MFMA_SOURCES, "shape99") is None
     assert bench.stored_traffic("no_such_summary.md", bench.MFMA_SOURCES, "shape0") is None
+
+
+def test_column_sum_traffic_summary():
+    summary = "gemvt_sums_kernel_gauss_fp32_20000x50000_traffic.md"
+    text = open(os.path.join(ROOT, "profiles", summary)).read()
+    assert "rocprofv3 --pmc FETCH_SIZE" in text and "rocprofv3 --pmc WRITE_SIZE" in text
+    for src in bench.GEMVT_SOURCES:  # every file the kernel is built from is named under the hash
+        assert src in text
+    stored = [line.split(":", 1)[1].strip() for line in text.splitlines() if line.startswith("- source_sha256:")]
+    assert len(stored) == 1
+    v = bench.stored_traffic(summary, bench.GEMVT_SOURCES)
+    if stored[0] == bench.kernel_source_hash(bench.GEMVT_SOURCES):
+        # within 1% of X once (20,000 x 50,000 FP32) plus the vectors
+        assert v is not None and abs(v / 4.0005e9 - 1) < 0.01
+    else:
+        assert v is None
