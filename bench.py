@@ -66,10 +66,13 @@ INT8_MFMA_PEAK_TOPS = 5000.0  # dense int8 matrix-core peak of the MI355X
 
 def mfma_kernel_names(xtr_variant: int, eta_variant: int) -> tuple[str, str]:
     """Kernel names behind the matrix-core pipeline shapes the tuner kept:
-    X~' R shapes 0-7 are `mfma_xtr_split_kernel`, 8-14 `mfma_xtr_lds_kernel`;
+    X~' R shapes 0-7 are `mfma_xtr_split_kernel`, 8-14 `mfma_xtr_lds_kernel`, 15
+    that kernel with its last round split plus `xtr_tail_kernel`;
     eta shapes 0-1 are `mfma_eta_kernel`, 2-7 `mfma_eta_split_kernel`, and
     8-12 that kernel on one workgroup per compute unit plus `eta_fixup_kernel`."""
     xk = "mfma_xtr_split_kernel" if xtr_variant < 8 else "mfma_xtr_lds_kernel"
+    if xtr_variant >= 15:
+        xk += "+xtr_tail_kernel"
     if eta_variant < 2:
         ek = "mfma_eta_kernel"
     elif eta_variant < 8:

@@ -378,7 +378,7 @@ typedef enum {
  * choices (-1: not yet tuned) and the tuning times in milliseconds (host
  * [COX_MFMA_VARIANTS] each, nullable; entries past a pass's shape count and
  * entries of a pass that was not timed are 0). */
-#define COX_MFMA_VARIANTS 15
+#define COX_MFMA_VARIANTS 16
 #define COX_MFMA_ETA_VARIANTS 13
 cox_status cox_mfma_tuning(cox_ctx *ctx, int32_t *xtr_variant, int32_t *eta_variant, float *xtr_ms, float *eta_ms);
 cox_status cox_timing_enable(cox_ctx *ctx, int32_t enable);

@@ -24,7 +24,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "cox.h")
 NMF_HEADER = os.path.join(os.path.dirname(_HERE), "include", "nmf.h")
 
 X_F32, X_FP8_E4M3, X_INT8 = 0, 1, 2
-MFMA_VARIANTS = 15  # COX_MFMA_VARIANTS: pipeline shapes of the X~' R pass (and the tuning arrays' length)
+MFMA_VARIANTS = 16  # COX_MFMA_VARIANTS: pipeline shapes of the X~' R pass (and the tuning arrays' length)
 ETA_VARIANTS = 13  # COX_MFMA_ETA_VARIANTS: pipeline shapes of the eta update
 MAX_COVARIATES = 64  # COX_MAX_COVARIATES
 MAX_REFIT = 1024  # COX_MAX_REFIT

@@ -104,6 +104,7 @@ struct cox_ctx {
     int32_t *sel_all = nullptr, *nsel_all = nullptr;  // 0 .. p - 1 and p: every column, for dense passes
     int32_t* nonfin = nullptr;   // [max_batch] a dense pass's coefficient vector holds a NaN or infinity
     long long* eta_part = nullptr;  // [ncu][2][Bmax16][256] partial sums of blocks two eta workgroups share
+    long long* xtr_tail = nullptr;  // [3][Bmax16][ncu * 256] X~' R sums of the split last round (shape 15)
     int ncu = 0;                 // compute units of the device
     int64_t dstride = 0;
     double *dscale = nullptr, *dmaxp = nullptr;
@@ -823,6 +824,9 @@ cox_status run_gemvt(cox_ctx* c, GemvtArgs g, int B, int rlimbs = 3)
                "quantise r");
         MfmaArgs m{c->x.X,   c->x.xt, c->n, c->p,      c->x.ldx,     c->limbs, c->rstride,
                    bpad,     rlimbs,  B,    c->qscale, c->part_xtr, 0};
+        m.tail = c->xtr_tail;
+        m.tail_cols = (int64_t)c->ncu * 256;
+        m.ncu = c->ncu;
         int& chosen = c->xtr_by_limbs[rlimbs];
         const int forced = forced_variant("COXHIP_MFMA_VARIANT", kMfmaVariants);
         if (forced >= 0) {
@@ -1113,7 +1117,9 @@ cox_status cox_setup(cox_ctx** out, const cox_matrix* X, const double* time, con
             (void)hipGetLastError();
             c->ncu = 0;
         }
-        if (ok && c->ncu > 0) ok = dalloc(c, &c->eta_part, (size_t)c->ncu * 2 * c->bpad_max * 256);
+        if (ok && c->ncu > 0)
+            ok = dalloc(c, &c->eta_part, (size_t)c->ncu * 2 * c->bpad_max * 256) &&
+                 dalloc(c, &c->xtr_tail, (size_t)3 * c->bpad_max * c->ncu * 256);
     }
     if (ok) {
         c->pinned_bytes = 64 * 1024;

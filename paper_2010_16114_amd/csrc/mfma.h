@@ -31,9 +31,14 @@ struct MfmaArgs {
                             // loader wavefronts, M tiles, stages of loads in flight): 8 = 4+4, 4, 3;
                             // 9 = 4+4, 4, 4; 10 = 4+4, 4, 5; 11 = 8+4, 2, 4; 12 = 8+4, 2, 3; with
                             // stages of 128 subjects (a whole 128-byte line per column): 13 = 4+4, 4, 2;
-                            // 14 = 13 with streaming (non-temporal) loads of X
+                            // 14 = 13 with streaming (non-temporal) loads of X; 15 = 14 with the
+                            // last, partly filled round of workgroups split three ways over subjects
+    long long* tail = nullptr;  // shape 15: [3][B][tail_cols] exact sums of the split blocks
+    int64_t tail_cols = 0;      // columns tail holds per (share, b): >= the split blocks' columns
+    int ncu = 0;                // shape 15: compute units of the device
+    int64_t nfull = 0;          // set by the launch: blocks of columns that run unsplit
 };
-constexpr int kMfmaVariants = 15;    // shapes of the X~' R pass
+constexpr int kMfmaVariants = 16;    // shapes of the X~' R pass
 constexpr int kMfmaEtaVariants = 13;  // shapes of the eta update
 
 // eta_b(i) += q_b * sum_{u < nsel} g(i, sel[u]) D_b(u), D in three int8 limbs.

@@ -241,7 +241,12 @@ __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_split_
 // in lanes 16 apart and go out as separate 16-byte requests.  In LDS a column
 // takes 16 (QC + 1) bytes (16 of padding), so that the 16 lanes of a fragment
 // read (16 consecutive columns, one 16-byte chunk each) hit distinct banks.
-template <int XT, int NG, int RL, int CW, int LW, int MT, int LDF, bool NTX = false, int QC = 4>
+//
+// KSPLIT > 1 splits the last, partly filled round of workgroups: each block of
+// columns from a.nfull on is taken by KSPLIT workgroups, one run of consecutive
+// stages each, which write their exact integer sums to a.tail for
+// xtr_tail_kernel to add (integer sums: the result equals the unsplit one).
+template <int XT, int NG, int RL, int CW, int LW, int MT, int LDF, bool NTX = false, int QC = 4, int KSPLIT = 1>
 __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_lds_kernel(MfmaArgs a)
 {
     static_assert(LDF >= 2, "the loaders' ring needs two slots");
@@ -265,13 +270,26 @@ __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_lds_ke
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int64_t n = a.n, p = a.p, ldx = a.ldx;
     const int64_t nstage = (n + SUBJ - 1) / SUBJ;
-    const int64_t nloop = (nstage + LDF - 1) / LDF * LDF;
-    const int64_t j0 = (int64_t)blockIdx.x * WCOLS;
+    int64_t blk = blockIdx.x, t0 = 0, t1 = nstage;  // block of columns, stages [t0, t1)
+    int part = -1;                                  // share of a split block, or -1
+    if constexpr (KSPLIT > 1) {
+        if (blk >= a.nfull) {
+            const int64_t v = blk - a.nfull;
+            blk = a.nfull + v / KSPLIT;
+            part = (int)(v % KSPLIT);
+            t0 = nstage * part / KSPLIT;
+            t1 = nstage * (part + 1) / KSPLIT;
+        }
+    }
+    const int64_t nst = t1 - t0;
+    const int64_t nloop = (nst + LDF - 1) / LDF * LDF;
+    const int64_t j0 = blk * WCOLS;
 
     if (wid >= CW) {
         // loaders.  X chunk c: column c / QC of the workgroup, subjects 16 (c % QC) .. + 15 of the
         // stage; a column past p, or a chunk that starts at or after n, loads the start of X (the
-        // limb rows of subjects n .. round_up(n, 256) are zero, and columns >= p are never stored)
+        // limb rows of subjects n .. round_up(n, 256) are zero, and columns >= p are never stored).
+        // t counts the workgroup's stages from t0; the ring slots and LDS buffers go by t
         const int lt = threadIdx.x - 64 * CW;
         const uint8_t* __restrict__ X = static_cast<const uint8_t*>(a.X);
         uint64_t xbase[XPT];
@@ -303,7 +321,7 @@ __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_lds_ke
         auto fetch = [&](int64_t t, v4i (&xg)[XPT], v4i (&rg)[RPT]) {
 #pragma unroll
             for (int k = 0; k < XPT; ++k) {
-                const int64_t row = t * SUBJ + xrow[k];
+                const int64_t row = (t0 + t) * SUBJ + xrow[k];
                 const v4i* src = reinterpret_cast<const v4i*>(X + (row < n ? xbase[k] + (uint64_t)row : 0));
                 if (xok[k]) {
                     if constexpr (NTX)
@@ -312,7 +330,7 @@ __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_lds_ke
                         xg[k] = *src;
                 }
             }
-            const int64_t kr = min(t, nstage - 1) * (int64_t)(16 * CHUNKS);
+            const int64_t kr = min(t0 + t, nstage - 1) * (int64_t)(16 * CHUNKS);
 #pragma unroll
             for (int k = 0; k < RPT; ++k)
                 if (rok[k]) rg[k] = *reinterpret_cast<const v4i*>(rsrc[k] + kr);
@@ -353,7 +371,7 @@ __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_lds_ke
     __syncthreads();  // the loaders' first stage is in LDS
     for (int64_t t = 0; t < nloop; ++t) {
         const int buf = (int)(t & 1);
-        if (t < nstage) {
+        if (t < nst) {
 #pragma unroll
             for (int h = 0; h < QC / 4; ++h) {  // 64 subjects per matrix-core step
                 v4i A[MT];
@@ -386,9 +404,24 @@ __global__ __launch_bounds__(64 * (CW + LW), (CW + LW) / 4) void mfma_xtr_lds_ke
                 if (j < p && b < a.B) {
                     int64_t tot = (int64_t)acc[mt][bq][v] + 256 * (int64_t)acc[mt][NG + bq][v];
                     if constexpr (RL == 3) tot += 65536 * (int64_t)acc[mt][2 * NG + bq][v];
-                    a.out[(int64_t)b * p + j] = a.qscale[b] * (double)tot;
+                    if (KSPLIT > 1 && part >= 0)
+                        a.tail[((int64_t)part * a.B + b) * a.tail_cols + (j - a.nfull * WCOLS)] = tot;
+                    else
+                        a.out[(int64_t)b * p + j] = a.qscale[b] * (double)tot;
                 }
             }
+}
+
+// The split blocks' sums: out[b][j0 + jj] = qscale_b (the sum over the ksplit shares).
+__global__ __launch_bounds__(kT) void xtr_tail_kernel(MfmaArgs a, int ksplit, int64_t j0, int64_t ptail)
+{
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i >= (int64_t)a.B * ptail) return;
+    const int b = (int)(i / ptail);
+    const int64_t jj = i - (int64_t)b * ptail;
+    long long tot = 0;
+    for (int k = 0; k < ksplit; ++k) tot += a.tail[((int64_t)k * a.B + b) * a.tail_cols + jj];
+    a.out[(int64_t)b * a.p + j0 + jj] = a.qscale[b] * (double)tot;
 }
 
 // Byte transpose of a 4 x 4 block: d[r] holds bytes (x_r0, x_r1, x_r2, x_r3);
@@ -1166,6 +1199,32 @@ hipError_t launch_lds(const MfmaArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+// Shape 15's launch: the blocks of columns that fill whole rounds of resident
+// workgroups run unsplit, and the rest (the last round's) are split KSPLIT ways.
+template <int XT, int NG, int RL, int CW, int LW, int MT, int LDF, bool NTX, int QC, int KSPLIT>
+hipError_t launch_lds_tail(const MfmaArgs& a, hipStream_t s)
+{
+    constexpr int WCOLS = 16 * MT * CW;
+    const void* fn = reinterpret_cast<const void*>(&mfma_xtr_lds_kernel<XT, NG, RL, CW, LW, MT, LDF, NTX, QC, KSPLIT>);
+    if (!a.tail || a.ncu < 1) return hipErrorInvalidValue;
+    int per_cu = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * (CW + LW), 0);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    const int64_t nblk = (a.p + WCOLS - 1) / WCOLS, slots = (int64_t)a.ncu * per_cu;
+    const int64_t ntail = nblk % slots;
+    MfmaArgs b = a;
+    b.nfull = nblk - ntail;
+    const int64_t j0 = b.nfull * WCOLS, ptail = a.p - j0;
+    if (ntail > 0 && ptail > a.tail_cols) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((mfma_xtr_lds_kernel<XT, NG, RL, CW, LW, MT, LDF, NTX, QC, KSPLIT>),
+                       dim3((unsigned)(b.nfull + KSPLIT * ntail)), dim3(64 * (CW + LW)), 0, s, b);
+    if (ntail > 0)
+        hipLaunchKernelGGL(xtr_tail_kernel, dim3((unsigned)((a.B * ptail + kT - 1) / kT)), dim3(kT), 0, s, b, KSPLIT,
+                           j0, ptail);
+    return hipGetLastError();
+}
+
 template <int XT, int NG, int RL>
 hipError_t launch_ng(const MfmaArgs& a, hipStream_t s)
 {
@@ -1180,6 +1239,7 @@ hipError_t launch_ng(const MfmaArgs& a, hipStream_t s)
     case 12: return launch_lds<XT, NG, RL, 8, 4, 2, 3>(a, s);
     case 13: return launch_lds<XT, NG, RL, 4, 4, 4, 2, false, 8>(a, s);
     case 14: return launch_lds<XT, NG, RL, 4, 4, 4, 2, true, 8>(a, s);
+    case 15: return launch_lds_tail<XT, NG, RL, 4, 4, 4, 2, true, 8, 3>(a, s);
     case 1: return launch_split<XT, NG, RL, 7, 1, 3, 1, 4>(a, s);
     case 2: return launch_split<XT, NG, RL, 6, 2, 3, 1, 6>(a, s);
     case 3: return launch_split<XT, NG, RL, 6, 2, 3, 1, 4>(a, s);

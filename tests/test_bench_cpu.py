@@ -14,7 +14,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def test_kernel_names_cover_every_shape():
     for v in range(P.MFMA_VARIANTS):
         xk, _ = bench.mfma_kernel_names(v, 0)
-        assert xk == ("mfma_xtr_split_kernel" if v < 8 else "mfma_xtr_lds_kernel")
+        assert xk.startswith("mfma_xtr_split_kernel" if v < 8 else "mfma_xtr_lds_kernel")
+        assert ("xtr_tail_kernel" in xk) == (v >= 15)
     for v in range(P.ETA_VARIANTS):
         _, ek = bench.mfma_kernel_names(0, v)
         assert ek.startswith("mfma_eta_kernel" if v < 2 else "mfma_eta_split_kernel")
