@@ -231,6 +231,30 @@ def test_every_pipeline_shape(prob, variant, monkeypatch):
         assert obj[b] == pytest.approx(tr[-1], rel=OBJ_TOL)
 
 
+@pytest.mark.parametrize("B", [64, 40])
+def test_xtr_split_tail_bit_identical(B, monkeypatch):
+    """X~' R shape 15 (the last, partly filled round of workgroups split three
+    ways over subjects, the shares' exact integer sums added by a second
+    kernel) gives bit for bit the iterates of shape 14, the same kernel
+    unsplit, at a width with whole rounds and a split ragged tail: p = 70,001
+    is 274 blocks of 256 columns, 256 of them one round on a 256-CU device,
+    18 split; n = 2,003 is 16 stages of 128 subjects (shares of 5, 5, 6)."""
+    d = coxsim.genotype_problem(2003, 70001, 12, 0.8, 515, days=True)
+    cox, _ = _setup(d, "fp8", B)
+    lams = coxsim.lambda_grid(cox.lambda_max(), B, 0.01)
+    sigma = 1.0 / (2.0 * cox.opnorm2()[0])
+    monkeypatch.setenv("COXHIP_ETA_VARIANT", "10")
+    out = []
+    for v in (14, 15):
+        monkeypatch.setenv("COXHIP_MFMA_VARIANT", str(v))
+        beta, _, obj, _ = cox.fit_path(lams, max_iter=8, tol=0.0, step=sigma)
+        assert cox.mfma_tuning()["xtr_variant"] == v
+        out.append((beta.cpu().numpy(), np.asarray(obj)))
+    assert (out[0][0] != 0).sum() > B  # many columns active
+    np.testing.assert_array_equal(out[1][0].view(np.uint32), out[0][0].view(np.uint32))
+    np.testing.assert_array_equal(out[1][1], out[0][1])
+
+
 # shares: one workgroup for all 12 blocks of 256 subjects, five (each share 2.4
 # blocks, so four blocks are split between two of them), eleven
 @pytest.mark.parametrize("ev,B", [(8, 64), (9, 64), (10, 64), (11, 64), (12, 64), (11, 40), (8, 20)])
