@@ -188,13 +188,28 @@ __global__ __launch_bounds__(kT) void eta_update_kernel(XDesc x, const int32_t* 
     eta_update_blk<XT, NB, VEC>(x, sel, nsel_p, dcoef, b0, nb, part, cstride, ncg, active, blockIdx.x, blockIdx.y);
 }
 
+// One workgroup per chunk of 1024 blocks of columns.  Each adds up the counts
+// of the blocks before its chunk itself (a few thousand integers at most), so
+// the chunks are compacted in parallel into one ascending list.
 __global__ __launch_bounds__(1024) void compact_kernel(const int32_t* __restrict__ cnt,
                                                        const int32_t* __restrict__ idx, int nblk,
                                                        int32_t* __restrict__ sel, int32_t* __restrict__ nsel)
 {
+    constexpr int NT = 1024;
     __shared__ int sh[17];
-    __shared__ int sstart[1024], scnt[1024];
-    compact_blk<1024>(cnt, idx, nblk, sel, nsel, sh, sstart, scnt);
+    __shared__ int sstart[NT], scnt[NT];
+    const int b0 = blockIdx.x * NT;
+    int pre = 0;
+    for (int k = threadIdx.x; k < b0; k += NT) pre += cnt[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) pre += __shfl_xor(pre, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = pre;
+    __syncthreads();
+    int carry = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) carry += sh[w];
+    __syncthreads();  // the scan below reuses sh
+    compact_blk<NT>(cnt, idx, nblk, sel, nsel, sh, sstart, scnt, b0, b0 + NT, carry);
 }
 
 template <int XT, int NB>
@@ -310,7 +325,10 @@ hipError_t launch_eta_update(const XDesc& x, const int32_t* sel, const int32_t* 
 hipError_t launch_compact(const int32_t* chg_cnt, const int32_t* chg_idx, int nblk, int32_t* sel, int32_t* nsel,
                           hipStream_t s)
 {
-    hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(1024), 0, s, chg_cnt, chg_idx, nblk, sel, nsel);
+    if (nblk < 0) return hipErrorInvalidValue;
+    const int nchunk = nblk > 0 ? (nblk + 1023) / 1024 : 1;
+    hipLaunchKernelGGL(compact_kernel, dim3((unsigned)nchunk), dim3(1024), 0, s, chg_cnt,
+                       chg_idx, nblk, sel, nsel);
     return hipGetLastError();
 }
 

@@ -125,17 +125,19 @@ __device__ __forceinline__ void eta_update_blk(const XDesc& x, const int32_t* __
 template <int NT>
 __device__ __forceinline__ void compact_blk(const int32_t* __restrict__ cnt, const int32_t* __restrict__ idx,
                                             int nblk, int32_t* __restrict__ sel, int32_t* __restrict__ nsel,
-                                            int* sh, int* sstart, int* scnt)
+                                            int* sh, int* sstart, int* scnt, int b0 = 0, int b1 = 0x7fffffff,
+                                            int carry = 0)
 {
     static_assert(NT % kGemvtCols == 0 && NT % 64 == 0 && NT <= 1024 && kGemvtCols <= 64,
                   "lane groups tile the workgroup");
     constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int grp = threadIdx.x / kGemvtCols, q = threadIdx.x % kGemvtCols;
-    int carry = 0;
-    for (int base = 0; base < nblk; base += NT) {
+    // blocks [b0, min(b1, nblk)); carry = the changed columns of the blocks before b0
+    const int bend = min(nblk, b1);
+    for (int base = b0; base < bend; base += NT) {
         const int blk = base + threadIdx.x;
-        const int c = blk < nblk ? cnt[blk] : 0;
+        const int c = blk < bend ? cnt[blk] : 0;
         int inc = c;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
@@ -165,7 +167,7 @@ __device__ __forceinline__ void compact_blk(const int32_t* __restrict__ cnt, con
         carry += tot;
         __syncthreads();
     }
-    if (threadIdx.x == 0) *nsel = carry;
+    if (threadIdx.x == 0 && bend == nblk) *nsel = carry;
 }
 
 }  // namespace gemvdev
